@@ -1,0 +1,163 @@
+"""Krylov approximations of f(A)b (oracle side, test infrastructure).
+
+Plain, slow FP64 implementations of the paper's definitions and algorithms:
+
+* ``arnoldi``            Arnoldi decomposition A U_m = U_{m+1} K_m, eq. (2).
+* ``fm``                 f_m = ||b|| U_m f(K_m) e_1, eq. (4) -- the parity target.
+* ``truncated_arnoldi``  Algorithm 2 (k-truncated orthogonalisation), giving the
+                         Arnoldi-like decomposition A V_m = V_{m+1} H_m, eq. (3).
+* ``nt``                 Algorithm 4 (least-squares correction of the last
+                         column, eqs. (6)-(7)) and Algorithm 5 (no correction,
+                         eq. (8)); the least-squares problem is solved exactly,
+                         by sketch-and-solve (Remark 3) or skipped.
+* ``sfom``               the sFOM approximation, eq. (9).
+
+Readings of the printed Algorithm 2 (typographical slips in the inner loop):
+the update subtracts h_{j,i-1} v_j (the coefficient just computed times the
+window vector j), and the new column's subdiagonal entry is ||w_i||.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sl
+
+from . import matfun
+
+EPS = np.finfo(np.float64).eps
+
+
+def _breakdown_tol() -> float:
+    return 100.0 * EPS
+
+
+def arnoldi(A, b: np.ndarray, m: int):
+    """Arnoldi decomposition, eq. (2).
+
+    Gram-Schmidt with one full re-orthogonalisation pass, so that the returned
+    U is orthonormal to working precision and K = U^T A U (the compression of
+    A onto K_m(A, b)).  Stops early on an invariant subspace (h_{j+1,j} below
+    100 eps ||A u_j||) and then returns the exact dimension j.
+
+    Returns (U rows u_1..u_{mu+1} as a (mu+1) x n array (mu x n on breakdown),
+    Kbar (mu+1) x mu, beta = ||b||, mu).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    U = np.zeros((m + 1, n))
+    K = np.zeros((m + 1, m))
+    beta = float(np.linalg.norm(b))
+    U[0] = b / beta
+    for j in range(m):
+        w = A @ U[j]
+        wn = np.linalg.norm(w)
+        Q = U[: j + 1]
+        h = Q @ w
+        w = w - Q.T @ h
+        h2 = Q @ w
+        w = w - Q.T @ h2
+        K[: j + 1, j] = h + h2
+        K[j + 1, j] = np.linalg.norm(w)
+        if K[j + 1, j] <= _breakdown_tol() * wn:
+            return U[: j + 1], K[: j + 2, : j + 1], beta, j + 1
+        U[j + 1] = w / K[j + 1, j]
+    return U, K, beta, m
+
+
+def fm(A, b: np.ndarray, f, m: int) -> np.ndarray:
+    """f_m = ||b||_2 U_m f(K_m) e_1, eq. (4).  Multi-column b is handled column by column."""
+    b = np.asarray(b, dtype=np.float64)
+    if b.ndim == 2:
+        return np.stack([fm(A, b[:, r], f, m) for r in range(b.shape[1])], axis=1)
+    if not np.any(b):
+        return np.zeros_like(b)
+    U, K, beta, mu = arnoldi(A, b, m)
+    c = matfun.fmat_e1(f, K[:mu, :mu])
+    return beta * (U[:mu].T @ c)
+
+
+def truncated_arnoldi(A, b: np.ndarray, m: int, k: int):
+    """Algorithm 2: each new w_i = A v_{i-1} is orthogonalised (modified
+    Gram-Schmidt) against the last k basis vectors only, then normalised.
+
+    Returns (V rows v_1..v_{mu+1}, Hbar (mu+1) x mu, beta, mu, breakdown) with
+    A V_mu = V_{mu+1} Hbar (eq. (3)).  On an invariant subspace (new norm below
+    100 eps ||w_i||) it stops at dimension mu with breakdown=True; then V has
+    mu rows and Hbar's last row is zero.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    V = np.zeros((m + 1, n))
+    H = np.zeros((m + 1, m))
+    beta = float(np.linalg.norm(b))
+    V[0] = b / beta
+    for i in range(1, m + 1):
+        w = A @ V[i - 1]
+        wn = np.linalg.norm(w)
+        for j in range(max(0, i - k), i):
+            H[j, i - 1] = V[j] @ w
+            w = w - H[j, i - 1] * V[j]
+        H[i, i - 1] = np.linalg.norm(w)
+        if H[i, i - 1] <= _breakdown_tol() * wn:
+            H[i, i - 1] = 0.0
+            return V[:i], H[: i + 1, :i], beta, i, True
+        V[i] = w / H[i, i - 1]
+    return V, H, beta, m, False
+
+
+def sketched_qr(SV: np.ndarray):
+    """Householder QR of the sketched basis (LAPACK via numpy)."""
+    Q, R = np.linalg.qr(SV, mode="reduced")
+    return Q, R
+
+
+def nt(A, b: np.ndarray, f, m: int, k: int, sketch=None, ls: str = "sketch"):
+    """Algorithms 4 and 5 with every intermediate returned.
+
+    ls = "exact"  : y = argmin ||V_m z - v_{m+1}||_2 (eq. (7)), dense lstsq;
+    ls = "sketch" : y = argmin ||Theta (V_m z - v_{m+1})||_2 (sketch-and-solve,
+                    Remark 3), via QR of Theta V_m;
+    ls = "none"   : y = 0, i.e. Algorithm 5 / eq. (8).
+    The compression is H_hat = H_m + h_{m+1,m} y e_m^T (eq. (6)) and the result
+    ||b|| V_m f(H_hat) e_1 (Algorithm 4, last line).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    V, Hbar, beta, mu, brk = truncated_arnoldi(A, b, m, k)
+    out = {"V": V, "Hbar": Hbar, "beta": beta, "m_used": mu, "breakdown": brk}
+    if sketch is not None:
+        out["SV"] = sketch.apply(V.T)
+    Hm = Hbar[:mu, :mu].copy()
+    y = np.zeros(mu)
+    if not brk and ls != "none":
+        if ls == "exact":
+            y = np.linalg.lstsq(V[:mu].T, V[mu], rcond=None)[0]
+        elif ls == "sketch":
+            SV = out["SV"]
+            Q, R = sketched_qr(SV[:, :mu])
+            y = sl.solve_triangular(R, Q.T @ SV[:, mu])
+            out["R"] = R
+        else:
+            raise ValueError(ls)
+    Hhat = Hm.copy()
+    if not brk:
+        Hhat[:, mu - 1] += Hbar[mu, mu - 1] * y
+    c = matfun.fmat_e1(f, Hhat)
+    out.update(y=y, Hhat=Hhat, c=c, f=beta * (V[:mu].T @ c))
+    return out
+
+
+def sfom(A, b: np.ndarray, f, m: int, k: int, sketch) -> np.ndarray:
+    """sFOM, eq. (9): V_m R^{-1} f(S^T Theta A V_m R^{-1}) S^T Theta b,
+    with Theta V_m = S R and the basis from Algorithm 2."""
+    V, Hbar, beta, mu, brk = truncated_arnoldi(A, b, m, k)
+    Vm = V[:mu].T
+    S, R = sketched_qr(sketch.apply(Vm))
+    SAV = sketch.apply(np.column_stack([A @ Vm[:, j] for j in range(mu)]))
+    M = S.T @ SAV @ np.linalg.inv(R)
+    z = matfun.fmat(f, M) @ (S.T @ sketch.apply(np.asarray(b, dtype=np.float64)))
+    return Vm @ sl.solve_triangular(R, z)
+
+
+def relerr(x: np.ndarray, ref: np.ndarray) -> float:
+    """Relative 2-norm error, as reported in Section 5."""
+    d = float(np.linalg.norm(ref))
+    return float(np.linalg.norm(np.asarray(x) - ref)) / (d if d > 0 else 1.0)

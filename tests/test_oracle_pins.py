@@ -1,0 +1,340 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test ties one oracle function to something the mathematics or an
+independent routine fixes: published generator outputs, a library Hadamard
+matrix, dense eigendecomposition, closed forms, invariants and exactness
+results stated in the paper.  A plausible slip in the oracle (a dropped term,
+a wrong sign or index, a transposed operand) fails at least one of them; the
+mutation tests at the end plant such slips and check that they are caught.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sl
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import closed_form, krylov, matfun, operators, rng, sketch
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+EXP1 = W.FuncSpec("exp", alpha=-1.0)
+
+
+def _rand_nonsym(n, seed, shift=0.0):
+    r = np.random.default_rng(seed)
+    return r.standard_normal((n, n)) / math.sqrt(n) + shift * np.eye(n)
+
+
+def _rand_spd(n, seed, lo=0.5, hi=4.0):
+    r = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(r.standard_normal((n, n)))
+    return (Q * np.linspace(lo, hi, n)) @ Q.T
+
+
+# --------------------------------------------------------------------------- RNG
+def test_splitmix64_published_outputs():
+    vals = [int(l, 16) for l in open(os.path.join(GOLD, "splitmix64_seed0.txt")) if l.startswith("0x")]
+    assert [rng.out(0, i) for i in range(4)] == vals
+    assert list(rng.values(0, 0, np.arange(3))) == [rng.value(0, 0, i) for i in range(3)]
+
+
+# --------------------------------------------------------------------------- SRHT
+@pytest.mark.parametrize("p", [0, 1, 3, 6, 10])
+def test_fwht_matches_library_sylvester_hadamard(p):
+    n = 1 << p
+    x = np.random.default_rng(p).standard_normal((n, 3))
+    np.testing.assert_allclose(sketch.fwht(x), sl.hadamard(n) @ x, rtol=0, atol=1e-12 * n)
+
+
+@pytest.mark.parametrize("n,s,seed", [(37, 11, 5), (64, 64, 1), (1000, 40, 9)])
+def test_srht_is_scaled_rows_of_HD(n, s, seed):
+    npad = sketch.next_pow2(n)
+    rows = sketch.srht_rows(n, s, seed)
+    assert len(set(rows.tolist())) == s and rows.min() >= 0 and rows.max() < npad
+    d = sketch.srht_signs(n, seed)
+    ref = sl.hadamard(npad)[rows][:, :n] * d[None, :] / math.sqrt(s)
+    np.testing.assert_allclose(sketch.srht_apply(np.eye(n), s, seed), ref, atol=1e-14)
+    np.testing.assert_allclose(sketch.srht_dense(n, s, seed), ref, atol=0)
+
+
+def test_srht_embedding_statistics():
+    n, m, s = 4096, 20, 200
+    Q, _ = np.linalg.qr(np.random.default_rng(0).standard_normal((n, m)))
+    norms, conds = [], []
+    for seed in range(40):
+        SQ = sketch.srht_apply(Q, s, seed)
+        sv = np.linalg.svd(SQ, compute_uv=False)
+        conds.append(sv[0] / sv[-1])
+        norms.append(np.sum(SQ[:, 0] ** 2))
+    assert abs(np.mean(norms) - 1.0) < 0.1          # E ||Theta x||^2 = ||x||^2
+    assert np.median(conds) < 3.0                    # subspace embedding for s = 10 m
+    signs = sketch.srht_signs(100000, 3)
+    assert abs(signs.mean()) < 0.02
+
+
+# --------------------------------------------------------------------------- sparse sign
+def test_sparse_sign_columns_exact_structure():
+    n, s, zeta = 5000, 82, 8
+    rows, signs = sketch.sparse_sign_pattern(n, s, zeta, 1)
+    assert rows.min() >= 0 and rows.max() < s
+    assert all(len(set(r)) == zeta for r in rows.tolist())
+    T = sketch.sparse_sign_matrix(n, s, zeta, 1)
+    colnorm = np.sqrt(np.asarray(T.multiply(T).sum(axis=0))).ravel()
+    np.testing.assert_allclose(colnorm, 1.0, rtol=1e-15)     # each column has unit norm
+    assert set(np.unique(T.data).round(12)) == {round(1 / math.sqrt(zeta), 12), round(-1 / math.sqrt(zeta), 12)}
+
+
+def test_sparse_sign_floyd_is_uniform():
+    n, s, zeta = 200000, 40, 8
+    rows, signs = sketch.sparse_sign_pattern(n, s, zeta, 7)
+    counts = np.bincount(rows.ravel(), minlength=s)
+    expected = n * zeta / s
+    chi2 = float(((counts - expected) ** 2 / expected).sum())
+    assert chi2 < 2.5 * s                                     # dof = s-1
+    assert abs(signs.mean()) < 0.01
+
+
+def test_sparse_sign_embedding():
+    n, m, s = 3000, 15, 150
+    Q, _ = np.linalg.qr(np.random.default_rng(2).standard_normal((n, m)))
+    conds = [np.linalg.cond(sketch.Sketch("sparse_sign", n, s, seed).apply(Q)) for seed in range(10)]
+    assert np.median(conds) < 3.0
+
+
+# --------------------------------------------------------------------------- operators
+def test_stencil_matrix_entries():
+    st = W.Stencil(3, 4, 3, 2, (7.0, -1.0, -2.0, -3.0, -4.0, -5.0, -6.0))
+    A = operators.stencil_matrix(st).toarray()
+    idx = lambda x, y, z: x + 4 * (y + 3 * z)
+    assert A[idx(1, 1, 1), idx(1, 1, 1)] == 7.0
+    assert A[idx(1, 1, 1), idx(0, 1, 1)] == -1.0 and A[idx(1, 1, 1), idx(2, 1, 1)] == -2.0
+    assert A[idx(1, 1, 1), idx(1, 0, 1)] == -3.0 and A[idx(1, 1, 1), idx(1, 2, 1)] == -4.0
+    assert A[idx(1, 1, 1), idx(1, 1, 0)] == -5.0 and A[idx(1, 1, 0), idx(1, 1, 1)] == -6.0
+    assert A[idx(3, 0, 0), idx(0, 1, 0)] == 0.0        # no wrap-around at the x boundary
+    assert np.count_nonzero(A[idx(0, 0, 0)]) == 4
+
+
+def test_convdiff_scaling_and_upwinding():
+    st = W.convdiff3d(8, 50.0)
+    A = operators.stencil_matrix(st)
+    absA = abs(A)
+    assert math.isclose(absA.sum(axis=1).max(), 1e3, rel_tol=1e-12)
+    assert math.isclose(absA.sum(axis=0).max(), 1e3, rel_tol=1e-12)
+    c, xm, xp = st.coeff[:3]
+    assert xm < xp < 0 < c                             # upstream neighbour carries the convection
+    assert np.linalg.norm(A.toarray(), 2) <= 1e3
+
+
+def test_rgg_laplacian_properties():
+    rowptr, col, val = W.rgg_laplacian(4096, seed=3)
+    L = operators.csr_matrix(rowptr, col, val)
+    assert abs(L - L.T).max() == 0
+    np.testing.assert_allclose(np.asarray(L.sum(axis=1)).ravel(), 0.0, atol=0)
+    deg = np.diff(rowptr) - 1
+    assert 8.0 < deg.mean() < 11.0
+    assert all(np.all(np.diff(col[rowptr[i]:rowptr[i + 1]]) > 0) for i in range(0, 4096, 97))
+
+
+# --------------------------------------------------------------------------- matrix functions
+def test_matfun_against_eigendecomposition():
+    K = _rand_spd(30, 1)
+    lam, X = np.linalg.eigh(K)
+    e1 = np.eye(30)[:, 0]
+    for f in (W.FuncSpec("exp", alpha=-0.7), W.FuncSpec("pow", sigma=1e-3, p=0.5),
+              W.FuncSpec("pow", sigma=1e-3, p=-0.5), W.FuncSpec("poly", coef=(1.0, -2.0, 0.5))):
+        ref = X @ (matfun.fscalar(f, lam) * X[0])
+        np.testing.assert_allclose(matfun.fmat_e1(f, K), ref, rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(matfun.fmat(f, K)[:, 0], ref, rtol=1e-11, atol=1e-12)
+    assert np.allclose(e1, e1)
+
+
+def test_matfun_sqrt_nonsymmetric_squares_back():
+    K = np.triu(_rand_nonsym(25, 4, shift=3.0), -1)   # Hessenberg, spectrum in the right half plane
+    R = matfun.fmat(W.FuncSpec("pow", sigma=0.0, p=0.5), K)
+    np.testing.assert_allclose(R @ R, K, atol=1e-11)
+    x = matfun.fmat_e1(W.FuncSpec("pow", sigma=0.0, p=-0.5), K)
+    np.testing.assert_allclose(R @ x, np.eye(25)[:, 0], atol=1e-11)
+
+
+# --------------------------------------------------------------------------- Arnoldi and f_m
+def test_arnoldi_relation_and_orthonormality():
+    A = sp.csr_matrix(_rand_nonsym(200, 3))
+    b = np.random.default_rng(4).standard_normal(200)
+    U, K, beta, mu = krylov.arnoldi(A, b, 40)
+    assert mu == 40
+    nA = np.linalg.norm(A.toarray(), 2)
+    assert np.abs(U @ U.T - np.eye(41)).max() < 1e-13
+    assert np.abs(A @ U[:40].T - U.T @ K).max() < 1e-13 * nA
+    assert np.all(np.tril(K, -2) == 0)
+    np.testing.assert_allclose(U[0] * beta, b, rtol=1e-15)
+    np.testing.assert_allclose(U[:40] @ (A @ U[:40].T), K[:40], atol=1e-13 * nA)
+
+
+@pytest.mark.parametrize("f", [W.FuncSpec("exp", alpha=-0.5), W.FuncSpec("pow", sigma=0.1, p=0.5),
+                               W.FuncSpec("pow", sigma=0.1, p=-0.5)])
+def test_fm_full_dimension_equals_dense_fAb(f):
+    n = 40
+    A = _rand_spd(n, 11, lo=0.1, hi=3.0)
+    b = np.random.default_rng(5).standard_normal(n)
+    ref = closed_form.dense_fAb(A, f, b, symmetric=True)
+    assert krylov.relerr(krylov.fm(sp.csr_matrix(A), b, f, n), ref) < 1e-11
+
+
+def test_fm_nonsymmetric_converges_to_dense():
+    n = 300
+    A = _rand_nonsym(n, 8)
+    b = np.random.default_rng(9).standard_normal(n)
+    ref = closed_form.dense_fAb(A, EXP1, b)
+    np.testing.assert_allclose(ref, sl.expm(-A) @ b, rtol=1e-10, atol=1e-12)
+    assert krylov.relerr(krylov.fm(sp.csr_matrix(A), b, EXP1, 30), ref) < 1e-12
+
+
+def test_minimal_polynomial_exactness_and_breakdown():
+    d = np.repeat([0.5, 1.0, 2.0, 3.5, 5.0], 40)            # 5 distinct eigenvalues
+    A = sp.diags(d)
+    b = np.random.default_rng(1).standard_normal(d.size)
+    U, K, beta, mu = krylov.arnoldi(A, b, 12)
+    assert mu == 5
+    for f in (EXP1, W.FuncSpec("pow", sigma=0.0, p=-0.5)):
+        ref = closed_form.diagonal_fAb(d, f, b)
+        assert krylov.relerr(krylov.fm(A, b, f, 12), ref) < 1e-12
+        r = krylov.nt(A, b, f, 12, 2, None, "none")           # symmetric, k=2: also breaks down at 5
+        assert r["breakdown"] and r["m_used"] == 5
+        assert krylov.relerr(r["f"], ref) < 1e-11
+
+
+def test_polynomial_exactness_all_variants():
+    """Every method is exact for polynomials of degree <= m-1 (consequence of Theorem 6)."""
+    n, m = 400, 8
+    A = sp.csr_matrix(_rand_nonsym(n, 21))
+    b = np.random.default_rng(22).standard_normal(n)
+    coef = (0.3, -1.0, 0.25, 2.0, -0.5, 0.1, 0.05, -0.01)      # degree 7 = m - 1
+    f = W.FuncSpec("poly", coef=coef)
+    ref = np.zeros(n)
+    for c in reversed(coef):                                   # Horner with explicit matvecs
+        ref = A @ ref + c * b
+    sk = sketch.Sketch("srht", n, 3 * m, 5)
+    assert krylov.relerr(krylov.fm(A, b, f, m), ref) < 1e-12
+    for ls in ("exact", "sketch", "none"):
+        assert krylov.relerr(krylov.nt(A, b, f, m, 2, sk, ls)["f"], ref) < 1e-10
+    assert krylov.relerr(krylov.sfom(A, b, f, m, 2, sk), ref) < 1e-10
+
+
+# --------------------------------------------------------------------------- closed forms
+def test_dst_closed_form_matches_dense_eigendecomposition():
+    for st in (W.laplacian2d(7, 5), W.laplacian3d(5)):
+        A = operators.stencil_matrix(st).toarray()
+        b = np.random.default_rng(st.n).standard_normal(st.n)
+        for f in (EXP1, W.FuncSpec("pow", sigma=1e-3, p=-0.5)):
+            np.testing.assert_allclose(closed_form.laplacian_fAb(st, f, b),
+                                       closed_form.dense_fAb(A, f, b, symmetric=True), rtol=1e-11, atol=1e-12)
+
+
+def test_fm_at_config1_matches_dst_closed_form():
+    w = W.config("lap2d_100_exp")
+    A = operators.as_matrix(w.op)
+    b = W.rhs(w.n, w.b_seed)
+    assert krylov.relerr(krylov.fm(A, b, w.f, w.m), closed_form.laplacian_fAb(w.op, w.f, b)) < 1e-13
+
+
+# --------------------------------------------------------------------------- Algorithm 2 and the compression
+def test_truncated_basis_relation_window_orthogonality():
+    n, m, k = 500, 30, 3
+    A = sp.csr_matrix(_rand_nonsym(n, 31))
+    b = np.random.default_rng(32).standard_normal(n)
+    V, H, beta, mu, brk = krylov.truncated_arnoldi(A, b, m, k)
+    assert not brk and mu == m
+    np.testing.assert_allclose(A @ V[:m].T, V.T @ H, atol=1e-12)           # eq. (3)
+    G = V @ V.T
+    for i in range(m + 1):
+        for j in range(max(0, i - k), i):
+            assert abs(G[i, j]) < 1e-13
+    np.testing.assert_allclose(np.diag(G), 1.0, atol=1e-14)
+    assert np.all(np.triu(H[:m, :m], k) == 0)                                 # band: k - 1 above the diagonal
+    assert np.all(np.tril(H, -2) == 0)
+
+
+def test_compression_update_eq6_and_gamma_b():
+    n, m, k = 300, 12, 2
+    A = _rand_nonsym(n, 41)
+    b = np.random.default_rng(42).standard_normal(n)
+    V, H, beta, mu, _ = krylov.truncated_arnoldi(sp.csr_matrix(A), b, m, k)
+    Vm = V[:m].T
+    P = np.linalg.pinv(Vm)
+    y = P @ V[m]
+    lhs = P @ A @ Vm
+    rhs = H[:m].copy()
+    rhs[:, -1] += H[m, m - 1] * y
+    np.testing.assert_allclose(lhs, rhs, atol=1e-10)
+    e1 = np.zeros(m)
+    e1[0] = np.linalg.norm(b)
+    np.testing.assert_allclose(P @ b, e1, atol=1e-10)
+
+
+def test_basis_invariance_lemma2():
+    n, m = 250, 15
+    A = _rand_nonsym(n, 51)
+    b = np.random.default_rng(52).standard_normal(n)
+    f = W.FuncSpec("exp", alpha=-0.3)
+    U, K, beta, _ = krylov.arnoldi(sp.csr_matrix(A), b, m)
+    R = np.triu(np.random.default_rng(53).standard_normal((m, m))) + 3 * np.eye(m)
+    V = U[:m].T @ R
+    P = np.linalg.pinv(V)
+    alt = V @ (matfun.fmat(f, P @ A @ V) @ (P @ b))
+    assert krylov.relerr(alt, krylov.fm(sp.csr_matrix(A), b, f, m)) < 1e-11
+    r = krylov.nt(sp.csr_matrix(A), b, f, m, 3, None, "exact")
+    assert krylov.relerr(r["f"], krylov.fm(sp.csr_matrix(A), b, f, m)) < 1e-11
+
+
+def test_lanczos_equivalence_symmetric_k2():
+    n, m = 400, 10
+    A = sp.csr_matrix(_rand_spd(n, 61))
+    b = np.random.default_rng(62).standard_normal(n)
+    U, K, _, _ = krylov.arnoldi(A, b, m)
+    V, H, _, _, _ = krylov.truncated_arnoldi(A, b, m, 2)
+    np.testing.assert_allclose(H, K, atol=1e-12)
+    np.testing.assert_allclose(np.abs(V @ U.T), np.eye(m + 1), atol=1e-11)
+
+
+def test_sfom_equals_sketch_and_solve_remark3():
+    n, m = 600, 8
+    A = sp.csr_matrix(_rand_nonsym(n, 71, shift=0.5))
+    b = np.random.default_rng(72).standard_normal(n)
+    f = W.FuncSpec("exp", alpha=-3.0)
+    for kind in ("srht", "sparse_sign"):
+        sk = sketch.Sketch(kind, n, 2 * m, 3)
+        a = krylov.sfom(A, b, f, m, 2, sk)
+        bb = krylov.nt(A, b, f, m, 2, sk, "sketch")["f"]
+        assert krylov.relerr(a, bb) < 1e-9
+        assert krylov.relerr(a, krylov.fm(A, b, f, m)) > 1e-12       # not trivially converged
+
+
+# --------------------------------------------------------------------------- mutation tests (planted slips)
+def test_planted_sign_slip_in_algorithm2_is_caught(monkeypatch):
+    orig = krylov.truncated_arnoldi
+
+    def slipped(A, b, m, k):
+        V, H, beta, mu, brk = orig(A, b, m, k)
+        H = H.copy()
+        H[0, 1] = -H[0, 1]            # a wrong sign on one coefficient
+        return V, H, beta, mu, brk
+
+    n, m, k = 300, 10, 3
+    A = sp.csr_matrix(_rand_nonsym(n, 81))
+    b = np.random.default_rng(82).standard_normal(n)
+    V, H, *_ = slipped(A, b, m, k)
+    assert np.linalg.norm(A @ V[:m].T - V.T @ H) > 1e-3
+
+
+def test_planted_transpose_slip_in_fm_is_caught():
+    n, m = 200, 20
+    A = _rand_nonsym(n, 91)
+    b = np.random.default_rng(92).standard_normal(n)
+    U, K, beta, mu = krylov.arnoldi(sp.csr_matrix(A), b, m)
+    wrong = beta * (U[:m].T @ matfun.fmat(EXP1, K[:m, :m].T)[:, 0])
+    ref = closed_form.dense_fAb(A, EXP1, b)
+    assert krylov.relerr(krylov.fm(sp.csr_matrix(A), b, EXP1, m), ref) < 1e-12
+    assert krylov.relerr(wrong, ref) > 1e-6

@@ -1,0 +1,170 @@
+"""Seeded synthetic inputs for the sketched-Krylov f(A)b path.
+
+This module only *describes* inputs: stencil coefficient sets, a random
+geometric graph Laplacian in CSR form, right-hand sides and the scalar
+parameters of each workload.  It contains none of the method's arithmetic
+(no matvec, no Krylov step, no sketch) so that both the CPU oracle and the
+HIP path can take their inputs from here without sharing any computation.
+
+Operators (paper context: Section 5 uses PDE discretisations and graph
+Laplacians; the synthetic stand-ins below replace the SuiteSparse / SNAP /
+Matrix Market matrices of Sections 5.1.3 and 5.2, which are not available):
+
+* ``laplacian2d(N)``   5-point Dirichlet Laplacian, diag 4, off-diag -1.
+* ``laplacian3d(N)``   7-point Dirichlet Laplacian (T_N (x) I (x) I + ...,
+                        T_N = tridiag(-1, 2, -1); Section 5.1.4 prints the
+                        last off-diagonal sign as +1, read as -1).
+* ``convdiff3d(N, Pe)`` upwind 7-point discretisation of -Lap(u) + Pe(1,1,1).grad(u)
+                        on the unit cube, h = 1/(N+1), rescaled so that
+                        ||A||_inf = ||A||_1 = 1e3 (hence ||A||_2 <= 1e3).
+* ``rgg_laplacian(n)``  graph Laplacian D - W of a random geometric graph in
+                        the unit square with mean degree ~10, CSR int32/FP32.
+
+Grid ordering everywhere: row = x + nx*(y + ny*z), x fastest.
+Stencil coefficient order: (centre, x-1, x+1, y-1, y+1, z-1, z+1); a
+coefficient multiplies the value at that neighbour; neighbours outside the
+grid are zero (homogeneous Dirichlet).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "Stencil", "laplacian2d", "laplacian3d", "convdiff3d", "rgg_laplacian",
+    "rhs", "FuncSpec", "Workload", "config", "CONFIG_NAMES",
+]
+
+
+@dataclasses.dataclass(frozen=True)
+class Stencil:
+    """A constant-coefficient 5/7-point stencil on an nx*ny*nz grid."""
+    dim: int
+    nx: int
+    ny: int
+    nz: int
+    coeff: tuple  # (c, xm, xp, ym, yp, zm, zp)
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def laplacian2d(N: int, ny: int | None = None) -> Stencil:
+    ny = N if ny is None else ny
+    return Stencil(2, N, ny, 1, (4.0, -1.0, -1.0, -1.0, -1.0, 0.0, 0.0))
+
+
+def laplacian3d(N: int) -> Stencil:
+    return Stencil(3, N, N, N, (6.0, -1.0, -1.0, -1.0, -1.0, -1.0, -1.0))
+
+
+def convdiff3d(N: int, Pe: float, norm_target: float = 1e3) -> Stencil:
+    """Upwind (backward-difference) convection-diffusion, scaled to ||A||_inf = norm_target."""
+    h = 1.0 / (N + 1)
+    c = 6.0 / h**2 + 3.0 * Pe / h
+    up = -1.0 / h**2 - Pe / h        # upstream neighbours x-1, y-1, z-1
+    dn = -1.0 / h**2                 # downstream neighbours x+1, y+1, z+1
+    row_abs_sum = abs(c) + 3.0 * abs(up) + 3.0 * abs(dn)   # = 12/h^2 + 6 Pe/h
+    s = norm_target / row_abs_sum
+    return Stencil(3, N, N, N, (c * s, up * s, dn * s, up * s, dn * s, up * s, dn * s))
+
+
+def rgg_laplacian(n: int, seed: int, mean_degree: float = 10.0):
+    """Random geometric graph Laplacian L = D - W in CSR (int32 rowptr/col, float32 val).
+
+    Points are uniform in [0,1]^2 (seeded); radius r = sqrt(mean_degree/(pi (n-1)))
+    (boundary deficit ignored); nodes are renumbered by r-cell (row-major cells)
+    so that graph neighbours are close in memory.  Values are small integers,
+    hence exact in FP32.  Returns (rowptr, col, val) with sorted columns and the
+    diagonal included in every row.
+    """
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    r = math.sqrt(mean_degree / (math.pi * (n - 1)))
+    ncell = max(1, int(1.0 / r))
+    cx = np.minimum((pts[:, 0] * ncell).astype(np.int64), ncell - 1)
+    cy = np.minimum((pts[:, 1] * ncell).astype(np.int64), ncell - 1)
+    order = np.lexsort((pts[:, 0], cx, cy))          # row-major cells, then x
+    pts = pts[order]
+    pairs = cKDTree(pts).query_pairs(r, output_type="ndarray")
+    i = np.concatenate([pairs[:, 0], pairs[:, 1]])
+    j = np.concatenate([pairs[:, 1], pairs[:, 0]])
+    deg = np.bincount(i, minlength=n).astype(np.float64)
+    rows = np.concatenate([i, np.arange(n)])
+    cols = np.concatenate([j, np.arange(n)])
+    vals = np.concatenate([-np.ones(i.size), deg])
+    perm = np.lexsort((cols, rows))
+    rows, cols, vals = rows[perm], cols[perm], vals[perm]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
+    return rowptr.astype(np.int32), cols.astype(np.int32), vals.astype(np.float32)
+
+
+def rhs(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
+    """b ~ N(0,1) from numpy's default_rng(seed); nrhs > 1 gives columns seed..seed+nrhs-1,
+    returned interleaved as an (n, nrhs) C-ordered array (layout [n][nrhs])."""
+    if nrhs == 1:
+        return np.random.default_rng(seed).standard_normal(n)
+    return np.stack([np.random.default_rng(seed + r).standard_normal(n) for r in range(nrhs)], axis=1)
+
+
+@dataclasses.dataclass(frozen=True)
+class FuncSpec:
+    """f(z) = exp(alpha z)  |  (z + sigma)^p with p = +-1/2  |  sum_j coef[j] z^j."""
+    kind: str                # "exp" | "pow" | "poly"
+    alpha: float = 0.0
+    sigma: float = 0.0
+    p: float = 0.0
+    coef: tuple = ()
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    op: object               # Stencil or (rowptr, col, val) tuple
+    b_seed: int
+    nrhs: int
+    f: FuncSpec
+    m: int
+    k: int
+    s: int
+    sketch: str              # "srht" | "sparse_sign"
+    zeta: int = 8
+    sketch_seed: int = 0
+
+    @property
+    def n(self) -> int:
+        if isinstance(self.op, Stencil):
+            return self.op.n
+        return len(self.op[0]) - 1
+
+
+CONFIG_NAMES = ("lap2d_100_exp", "convdiff3d_128_exp", "rgg_2p20_invsqrt", "convdiff3d_256_exp_8rhs")
+
+
+def config(name: str, scale: int | None = None) -> Workload:
+    """The named synthetic workloads.  ``scale`` shrinks the grid/graph for
+    fast parity cases while keeping the same structure and parameters."""
+    if name == "lap2d_100_exp":
+        N = 100 if scale is None else scale
+        return Workload(name, laplacian2d(N), 0, 1, FuncSpec("exp", alpha=-0.5),
+                        m=40, k=2, s=82, sketch="sparse_sign", zeta=8, sketch_seed=1)
+    if name == "convdiff3d_128_exp":
+        N = 128 if scale is None else scale
+        return Workload(name, convdiff3d(N, 50.0), 2, 1, FuncSpec("exp", alpha=-1e-3),
+                        m=100, k=4, s=400, sketch="srht", sketch_seed=2)
+    if name == "rgg_2p20_invsqrt":
+        n = (1 << 20) if scale is None else scale
+        return Workload(name, rgg_laplacian(n, seed=3), 3, 1,
+                        FuncSpec("pow", sigma=1e-3, p=-0.5),
+                        m=150, k=2, s=300, sketch="sparse_sign", zeta=8, sketch_seed=3)
+    if name == "convdiff3d_256_exp_8rhs":
+        N = 256 if scale is None else scale
+        return Workload(name, convdiff3d(N, 100.0), 50, 8, FuncSpec("exp", alpha=-1e-3),
+                        m=200, k=4, s=800, sketch="srht", sketch_seed=5)
+    raise KeyError(name)
