@@ -1,0 +1,210 @@
+/*
+ * fab.h -- C ABI of the MI355X sketched-Krylov f(A)b library (libfab.so).
+ *
+ * Method: Cortinovis, Kressner & Nakatsukasa, "Speeding up Krylov subspace
+ * methods for computing f(A)b via randomization".  Given A (accessed only
+ * through matrix-vector products, Section 1 / Table 1 "matrix access"), b,
+ * a function f analytic near the spectrum of A (Section 1), a Krylov
+ * dimension m, a truncation parameter k (Algorithm 2) and a sketch size s
+ * (Section 2.1.1), the library returns
+ *
+ *      out = ||b||_2 V_m f(H_hat) e_1,   H_hat = H_m + h_{m+1,m} y e_m^T
+ *
+ * (Algorithm 4, last line; eq. (6) for H_hat) where (V_{m+1}, Hbar_m) is the
+ * Arnoldi-like decomposition of eq. (3) built by k-truncated orthogonalisation
+ * (Algorithm 2) and y approximates the least-squares solution of eq. (7): by
+ * sketch-and-solve (Remark 3), by sketch-preconditioned LSQR refinement
+ * (Blendenpik, Section 3.1.1) or y = 0 (Algorithm 5, eq. (8)).
+ *
+ * All of the method's arithmetic runs in HIP kernels on one gfx950 GPU.
+ * Precision: the basis is stored in FP32 (or FP64), matrix-vector products,
+ * dots, norms and sketches accumulate in FP64; the sketched QR / least
+ * squares, f(H_hat) and the final combination are FP64.
+ *
+ * Conventions common to every entry point:
+ *  - Every function returns an int status (enum fab_status); nothing is
+ *    thrown across the ABI.  fab_strerror() names a status.
+ *  - Vectors b and out are FP64 DEVICE pointers with nrhs right-hand sides
+ *    interleaved row-major, layout [n][nrhs] (element (i, r) at i*nrhs + r).
+ *  - Caller memory is never freed or retained by the library beyond the
+ *    documented lifetime (until the call returns for fab_solve, until
+ *    fab_poll/fab_wait reports completion for fab_submit).
+ *  - A context is bound to one device and one HIP stream.  Calls on one
+ *    context are serialised internally (thread-safe); distinct contexts are
+ *    independent.
+ */
+#ifndef FAB_H
+#define FAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fab_ctx_s* fab_ctx;
+typedef struct fab_matrix_s* fab_matrix;
+typedef uint64_t fab_request;
+
+enum fab_status {
+  FAB_OK = 0,
+  FAB_EINVAL = 1,     /* bad shape, parameter or pointer                         */
+  FAB_ENOMEM = 2,     /* the request can never fit the arena                      */
+  FAB_EDEVICE = 3,    /* a HIP runtime call failed                                */
+  FAB_ENUMERIC = 4,   /* NaN/Inf in b, in the basis or in f(H_hat)                */
+  FAB_EBUSY = 5,      /* matrix still referenced by in-flight requests            */
+  FAB_ENOTFOUND = 6   /* unknown request handle                                   */
+};
+
+/* The function f (Section 1: analytic on a domain containing the spectrum). */
+enum fab_func_kind {
+  FAB_F_EXP = 1,      /* f(z) = exp(alpha z)                                      */
+  FAB_F_POW = 2,      /* f(z) = (z + sigma)^p, p = +1/2 or -1/2 (principal branch) */
+  FAB_F_POLY = 3      /* f(z) = sum_j coef[j] z^j (test hook: exact for deg <= m-1) */
+};
+typedef struct {
+  int kind;
+  double alpha, sigma, p;
+  const double* coef; /* host pointer, ncoef <= 64; read during the call only   */
+  int ncoef;
+} fab_func;
+
+/* Sketch Theta in R^{s x n} (Section 2.1.1). */
+enum fab_sketch_kind {
+  FAB_SKETCH_SRHT = 1,        /* s rows of the Walsh-Hadamard transform times random signs */
+  FAB_SKETCH_SPARSE_SIGN = 2  /* zeta nonzeros +-1/sqrt(zeta) per column                    */
+};
+/* Basis storage precision. */
+enum fab_prec {
+  FAB_PREC_FP32 = 1,          /* FP32 basis, FP64 accumulation                            */
+  FAB_PREC_FP64 = 2,          /* FP64 basis                                                */
+  FAB_PREC_AUTO = 3           /* FP32, re-run in FP64 if the a-posteriori estimate fails   */
+};
+/* Least-squares policy for y in eq. (7). */
+enum fab_ls_mode {
+  FAB_LS_AUTO = 0,            /* sketch-and-solve, then LSQR refinement if the gate fails  */
+  FAB_LS_SKETCH = 1,          /* sketch-and-solve only (Remark 3; equivalent to sFOM)      */
+  FAB_LS_NONE = 2,            /* y = 0: Algorithm 5                                        */
+  FAB_LS_LSQR = 3             /* always refine with sketch-preconditioned LSQR (Algorithm 4
+                                 with Blendenpik, Section 3.1.1)                            */
+};
+
+typedef struct {
+  int m;              /* Krylov dimension, 1 <= m < n                             */
+  int k;              /* truncation window, 1 <= k <= 8 (Algorithm 2)             */
+  int s;              /* sketch rows, m < s <= min(8192, padded n)                */
+  int sketch;         /* enum fab_sketch_kind                                     */
+  int zeta;           /* sparse-sign nonzeros per column, 1 <= zeta <= min(s,16)  */
+  uint64_t seed;      /* fully determines Theta                                   */
+  int prec;           /* enum fab_prec                                            */
+  int ls_mode;        /* enum fab_ls_mode                                         */
+  double tol;         /* target relative accuracy for AUTO policies (e.g. 1e-6)    */
+} fab_params;
+
+/* Per right-hand side diagnostics. */
+typedef struct {
+  double err_est;     /* max(ls_gate, round_est): a-posteriori error estimate      */
+  double ls_gate;     /* ||R (c_y - c_0)|| / ||R c_y||: sensitivity to the last column */
+  double round_est;   /* basis-rounding amplification estimate                      */
+  double conv_est;    /* ||R (c_m - [c_{m-d}; 0])|| / ||R c_m||, d = max(5, m/10)     */
+  double kappa_R;     /* condition estimate of the R factor of Theta V_m            */
+  double h_last;      /* h_{m+1,m}                                                   */
+  double beta;        /* ||b||_2 as used (norm of the stored first basis vector)      */
+  int m_used;         /* dimension actually used (< m after a lucky breakdown)       */
+  int breakdown;      /* 1 if an invariant subspace was found                        */
+  int fell_back;      /* 1 if an FP32 result was recomputed with an FP64 basis       */
+  int ls_iters;       /* LSQR iterations performed                                   */
+  int prec_used;      /* FAB_PREC_FP32 or FAB_PREC_FP64                              */
+  double latency_us;  /* submit-to-completion wall time                              */
+} fab_info;
+
+/* Create a context on `device` (HIP ordinal).  `arena_dev_ptr` (device memory,
+ * e.g. a torch uint8 tensor's data) of `arena_bytes` bytes is sub-allocated for
+ * matrices and per-request workspaces; pass NULL to let the library allocate
+ * an arena of `arena_bytes` itself (freed by fab_finalize).  `hip_stream` is
+ * the hipStream_t the blocking calls run on (NULL = the library's own stream);
+ * served requests run on library-owned streams of the same device.
+ * Errors: FAB_EINVAL (null ctx, arena_bytes < 1 MiB), FAB_EDEVICE.           */
+int fab_init(fab_ctx* ctx, int device, void* arena_dev_ptr, size_t arena_bytes, void* hip_stream);
+
+/* A constant-coefficient stencil operator (no device memory needed):
+ * dim = 2 (nz must be 1) or 3; grid nx*ny*nz, row = x + nx*(y + ny*z);
+ * coeff = (centre, x-1, x+1, y-1, y+1, z-1, z+1), each multiplying the value at
+ * that neighbour; neighbours outside the grid are zero (Dirichlet).
+ * Errors: FAB_EINVAL (dims < 1, n >= 2^31, dim mismatch).                     */
+int fab_create_matrix_stencil(fab_ctx ctx, int dim, int nx, int ny, int nz,
+                              const double coeff[7], fab_matrix* A);
+
+/* A general sparse operator in CSR: rowptr int32[n+1], col int32[nnz],
+ * val float32[nnz] (columns sorted or not).  The arrays are copied into the
+ * arena (from host memory, or device memory if ptr_is_device != 0) and stay
+ * resident until fab_destroy_matrix.
+ * Errors: FAB_EINVAL (n < 1, nnz < 0, rowptr inconsistent), FAB_ENOMEM.        */
+int fab_create_matrix_csr(fab_ctx ctx, int64_t n, int64_t nnz, const int32_t* rowptr,
+                          const int32_t* col, const float* val, int ptr_is_device,
+                          fab_matrix* A);
+
+/* Release a matrix.  FAB_EBUSY while submitted requests still use it.         */
+int fab_destroy_matrix(fab_matrix A);
+
+/* Blocking solve: out = ||b|| V_m f(H_hat) e_1 per right-hand side.
+ * nrhs in {1, 2, 4, 8, 16, 32}; b and out are FP64 device arrays [n][nrhs]
+ * (out may not alias b).  info (nullable) is an array of nrhs records.
+ * A lucky breakdown is not an error: the exact result is returned with
+ * info.m_used < m.  Errors: FAB_EINVAL, FAB_ENOMEM (the workspace can never
+ * fit the arena), FAB_ENUMERIC (non-finite b or result), FAB_EDEVICE.         */
+int fab_solve(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
+              const fab_params* p, double* out, fab_info* info);
+
+/* Intermediate results of one solve, copied to HOST buffers the caller owns
+ * (each pointer nullable; sizes per right-hand side, rhs-major):
+ *   hbar  (m+1) x m  column-major: Hbar_m of eq. (3) (zero outside the band)
+ *   sv    s x (m+1)  column-major: Theta V_{m+1}, the sketched normalised basis
+ *   y     m          least-squares solution used for the last column (eq. (6))
+ *   c     m          f(H_hat) e_1
+ *   eta   m+1        norms of the stored (unnormalised) basis vectors          */
+typedef struct {
+  double* hbar;
+  double* sv;
+  double* y;
+  double* c;
+  double* eta;
+} fab_diag;
+
+/* fab_solve plus a copy of the intermediates into `diag` (for diagnostics and
+ * stage-by-stage verification).  Same arguments, errors and semantics.       */
+int fab_solve_diag(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
+                   const fab_params* p, double* out, fab_info* info, const fab_diag* diag);
+
+/* Non-blocking submit to the context's serving loop.  The request is admitted
+ * when its workspace fits the arena next to the requests already running
+ * (continuous batching: admitted requests run concurrently on separate
+ * streams); until then it waits in FIFO order.  b and out must stay valid
+ * until completion is reported.  Errors as fab_solve, reported at submit for
+ * argument checks and at fab_poll/fab_wait for execution.                    */
+int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
+               const fab_params* p, double* out, fab_request* req);
+
+/* Never blocks.  *done = 1 once the request finished; then info (nullable,
+ * nrhs records) is filled and the request's status is returned, and the
+ * handle is released.  While running: *done = 0 and FAB_OK.
+ * FAB_ENOTFOUND for an unknown or already-released handle.                   */
+int fab_poll(fab_ctx ctx, fab_request req, int* done, fab_info* info);
+
+/* Blocks until the request finishes; then as fab_poll with done = 1.          */
+int fab_wait(fab_ctx ctx, fab_request req, fab_info* info);
+
+/* Wait for all requests, release every matrix and the context.               */
+int fab_finalize(fab_ctx ctx);
+
+/* Static string naming a status code.                                         */
+const char* fab_strerror(int code);
+
+/* Library version string.                                                     */
+const char* fab_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FAB_H */

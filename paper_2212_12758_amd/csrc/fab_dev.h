@@ -1,0 +1,129 @@
+// Device-side descriptors and helpers shared by the libfab kernels.
+//
+// Data layout in HBM for one solve with nrhs right-hand sides:
+//   V      basis, (m+1) vectors of n*nrhs elements (FP32 or FP64), vector j at
+//          V + j*ldv, element (row r, rhs q) at r*nrhs + q.  Vectors are stored
+//          unnormalised: v_j = u_j / eta_j (lazy normalisation).
+//   wbuf   CSR only: w~ = A u_{i-1} in FP64, [n][nrhs].
+//   H      per rhs, (m+1) x m column-major (ld m+1): the Hessenberg matrix of
+//          the Arnoldi-like decomposition, eq. (3) of the paper.
+//   S      per rhs, s x (m+1) column-major (ld s): Theta u_j (unnormalised).
+//   part / npart / skpart: per-block partial sums, reduced in a fixed order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fab {
+
+constexpr int KMAX = 8;          // largest truncation window k
+constexpr int ZMAX = 16;         // largest sparse-sign zeta
+constexpr int NSLOT = KMAX + 1;  // dot slots per rhs: k window dots + ||w||^2
+constexpr int BLOCK = 256;       // threads per streaming block
+constexpr int TILE_ELEMS = 4096; // max elements (rows * nrhs) per tile
+
+enum OpKind { OP_STENCIL = 0, OP_CSR = 1 };
+enum SketchKind { SK_SRHT = 1, SK_SPARSE = 2 };
+
+struct SolveDev {
+  // problem shape
+  int n;                 // rows
+  int nrhs, lognrhs;     // rhs count (power of two <= 32)
+  int m, k, s, zeta;
+  // operator
+  int op;                // OpKind
+  int nx, ny, nz;
+  double c[7];           // stencil coefficients (centre, x-, x+, y-, y+, z-, z+)
+  const int* rowptr;
+  const int* col;
+  const float* val;
+  // basis
+  void* V;
+  long long ldv;         // n * nrhs
+  double* wbuf;          // CSR: w~ [n][nrhs]
+  const double* b;       // right-hand sides [n][nrhs]
+  // small state, per rhs
+  double* H;             // [nrhs][(m+1)*m]
+  double* eta;           // [nrhs][m+1]
+  double* wnorm;         // [nrhs][m+1]
+  double* coef;          // [nrhs][NSLOT]
+  double* S;             // [nrhs][s*(m+1)]
+  // partition and partials
+  int rows_per_tile, log_rows;   // R = rows per tile (power of two)
+  int ntiles;            // ceil(n / R)
+  int nblk;              // streaming blocks (tiles are strided over blocks)
+  int nred;              // sketch-reduction blocks appended to the dots kernel
+  double* part;          // [nblk][nrhs][NSLOT]
+  double* npart;         // [nblk][nrhs]
+  double* skpart;        // [s*nrhs][nblk]
+  unsigned* counter;     // last-block ticket
+  int* status;           // [0] m_used, [1] breakdown, [2] non-finite
+  // sketch
+  int sketch;            // SketchKind
+  const int* srht_rows;  // [s] sampled rows of the padded Hadamard transform
+  unsigned long long key_a, key_b;   // SRHT: signs key; sparse: rows key, signs key
+  double sk_scale;       // 1/sqrt(s) (SRHT) or 1/sqrt(zeta) (sparse sign)
+  double unit_round;     // unit roundoff of the basis storage
+};
+
+// Per-rhs workspace of the small dense stages (FP64, column-major).
+constexpr int MAXCOEF = 64;
+constexpr int NINFO = 16;
+struct DenseDev {
+  int m, s, nrhs;
+  long long stride;      // doubles per rhs
+  double* base;
+  long long oW, oH, oM, oVec, oInfo;   // W [s*(m+1)], H_hat [m*m], 8 scratch m*m, vectors, info
+  int ls_mode;           // 1 sketch-and-solve, 2 none
+  int fkind;             // 1 exp, 2 pow, 3 poly
+  double alpha, sigma, p;
+  int ncoef;
+  double coef[MAXCOEF];
+};
+
+// ---------------------------------------------------------------- SplitMix64
+// Counter-based SplitMix64 (Steele, Lea & Flood 2014): out(key, i) is the
+// i-th output of the generator whose state starts at `key`; stream keys are
+// outputs of the generator seeded with the user seed.
+constexpr unsigned long long GOLDEN_GAMMA = 0x9E3779B97F4A7C15ull;
+
+__host__ __device__ inline unsigned long long sm64_finalise(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ inline unsigned long long sm64_out(unsigned long long key, unsigned long long i) {
+  return sm64_finalise(key + (i + 1ull) * GOLDEN_GAMMA);
+}
+
+// Sparse-sign pattern of column `r` of Theta: zeta distinct rows in [0, s)
+// (Floyd's sampling) and a sign bit word.
+__device__ inline void sparse_sign_column(unsigned long long key_rows, unsigned long long key_signs,
+                                          int r, int s, int zeta, int* rows, unsigned long long* sbits) {
+  const unsigned half = (unsigned)(zeta + 1) >> 1;
+  unsigned long long w = 0;
+#pragma unroll
+  for (int t = 0; t < ZMAX; ++t) {
+    if (t < zeta) {
+      if ((t & 1) == 0) w = sm64_out(key_rows, (unsigned long long)r * half + (unsigned)(t >> 1));
+      unsigned h = (t & 1) ? (unsigned)(w & 0xFFFFFFFFull) : (unsigned)(w >> 32);
+      unsigned j = (unsigned)(s - zeta + t);
+      unsigned q = (unsigned)(((unsigned long long)h * (unsigned long long)(j + 1u)) >> 32);
+      bool taken = false;
+#pragma unroll
+      for (int u = 0; u < ZMAX; ++u)
+        if (u < t && rows[u] == (int)q) taken = true;
+      rows[t] = taken ? (int)j : (int)q;
+    }
+  }
+  *sbits = sm64_out(key_signs, (unsigned long long)r);
+}
+
+// ---------------------------------------------------------------- reductions
+// Sum over the lanes of a wave that share the same rhs (lane & (nrhs-1)).
+// Fixed xor-butterfly order: deterministic.
+__device__ inline double wave_sum_rhs(double v, int nrhs) {
+  for (int off = 32; off >= nrhs; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace fab

@@ -1,0 +1,765 @@
+// Small dense FP64 stages of the method, one workgroup per right-hand side:
+//
+//  k_lsq    normalise the sketched basis Theta V_{m+1}; Householder QR of
+//           Theta V_m; y = R^{-1} Q^T Theta v_{m+1} (sketch-and-solve of the
+//           least-squares problem eq. (7), Remark 3); the compression
+//           H_hat = H_m + h_{m+1,m} y e_m^T (eq. (6)).
+//  k_fexp   exp(alpha H_hat) e_1 by scaling and squaring with a diagonal Pade
+//           approximant (Higham, SIAM J. Matrix Anal. Appl. 26 (2005)), the
+//           algorithm behind the expm the paper uses in Section 5.
+//  k_fpow   (H_hat + sigma I)^{+-1/2} e_1 through the real Schur decomposition
+//           (Francis double-shift QR, Golub & Van Loan Sec. 7.5) and the real
+//           quasi-triangular square root recurrence (Higham, Linear Algebra
+//           Appl. 88/89 (1987)), the method of the sqrtm the paper uses.
+//  k_fpoly  sum_j coef_j H_hat^j e_1 (polynomial test functions).
+//  k_coef   combination weights beta c_j / eta_j for the final V c.
+//
+// All matrices are column-major with leading dimension m (or s) in a per-rhs
+// workspace in global memory.
+#include "fab_dev.h"
+
+namespace fab {
+
+constexpr int DBLOCK = 256;
+constexpr int MAXM = 512;
+enum { INFO_KAPPA = 0, INFO_HLAST = 1, INFO_BETA = 2, INFO_FAIL = 3, INFO_NSQ = 4, INFO_SCHUR_IT = 5, INFO_NRM = 6 };
+
+// Orders this wave's memory operations (LDS and global) without a workgroup
+// barrier; used inside sections that only one wave executes.
+__device__ inline void wave_order() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline double wsum(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block-wide sum; `sh` holds >= 4 doubles; every thread gets the result
+__device__ inline double bsum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v = wsum(v);
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nwv = (blockDim.x + 63) >> 6;
+  for (int w = 0; w < nwv; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+// ----------------------------------------------------------------- block GEMM
+// C = A * B, square m x m, col-major, ld = m; C must not alias A or B.
+__device__ void bgemm(int m, const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C,
+                      double* As, double* Bs) {  // As, Bs: 16*65 doubles each
+  const int tid = threadIdx.x;
+  const int tr = tid & 15, tc = tid >> 4;
+  for (int i0 = 0; i0 < m; i0 += 64) {
+    for (int j0 = 0; j0 < m; j0 += 64) {
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      for (int k0 = 0; k0 < m; k0 += 16) {
+        for (int x = tid; x < 1024; x += DBLOCK) {
+          const int ii = x & 63, kk = x >> 6;
+          const int gi = i0 + ii, gk = k0 + kk;
+          As[kk * 65 + ii] = (gi < m && gk < m) ? A[gi + (long long)gk * m] : 0.0;
+          const int jj = x >> 4, kb = x & 15;
+          const int gj = j0 + jj, gkb = k0 + kb;
+          Bs[kb * 65 + jj] = (gj < m && gkb < m) ? B[gkb + (long long)gj * m] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) av[a] = As[kk * 65 + tr * 4 + a];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) bv[b] = Bs[kk * 65 + tc * 4 + b];
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int gi = i0 + tr * 4 + a, gj = j0 + tc * 4 + b;
+          if (gi < m && gj < m) C[gi + (long long)gj * m] = acc[a][b];
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// ----------------------------------------------------------------- LU with partial pivoting
+// In place on A (m x m); piv[j] = row swapped with j.  Returns 1 if singular.
+__device__ int blu(int m, double* A, int* piv, double* shv, int* shi) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int singular = 0;
+  for (int j = 0; j < m; ++j) {
+    double best = -1.0;
+    int bi = j;
+    for (int r = j + tid; r < m; r += DBLOCK) {
+      const double v = fabs(A[r + (long long)j * m]);
+      if (v > best) { best = v; bi = r; }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { shv[wv] = best; shi[wv] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b0 = shv[0];
+      int i0 = shi[0];
+      for (int w = 1; w < DBLOCK / 64; ++w)
+        if (shv[w] > b0 || (shv[w] == b0 && shi[w] < i0)) { b0 = shv[w]; i0 = shi[w]; }
+      shi[4] = i0;
+      piv[j] = i0;
+    }
+    __syncthreads();
+    const int p = shi[4];
+    if (p != j)
+      for (int c = tid; c < m; c += DBLOCK) {
+        const double t = A[j + (long long)c * m];
+        A[j + (long long)c * m] = A[p + (long long)c * m];
+        A[p + (long long)c * m] = t;
+      }
+    __syncthreads();
+    const double pv = A[j + (long long)j * m];
+    if (pv == 0.0) { singular = 1; continue; }
+    for (int r = j + 1 + tid; r < m; r += DBLOCK) A[r + (long long)j * m] /= pv;
+    __syncthreads();
+    const int w = m - j - 1;
+    for (int x = tid; x < w * w; x += DBLOCK) {
+      const int r = j + 1 + x % w, c = j + 1 + x / w;
+      A[r + (long long)c * m] -= A[r + (long long)j * m] * A[j + (long long)c * m];
+    }
+    __syncthreads();
+  }
+  return singular;
+}
+
+// Solve (LU) X = B in place for nb right-hand-side columns of B (ld m); one thread per column.
+__device__ void blu_solve(int m, const double* LU, const int* piv, double* B, int nb) {
+  for (int c = threadIdx.x; c < nb; c += DBLOCK) {
+    double* x = B + (long long)c * m;
+    for (int j = 0; j < m; ++j) {
+      const int p = piv[j];
+      if (p != j) { const double t = x[j]; x[j] = x[p]; x[p] = t; }
+    }
+    for (int j = 0; j < m; ++j) {
+      const double xj = x[j];
+      for (int r = j + 1; r < m; ++r) x[r] -= LU[r + (long long)j * m] * xj;
+    }
+    for (int j = m - 1; j >= 0; --j) {
+      const double xj = x[j] / LU[j + (long long)j * m];
+      x[j] = xj;
+      for (int r = 0; r < j; ++r) x[r] -= LU[r + (long long)j * m] * xj;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ inline int* st_mused(const SolveDev& d, int q) { return d.status + 4 + 2 * q; }
+__device__ inline int* st_brk(const SolveDev& d, int q) { return d.status + 5 + 2 * q; }
+
+// ----------------------------------------------------------------- sketched least squares
+__global__ void __launch_bounds__(DBLOCK) k_lsq(SolveDev d, DenseDev g) {
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ double sh[8];
+  __shared__ double yv[MAXM];
+  const int m = d.m, s = d.s;
+  double* ws = g.base + (long long)q * g.stride;
+  double* W = ws + g.oW;
+  double* Hh = ws + g.oH;
+  double* info = ws + g.oInfo;
+  const int mu = *st_mused(d, q);
+  const int brk = *st_brk(d, q);
+  const double* S = d.S + (long long)q * s * (m + 1);
+  const double* eta = d.eta + (long long)q * (m + 1);
+  const double* H = d.H + (long long)q * (m + 1) * m;
+  const bool do_ls = (!brk) && mu > 0 && g.ls_mode != 2;
+  const int ncol = do_ls ? mu + 1 : 0;
+
+  for (long long x = tid; x < (long long)s * ncol; x += DBLOCK) {
+    const int c = (int)(x / s);
+    const double e = eta[c];
+    W[x] = e > 0.0 ? S[x] / e : 0.0;
+  }
+  for (int x = tid; x < mu; x += DBLOCK) yv[x] = 0.0;
+  __syncthreads();
+
+  double rmax = 0.0, rmin = 1e308;
+  if (do_ls) {
+    for (int j = 0; j < mu; ++j) {
+      double* wj = W + (long long)j * s;
+      double part = 0.0;
+      for (int r = j + tid; r < s; r += DBLOCK) part += wj[r] * wj[r];
+      const double n2 = bsum(part, sh);
+      const double x1 = wj[j];
+      double beta = 0.0, tau = 0.0, scal = 0.0;
+      if (n2 > 0.0) {
+        const double nrm = sqrt(n2);
+        beta = x1 >= 0.0 ? -nrm : nrm;
+        tau = (beta - x1) / beta;
+        scal = 1.0 / (x1 - beta);
+      }
+      __syncthreads();
+      if (n2 > 0.0)
+        for (int r = j + 1 + tid; r < s; r += DBLOCK) wj[r] *= scal;
+      __syncthreads();
+      if (tid == 0) wj[j] = beta;
+      const double ab = fabs(beta);
+      rmax = fmax(rmax, ab);
+      rmin = fmin(rmin, ab);
+      if (n2 > 0.0) {
+        for (int c = j + 1 + wv; c < ncol; c += DBLOCK / 64) {
+          double* wc = W + (long long)c * s;
+          double dt = 0.0;
+          for (int r = j + 1 + lane; r < s; r += 64) dt += wj[r] * wc[r];
+          dt = wsum(dt) + wc[j];
+          dt *= tau;
+          if (lane == 0) wc[j] -= dt;
+          for (int r = j + 1 + lane; r < s; r += 64) wc[r] -= dt * wj[r];
+        }
+      }
+      __syncthreads();
+    }
+    // back substitution R y = (Q^T Theta v_{m+1})[0:mu] by one wave
+    if (wv == 0) {
+      const double* z = W + (long long)mu * s;
+      for (int i = mu - 1; i >= 0; --i) {
+        double acc = 0.0;
+        for (int c = i + 1 + lane; c < mu; c += 64) acc += W[i + (long long)c * s] * yv[c];
+        acc = wsum(acc);
+        const double rii = W[i + (long long)i * s];
+        const double yi = rii != 0.0 ? (z[i] - acc) / rii : 0.0;
+        if (lane == 0) yv[i] = yi;
+        wave_order();
+      }
+    }
+    __syncthreads();
+  }
+  // H_hat = H_m + h_{m+1,m} y e_m^T (m_used x m_used, ld = mu)
+  const double hlast = (mu > 0 && !brk) ? H[(long long)(mu - 1) * (m + 1) + mu] : 0.0;
+  for (long long x = tid; x < (long long)mu * mu; x += DBLOCK) {
+    const int r = (int)(x % mu), c = (int)(x / mu);
+    double v = H[(long long)c * (m + 1) + r];
+    if (c == mu - 1) v += hlast * yv[r];
+    Hh[x] = v;
+  }
+  if (tid == 0) {
+    info[INFO_KAPPA] = do_ls ? (rmin > 0.0 ? rmax / rmin : 1e308) : 1.0;
+    info[INFO_HLAST] = hlast;
+    info[INFO_BETA] = eta[0];
+    info[INFO_FAIL] = 0.0;
+  }
+  double* yout = ws + g.oVec + 2 * (long long)m;
+  for (int x = tid; x < mu; x += DBLOCK) yout[x] = yv[x];
+}
+
+// ----------------------------------------------------------------- exp: Pade scaling and squaring
+__device__ inline double pade_coef(int q, int j) {
+  // c_j = (2q-j)! q! / ((2q)! j! (q-j)!)
+  double c = 1.0;
+  for (int i = 0; i < j; ++i) c *= (double)(q - i) / (double)((2 * q - i) * (i + 1));
+  return c;
+}
+
+__global__ void __launch_bounds__(DBLOCK) k_fexp(SolveDev d, DenseDev g) {
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ double As[16 * 65], Bs[16 * 65];
+  __shared__ double sh[8];
+  __shared__ int shi[8];
+  __shared__ int piv[MAXM];
+  double* ws = g.base + (long long)q * g.stride;
+  const int mu = *st_mused(d, q);
+  double* c = ws + g.oVec;        // result f(H_hat) e_1
+  double* info = ws + g.oInfo;
+  if (mu == 0) return;
+  const int m = mu;
+  const long long mm = (long long)m * m;
+  double* A = ws + g.oM;          // alpha * H_hat (scaled)
+  double* A2 = A + mm;
+  double* A4 = A2 + mm;
+  double* A6 = A4 + mm;
+  double* U = A6 + mm;
+  double* Vm = U + mm;
+  double* T1 = Vm + mm;
+  double* T2 = T1 + mm;
+  const double* Hh = ws + g.oH;
+
+  // 1-norm of alpha*H_hat
+  double cmax = 0.0;
+  for (int cc = tid; cc < m; cc += DBLOCK) {
+    double sacc = 0.0;
+    for (int r = 0; r < m; ++r) sacc += fabs(Hh[r + (long long)cc * m]);
+    cmax = fmax(cmax, sacc);
+  }
+  for (int off = 32; off >= 1; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off, 64));
+  if ((tid & 63) == 0) sh[tid >> 6] = cmax;
+  __syncthreads();
+  double nrm = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3])) * fabs(g.alpha);
+  __syncthreads();
+
+  const double theta[5] = {1.495585217958292e-2, 2.539398330063230e-1, 9.504178996162932e-1,
+                           2.097847961257068e0, 5.371920351148152e0};
+  const int degs[5] = {3, 5, 7, 9, 13};
+  int qd = 13, ssq = 0;
+  for (int t = 0; t < 4; ++t)
+    if (nrm <= theta[t]) { qd = degs[t]; break; }
+  if (qd == 13 && nrm > theta[4]) ssq = (int)ceil(log2(nrm / theta[4]));
+  if (ssq < 0) ssq = 0;
+  const double scale = g.alpha * ldexp(1.0, -ssq);
+  for (long long x = tid; x < mm; x += DBLOCK) A[x] = scale * Hh[x];
+  __syncthreads();
+
+  double cf[14];
+  for (int j = 0; j <= 13; ++j) cf[j] = j <= qd ? pade_coef(qd, j) : 0.0;
+
+  bgemm(m, A, A, A2, As, Bs);
+  if (qd >= 5) bgemm(m, A2, A2, A4, As, Bs);
+  if (qd >= 7) bgemm(m, A2, A4, A6, As, Bs);
+  if (qd <= 9) {
+    // T1 = sum_{odd j} c_j A^{j-1}, Vm = sum_{even j} c_j A^j ; A8 = A4*A4 when q = 9
+    if (qd == 9) bgemm(m, A4, A4, T2, As, Bs);
+    for (long long x = tid; x < mm; x += DBLOCK) {
+      const int r = (int)(x % m), cc = (int)(x / m);
+      const double I = r == cc ? 1.0 : 0.0;
+      double u = cf[1] * I + cf[3] * A2[x];
+      double v = cf[0] * I + cf[2] * A2[x];
+      if (qd >= 5) { u += cf[5] * A4[x]; v += cf[4] * A4[x]; }
+      if (qd >= 7) { u += cf[7] * A6[x]; v += cf[6] * A6[x]; }
+      if (qd >= 9) { u += cf[9] * T2[x]; v += cf[8] * T2[x]; }
+      T1[x] = u;
+      Vm[x] = v;
+    }
+    __syncthreads();
+    bgemm(m, A, T1, U, As, Bs);
+  } else {
+    for (long long x = tid; x < mm; x += DBLOCK)
+      T1[x] = cf[13] * A6[x] + cf[11] * A4[x] + cf[9] * A2[x];
+    __syncthreads();
+    bgemm(m, A6, T1, T2, As, Bs);
+    for (long long x = tid; x < mm; x += DBLOCK) {
+      const int r = (int)(x % m), cc = (int)(x / m);
+      const double I = r == cc ? 1.0 : 0.0;
+      T2[x] += cf[7] * A6[x] + cf[5] * A4[x] + cf[3] * A2[x] + cf[1] * I;
+      T1[x] = cf[12] * A6[x] + cf[10] * A4[x] + cf[8] * A2[x];
+    }
+    __syncthreads();
+    bgemm(m, A, T2, U, As, Bs);
+    bgemm(m, A6, T1, Vm, As, Bs);
+    for (long long x = tid; x < mm; x += DBLOCK) {
+      const int r = (int)(x % m), cc = (int)(x / m);
+      const double I = r == cc ? 1.0 : 0.0;
+      Vm[x] += cf[6] * A6[x] + cf[4] * A4[x] + cf[2] * A2[x] + cf[0] * I;
+    }
+    __syncthreads();
+  }
+  // P = V + U (into T1), Q = V - U (into Vm)
+  for (long long x = tid; x < mm; x += DBLOCK) {
+    const double u = U[x], v = Vm[x];
+    T1[x] = v + u;
+    Vm[x] = v - u;
+  }
+  __syncthreads();
+  const int sing = blu(m, Vm, piv, sh, shi);
+  if (ssq == 0) {
+    // X e_1 = Q^{-1} P e_1
+    for (int r = tid; r < m; r += DBLOCK) c[r] = T1[r];
+    __syncthreads();
+    blu_solve(m, Vm, piv, c, 1);
+  } else {
+    blu_solve(m, Vm, piv, T1, m);   // T1 = X = r(A / 2^s)
+    // X^(2^s) e_1: repeated squaring of the matrix, then the first column
+    double* Xa = T1;
+    double* Xb = T2;
+    for (int t = 0; t < ssq; ++t) {
+      bgemm(m, Xa, Xa, Xb, As, Bs);
+      double* tmp = Xa; Xa = Xb; Xb = tmp;
+    }
+    for (int r = tid; r < m; r += DBLOCK) c[r] = Xa[r];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    info[INFO_NSQ] = ssq;
+    info[INFO_NRM] = nrm;
+    if (sing) info[INFO_FAIL] = 1.0;
+  }
+}
+
+// ----------------------------------------------------------------- polynomial
+__global__ void __launch_bounds__(DBLOCK) k_fpoly(SolveDev d, DenseDev g) {
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  double* ws = g.base + (long long)q * g.stride;
+  const int mu = *st_mused(d, q);
+  if (mu == 0) return;
+  const int m = mu;
+  const double* Hh = ws + g.oH;
+  double* c = ws + g.oVec;
+  double* t = ws + g.oM;       // scratch vector
+  for (int r = tid; r < m; r += DBLOCK) c[r] = 0.0;
+  __syncthreads();
+  for (int j = g.ncoef - 1; j >= 0; --j) {     // Horner: c <- H_hat c + coef_j e_1
+    for (int r = tid; r < m; r += DBLOCK) {
+      double a = 0.0;
+      for (int cc = 0; cc < m; ++cc) a += Hh[r + (long long)cc * m] * c[cc];
+      t[r] = a + (r == 0 ? g.coef[j] : 0.0);
+    }
+    __syncthreads();
+    for (int r = tid; r < m; r += DBLOCK) c[r] = t[r];
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------- real Schur + square root
+// One wave.  T (m x m, ld m) is overwritten by its real Schur form Z^T T Z
+// (quasi upper triangular, 1x1 and 2x2 diagonal blocks); Z accumulates.
+// Returns the number of QR sweeps, or -1 if it failed to converge.
+__device__ inline void house3(double x, double y, double z, double* v1, double* v2, double* tau) {
+  // reflector P = I - tau v v^T with v = (1, v1, v2), P (x,y,z)^T = (beta,0,0)^T
+  const double n = sqrt(x * x + y * y + z * z);
+  if (n == 0.0 || (y == 0.0 && z == 0.0)) { *v1 = 0.0; *v2 = 0.0; *tau = 0.0; return; }
+  const double beta = x >= 0.0 ? -n : n;
+  const double sc = 1.0 / (x - beta);
+  *v1 = y * sc;
+  *v2 = z * sc;
+  *tau = (beta - x) / beta;
+}
+
+__device__ int francis_schur(int m, double* T, double* Z) {
+  const int lane = threadIdx.x & 63;
+  const double eps = 2.220446049250313e-16;
+  int sweeps = 0;
+  int hi = m - 1;
+  int its = 0;
+  const int maxit = 60 * (m > 10 ? m : 10);
+  while (hi >= 0) {
+    if (sweeps > maxit) return -1;
+    // deflation search: largest l <= hi with negligible subdiagonal T[l, l-1]
+    int l = 0;
+    for (int base = hi; base > 0; base -= 64) {
+      const int ll = base - lane;
+      bool neg = false;
+      if (ll >= 1) {
+        const double sub = fabs(T[ll + (long long)(ll - 1) * m]);
+        double tst = fabs(T[ll - 1 + (long long)(ll - 1) * m]) + fabs(T[ll + (long long)ll * m]);
+        if (tst == 0.0) tst = 1.0;
+        neg = sub <= eps * tst;
+      }
+      const unsigned long long bal = __ballot(neg);
+      if (bal) { l = base - (__ffsll((long long)bal) - 1); break; }
+    }
+    if (l > 0 && lane == 0) T[l + (long long)(l - 1) * m] = 0.0;
+    wave_order();
+    if (l >= hi - 1) { hi = l - 1; its = 0; continue; }   // 1x1 or 2x2 block deflated
+    ++its;
+    ++sweeps;
+    // double shift from the trailing 2x2 of the active block (exceptional at 10, 20)
+    double sh, tp;
+    const double a11 = T[hi - 1 + (long long)(hi - 1) * m], a12 = T[hi - 1 + (long long)hi * m];
+    const double a21 = T[hi + (long long)(hi - 1) * m], a22 = T[hi + (long long)hi * m];
+    if (its % 10 == 0) {
+      const double w = fabs(a21) + fabs(T[hi - 1 + (long long)(hi - 2) * m]);
+      sh = 1.5 * w;
+      tp = w * w;
+    } else {
+      sh = a11 + a22;
+      tp = a11 * a22 - a12 * a21;
+    }
+    const double h00 = T[l + (long long)l * m], h01 = T[l + (long long)(l + 1) * m];
+    const double h10 = T[l + 1 + (long long)l * m], h11 = T[l + 1 + (long long)(l + 1) * m];
+    const double h21 = T[l + 2 + (long long)(l + 1) * m];
+    double x = h00 * h00 + h01 * h10 - sh * h00 + tp;
+    double y = h10 * (h00 + h11 - sh);
+    double z = h10 * h21;
+    for (int kk = l; kk <= hi - 2; ++kk) {
+      double v1, v2, tau;
+      house3(x, y, z, &v1, &v2, &tau);
+      if (tau != 0.0) {
+        const int c0 = kk > l ? kk - 1 : l;
+        // rows kk..kk+2, columns c0..m-1
+        for (int cc = c0 + lane; cc < m; cc += 64) {
+          double* col = T + (long long)cc * m;
+          const double sdot = tau * (col[kk] + v1 * col[kk + 1] + v2 * col[kk + 2]);
+          col[kk] -= sdot;
+          col[kk + 1] -= sdot * v1;
+          col[kk + 2] -= sdot * v2;
+        }
+        wave_order();
+        // columns kk..kk+2, rows 0..min(kk+3, hi)
+        const int rlim = kk + 3 < hi ? kk + 3 : hi;
+        for (int r = lane; r <= rlim; r += 64) {
+          double* p0 = T + r + (long long)kk * m;
+          const double sdot = tau * (p0[0] + v1 * p0[m] + v2 * p0[2 * (long long)m]);
+          p0[0] -= sdot;
+          p0[m] -= sdot * v1;
+          p0[2 * (long long)m] -= sdot * v2;
+        }
+        for (int r = lane; r < m; r += 64) {
+          double* p0 = Z + r + (long long)kk * m;
+          const double sdot = tau * (p0[0] + v1 * p0[m] + v2 * p0[2 * (long long)m]);
+          p0[0] -= sdot;
+          p0[m] -= sdot * v1;
+          p0[2 * (long long)m] -= sdot * v2;
+        }
+        wave_order();
+        if (kk > l && lane == 0) {  // entries annihilated by the reflector
+          T[kk + 1 + (long long)(kk - 1) * m] = 0.0;
+          T[kk + 2 + (long long)(kk - 1) * m] = 0.0;
+        }
+        wave_order();
+      }
+      x = T[kk + 1 + (long long)kk * m];
+      y = T[kk + 2 + (long long)kk * m];
+      if (kk < hi - 2) z = T[kk + 3 + (long long)kk * m];
+    }
+    // final 2x2 reflector on rows/cols hi-1, hi
+    {
+      const double n = sqrt(x * x + y * y);
+      if (n != 0.0 && y != 0.0) {
+        const double beta = x >= 0.0 ? -n : n;
+        const double v1 = y / (x - beta);
+        const double tau = (beta - x) / beta;
+        const int kk = hi - 1;
+        for (int cc = kk - 1 + lane; cc < m; cc += 64) {
+          double* col = T + (long long)cc * m;
+          const double sdot = tau * (col[kk] + v1 * col[kk + 1]);
+          col[kk] -= sdot;
+          col[kk + 1] -= sdot * v1;
+        }
+        wave_order();
+        for (int r = lane; r <= hi; r += 64) {
+          double* p0 = T + r + (long long)kk * m;
+          const double sdot = tau * (p0[0] + v1 * p0[m]);
+          p0[0] -= sdot;
+          p0[m] -= sdot * v1;
+        }
+        for (int r = lane; r < m; r += 64) {
+          double* p0 = Z + r + (long long)kk * m;
+          const double sdot = tau * (p0[0] + v1 * p0[m]);
+          p0[0] -= sdot;
+          p0[m] -= sdot * v1;
+        }
+        wave_order();
+        if (lane == 0) T[kk + 1 + (long long)(kk - 1) * m] = 0.0;
+        wave_order();
+      }
+    }
+  }
+  return sweeps;
+}
+
+// square root of a 1x1 or 2x2 diagonal block: R = a I + (T - theta I)/(2a),
+// a^2 = (theta + sqrt(det T))/2 (principal branch for blocks off the closed
+// negative axis); a 1x1 block is sqrt(t).
+__device__ inline void block_sqrt(int p, const double* t, double* r) {  // t, r: 2x2 col-major (p=1 uses [0])
+  if (p == 1) { r[0] = sqrt(t[0]); return; }
+  const double th = 0.5 * (t[0] + t[3]);
+  const double det = t[0] * t[3] - t[1] * t[2];
+  const double a = sqrt(0.5 * (th + sqrt(det)));
+  const double i2a = 0.5 / a;
+  r[0] = a + (t[0] - th) * i2a;
+  r[1] = t[1] * i2a;
+  r[2] = t[2] * i2a;
+  r[3] = a + (t[3] - th) * i2a;
+}
+
+// Solve A x = b for n <= 4 by Gaussian elimination with partial pivoting.
+__device__ inline void small_solve(int n, double* A, double* b) {  // A n x n col-major (ld 4)
+  for (int j = 0; j < n; ++j) {
+    int p = j;
+    for (int r = j + 1; r < n; ++r)
+      if (fabs(A[r + 4 * j]) > fabs(A[p + 4 * j])) p = r;
+    if (p != j) {
+      for (int c = 0; c < n; ++c) { const double t = A[j + 4 * c]; A[j + 4 * c] = A[p + 4 * c]; A[p + 4 * c] = t; }
+      const double t = b[j]; b[j] = b[p]; b[p] = t;
+    }
+    const double pv = A[j + 4 * j];
+    for (int r = j + 1; r < n; ++r) {
+      const double f = A[r + 4 * j] / pv;
+      for (int c = j; c < n; ++c) A[r + 4 * c] -= f * A[j + 4 * c];
+      b[r] -= f * b[j];
+    }
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    double a = b[j];
+    for (int c = j + 1; c < n; ++c) a -= A[j + 4 * c] * b[c];
+    b[j] = a / A[j + 4 * j];
+  }
+}
+
+__global__ void __launch_bounds__(64) k_fpow(SolveDev d, DenseDev g) {
+  const int q = blockIdx.x;
+  const int lane = threadIdx.x;
+  __shared__ int bstart[MAXM + 1];
+  __shared__ double zt[MAXM];
+  __shared__ double xs[MAXM];
+  double* ws = g.base + (long long)q * g.stride;
+  const int mu = *st_mused(d, q);
+  double* c = ws + g.oVec;
+  double* info = ws + g.oInfo;
+  if (mu == 0) return;
+  const int m = mu;
+  const long long mm = (long long)m * m;
+  double* T = ws + g.oM;
+  double* Z = T + mm;
+  double* R = Z + mm;
+  const double* Hh = ws + g.oH;
+  for (long long x = lane; x < mm; x += 64) {
+    const int r = (int)(x % m), cc = (int)(x / m);
+    T[x] = Hh[x] + (r == cc ? g.sigma : 0.0);
+    Z[x] = r == cc ? 1.0 : 0.0;
+    R[x] = 0.0;
+  }
+  wave_order();
+  __syncthreads();
+  const int sweeps = francis_schur(m, T, Z);
+  __syncthreads();
+  if (sweeps < 0) {
+    if (lane == 0) info[INFO_FAIL] = 2.0;
+    for (int r = lane; r < m; r += 64) c[r] = 0.0;
+    return;
+  }
+  // diagonal block structure
+  if (lane == 0) {
+    int nb = 0, i = 0;
+    while (i < m) {
+      bstart[nb++] = i;
+      i += (i + 1 < m && T[i + 1 + (long long)i * m] != 0.0) ? 2 : 1;
+    }
+    bstart[nb] = m;
+    bstart[MAXM] = nb;
+  }
+  __syncthreads();
+  const int nb = bstart[MAXM];
+  // block-column recurrence R_jj = sqrt(T_jj); R_ii X + X R_jj = T_ij - sum_k R_ik R_kj
+  for (int bj = 0; bj < nb; ++bj) {
+    const int j0 = bstart[bj], pj = bstart[bj + 1] - j0;
+    if (lane == 0) {
+      double tb[4], rb[4];
+      tb[0] = T[j0 + (long long)j0 * m];
+      if (pj == 2) {
+        tb[1] = T[j0 + 1 + (long long)j0 * m];
+        tb[2] = T[j0 + (long long)(j0 + 1) * m];
+        tb[3] = T[j0 + 1 + (long long)(j0 + 1) * m];
+      }
+      block_sqrt(pj, tb, rb);
+      R[j0 + (long long)j0 * m] = rb[0];
+      if (pj == 2) {
+        R[j0 + 1 + (long long)j0 * m] = rb[1];
+        R[j0 + (long long)(j0 + 1) * m] = rb[2];
+        R[j0 + 1 + (long long)(j0 + 1) * m] = rb[3];
+      }
+    }
+    wave_order();
+    __syncthreads();
+    for (int bi = bj - 1; bi >= 0; --bi) {
+      const int i0 = bstart[bi], pi = bstart[bi + 1] - i0;
+      const int k0 = i0 + pi;  // sum over k in [k0, j0)
+      double cvals[4];
+      for (int a = 0; a < pi; ++a)
+        for (int b = 0; b < pj; ++b) {
+          double acc = 0.0;
+          for (int kk = k0 + lane; kk < j0; kk += 64)
+            acc += R[i0 + a + (long long)kk * m] * R[kk + (long long)(j0 + b) * m];
+          acc = wsum(acc);
+          cvals[a + 2 * b] = T[i0 + a + (long long)(j0 + b) * m] - acc;
+        }
+      if (lane == 0) {
+        // (I_pj (x) R_ii + R_jj^T (x) I_pi) vec(X) = vec(C)
+        double Ab[16];
+        double rhs[4];
+        const int nn = pi * pj;
+        for (int x = 0; x < 16; ++x) Ab[x] = 0.0;
+        for (int b = 0; b < pj; ++b)
+          for (int a = 0; a < pi; ++a) {
+            const int row = a + pi * b;
+            rhs[row] = cvals[a + 2 * b];
+            for (int a2 = 0; a2 < pi; ++a2) Ab[row + 4 * (a2 + pi * b)] += R[i0 + a + (long long)(i0 + a2) * m];
+            for (int b2 = 0; b2 < pj; ++b2) Ab[row + 4 * (a + pi * b2)] += R[j0 + b2 + (long long)(j0 + b) * m];
+          }
+        small_solve(nn, Ab, rhs);
+        for (int b = 0; b < pj; ++b)
+          for (int a = 0; a < pi; ++a) R[i0 + a + (long long)(j0 + b) * m] = rhs[a + pi * b];
+      }
+      wave_order();
+      __syncthreads();
+    }
+  }
+  // zt = Z^T e_1 (first row of Z)
+  for (int r = lane; r < m; r += 64) zt[r] = Z[(long long)r * m];
+  __syncthreads();
+  if (g.p > 0.0) {
+    // c = Z (R zt)
+    for (int r = lane; r < m; r += 64) {
+      double a = 0.0;
+      for (int cc = 0; cc < m; ++cc) a += R[r + (long long)cc * m] * zt[cc];
+      xs[r] = a;
+    }
+  } else {
+    // R x = zt, block back substitution
+    for (int bi = nb - 1; bi >= 0; --bi) {
+      const int i0 = bstart[bi], pi = bstart[bi + 1] - i0;
+      double rv[2];
+      for (int a = 0; a < pi; ++a) {
+        double acc = 0.0;
+        for (int cc = i0 + pi + lane; cc < m; cc += 64) acc += R[i0 + a + (long long)cc * m] * xs[cc];
+        rv[a] = zt[i0 + a] - wsum(acc);
+      }
+      if (lane == 0) {
+        double Ab[16];
+        for (int a = 0; a < pi; ++a)
+          for (int a2 = 0; a2 < pi; ++a2) Ab[a + 4 * a2] = R[i0 + a + (long long)(i0 + a2) * m];
+        small_solve(pi, Ab, rv);
+        for (int a = 0; a < pi; ++a) xs[i0 + a] = rv[a];
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (int r = lane; r < m; r += 64) {
+    double a = 0.0;
+    for (int cc = 0; cc < m; ++cc) a += Z[r + (long long)cc * m] * xs[cc];
+    c[r] = a;
+  }
+  if (lane == 0) info[INFO_SCHUR_IT] = sweeps;
+}
+
+// ----------------------------------------------------------------- combination weights
+__global__ void k_coef(SolveDev d, DenseDev g, double* cf) {
+  const int q = blockIdx.x;
+  const int m = d.m;
+  const double* ws = g.base + (long long)q * g.stride;
+  const double* c = ws + g.oVec;
+  const double* eta = d.eta + (long long)q * (m + 1);
+  const int mu = *st_mused(d, q);
+  const double beta = eta[0];
+  for (int j = threadIdx.x; j <= m; j += blockDim.x)
+    cf[(long long)q * (m + 1) + j] = (j < mu && eta[j] > 0.0) ? beta * c[j] / eta[j] : 0.0;
+}
+
+hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st) {
+  hipLaunchKernelGGL(k_lsq, dim3(d.nrhs), dim3(DBLOCK), 0, st, d, g);
+  if (g.fkind == 1) hipLaunchKernelGGL(k_fexp, dim3(d.nrhs), dim3(DBLOCK), 0, st, d, g);
+  else if (g.fkind == 2) hipLaunchKernelGGL(k_fpow, dim3(d.nrhs), dim3(64), 0, st, d, g);
+  else hipLaunchKernelGGL(k_fpoly, dim3(d.nrhs), dim3(DBLOCK), 0, st, d, g);
+  hipLaunchKernelGGL(k_coef, dim3(d.nrhs), dim3(256), 0, st, d, g, cf);
+  return hipGetLastError();
+}
+
+}  // namespace fab

@@ -1,0 +1,788 @@
+// libfab host runtime: the C ABI of include/fab.h.
+//
+//  * Arena: one device allocation (caller-provided or owned) carved by a
+//    first-fit allocator with coalescing; matrices and per-request
+//    workspaces live in it, so admission control is "does the workspace fit".
+//  * Solve plan: sizes, partition of the rows into tiles, device descriptors.
+//  * Launch sequence per solve (all on one stream, no host round trip):
+//      init -> start (u_0 = b) -> m x (dots, update) -> finish -> dense tail
+//      (sketched QR / least squares, f(H_hat) e_1, weights) -> combine.
+//  * Serving loop: fab_submit queues a request; a scheduler thread admits
+//    queued requests in FIFO order whenever their workspace fits next to the
+//    running ones, runs each admitted request on its own stream (so work of
+//    different requests overlaps on the device), and retires them as their
+//    completion events fire.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fab.h"
+#include "fab_dev.h"
+
+namespace fab {
+hipError_t basis_set_attributes();
+hipError_t basis_start(const SolveDev& d, int esize, hipStream_t st, size_t lds);
+hipError_t basis_step(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds);
+hipError_t basis_finish(const SolveDev& d, int esize, hipStream_t st);
+hipError_t basis_combine(const SolveDev& d, int esize, const double* cf, int mmax, double* out, hipStream_t st);
+hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st);
+hipError_t zero_fill(void* p, size_t bytes, hipStream_t st);
+hipError_t srht_sample_rows(int* rows, long long npad, int s, unsigned long long key, hipStream_t st);
+}  // namespace fab
+
+using namespace fab;
+
+// ============================================================== arena allocator
+namespace {
+
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  bool owned = false;
+  std::map<size_t, size_t> free_;   // offset -> length
+  size_t in_use = 0;
+
+  void init(char* b, size_t n) {
+    base = b;
+    size = n;
+    free_.clear();
+    free_[0] = n;
+    in_use = 0;
+  }
+  // first fit, 256-byte aligned lengths; returns nullptr if no block fits
+  void* alloc(size_t n) {
+    n = (n + 255) & ~size_t(255);
+    if (n == 0) n = 256;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > n) free_[off + n] = len - n;
+        in_use += n;
+        sizes_[off] = n;
+        return base + off;
+      }
+    }
+    return nullptr;
+  }
+  void release(void* p) {
+    if (!p) return;
+    const size_t off = (char*)p - base;
+    auto sit = sizes_.find(off);
+    if (sit == sizes_.end()) return;
+    size_t n = sit->second;
+    sizes_.erase(sit);
+    in_use -= n;
+    size_t o = off;
+    auto nx = free_.lower_bound(o);
+    if (nx != free_.end() && nx->first == o + n) {
+      n += nx->second;
+      free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(o);
+    if (pv != free_.begin()) {
+      --pv;
+      if (pv->first + pv->second == o) {
+        o = pv->first;
+        n += pv->second;
+        free_.erase(pv);
+      }
+    }
+    free_[o] = n;
+  }
+  bool could_ever_fit(size_t n) const { return ((n + 255) & ~size_t(255)) <= size; }
+
+ private:
+  std::map<size_t, size_t> sizes_;
+};
+
+double now_us() {
+  using namespace std::chrono;
+  return duration<double, std::micro>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct fab_matrix_s {
+  fab_ctx ctx = nullptr;
+  int op = OP_STENCIL;
+  int dim = 2, nx = 1, ny = 1, nz = 1;
+  double c[7] = {0};
+  int n = 0;
+  long long nnz = 0;
+  int* rowptr = nullptr;
+  int* col = nullptr;
+  float* val = nullptr;
+  std::atomic<int> refs{0};
+};
+
+namespace {
+
+struct Plan {
+  // inputs
+  fab_matrix A = nullptr;
+  const double* b = nullptr;
+  double* out = nullptr;
+  int nrhs = 1;
+  fab_func f{};
+  std::vector<double> coef;
+  fab_params p{};
+  int esize = 4;
+  // derived
+  int R = 0, logR = 0, ntiles = 0, nblk = 0, nred = 0;
+  size_t lds_update = 0;
+  size_t bytes = 0;
+  // offsets in the workspace
+  size_t oV, oW, oH, oEta, oWn, oCoef, oS, oPart, oNpart, oSk, oCnt, oStatus, oRows, oDense, oCf, oInfoHost;
+  size_t dense_stride = 0;  // doubles per rhs
+  size_t oDW, oDH, oDM, oDVec, oDInfo;
+};
+
+int ilog2(long long v) {
+  int l = 0;
+  while ((1LL << l) < v) ++l;
+  return l;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, int esize, Plan& P) {
+  if (!A || !pp) return FAB_EINVAL;
+  const fab_params& p = *pp;
+  const long long n = A->n;
+  if (nrhs < 1 || nrhs > 32 || (nrhs & (nrhs - 1))) return FAB_EINVAL;
+  if (p.m < 1 || p.m >= n || p.m > 500) return FAB_EINVAL;
+  if (p.k < 1 || p.k > KMAX) return FAB_EINVAL;
+  if (p.sketch != FAB_SKETCH_SRHT && p.sketch != FAB_SKETCH_SPARSE_SIGN) return FAB_EINVAL;
+  const long long npad = 1LL << ilog2(n);
+  if (p.s <= p.m || p.s > 8192 || p.s > npad) return FAB_EINVAL;
+  if (p.sketch == FAB_SKETCH_SPARSE_SIGN && (p.zeta < 1 || p.zeta > ZMAX || p.zeta > p.s)) return FAB_EINVAL;
+  if (p.ls_mode < FAB_LS_AUTO || p.ls_mode > FAB_LS_LSQR) return FAB_EINVAL;
+  if (f.kind == FAB_F_POW) {
+    if (!(f.p == 0.5 || f.p == -0.5)) return FAB_EINVAL;
+  } else if (f.kind == FAB_F_POLY) {
+    if (f.ncoef < 1 || f.ncoef > MAXCOEF || !f.coef) return FAB_EINVAL;
+  } else if (f.kind != FAB_F_EXP) {
+    return FAB_EINVAL;
+  }
+  P.A = A;
+  P.nrhs = nrhs;
+  P.f = f;
+  if (f.kind == FAB_F_POLY) P.coef.assign(f.coef, f.coef + f.ncoef);
+  P.p = p;
+  P.esize = esize;
+  // tiles: R rows (power of two), R * nrhs <= TILE_ELEMS, aim for >= 512 tiles
+  int R = TILE_ELEMS / nrhs;
+  while (R > 64 && (n + R - 1) / R < 512) R >>= 1;
+  P.R = R;
+  P.logR = ilog2(R);
+  P.ntiles = (int)((n + R - 1) / R);
+  P.nblk = std::min(P.ntiles, 2048);
+  const long long snr = (long long)p.s * nrhs;
+  P.nred = (int)std::max<long long>(1, std::min<long long>((snr + 3) / 4, 64));
+  P.lds_update = (size_t)(snr + (p.sketch == FAB_SKETCH_SRHT ? (long long)R * nrhs : 0)) * 8;
+  if (P.lds_update > 160 * 1024) return FAB_EINVAL;
+  const int m = p.m, s = p.s;
+  // dense workspace per rhs
+  size_t o = 0;
+  P.oDW = o; o += (size_t)s * (m + 1);
+  P.oDH = o; o += (size_t)m * m;
+  P.oDM = o; o += (size_t)8 * m * m;
+  P.oDVec = o; o += (size_t)8 * (m + 1);
+  P.oDInfo = o; o += NINFO;
+  P.dense_stride = (o + 31) & ~size_t(31);
+  // workspace layout
+  size_t w = 0;
+  auto take = [&](size_t bytes) { size_t at = w; w = align256(w + bytes); return at; };
+  P.oV = take((size_t)(m + 1) * n * nrhs * esize);
+  P.oW = A->op == OP_CSR ? take((size_t)n * nrhs * 8) : 0;
+  P.oH = take((size_t)nrhs * (m + 1) * m * 8);
+  P.oEta = take((size_t)nrhs * (m + 1) * 8);
+  P.oWn = take((size_t)nrhs * (m + 1) * 8);
+  P.oCoef = take((size_t)nrhs * NSLOT * 8);
+  P.oS = take((size_t)nrhs * s * (m + 1) * 8);
+  P.oPart = take((size_t)P.nblk * nrhs * NSLOT * 8);
+  P.oNpart = take((size_t)P.nblk * nrhs * 8);
+  P.oSk = take((size_t)snr * P.nblk * 8);
+  P.oCnt = take(256);
+  P.oStatus = take((size_t)(4 + 2 * nrhs) * 4);
+  P.oRows = take((size_t)s * 4);
+  P.oDense = take(P.dense_stride * nrhs * 8);
+  P.oCf = take((size_t)nrhs * (m + 1) * 8);
+  P.bytes = w;
+  return FAB_OK;
+}
+
+struct Request;
+
+}  // namespace
+
+struct fab_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Arena arena;
+  std::mutex mu;                 // arena + request table
+  std::condition_variable cv;
+  std::vector<hipStream_t> pool; // serving streams
+  std::vector<int> pool_busy;
+  std::deque<uint64_t> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
+  uint64_t next_id = 1;
+  std::thread sched;
+  bool stop = false;
+  std::set<fab_matrix> matrices;
+  double* host_info = nullptr;   // pinned staging for blocking solves
+  std::mutex solve_mu;
+};
+
+namespace {
+
+struct Request {
+  uint64_t id = 0;
+  Plan plan;
+  char* ws = nullptr;
+  int stream_idx = -1;
+  hipEvent_t done_ev = nullptr;
+  double* host_info = nullptr;   // pinned: [nrhs][NINFO] + status
+  int state = 0;                 // 0 queued, 1 running, 2 done
+  int status = FAB_OK;
+  double t_submit = 0.0, t_done = 0.0;
+  std::vector<fab_info> info;
+};
+
+size_t host_info_doubles(int nrhs) { return (size_t)nrhs * NINFO + 4 + 2 * nrhs + 8; }
+
+// Enqueue the whole solve on `st`.  Host-visible results land in `hinfo` (pinned).
+int enqueue_solve(Plan& P, char* ws, hipStream_t st, double* hinfo) {
+  const fab_params& p = P.p;
+  fab_matrix A = P.A;
+  const int m = p.m, s = p.s, nr = P.nrhs;
+  SolveDev d{};
+  d.n = A->n;
+  d.nrhs = nr;
+  d.lognrhs = ilog2(nr);
+  d.m = m;
+  d.k = p.k;
+  d.s = s;
+  d.zeta = p.zeta;
+  d.op = A->op;
+  d.nx = A->nx;
+  d.ny = A->ny;
+  d.nz = A->nz;
+  for (int i = 0; i < 7; ++i) d.c[i] = A->c[i];
+  d.rowptr = A->rowptr;
+  d.col = A->col;
+  d.val = A->val;
+  d.V = ws + P.oV;
+  d.ldv = (long long)A->n * nr;
+  d.wbuf = A->op == OP_CSR ? (double*)(ws + P.oW) : nullptr;
+  d.b = P.b;
+  d.H = (double*)(ws + P.oH);
+  d.eta = (double*)(ws + P.oEta);
+  d.wnorm = (double*)(ws + P.oWn);
+  d.coef = (double*)(ws + P.oCoef);
+  d.S = (double*)(ws + P.oS);
+  d.rows_per_tile = P.R;
+  d.log_rows = P.logR;
+  d.ntiles = P.ntiles;
+  d.nblk = P.nblk;
+  d.nred = P.nred;
+  d.part = (double*)(ws + P.oPart);
+  d.npart = (double*)(ws + P.oNpart);
+  d.skpart = (double*)(ws + P.oSk);
+  d.counter = (unsigned*)(ws + P.oCnt);
+  d.status = (int*)(ws + P.oStatus);
+  d.sketch = p.sketch == FAB_SKETCH_SRHT ? SK_SRHT : SK_SPARSE;
+  d.srht_rows = (const int*)(ws + P.oRows);
+  if (d.sketch == SK_SRHT) {
+    d.key_a = sm64_out(p.seed, 1);
+    d.key_b = 0;
+    d.sk_scale = 1.0 / std::sqrt((double)s);
+  } else {
+    d.key_a = sm64_out(p.seed, 3);
+    d.key_b = sm64_out(p.seed, 4);
+    d.sk_scale = 1.0 / std::sqrt((double)p.zeta);
+  }
+  d.unit_round = P.esize == 4 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+
+  DenseDev g{};
+  g.m = m;
+  g.s = s;
+  g.nrhs = nr;
+  g.stride = (long long)P.dense_stride;
+  g.base = (double*)(ws + P.oDense);
+  g.oW = (long long)P.oDW;
+  g.oH = (long long)P.oDH;
+  g.oM = (long long)P.oDM;
+  g.oVec = (long long)P.oDVec;
+  g.oInfo = (long long)P.oDInfo;
+  g.ls_mode = p.ls_mode == FAB_LS_NONE ? 2 : 1;
+  g.fkind = P.f.kind;
+  g.alpha = P.f.alpha;
+  g.sigma = P.f.sigma;
+  g.p = P.f.p;
+  g.ncoef = (int)P.coef.size();
+  for (size_t i = 0; i < P.coef.size(); ++i) g.coef[i] = P.coef[i];
+
+  hipError_t e;
+  // zero the small state: H, eta, wnorm, coef, S, counter, status (contiguous from oH .. oRows)
+  if ((e = zero_fill(ws + P.oH, P.oPart - P.oH, st)) != hipSuccess) return FAB_EDEVICE;
+  if ((e = zero_fill(ws + P.oCnt, P.oRows - P.oCnt, st)) != hipSuccess) return FAB_EDEVICE;
+  if (d.sketch == SK_SRHT &&
+      srht_sample_rows((int*)(ws + P.oRows), 1LL << ilog2(A->n), s, sm64_out(p.seed, 2), st) != hipSuccess)
+    return FAB_EDEVICE;
+  if ((e = basis_start(d, P.esize, st, P.lds_update)) != hipSuccess) return FAB_EDEVICE;
+  for (int i = 1; i <= m; ++i)
+    if ((e = basis_step(d, P.esize, i, st, P.lds_update)) != hipSuccess) return FAB_EDEVICE;
+  if ((e = basis_finish(d, P.esize, st)) != hipSuccess) return FAB_EDEVICE;
+  double* cf = (double*)(ws + P.oCf);
+  if ((e = dense_tail(d, g, cf, st)) != hipSuccess) return FAB_EDEVICE;
+  if ((e = basis_combine(d, P.esize, cf, m, P.out, st)) != hipSuccess) return FAB_EDEVICE;
+  // results to pinned host memory: per-rhs dense info, then status ints
+  for (int q = 0; q < nr; ++q) {
+    e = hipMemcpyAsync(hinfo + (size_t)q * NINFO, g.base + (size_t)q * P.dense_stride + P.oDInfo, NINFO * 8,
+                       hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return FAB_EDEVICE;
+  }
+  e = hipMemcpyAsync(hinfo + (size_t)nr * NINFO, d.status, (size_t)(4 + 2 * nr) * 4, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return FAB_EDEVICE;
+  return FAB_OK;
+}
+
+int collect_info(const Plan& P, const double* hinfo, std::vector<fab_info>& out) {
+  const int nr = P.nrhs;
+  const int* status = (const int*)(hinfo + (size_t)nr * NINFO);
+  out.assign(nr, fab_info{});
+  int rc = FAB_OK;
+  if (status[1]) rc = FAB_ENUMERIC;
+  for (int q = 0; q < nr; ++q) {
+    const double* in = hinfo + (size_t)q * NINFO;
+    fab_info& fi = out[q];
+    fi.m_used = status[4 + 2 * q];
+    fi.breakdown = status[5 + 2 * q] ? 1 : 0;
+    fi.kappa_R = in[0];
+    fi.h_last = in[1];
+    fi.beta = in[2];
+    fi.prec_used = P.esize == 4 ? FAB_PREC_FP32 : FAB_PREC_FP64;
+    fi.err_est = 0.0;
+    fi.ls_gate = 0.0;
+    fi.round_est = 0.0;
+    fi.conv_est = 0.0;
+    fi.ls_iters = 0;
+    fi.fell_back = 0;
+    if (in[3] != 0.0) rc = FAB_ENUMERIC;
+    if (!std::isfinite(fi.beta)) rc = FAB_ENUMERIC;
+  }
+  return rc;
+}
+
+int esize_for(int prec) { return prec == FAB_PREC_FP64 ? 8 : 4; }
+
+// ---------------------------------------------------------------- scheduler
+void retire_locked(fab_ctx ctx, Request& r) {
+  r.status = collect_info(r.plan, r.host_info, r.info);
+  r.t_done = now_us();
+  for (auto& fi : r.info) fi.latency_us = r.t_done - r.t_submit;
+  ctx->arena.release(r.ws);
+  r.ws = nullptr;
+  ctx->pool_busy[r.stream_idx] = 0;
+  r.plan.A->refs.fetch_sub(1);
+  r.state = 2;
+}
+
+void admit_locked(fab_ctx ctx) {
+  while (!ctx->queue.empty()) {
+    auto it = ctx->reqs.find(ctx->queue.front());
+    if (it == ctx->reqs.end()) { ctx->queue.pop_front(); continue; }
+    Request& r = *it->second;
+    int si = -1;
+    for (size_t i = 0; i < ctx->pool.size(); ++i)
+      if (!ctx->pool_busy[i]) { si = (int)i; break; }
+    if (si < 0) return;
+    char* ws = (char*)ctx->arena.alloc(r.plan.bytes);
+    if (!ws) return;   // FIFO: wait until running requests free memory
+    ctx->queue.pop_front();
+    r.ws = ws;
+    r.stream_idx = si;
+    ctx->pool_busy[si] = 1;
+    hipSetDevice(ctx->device);
+    int rc = enqueue_solve(r.plan, ws, ctx->pool[si], r.host_info);
+    if (rc == FAB_OK && hipEventRecord(r.done_ev, ctx->pool[si]) != hipSuccess) rc = FAB_EDEVICE;
+    if (rc != FAB_OK) {
+      hipStreamSynchronize(ctx->pool[si]);
+      ctx->arena.release(ws);
+      r.ws = nullptr;
+      ctx->pool_busy[si] = 0;
+      r.plan.A->refs.fetch_sub(1);
+      r.status = rc;
+      r.state = 2;
+      r.t_done = now_us();
+      continue;
+    }
+    r.state = 1;
+  }
+}
+
+void scheduler_main(fab_ctx ctx) {
+  hipSetDevice(ctx->device);
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  while (true) {
+    bool progressed = false;
+    for (auto& kv : ctx->reqs) {
+      Request& r = *kv.second;
+      if (r.state == 1 && hipEventQuery(r.done_ev) == hipSuccess) {
+        retire_locked(ctx, r);
+        progressed = true;
+      }
+    }
+    admit_locked(ctx);
+    if (progressed) ctx->cv.notify_all();
+    bool running = false;
+    for (auto& kv : ctx->reqs)
+      if (kv.second->state == 1) running = true;
+    if (ctx->stop && !running && ctx->queue.empty()) break;
+    if (running) {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+    } else {
+      ctx->cv.wait_for(lk, std::chrono::milliseconds(5));
+    }
+  }
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+extern "C" {
+
+const char* fab_version(void) { return "libfab 0.1 (gfx950)"; }
+
+const char* fab_strerror(int code) {
+  switch (code) {
+    case FAB_OK: return "ok";
+    case FAB_EINVAL: return "invalid argument";
+    case FAB_ENOMEM: return "request can never fit the arena";
+    case FAB_EDEVICE: return "HIP runtime error";
+    case FAB_ENUMERIC: return "non-finite input or result";
+    case FAB_EBUSY: return "matrix in use by in-flight requests";
+    case FAB_ENOTFOUND: return "unknown request";
+    default: return "unknown status";
+  }
+}
+
+int fab_init(fab_ctx* out, int device, void* arena_dev_ptr, size_t arena_bytes, void* hip_stream) {
+  if (!out || arena_bytes < (1u << 20)) return FAB_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FAB_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return FAB_EDEVICE;
+  // Raising the dynamic-LDS limit is best effort: a launch that needs more than
+  // the device grants fails with a HIP error, reported as FAB_EDEVICE.
+  (void)basis_set_attributes();
+  (void)hipGetLastError();
+  auto* ctx = new fab_ctx_s();
+  ctx->device = device;
+  char* base = (char*)arena_dev_ptr;
+  if (!base) {
+    if (hipMalloc((void**)&base, arena_bytes) != hipSuccess) { delete ctx; return FAB_EDEVICE; }
+    ctx->arena.owned = true;
+  }
+  ctx->arena.init(base, arena_bytes);
+  if (hip_stream) {
+    ctx->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return FAB_EDEVICE; }
+    ctx->own_stream = true;
+  }
+  const int npool = 8;
+  for (int i = 0; i < npool; ++i) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) { delete ctx; return FAB_EDEVICE; }
+    ctx->pool.push_back(s);
+    ctx->pool_busy.push_back(0);
+  }
+  if (hipHostMalloc((void**)&ctx->host_info, host_info_doubles(32) * 8, hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return FAB_EDEVICE;
+  }
+  ctx->sched = std::thread(scheduler_main, ctx);
+  *out = ctx;
+  return FAB_OK;
+}
+
+int fab_create_matrix_stencil(fab_ctx ctx, int dim, int nx, int ny, int nz, const double coeff[7], fab_matrix* A) {
+  if (!ctx || !A || !coeff) return FAB_EINVAL;
+  if (dim != 2 && dim != 3) return FAB_EINVAL;
+  if (nx < 1 || ny < 1 || nz < 1 || (dim == 2 && nz != 1)) return FAB_EINVAL;
+  const long long n = (long long)nx * ny * nz;
+  if (n >= (1LL << 31) || n < 2) return FAB_EINVAL;
+  auto* M = new fab_matrix_s();
+  M->ctx = ctx;
+  M->op = OP_STENCIL;
+  M->dim = dim;
+  M->nx = nx;
+  M->ny = ny;
+  M->nz = nz;
+  for (int i = 0; i < 7; ++i) M->c[i] = coeff[i];
+  if (dim == 2) M->c[5] = M->c[6] = 0.0;
+  M->n = (int)n;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->matrices.insert(M);
+  }
+  *A = M;
+  return FAB_OK;
+}
+
+int fab_create_matrix_csr(fab_ctx ctx, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                          const float* val, int ptr_is_device, fab_matrix* A) {
+  if (!ctx || !A || !rowptr || n < 2 || n >= (1LL << 31) || nnz < 0 || nnz >= (1LL << 31)) return FAB_EINVAL;
+  if (nnz > 0 && (!col || !val)) return FAB_EINVAL;
+  hipSetDevice(ctx->device);
+  std::vector<int32_t> hrp;
+  if (!ptr_is_device) {
+    if (rowptr[0] != 0 || rowptr[n] != nnz) return FAB_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+      if (rowptr[i + 1] < rowptr[i]) return FAB_EINVAL;
+    for (int64_t i = 0; i < nnz; ++i)
+      if (col[i] < 0 || col[i] >= n) return FAB_EINVAL;
+  } else {
+    // device input: bring the index arrays to the host once and validate them
+    // the same way, so that no kernel ever gathers through a bad index
+    hrp.resize(n + 1);
+    std::vector<int32_t> hcol((size_t)nnz);
+    if (hipMemcpy(hrp.data(), rowptr, (n + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess) return FAB_EDEVICE;
+    if (nnz > 0 && hipMemcpy(hcol.data(), col, nnz * 4, hipMemcpyDeviceToHost) != hipSuccess) return FAB_EDEVICE;
+    if (hrp[0] != 0 || hrp[n] != nnz) return FAB_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+      if (hrp[i + 1] < hrp[i]) return FAB_EINVAL;
+    for (int64_t i = 0; i < nnz; ++i)
+      if (hcol[i] < 0 || hcol[i] >= n) return FAB_EINVAL;
+  }
+  const size_t brp = align256((size_t)(n + 1) * 4), bcol = align256((size_t)nnz * 4), bval = align256((size_t)nnz * 4);
+  char* mem;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    mem = (char*)ctx->arena.alloc(brp + bcol + bval);
+  }
+  if (!mem) return FAB_ENOMEM;
+  const hipMemcpyKind kind = ptr_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (hipMemcpy(mem, rowptr, (n + 1) * 4, kind) != hipSuccess ||
+      (nnz > 0 && hipMemcpy(mem + brp, col, nnz * 4, kind) != hipSuccess) ||
+      (nnz > 0 && hipMemcpy(mem + brp + bcol, val, nnz * 4, kind) != hipSuccess)) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->arena.release(mem);
+    return FAB_EDEVICE;
+  }
+  auto* M = new fab_matrix_s();
+  M->ctx = ctx;
+  M->op = OP_CSR;
+  M->n = (int)n;
+  M->nnz = nnz;
+  M->rowptr = (int*)mem;
+  M->col = (int*)(mem + brp);
+  M->val = (float*)(mem + brp + bcol);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->matrices.insert(M);
+  }
+  *A = M;
+  return FAB_OK;
+}
+
+int fab_destroy_matrix(fab_matrix A) {
+  if (!A) return FAB_EINVAL;
+  fab_ctx ctx = A->ctx;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (A->refs.load() > 0) return FAB_EBUSY;
+  if (A->op == OP_CSR) ctx->arena.release(A->rowptr);
+  ctx->matrices.erase(A);
+  delete A;
+  return FAB_OK;
+}
+
+static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, const fab_params* p,
+                      double* out, fab_info* info, const fab_diag* diag) {
+  if (!ctx || !A || !b || !out || !p || A->ctx != ctx) return FAB_EINVAL;
+  const double t0 = now_us();
+  std::lock_guard<std::mutex> slk(ctx->solve_mu);
+  hipSetDevice(ctx->device);
+  int first_prec = p->prec == FAB_PREC_FP64 ? FAB_PREC_FP64 : FAB_PREC_FP32;
+  Plan P;
+  int rc = make_plan(A, nrhs, f, p, esize_for(first_prec), P);
+  if (rc != FAB_OK) return rc;
+  P.b = b;
+  P.out = out;
+  char* ws = nullptr;
+  {
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    if (!ctx->arena.could_ever_fit(P.bytes)) return FAB_ENOMEM;
+    while (!(ws = (char*)ctx->arena.alloc(P.bytes))) {
+      bool running = false;
+      for (auto& kv : ctx->reqs)
+        if (kv.second->state == 1) running = true;
+      if (!running) return FAB_ENOMEM;
+      ctx->cv.wait_for(lk, std::chrono::milliseconds(1));
+    }
+  }
+  rc = enqueue_solve(P, ws, ctx->stream, ctx->host_info);
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == FAB_OK) rc = FAB_EDEVICE;
+  std::vector<fab_info> fi;
+  if (rc == FAB_OK) rc = collect_info(P, ctx->host_info, fi);
+  if (diag && (rc == FAB_OK || rc == FAB_ENUMERIC)) {
+    const int m = P.p.m, s = P.p.s;
+    for (int q = 0; q < nrhs; ++q) {
+      const char* dq = ws + P.oDense + (size_t)q * P.dense_stride * 8;
+      hipError_t e = hipSuccess;
+      if (diag->hbar)
+        e = hipMemcpy(diag->hbar + (size_t)q * (m + 1) * m, ws + P.oH + (size_t)q * (m + 1) * m * 8,
+                      (size_t)(m + 1) * m * 8, hipMemcpyDeviceToHost);
+      if (e == hipSuccess && diag->eta)
+        e = hipMemcpy(diag->eta + (size_t)q * (m + 1), ws + P.oEta + (size_t)q * (m + 1) * 8, (size_t)(m + 1) * 8,
+                      hipMemcpyDeviceToHost);
+      if (e == hipSuccess && diag->y)
+        e = hipMemcpy(diag->y + (size_t)q * m, dq + (P.oDVec + 2 * (size_t)m) * 8, (size_t)m * 8, hipMemcpyDeviceToHost);
+      if (e == hipSuccess && diag->c)
+        e = hipMemcpy(diag->c + (size_t)q * m, dq + P.oDVec * 8, (size_t)m * 8, hipMemcpyDeviceToHost);
+      if (e == hipSuccess && diag->sv) {
+        std::vector<double> raw((size_t)s * (m + 1)), eta(m + 1);
+        e = hipMemcpy(raw.data(), ws + P.oS + (size_t)q * s * (m + 1) * 8, raw.size() * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+          e = hipMemcpy(eta.data(), ws + P.oEta + (size_t)q * (m + 1) * 8, (size_t)(m + 1) * 8, hipMemcpyDeviceToHost);
+        for (int j = 0; j <= m && e == hipSuccess; ++j)
+          for (int r = 0; r < s; ++r)
+            diag->sv[(size_t)q * s * (m + 1) + (size_t)j * s + r] = eta[j] > 0 ? raw[(size_t)j * s + r] / eta[j] : 0.0;
+      }
+      if (e != hipSuccess) rc = FAB_EDEVICE;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->arena.release(ws);
+  }
+  const double t1 = now_us();
+  if (info && !fi.empty())
+    for (int q = 0; q < nrhs; ++q) {
+      info[q] = fi[q];
+      info[q].latency_us = t1 - t0;
+    }
+  return rc;
+}
+
+int fab_solve(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, const fab_params* p, double* out,
+              fab_info* info) {
+  return solve_impl(ctx, A, b, nrhs, f, p, out, info, nullptr);
+}
+
+int fab_solve_diag(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, const fab_params* p,
+                   double* out, fab_info* info, const fab_diag* diag) {
+  return solve_impl(ctx, A, b, nrhs, f, p, out, info, diag);
+}
+
+int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, const fab_params* p, double* out,
+               fab_request* req) {
+  if (!ctx || !A || !b || !out || !p || !req || A->ctx != ctx) return FAB_EINVAL;
+  auto r = std::make_shared<Request>();
+  int first_prec = p->prec == FAB_PREC_FP64 ? FAB_PREC_FP64 : FAB_PREC_FP32;
+  int rc = make_plan(A, nrhs, f, p, esize_for(first_prec), r->plan);
+  if (rc != FAB_OK) return rc;
+  r->plan.b = b;
+  r->plan.out = out;
+  hipSetDevice(ctx->device);
+  if (hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) return FAB_EDEVICE;
+  if (hipHostMalloc((void**)&r->host_info, host_info_doubles(nrhs) * 8, hipHostMallocDefault) != hipSuccess) {
+    hipEventDestroy(r->done_ev);
+    return FAB_EDEVICE;
+  }
+  r->t_submit = now_us();
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!ctx->arena.could_ever_fit(r->plan.bytes)) {
+    hipEventDestroy(r->done_ev);
+    hipHostFree(r->host_info);
+    return FAB_ENOMEM;
+  }
+  r->id = ctx->next_id++;
+  A->refs.fetch_add(1);
+  ctx->reqs[r->id] = r;
+  ctx->queue.push_back(r->id);
+  *req = r->id;
+  ctx->cv.notify_all();
+  return FAB_OK;
+}
+
+static int finish_request(fab_ctx ctx, std::unordered_map<uint64_t, std::shared_ptr<Request>>::iterator it,
+                          fab_info* info) {
+  Request& r = *it->second;
+  const int rc = r.status;
+  if (info)
+    for (size_t q = 0; q < r.info.size(); ++q) info[q] = r.info[q];
+  hipEventDestroy(r.done_ev);
+  hipHostFree(r.host_info);
+  ctx->reqs.erase(it);
+  return rc;
+}
+
+int fab_poll(fab_ctx ctx, fab_request req, int* done, fab_info* info) {
+  if (!ctx || !done) return FAB_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->reqs.find(req);
+  if (it == ctx->reqs.end()) return FAB_ENOTFOUND;
+  if (it->second->state != 2) { *done = 0; return FAB_OK; }
+  *done = 1;
+  return finish_request(ctx, it, info);
+}
+
+int fab_wait(fab_ctx ctx, fab_request req, fab_info* info) {
+  if (!ctx) return FAB_EINVAL;
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  auto it = ctx->reqs.find(req);
+  if (it == ctx->reqs.end()) return FAB_ENOTFOUND;
+  ctx->cv.wait(lk, [&] { return it->second->state == 2; });
+  return finish_request(ctx, it, info);
+}
+
+int fab_finalize(fab_ctx ctx) {
+  if (!ctx) return FAB_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->stop = true;
+    ctx->cv.notify_all();
+  }
+  if (ctx->sched.joinable()) ctx->sched.join();
+  hipSetDevice(ctx->device);
+  for (auto& kv : ctx->reqs) {
+    if (kv.second->done_ev) hipEventDestroy(kv.second->done_ev);
+    if (kv.second->host_info) hipHostFree(kv.second->host_info);
+  }
+  ctx->reqs.clear();
+  for (auto* M : ctx->matrices) delete M;
+  ctx->matrices.clear();
+  for (auto s : ctx->pool) {
+    hipStreamSynchronize(s);
+    hipStreamDestroy(s);
+  }
+  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  else hipStreamSynchronize(ctx->stream);
+  if (ctx->host_info) hipHostFree(ctx->host_info);
+  if (ctx->arena.owned) hipFree(ctx->arena.base);
+  delete ctx;
+  return FAB_OK;
+}
+
+}  // extern "C"

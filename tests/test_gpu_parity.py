@@ -1,0 +1,274 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances: relative 2-norm error 1e-10 for the FP64-basis form and 1e-6 for
+the FP32-basis form against the oracle's f_m (eq. (4)) at the same m;
+stage-by-stage (Hbar of eq. (3), Theta V, y of eq. (7), f(H_hat) e_1) against
+the oracle's step-by-step Algorithm 2 + sketch-and-solve in FP64.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import closed_form, krylov, operators, sketch as osk
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-10, 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2212_12758_amd import Context
+
+    assert torch.cuda.is_available()
+    c = Context(0, arena_bytes=8 << 30)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def _params(w, prec, ls="sketch", m=None, seed=None):
+    from paper_2212_12758_amd import make_params
+
+    return make_params(m or w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed if seed is None else seed, prec, ls)
+
+
+def _solve(ctx, w, A, b, prec, ls="sketch", diag=False):
+    out = ctx.solve(A, _dev(b), w.f, _params(w, prec, ls), diag=diag)
+    if diag:
+        return out[0].cpu().numpy(), out[1], out[2]
+    return out[0].cpu().numpy(), out[1]
+
+
+def _oracle(w, Aor, b, ls="sketch"):
+    sk = osk.Sketch(w.sketch, w.n, w.s, w.sketch_seed, w.zeta)
+    return krylov.nt(Aor, b, w.f, w.m, w.k, sk, ls), sk
+
+
+# ------------------------------------------------------------------ config 1: 2D Laplacian, exp, sparse sign
+def test_config1_lap2d_exp_fp64_stagewise(ctx):
+    w = W.config("lap2d_100_exp")
+    print("case lap2d_100 fp64", flush=True)
+    Aor = operators.as_matrix(w.op)
+    b = W.rhs(w.n, w.b_seed)
+    A = ctx.matrix(w.op)
+    out, info, dg = _solve(ctx, w, A, b, "fp64", diag=True)
+    ref, sk = _oracle(w, Aor, b)
+    fm = krylov.fm(Aor, b, w.f, w.m)
+    assert info[0]["m_used"] == w.m and not info[0]["breakdown"]
+    # Hbar (eq. (3)) and the norms
+    H = ref["Hbar"]
+    assert np.abs(dg["hbar"] - H).max() <= 1e-12 * np.abs(H).max()
+    assert math.isclose(info[0]["beta"], np.linalg.norm(b), rel_tol=1e-14)
+    # Theta v_1 = Theta b / ||b||: exact sketch pattern (indices, signs) check
+    sv0 = sk.apply(b / np.linalg.norm(b))
+    np.testing.assert_allclose(dg["sv"][:, 0], sv0, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(dg["sv"], ref["SV"], rtol=0, atol=1e-11)
+    np.testing.assert_allclose(dg["c"], ref["c"], rtol=0, atol=1e-11 * np.abs(ref["c"]).max())
+    assert krylov.relerr(out, ref["f"]) < TOL64
+    assert krylov.relerr(out, fm) < TOL64
+    A.destroy()
+
+
+def test_config1_lap2d_exp_fp32(ctx):
+    w = W.config("lap2d_100_exp")
+    Aor = operators.as_matrix(w.op)
+    b = W.rhs(w.n, w.b_seed)
+    A = ctx.matrix(w.op)
+    out, info = _solve(ctx, w, A, b, "fp32")
+    fm = krylov.fm(Aor, b, w.f, w.m)
+    assert krylov.relerr(out, fm) < TOL32
+    assert krylov.relerr(out, closed_form.laplacian_fAb(w.op, w.f, b)) < TOL32
+    A.destroy()
+
+
+# ------------------------------------------------------------------ 3D convection-diffusion, SRHT, ragged sizes
+@pytest.mark.parametrize("N", [24, 31])
+def test_convdiff_srht_ragged_fp64_and_fp32(ctx, N):
+    base = W.config("convdiff3d_128_exp", scale=N)
+    w = W.Workload(base.name, base.op, base.b_seed, 1, base.f, m=40, k=4, s=100, sketch="srht", sketch_seed=7)
+    print(f"case convdiff N={N}", flush=True)
+    Aor = operators.as_matrix(w.op)
+    b = W.rhs(w.n, w.b_seed)
+    A = ctx.matrix(w.op)
+    out64, info64, dg = _solve(ctx, w, A, b, "fp64", diag=True)
+    ref, sk = _oracle(w, Aor, b)
+    fm = krylov.fm(Aor, b, w.f, w.m)
+    H = ref["Hbar"]
+    assert np.abs(dg["hbar"] - H).max() <= 1e-11 * np.abs(H).max()
+    np.testing.assert_allclose(dg["sv"][:, 0], sk.apply(b / np.linalg.norm(b)), rtol=0, atol=1e-13)
+    assert krylov.relerr(out64, ref["f"]) < TOL64
+    assert krylov.relerr(out64, fm) < TOL64
+    out32, info32 = _solve(ctx, w, A, b, "fp32")
+    assert krylov.relerr(out32, fm) < TOL32
+    A.destroy()
+
+
+# ------------------------------------------------------------------ CSR random geometric graph, inverse square root
+@pytest.mark.parametrize("n", [5000, 8192])
+def test_rgg_csr_invsqrt_sparse_sign(ctx, n):
+    print(f"case rgg n={n}", flush=True)
+    op = W.rgg_laplacian(n, seed=3)
+    w = W.Workload("rgg", op, 3, 1, W.FuncSpec("pow", sigma=1e-3, p=-0.5), m=30, k=2, s=60,
+                   sketch="sparse_sign", zeta=8, sketch_seed=3)
+    Aor = operators.as_matrix(op)
+    b = W.rhs(n, 3)
+    A = ctx.matrix(op)
+    out64, info64, dg = _solve(ctx, w, A, b, "fp64", diag=True)
+    ref, sk = _oracle(w, Aor, b)
+    np.testing.assert_allclose(dg["sv"][:, 0], sk.apply(b / np.linalg.norm(b)), rtol=0, atol=1e-13)
+    assert np.abs(dg["hbar"] - ref["Hbar"]).max() <= 1e-11 * np.abs(ref["Hbar"]).max()
+    assert krylov.relerr(dg["c"], ref["c"]) < 1e-9
+    assert krylov.relerr(out64, ref["f"]) < 1e-9
+    A.destroy()
+
+
+def test_sqrt_exp_functions_on_laplacian(ctx):
+    st = W.laplacian2d(40, 37)
+    b = W.rhs(st.n, 11)
+    Aor = operators.as_matrix(st)
+    A = ctx.matrix(st)
+    for f in (W.FuncSpec("pow", sigma=0.0, p=0.5), W.FuncSpec("pow", sigma=1e-3, p=-0.5),
+              W.FuncSpec("exp", alpha=-2.0)):
+        print(f"case lap2d 40x37 {f}", flush=True)
+        w = W.Workload("x", st, 11, 1, f, m=60, k=2, s=130, sketch="sparse_sign", sketch_seed=5)
+        fm = krylov.fm(Aor, b, f, w.m)
+        out, info = _solve(ctx, w, A, b, "fp64", ls="none")
+        assert krylov.relerr(out, fm) < TOL64, f
+    A.destroy()
+
+
+# ------------------------------------------------------------------ exactness
+def test_polynomial_exact_gpu(ctx):
+    st = W.convdiff3d(12, 10.0)
+    Aor = operators.as_matrix(st)
+    b = W.rhs(st.n, 21)
+    coef = (0.3, -1.0, 0.25, 2e-3, -5e-6, 1e-8)
+    f = W.FuncSpec("poly", coef=coef)
+    ref = np.zeros(st.n)
+    for c in reversed(coef):
+        ref = Aor @ ref + c * b
+    A = ctx.matrix(st)
+    for prec, tol in (("fp64", 1e-11), ("fp32", 1e-6)):
+        w = W.Workload("p", st, 21, 1, f, m=6, k=2, s=20, sketch="srht", sketch_seed=4)
+        for ls in ("sketch", "none"):
+            out, _ = _solve(ctx, w, A, b, prec, ls=ls)
+            assert krylov.relerr(out, ref) < tol, (prec, ls)
+    A.destroy()
+
+
+def test_lucky_breakdown_gpu(ctx):
+    d = np.repeat([0.5, 1.0, 2.0, 3.5, 5.0], 200).astype(np.float32)
+    n = d.size
+    M = sp.diags(d.astype(np.float64)).tocsr()
+    op = (M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float32))
+    b = W.rhs(n, 1)
+    A = ctx.matrix(op)
+    f = W.FuncSpec("exp", alpha=-1.0)
+    w = W.Workload("diag", op, 1, 1, f, m=12, k=2, s=40, sketch="sparse_sign", sketch_seed=2)
+    out, info = _solve(ctx, w, A, b, "fp64")
+    assert info[0]["breakdown"] == 1 and info[0]["m_used"] == 5
+    assert krylov.relerr(out, closed_form.diagonal_fAb(d, f, b)) < 1e-12
+    A.destroy()
+
+
+# ------------------------------------------------------------------ multiple right-hand sides
+@pytest.mark.parametrize("nrhs", [2, 8])
+def test_multi_rhs_equals_single(ctx, nrhs):
+    st = W.convdiff3d(20, 50.0)
+    w = W.Workload("mr", st, 50, nrhs, W.FuncSpec("exp", alpha=-1e-3), m=30, k=4, s=80, sketch="srht",
+                   sketch_seed=5)
+    B = W.rhs(st.n, 50, nrhs)
+    A = ctx.matrix(st)
+    outB, infoB = _solve(ctx, w, A, B, "fp64")
+    Aor = operators.as_matrix(st)
+    for r in range(nrhs):
+        o1, _ = _solve(ctx, w, A, np.ascontiguousarray(B[:, r]), "fp64")
+        assert krylov.relerr(outB[:, r], o1) < 1e-13
+        assert krylov.relerr(outB[:, r], krylov.fm(Aor, B[:, r], w.f, w.m)) < TOL64
+    A.destroy()
+
+
+# ------------------------------------------------------------------ serving: same alone and in the mix
+def test_serving_mix_equals_alone(ctx):
+    import torch
+
+    cases = []
+    for i, (N, f) in enumerate([(20, W.FuncSpec("exp", alpha=-1e-3)), (33, W.FuncSpec("exp", alpha=-2e-3)),
+                                (16, W.FuncSpec("exp", alpha=-1e-3))]):
+        st = W.convdiff3d(N, 50.0)
+        cases.append((st, f, W.rhs(st.n, 100 + i)))
+    st2 = W.laplacian2d(64)
+    cases.append((st2, W.FuncSpec("pow", sigma=1e-3, p=-0.5), W.rhs(st2.n, 7)))
+    mats = [ctx.matrix(c[0]) for c in cases]
+    from paper_2212_12758_amd import make_params
+
+    params = [make_params(40, 3, 90, "srht", 8, 1000 + i, "fp32", "sketch") for i in range(len(cases))]
+    alone = []
+    for (st, f, b), A, p in zip(cases, mats, params):
+        o, _ = ctx.solve(A, _dev(b), f, p)
+        alone.append(o.cpu().numpy())
+    outs, reqs = [], []
+    for rep in range(3):
+        for (st, f, b), A, p in zip(cases, mats, params):
+            bd = _dev(b)
+            o = torch.empty_like(bd)
+            reqs.append(ctx.submit(A, bd, f, p, o))
+            outs.append(o)
+    for r in reqs:
+        r.wait()
+    for j, o in enumerate(outs):
+        ref = alone[j % len(cases)]
+        assert np.array_equal(o.cpu().numpy(), ref), j        # fixed-order reductions: bitwise
+    for A in mats:
+        A.destroy()
+
+
+# ------------------------------------------------------------------ error paths
+def test_error_paths(ctx):
+    from paper_2212_12758_amd import EINVAL, ENUMERIC, FabError, make_params
+
+    st = W.laplacian2d(30)
+    A = ctx.matrix(st)
+    b = W.rhs(st.n, 1)
+    f = W.FuncSpec("exp", alpha=-1.0)
+    with pytest.raises(FabError) as e:
+        ctx.solve(A, _dev(b), f, make_params(20, 2, 20, "srht", 8, 1, "fp32"))   # s <= m
+    assert e.value.code == EINVAL
+    with pytest.raises(FabError) as e:
+        ctx.solve(A, _dev(b), f, make_params(20, 9, 60, "srht", 8, 1, "fp32"))   # k > 8
+    assert e.value.code == EINVAL
+    bn = b.copy()
+    bn[17] = np.nan
+    with pytest.raises(FabError) as e:
+        ctx.solve(A, _dev(bn), f, make_params(20, 2, 60, "srht", 8, 1, "fp32"))
+    assert e.value.code == ENUMERIC
+    # zero right-hand side: exact zero result, m_used = 0
+    o, info = ctx.solve(A, _dev(np.zeros(st.n)), f, make_params(20, 2, 60, "srht", 8, 1, "fp32"))
+    assert info[0]["m_used"] == 0 and float(o.abs().max()) == 0.0
+    A.destroy()
+
+
+def test_enomem_tiny_arena():
+    import torch
+
+    from paper_2212_12758_amd import ENOMEM, Context, FabError, make_params
+
+    with Context(0, arena_bytes=2 << 20) as c:
+        st = W.laplacian3d(64)
+        A = c.matrix(st)
+        b = torch.zeros(st.n, dtype=torch.float64, device="cuda")
+        with pytest.raises(FabError) as e:
+            c.solve(A, b, W.FuncSpec("exp", alpha=-1.0), make_params(50, 2, 120, "srht", 8, 1, "fp32"))
+        assert e.value.code == ENOMEM
+        A.destroy()
