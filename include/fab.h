@@ -195,6 +195,24 @@ int fab_poll(fab_ctx ctx, fab_request req, int* done, fab_info* info);
 /* Blocks until the request finishes; then as fab_poll with done = 1.          */
 int fab_wait(fab_ctx ctx, fab_request req, fab_info* info);
 
+/* Kernel timing for measurement.  For the classes selected by a bit mask,
+ * blocking solves on this context record a HIP event pair on the context's
+ * stream around every launch and accumulate the elapsed times per class:      */
+enum fab_kernel_class {
+  FAB_K_DOTS = 0,     /* matvec + window dots + reductions (one per Krylov step)  */
+  FAB_K_UPDATE = 1,   /* Gram-Schmidt update + norm + fused sketch (one per step) */
+  FAB_K_COMBINE = 2,  /* out = beta V_m c                                          */
+  FAB_K_DENSE = 3,    /* sketched QR / least squares, f(H_hat) e_1, weights         */
+  FAB_K_OTHER = 4,    /* first vector, final reduction                             */
+  FAB_K_NCLASS = 5
+};
+/* Time the classes whose bit (1 << class) is set in class_mask; 0 disables.
+ * Errors: FAB_EINVAL (null ctx, mask out of range).                          */
+int fab_profile_enable(fab_ctx ctx, int class_mask);
+/* Launch count and summed duration in ms of class `cls` since the last reset;
+ * reset != 0 clears that class.  Errors: FAB_EINVAL (bad ctx or class).        */
+int fab_profile_read(fab_ctx ctx, int cls, long long* launches, double* total_ms, int reset);
+
 /* Wait for all requests, release every matrix and the context.               */
 int fab_finalize(fab_ctx ctx);
 

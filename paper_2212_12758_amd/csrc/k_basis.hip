@@ -333,15 +333,22 @@ __global__ void __launch_bounds__(BLOCK) k_combine(SolveDev d, const double* __r
 
 // ------------------------------------------------------------------ host launchers
 template <typename T>
-static hipError_t launch_step_t(const SolveDev& d, int i, hipStream_t st, size_t lds_update) {
-  if (d.op == OP_STENCIL) {
+static hipError_t launch_dots_t(const SolveDev& d, int i, hipStream_t st) {
+  if (d.op == OP_STENCIL)
     hipLaunchKernelGGL((k_dots<T, OP_STENCIL>), dim3(d.nblk + d.nred), dim3(BLOCK), 0, st, d, i, d.nblk);
+  else
+    hipLaunchKernelGGL((k_dots<T, OP_CSR>), dim3(d.nblk + d.nred), dim3(BLOCK), 0, st, d, i, d.nblk);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_update_t(const SolveDev& d, int i, hipStream_t st, size_t lds_update) {
+  if (d.op == OP_STENCIL) {
     if (d.sketch == SK_SRHT)
       hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SRHT, false>), dim3(d.nblk), dim3(BLOCK), lds_update, st, d, i);
     else
       hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SPARSE, false>), dim3(d.nblk), dim3(BLOCK), lds_update, st, d, i);
   } else {
-    hipLaunchKernelGGL((k_dots<T, OP_CSR>), dim3(d.nblk + d.nred), dim3(BLOCK), 0, st, d, i, d.nblk);
     if (d.sketch == SK_SRHT)
       hipLaunchKernelGGL((k_update<T, OP_CSR, SK_SRHT, false>), dim3(d.nblk), dim3(BLOCK), lds_update, st, d, i);
     else
@@ -388,8 +395,11 @@ hipError_t basis_set_attributes() {
 hipError_t basis_start(const SolveDev& d, int esize, hipStream_t st, size_t lds) {
   return esize == 4 ? launch_start_t<float>(d, st, lds) : launch_start_t<double>(d, st, lds);
 }
-hipError_t basis_step(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds) {
-  return esize == 4 ? launch_step_t<float>(d, i, st, lds) : launch_step_t<double>(d, i, st, lds);
+hipError_t basis_dots(const SolveDev& d, int esize, int i, hipStream_t st) {
+  return esize == 4 ? launch_dots_t<float>(d, i, st) : launch_dots_t<double>(d, i, st);
+}
+hipError_t basis_update(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds) {
+  return esize == 4 ? launch_update_t<float>(d, i, st, lds) : launch_update_t<double>(d, i, st, lds);
 }
 hipError_t basis_finish(const SolveDev& d, int esize, hipStream_t st) {
   return esize == 4 ? launch_finish_t<float>(d, st) : launch_finish_t<double>(d, st);

@@ -36,7 +36,8 @@
 namespace fab {
 hipError_t basis_set_attributes();
 hipError_t basis_start(const SolveDev& d, int esize, hipStream_t st, size_t lds);
-hipError_t basis_step(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds);
+hipError_t basis_dots(const SolveDev& d, int esize, int i, hipStream_t st);
+hipError_t basis_update(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds);
 hipError_t basis_finish(const SolveDev& d, int esize, hipStream_t st);
 hipError_t basis_combine(const SolveDev& d, int esize, const double* cf, int mmax, double* out, hipStream_t st);
 hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st);
@@ -229,6 +230,40 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
 
 struct Request;
 
+// Optional per-launch timing with HIP events on the solve's stream.
+struct Prof {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, size_t>> marks;   // (class, index of the start event)
+  double total_ms[FAB_K_NCLASS] = {0};
+  long long count[FAB_K_NCLASS] = {0};
+  int mask = 0;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(int cls, hipStream_t st) {
+    marks.emplace_back(cls, used);
+    hipEventRecord(next(), st);
+  }
+  void end(hipStream_t st) { hipEventRecord(next(), st); }
+  void harvest() {   // after the stream was synchronised
+    for (auto& mk : marks) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pool[mk.second], pool[mk.second + 1]) == hipSuccess) {
+        total_ms[mk.first] += ms;
+        count[mk.first] += 1;
+      }
+    }
+    marks.clear();
+    used = 0;
+  }
+};
+
 }  // namespace
 
 struct fab_ctx_s {
@@ -248,6 +283,7 @@ struct fab_ctx_s {
   std::set<fab_matrix> matrices;
   double* host_info = nullptr;   // pinned staging for blocking solves
   std::mutex solve_mu;
+  Prof prof;
 };
 
 namespace {
@@ -268,7 +304,7 @@ struct Request {
 size_t host_info_doubles(int nrhs) { return (size_t)nrhs * NINFO + 4 + 2 * nrhs + 8; }
 
 // Enqueue the whole solve on `st`.  Host-visible results land in `hinfo` (pinned).
-int enqueue_solve(Plan& P, char* ws, hipStream_t st, double* hinfo) {
+int enqueue_solve(Plan& P, char* ws, hipStream_t st, double* hinfo, Prof* prof = nullptr) {
   const fab_params& p = P.p;
   fab_matrix A = P.A;
   const int m = p.m, s = p.s, nr = P.nrhs;
@@ -346,13 +382,40 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, double* hinfo) {
   if (d.sketch == SK_SRHT &&
       srht_sample_rows((int*)(ws + P.oRows), 1LL << ilog2(A->n), s, sm64_out(p.seed, 2), st) != hipSuccess)
     return FAB_EDEVICE;
-  if ((e = basis_start(d, P.esize, st, P.lds_update)) != hipSuccess) return FAB_EDEVICE;
-  for (int i = 1; i <= m; ++i)
-    if ((e = basis_step(d, P.esize, i, st, P.lds_update)) != hipSuccess) return FAB_EDEVICE;
-  if ((e = basis_finish(d, P.esize, st)) != hipSuccess) return FAB_EDEVICE;
+  int open_cls = -1;
+  auto B = [&](int cls) {
+    if (prof && (prof->mask >> cls) & 1) { prof->begin(cls, st); open_cls = cls; }
+  };
+  auto E = [&]() {
+    if (open_cls >= 0) { prof->end(st); open_cls = -1; }
+  };
+  B(FAB_K_OTHER);
+  e = basis_start(d, P.esize, st, P.lds_update);
+  E();
+  if (e != hipSuccess) return FAB_EDEVICE;
+  for (int i = 1; i <= m; ++i) {
+    B(FAB_K_DOTS);
+    e = basis_dots(d, P.esize, i, st);
+    E();
+    if (e != hipSuccess) return FAB_EDEVICE;
+    B(FAB_K_UPDATE);
+    e = basis_update(d, P.esize, i, st, P.lds_update);
+    E();
+    if (e != hipSuccess) return FAB_EDEVICE;
+  }
+  B(FAB_K_OTHER);
+  e = basis_finish(d, P.esize, st);
+  E();
+  if (e != hipSuccess) return FAB_EDEVICE;
   double* cf = (double*)(ws + P.oCf);
-  if ((e = dense_tail(d, g, cf, st)) != hipSuccess) return FAB_EDEVICE;
-  if ((e = basis_combine(d, P.esize, cf, m, P.out, st)) != hipSuccess) return FAB_EDEVICE;
+  B(FAB_K_DENSE);
+  e = dense_tail(d, g, cf, st);
+  E();
+  if (e != hipSuccess) return FAB_EDEVICE;
+  B(FAB_K_COMBINE);
+  e = basis_combine(d, P.esize, cf, m, P.out, st);
+  E();
+  if (e != hipSuccess) return FAB_EDEVICE;
   // results to pinned host memory: per-rhs dense info, then status ints
   for (int q = 0; q < nr; ++q) {
     e = hipMemcpyAsync(hinfo + (size_t)q * NINFO, g.base + (size_t)q * P.dense_stride + P.oDInfo, NINFO * 8,
@@ -641,8 +704,9 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
       ctx->cv.wait_for(lk, std::chrono::milliseconds(1));
     }
   }
-  rc = enqueue_solve(P, ws, ctx->stream, ctx->host_info);
+  rc = enqueue_solve(P, ws, ctx->stream, ctx->host_info, ctx->prof.mask ? &ctx->prof : nullptr);
   if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == FAB_OK) rc = FAB_EDEVICE;
+  if (ctx->prof.mask) ctx->prof.harvest();
   std::vector<fab_info> fi;
   if (rc == FAB_OK) rc = collect_info(P, ctx->host_info, fi);
   if (diag && (rc == FAB_OK || rc == FAB_ENUMERIC)) {
@@ -693,6 +757,25 @@ int fab_solve(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, 
 int fab_solve_diag(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, const fab_params* p,
                    double* out, fab_info* info, const fab_diag* diag) {
   return solve_impl(ctx, A, b, nrhs, f, p, out, info, diag);
+}
+
+int fab_profile_enable(fab_ctx ctx, int class_mask) {
+  if (!ctx || class_mask < 0 || class_mask >= (1 << FAB_K_NCLASS)) return FAB_EINVAL;
+  std::lock_guard<std::mutex> slk(ctx->solve_mu);
+  ctx->prof.mask = class_mask;
+  return FAB_OK;
+}
+
+int fab_profile_read(fab_ctx ctx, int cls, long long* launches, double* total_ms, int reset) {
+  if (!ctx || cls < 0 || cls >= FAB_K_NCLASS) return FAB_EINVAL;
+  std::lock_guard<std::mutex> slk(ctx->solve_mu);
+  if (launches) *launches = ctx->prof.count[cls];
+  if (total_ms) *total_ms = ctx->prof.total_ms[cls];
+  if (reset) {
+    ctx->prof.count[cls] = 0;
+    ctx->prof.total_ms[cls] = 0.0;
+  }
+  return FAB_OK;
 }
 
 int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, const fab_params* p, double* out,
@@ -780,6 +863,7 @@ int fab_finalize(fab_ctx ctx) {
   if (ctx->own_stream) hipStreamDestroy(ctx->stream);
   else hipStreamSynchronize(ctx->stream);
   if (ctx->host_info) hipHostFree(ctx->host_info);
+  for (auto ev : ctx->prof.pool) hipEventDestroy(ev);
   if (ctx->arena.owned) hipFree(ctx->arena.base);
   delete ctx;
   return FAB_OK;

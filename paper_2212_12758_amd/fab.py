@@ -69,6 +69,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fab_poll.argtypes = [vp, u64, C.POINTER(i), C.POINTER(fab_info)]
     lib.fab_wait.argtypes = [vp, u64, C.POINTER(fab_info)]
     lib.fab_finalize.argtypes = [vp]
+    lib.fab_profile_enable.argtypes = [vp, i]
+    lib.fab_profile_read.argtypes = [vp, i, C.POINTER(C.c_longlong), C.POINTER(C.c_double), i]
     lib.fab_strerror.argtypes = [i]
     lib.fab_strerror.restype = C.c_char_p
     lib.fab_version.restype = C.c_char_p
@@ -202,6 +204,22 @@ class Context:
         _check(self.lib.fab_submit(self.handle, A.handle, C.c_void_p(b.data_ptr()), self._shape(b), ff,
                                    C.byref(params), C.c_void_p(out.data_ptr()), C.byref(req)), "fab_submit")
         return Request(self, req.value, self._shape(b), (b, out, keep))
+
+    # ---------------------------------------------------------------- measurement
+    K_DOTS, K_UPDATE, K_COMBINE, K_DENSE, K_OTHER = range(5)
+
+    def profile(self, classes=()):
+        """Record HIP events around launches of the given kernel classes (blocking solves)."""
+        mask = 0
+        for c in classes:
+            mask |= 1 << c
+        _check(self.lib.fab_profile_enable(self.handle, mask), "fab_profile_enable")
+
+    def profile_read(self, cls: int, reset: bool = True):
+        """(launches, total_ms) for one kernel class since the last reset."""
+        n, t = C.c_longlong(), C.c_double()
+        _check(self.lib.fab_profile_read(self.handle, cls, C.byref(n), C.byref(t), int(reset)), "fab_profile_read")
+        return n.value, t.value
 
     def close(self):
         if getattr(self, "handle", None):
