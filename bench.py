@@ -91,8 +91,7 @@ def main():
 
     for _ in range(args.warmup):
         ctx.solve(A, bd, w.f, p32, out)
-    ctx.profile([ctx.K_UPDATE])
-    ctx.profile_read(ctx.K_UPDATE, reset=True)
+    # timed region: K complete solves (replayed HIP graphs of the launch sequence)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -102,13 +101,27 @@ def main():
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    nlaunch, tot_ms = ctx.profile_read(ctx.K_UPDATE, reset=True)
-    ctx.profile([])
     elapsed = t1 - t0
     value = args.steps / elapsed
-    upd_ms = tot_ms / max(1, nlaunch)
-    achieved = ab32["update_per_launch"] / (upd_ms * 1e-3) / 1e9
     res32 = out.cpu().numpy()
+
+    # kernel timing region: the same K solves with direct launches and a HIP
+    # event pair around every launch of the dominant kernel on its stream
+    ctx.profile([ctx.K_UPDATE, ctx.K_DOTS])
+    for c in range(5):
+        ctx.profile_read(c, reset=True)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.solve(A, bd, w.f, p32, out)
+    torch.cuda.synchronize()
+    prof_elapsed = time.perf_counter() - p0
+    nlaunch, tot_ms = ctx.profile_read(ctx.K_UPDATE, reset=True)
+    nd, dots_ms = ctx.profile_read(ctx.K_DOTS, reset=True)
+    ctx.profile([])
+    upd_ms = tot_ms / max(1, nlaunch)
+    achieved = ab32["update_per_launch"] / (upd_ms * 1e-3) / 1e9 if upd_ms > 0 else None
+    dots_us = 1e3 * dots_ms / max(1, nd)
 
     fp64_rate = None
     if not args.no_fp64:
@@ -153,10 +166,13 @@ def main():
             "fp32_over_fp64": (value / fp64_rate) if fp64_rate else None,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": None,
                      "kernel": "k_update (Gram-Schmidt update + norm + fused SRHT)",
                      "bytes_per_launch": ab32["update_per_launch"], "mean_launch_us": upd_ms * 1e3,
-                     "launches": nlaunch},
+                     "launches": nlaunch, "timing": "HIP events around each launch, direct launches, "
+                     f"{args.steps} solves ({1e3 * prof_elapsed / args.steps:.2f} ms/solve in that region)",
+                     "dots_kernel_mean_us": dots_us,
+                     "dots_kernel_GBps": ab32["dots_per_launch"] / (dots_us * 1e-6) / 1e9 if dots_us > 0 else None},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

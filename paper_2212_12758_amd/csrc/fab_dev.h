@@ -48,7 +48,8 @@ struct SolveDev {
   double* coef;          // [nrhs][NSLOT]
   double* S;             // [nrhs][s*(m+1)]
   // partition and partials
-  int rows_per_tile, log_rows;   // R = rows per tile (power of two)
+  int log_tile;          // tile = 2^log_tile elements (9 or 12)
+  int rows_per_tile, log_rows;   // R = rows per tile = 2^log_tile / nrhs
   int ntiles;            // ceil(n / R)
   int nblk;              // streaming blocks (tiles are strided over blocks)
   int nred;              // sketch-reduction blocks appended to the dots kernel
@@ -72,7 +73,7 @@ struct DenseDev {
   int m, s, nrhs;
   long long stride;      // doubles per rhs
   double* base;
-  long long oW, oH, oM, oVec, oInfo;   // W [s*(m+1)], H_hat [m*m], 8 scratch m*m, vectors, info
+  long long oW, oR, oH, oM, oVec, oInfo;   // Q [s*(m+1)], R [(m+1)^2], H_hat [m*m], 8 scratch m*m, vectors, info
   int ls_mode;           // 1 sketch-and-solve, 2 none
   int fkind;             // 1 exp, 2 pow, 3 poly
   double alpha, sigma, p;

@@ -22,29 +22,166 @@
 // Vectors are kept unnormalised (v_j = u_j / eta_j); every scale is applied
 // to scalars, never by an extra pass over the vectors.  All arithmetic on
 // vector elements is FP64 whatever the storage type.
+//
+// Work layout: tiles of TILE = 2^LT consecutive elements (rows x rhs); a
+// block of TILE/8 threads owns one tile at a time and each thread owns 8
+// consecutive elements, moved with 16-byte vector loads and stores.  Basis
+// columns start on 256-byte boundaries.  QC = 1 when there is one right-hand
+// side (one accumulator per quantity); QC = 8 otherwise (one per element).
 #include "fab_dev.h"
 
 namespace fab {
 
+constexpr int EPT = 8;   // elements per thread per tile
+
+// ------------------------------------------------------------------ 8-element memory helpers
+__device__ inline void load8(const float* __restrict__ p, double* v) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  const float4 b = *reinterpret_cast<const float4*>(p + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+__device__ inline void load8(const double* __restrict__ p, double* v) {
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const double2 a = *reinterpret_cast<const double2*>(p + 2 * h);
+    v[2 * h] = a.x;
+    v[2 * h + 1] = a.y;
+  }
+}
+__device__ inline void store8(float* __restrict__ p, const double* v, double* rounded) {
+  float4 a, b;
+  a.x = (float)v[0]; a.y = (float)v[1]; a.z = (float)v[2]; a.w = (float)v[3];
+  b.x = (float)v[4]; b.y = (float)v[5]; b.z = (float)v[6]; b.w = (float)v[7];
+  *reinterpret_cast<float4*>(p) = a;
+  *reinterpret_cast<float4*>(p + 4) = b;
+  rounded[0] = a.x; rounded[1] = a.y; rounded[2] = a.z; rounded[3] = a.w;
+  rounded[4] = b.x; rounded[5] = b.y; rounded[6] = b.z; rounded[7] = b.w;
+}
+__device__ inline void store8(double* __restrict__ p, const double* v, double* rounded) {
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    double2 a;
+    a.x = v[2 * h];
+    a.y = v[2 * h + 1];
+    *reinterpret_cast<double2*>(p + 2 * h) = a;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) rounded[j] = v[j];
+}
 template <typename T>
-__device__ inline double stencil_apply(const SolveDev& d, const T* __restrict__ u, int r, long long e) {
+__device__ inline double ldg1(const T* __restrict__ u, long long x, long long nel) {
+  return (x >= 0 && x < nel) ? (double)u[x] : 0.0;
+}
+template <typename T>
+constexpr int vec_align() { return 16 / (int)sizeof(T); }
+
+// u[e+off .. e+off+7]: vector load when aligned and in range, else guarded scalars.
+template <typename T>
+__device__ inline void fetch8(const T* __restrict__ u, long long e, long long off, long long nel, double* v) {
+  const long long a = e + off;
+  if ((off % vec_align<T>()) == 0 && a >= 0 && a + EPT <= nel) {
+    load8(u + a, v);
+  } else {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) v[j] = ldg1(u, a + j, nel);
+  }
+}
+
+template <typename T>
+__device__ inline void get8(const T* __restrict__ p, long long e, long long nel, double* v) {
+  if (e + EPT <= nel) {
+    load8(p + e, v);
+  } else {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) v[j] = ldg1(p, e + j, nel);
+  }
+}
+
+// Boundary masks of elements e..e+7 (row = element >> lognrhs): bit j of
+// mx0 is set when element j has an x-1 neighbour, mx1 for x+1, etc.
+struct Masks8 {
+  unsigned mx0, mx1, my0, my1, mz0, mz1;
+};
+__device__ inline Masks8 masks8(const SolveDev& d, long long e) {
+  const int r0 = (int)(e >> d.lognrhs);
+  int x = r0 % d.nx;
+  const int yz = r0 / d.nx;
+  int y = yz % d.ny;
+  int z = yz / d.ny;
+  int rp = r0;
+  Masks8 mk{0u, 0u, 0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int r = (int)((e + j) >> d.lognrhs);
+    if (r != rp) {
+      rp = r;
+      if (++x == d.nx) {
+        x = 0;
+        if (++y == d.ny) { y = 0; ++z; }
+      }
+    }
+    mk.mx0 |= (unsigned)(x > 0) << j;
+    mk.mx1 |= (unsigned)(x < d.nx - 1) << j;
+    mk.my0 |= (unsigned)(y > 0) << j;
+    mk.my1 |= (unsigned)(y < d.ny - 1) << j;
+    mk.mz0 |= (unsigned)(z > 0) << j;
+    mk.mz1 |= (unsigned)(z < d.nz - 1) << j;
+  }
+  return mk;
+}
+
+// Values at e+j-S (DIR < 0) or e+j+S (DIR > 0), j = 0..7, for a shift S < 8
+// known at compile time: inside the group they are centre values.
+template <typename T, int S, int DIR>
+__device__ inline void shifted8(const T* __restrict__ u, long long e, long long nel, const double* c, double* nb) {
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int src = j + DIR * S;
+    nb[j] = (src >= 0 && src < EPT) ? c[src >= 0 && src < EPT ? src : 0] : ldg1(u, e + src, nel);
+  }
+}
+
+template <typename T, int DIR>
+__device__ inline void xneighbour8(const T* __restrict__ u, long long e, long long nel, int nr, const double* c,
+                                   double* nb) {
+  if (nr == 1) shifted8<T, 1, DIR>(u, e, nel, c, nb);
+  else if (nr == 2) shifted8<T, 2, DIR>(u, e, nel, c, nb);
+  else if (nr == 4) shifted8<T, 4, DIR>(u, e, nel, c, nb);
+  else fetch8(u, e, (long long)DIR * nr, nel, nb);
+}
+
+// w = A u at elements e..e+7 for the stencil operator; c holds u[e..e+7].
+template <typename T>
+__device__ inline void stencil8(const SolveDev& d, const T* __restrict__ u, long long e, long long nel,
+                                const double* c, double* w) {
+  const Masks8 mk = masks8(d, e);
   const int nr = d.nrhs;
-  const int x = r % d.nx;
-  const int yz = r / d.nx;
-  const int y = yz % d.ny;
-  const int z = yz / d.ny;
-  double w = d.c[0] * (double)u[e];
-  if (x > 0) w += d.c[1] * (double)u[e - nr];
-  if (x < d.nx - 1) w += d.c[2] * (double)u[e + nr];
+  double nb[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) w[j] = d.c[0] * c[j];
+  xneighbour8<T, -1>(u, e, nel, nr, c, nb);
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) w[j] += d.c[1] * (((mk.mx0 >> j) & 1u) ? nb[j] : 0.0);
+  xneighbour8<T, 1>(u, e, nel, nr, c, nb);
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) w[j] += d.c[2] * (((mk.mx1 >> j) & 1u) ? nb[j] : 0.0);
   const long long sy = (long long)d.nx * nr;
-  if (y > 0) w += d.c[3] * (double)u[e - sy];
-  if (y < d.ny - 1) w += d.c[4] * (double)u[e + sy];
+  fetch8(u, e, -sy, nel, nb);
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) w[j] += d.c[3] * (((mk.my0 >> j) & 1u) ? nb[j] : 0.0);
+  fetch8(u, e, sy, nel, nb);
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) w[j] += d.c[4] * (((mk.my1 >> j) & 1u) ? nb[j] : 0.0);
   if (d.nz > 1) {
     const long long sz = sy * d.ny;
-    if (z > 0) w += d.c[5] * (double)u[e - sz];
-    if (z < d.nz - 1) w += d.c[6] * (double)u[e + sz];
+    fetch8(u, e, -sz, nel, nb);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) w[j] += d.c[5] * (((mk.mz0 >> j) & 1u) ? nb[j] : 0.0);
+    fetch8(u, e, sz, nel, nb);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) w[j] += d.c[6] * (((mk.mz1 >> j) & 1u) ? nb[j] : 0.0);
   }
-  return w;
 }
 
 template <typename T>
@@ -55,6 +192,20 @@ __device__ inline double csr_apply(const SolveDev& d, const T* __restrict__ u, i
   return w;
 }
 
+template <typename T, int OP>
+__device__ inline void apply8(const SolveDev& d, const T* __restrict__ src, long long e, long long nel,
+                              const double* c, double* w) {
+  if (OP == OP_STENCIL) {
+    stencil8(d, src, e, nel, c, w);
+  } else {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const long long x = e + j;
+      w[j] = x < nel ? csr_apply(d, src, (int)(x >> d.lognrhs), (int)(x & (d.nrhs - 1))) : 0.0;
+    }
+  }
+}
+
 __device__ inline double wave_sum_all(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -63,66 +214,130 @@ __device__ inline double wave_sum_all(double v) {
 __device__ inline int* rhs_mused(const SolveDev& d, int q) { return d.status + 4 + 2 * q; }
 __device__ inline int* rhs_brk(const SolveDev& d, int q) { return d.status + 5 + 2 * q; }
 
+// Fixed-order block-wide sums of RC values per thread; result in out[0..RC) for every thread.
+template <int BLOCK, int RC>
+__device__ inline void block_sums(const double* a, double* red /* [BLOCK/64][RC] */, double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < RC; ++c) {
+    const double v = wave_sum_all(a[c]);
+    if (lane == 0) red[wv * RC + c] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < RC; ++c) {
+    double t = 0.0;
+    for (int w = 0; w < BLOCK / 64; ++w) t += red[w * RC + c];
+    out[c] = t;
+  }
+  __syncthreads();
+}
+
+// element j of thread tid: accumulator slot and rhs
+template <int QC>
+__device__ inline int slot_of(int j) { return QC == 1 ? 0 : j; }
+template <int QC>
+__device__ inline int rhs_of(int tid, int j, int nr) { return QC == 1 ? 0 : ((tid * EPT + j) & (nr - 1)); }
+
 // ------------------------------------------------------------------ pass 1
 // i in 1..m: dots for column i-1.  i == m+1 with nstream == 0: finishing pass
 // (norm of u_m, subdiagonal h_{m+1,m}, sketch column m).
-template <typename T, int OP>
-__global__ void __launch_bounds__(BLOCK) k_dots(SolveDev d, int i, int nstream) {
+template <typename T, int OP, int LT, int QC, int KT>
+__global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int nstream) {
+  constexpr int BLOCK = 1 << (LT - 3);
+  constexpr int NW = BLOCK / 64;
+  constexpr int RC = 10;
   if (d.status[0]) return;  // every rhs has broken down already
-  __shared__ double red[BLOCK / 64][NSLOT * 32];
+  __shared__ double red[NW * RC];
+  __shared__ double sums[NSLOT * 32 + 32];
   __shared__ unsigned ticket;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nr = d.nrhs;
   const int j0 = i - d.k > 0 ? i - d.k : 0;
   const int nw = i - j0;
   const T* __restrict__ V = (const T*)d.V;
+  const int RS = NSLOT * nr;   // partial values per block: slot-major (sl * nr + q)
 
   if ((int)blockIdx.x < nstream) {
-    const int q = tid & (nr - 1);
-    double acc[NSLOT];
+    double acc[NSLOT][QC];
 #pragma unroll
-    for (int sl = 0; sl < NSLOT; ++sl) acc[sl] = 0.0;
+    for (int sl = 0; sl < NSLOT; ++sl)
+#pragma unroll
+      for (int c = 0; c < QC; ++c) acc[sl][c] = 0.0;
     const T* __restrict__ src = V + (long long)(i - 1) * d.ldv;
-    const long long tile_elems = (long long)d.rows_per_tile * nr;
     const long long nel = (long long)d.n * nr;
     for (int t = blockIdx.x; t < d.ntiles; t += d.nblk) {
-      const long long e0 = (long long)t * tile_elems;
-      const long long e1 = e0 + tile_elems < nel ? e0 + tile_elems : nel;
-      for (long long e = e0 + tid; e < e1; e += BLOCK) {
-        const int r = (int)(e >> d.lognrhs);
-        double w;
-        if (OP == OP_STENCIL) {
-          w = stencil_apply(d, src, r, e);
+      const long long e = ((long long)t << LT) + (long long)tid * EPT;
+      if (e >= nel) continue;
+      double c[EPT], w[EPT];
+      get8(src, e, nel, c);
+      apply8<T, OP>(d, src, e, nel, c, w);
+      if (OP == OP_CSR) {
+        if (e + EPT <= nel) {
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            double2 o;
+            o.x = w[2 * h];
+            o.y = w[2 * h + 1];
+            *reinterpret_cast<double2*>(d.wbuf + e + 2 * h) = o;
+          }
         } else {
-          w = csr_apply(d, src, r, q);
-          d.wbuf[e] = w;
+          for (int j = 0; j < EPT; ++j)
+            if (e + j < nel) d.wbuf[e + j] = w[j];
         }
-#pragma unroll
-        for (int jj = 0; jj < KMAX; ++jj)
-          if (jj < nw) acc[jj] += (double)V[(long long)(j0 + jj) * d.ldv + e] * w;
-        acc[KMAX] += w * w;
       }
-    }
 #pragma unroll
-    for (int sl = 0; sl < NSLOT; ++sl) {
-      const double v = wave_sum_rhs(acc[sl], nr);
-      if (lane < nr) red[wv][sl * nr + lane] = v;
+      for (int jj = 0; jj < KT; ++jj) {
+        if (jj < nw) {
+          double uj[EPT];
+          if (jj == nw - 1) {
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) uj[j] = c[j];
+          } else {
+            get8(V + (long long)(j0 + jj) * d.ldv, e, nel, uj);
+          }
+#pragma unroll
+          for (int j = 0; j < EPT; ++j) acc[jj][slot_of<QC>(j)] += uj[j] * w[j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) acc[KMAX][slot_of<QC>(j)] += w[j] * w[j];
+    }
+    // per (slot, rhs) block partials, fixed order
+    __shared__ double pblk[NSLOT * 32];
+    for (int q = 0; q < nr; ++q) {
+      double a[RC];
+#pragma unroll
+      for (int sl = 0; sl < RC; ++sl) a[sl] = 0.0;
+#pragma unroll
+      for (int sl = 0; sl < NSLOT; ++sl)
+#pragma unroll
+        for (int c = 0; c < QC; ++c)
+          if (rhs_of<QC>(tid, c, nr) == q) a[sl] += acc[sl][c];
+      double o[RC];
+      block_sums<BLOCK, RC>(a, red, o);
+      if (tid < NSLOT) pblk[tid * nr + q] = o[tid];
     }
     __syncthreads();
-    for (int x = tid; x < NSLOT * nr; x += BLOCK) {
-      const double v = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
-      const int sl = x / nr, qq = x - sl * nr;
-      d.part[((long long)blockIdx.x * nr + qq) * NSLOT + sl] = v;
-    }
+    for (int x = tid; x < RS; x += BLOCK) d.part[(long long)blockIdx.x * RS + x] = pblk[x];
   } else {
     // reduce the sketch partials of column i-1: one wave per (row, rhs)
-    const int nwaves = (gridDim.x - nstream) * (BLOCK / 64);
-    const int wid = (blockIdx.x - nstream) * (BLOCK / 64) + wv;
+    const int nwaves = (gridDim.x - nstream) * NW;
+    const int wid = (blockIdx.x - nstream) * NW + wv;
     const int col = i - 1;
     for (int rho = wid; rho < d.s * nr; rho += nwaves) {
       double v = 0.0;
       const double* p = d.skpart + (long long)rho * d.nblk;
-      for (int b = lane; b < d.nblk; b += 64) v += p[b];
+      for (int b0 = 0; b0 < d.nblk; b0 += 512) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int b = b0 + lane + 64 * u;
+          x[u] = b < d.nblk ? p[b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += x[u];
+      }
       v = wave_sum_all(v);
       if (lane == 0) {
         const int pr = rho >> d.lognrhs, qq = rho & (nr - 1);
@@ -131,71 +346,94 @@ __global__ void __launch_bounds__(BLOCK) k_dots(SolveDev d, int i, int nstream) 
     }
   }
 
-  // ---- last block: scalar reduction in a fixed order
-  __threadfence();
+  // ---- last block: scalar reduction in a fixed order.  The barrier makes
+  // every wave's partial stores complete in this XCD's L2; one thread then
+  // releases them device-wide and takes a ticket.  The last block acquires
+  // once before reading everybody's partials.
   __syncthreads();
-  if (tid == 0) ticket = atomicAdd(d.counter, 1u);
+  if (tid == 0) {
+    __threadfence();
+    ticket = atomicAdd(d.counter, 1u);
+  }
   __syncthreads();
   if (ticket != gridDim.x - 1) return;
-  __threadfence();
+  if (tid == 0) __threadfence();
+  __syncthreads();
+
+  // rows 0..RS-1: dot partials (when nstream > 0); rows RS..RS+nr-1: norm partials of u_{i-1}
+  const int RT = RS + nr;
+  for (int r0 = 0; r0 < RT; r0 += RC) {
+    double a[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) a[c] = 0.0;
+    for (int b = tid; b < d.nblk; b += BLOCK) {
+#pragma unroll
+      for (int c = 0; c < RC; ++c) {
+        const int rr = r0 + c;
+        if (rr < RS) {
+          if (b < nstream) a[c] += d.part[(long long)b * RS + rr];
+        } else if (rr < RT) {
+          a[c] += d.npart[(long long)b * nr + (rr - RS)];
+        }
+      }
+    }
+    double o[RC];
+    block_sums<BLOCK, RC>(a, red, o);
+    if (tid < RC && r0 + tid < RT) sums[r0 + tid] = o[tid];
+  }
+  __syncthreads();
 
   const int m = d.m;
-  for (int qq = wv; qq < nr; qq += BLOCK / 64) {
-    double nn = 0.0;
-    for (int b = lane; b < d.nblk; b += 64) nn += d.npart[(long long)b * nr + qq];
-    nn = wave_sum_all(nn);
-    double sums[NSLOT];
+  for (int qq = tid; qq < nr; qq += BLOCK) {
+    double* eta = d.eta + (long long)qq * (m + 1);
+    double* H = d.H + (long long)qq * (m + 1) * m;
+    double* wn = d.wnorm + (long long)qq * (m + 1);
+    double* cf = d.coef + (long long)qq * NSLOT;
+    int* mused = rhs_mused(d, qq);
+    int* brk = rhs_brk(d, qq);
+    // all loads first (one latency), then the scalar logic
+    const int brk0 = *brk;
+    const double wprev = i >= 2 ? wn[i - 2] : 0.0;
+    const double eta_prev = sqrt(sums[RS + qq]);  // ||u_{i-1}||, the newest window member
+    double ej[KMAX];
 #pragma unroll
-    for (int sl = 0; sl < NSLOT; ++sl) {
-      double v = 0.0;
-      if (nstream > 0)
-        for (int b = lane; b < nstream; b += 64) v += d.part[((long long)b * nr + qq) * NSLOT + sl];
-      sums[sl] = wave_sum_all(v);
-    }
-    if (lane == 0) {
-      double* eta = d.eta + (long long)qq * (m + 1);
-      double* H = d.H + (long long)qq * (m + 1) * m;
-      double* wn = d.wnorm + (long long)qq * (m + 1);
-      double* cf = d.coef + (long long)qq * NSLOT;
-      int* mused = rhs_mused(d, qq);
-      int* brk = rhs_brk(d, qq);
-      const double eta_prev = sqrt(nn);  // ||u_{i-1}||
-      eta[i - 1] = eta_prev;
-      if (!*brk) {
-        if (!isfinite(eta_prev)) {
-          d.status[1] = 1;
-          *brk = 1;
-          *mused = i - 1;
-        } else if (i == 1) {
-          if (eta_prev == 0.0) { *brk = 1; *mused = 0; }
-        } else if (eta_prev <= 100.0 * d.unit_round * wn[i - 2]) {
-          *brk = 1;  // invariant subspace of dimension i-1
-          *mused = i - 1;
-          H[(long long)(i - 2) * (m + 1) + (i - 1)] = 0.0;
-        } else {
-          H[(long long)(i - 2) * (m + 1) + (i - 1)] = eta_prev;
-        }
-      }
-      if (*brk || nstream == 0) {
-#pragma unroll
-        for (int sl = 0; sl < NSLOT; ++sl) cf[sl] = 0.0;
-        if (!*brk) *mused = m;
+    for (int jj = 0; jj < KMAX; ++jj) ej[jj] = (jj < nw - 1) ? eta[j0 + jj] : eta_prev;
+    eta[i - 1] = eta_prev;
+    int b = brk0, mu = -1;
+    if (!b) {
+      if (!isfinite(eta_prev)) {
+        d.status[1] = 1;
+        b = 1;
+        mu = i - 1;
+      } else if (i == 1) {
+        if (eta_prev == 0.0) { b = 1; mu = 0; }
+      } else if (eta_prev <= 100.0 * d.unit_round * wprev) {
+        b = 1;  // invariant subspace of dimension i-1
+        mu = i - 1;
+        H[(long long)(i - 2) * (m + 1) + (i - 1)] = 0.0;
       } else {
-        wn[i - 1] = sqrt(sums[KMAX]) / eta_prev;
-        cf[0] = 1.0 / eta_prev;
+        H[(long long)(i - 2) * (m + 1) + (i - 1)] = eta_prev;
+      }
+    }
+    if (b || nstream == 0) {
+      for (int sl = 0; sl < NSLOT; ++sl) cf[sl] = 0.0;
+      if (!b) mu = m;
+    } else {
+      wn[i - 1] = sqrt(sums[KMAX * nr + qq]) / eta_prev;
+      cf[0] = 1.0 / eta_prev;
 #pragma unroll
-        for (int jj = 0; jj < KMAX; ++jj) {
-          if (jj < nw) {
-            const double ej = eta[j0 + jj];
-            const double h = sums[jj] / (ej * eta_prev);
-            H[(long long)(i - 1) * (m + 1) + (j0 + jj)] = h;
-            cf[1 + jj] = h / ej;
-          } else {
-            cf[1 + jj] = 0.0;
-          }
+      for (int jj = 0; jj < KMAX; ++jj) {
+        if (jj < nw) {
+          const double h = sums[jj * nr + qq] / (ej[jj] * eta_prev);
+          H[(long long)(i - 1) * (m + 1) + (j0 + jj)] = h;
+          cf[1 + jj] = h / ej[jj];
+        } else {
+          cf[1 + jj] = 0.0;
         }
       }
     }
+    if (b != brk0) *brk = b;
+    if (mu >= 0) *mused = mu;
   }
   __syncthreads();
   if (tid == 0) {
@@ -206,18 +444,88 @@ __global__ void __launch_bounds__(BLOCK) k_dots(SolveDev d, int i, int nstream) 
   }
 }
 
+// ------------------------------------------------------------------ Walsh-Hadamard transform of a tile
+// X holds the tile (padded index padx(e) = e + e/32).  On entry each thread
+// holds its 8 consecutive elements in v (index bits 0..2); the transform acts
+// on index bits [lnr, LT) (the row bits of the tile), in three-bit phases:
+// registers hold three index bits, LDS transposes move between phases.  On
+// exit the transformed tile is in X.
+__device__ inline int padx(int e) { return e + (e >> 5); }
+
+__device__ inline void butterflies3_unused(double* v, int p, int lnr) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    if (p + b >= lnr) {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j)
+        if (!(j & (1 << b))) {
+          const double x = v[j], y = v[j | (1 << b)];
+          v[j] = x + y;
+          v[j | (1 << b)] = x - y;
+        }
+    }
+  }
+}
+
+__device__ inline void butterflies_range(double* v, int pos, int lo, int hi) {
+  // stages on index bits [lo, hi) while registers hold bits pos, pos+1, pos+2
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    if (pos + b >= lo && pos + b < hi) {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j)
+        if (!(j & (1 << b))) {
+          const double x = v[j], y = v[j | (1 << b)];
+          v[j] = x + y;
+          v[j | (1 << b)] = x - y;
+        }
+    }
+  }
+}
+
+template <int LT>
+__device__ inline void fwht_tile(double* v, double* X, int lnr) {
+  const int tid = threadIdx.x;
+  butterflies_range(v, 0, lnr, 3);
+  int cur = 0;
+#pragma unroll
+  for (int p = 3; p < LT; p += 3) {
+    const int pos = p + 3 <= LT ? p : LT - 3;   // a last partial phase reuses done bits
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = (tid & ((1 << cur) - 1)) | (j << cur) | ((tid >> cur) << (cur + 3));
+      X[padx(e)] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = (tid & ((1 << pos) - 1)) | (j << pos) | ((tid >> pos) << (pos + 3));
+      v[j] = X[padx(e)];
+    }
+    __syncthreads();
+    cur = pos;
+    butterflies_range(v, pos, p > lnr ? p : lnr, p + 3 < LT ? p + 3 : LT);
+  }
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int e = (tid & ((1 << cur) - 1)) | (j << cur) | ((tid >> cur) << (cur + 3));
+    X[padx(e)] = v[j];
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ pass 2
 // START: u_0 = fl(b).  Otherwise u_i = cf0 * w~ - sum_j cf_{1+j} u_{j0+j}.
-template <typename T, int OP, int SK, bool START>
-__global__ void __launch_bounds__(BLOCK) k_update(SolveDev d, int i) {
+template <typename T, int OP, int SK, bool START, int LT, int QC, int KT>
+__global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
+  constexpr int BLOCK = 1 << (LT - 3);
+  constexpr int TILE = 1 << LT;
+  constexpr int NW = BLOCK / 64;
   if (d.status[0]) return;
   extern __shared__ double lds[];
-  __shared__ double nred[BLOCK / 64][32];
+  __shared__ double nred[NW][32];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nr = d.nrhs;
-  const int q = tid & (nr - 1);
-  const int R = d.rows_per_tile;
-  const int tile_elems = R * nr;
   const long long nel = (long long)d.n * nr;
   const int j0 = i - d.k > 0 ? i - d.k : 0;
   const int nw = START ? 0 : i - j0;
@@ -225,80 +533,99 @@ __global__ void __launch_bounds__(BLOCK) k_update(SolveDev d, int i) {
   const T* __restrict__ src = START ? nullptr : V + (long long)(i - 1) * d.ldv;
   T* __restrict__ dst = V + (long long)i * d.ldv;
 
-  double cw = 1.0;
-  double cj[KMAX];
-  {
-    const double* cf = d.coef + (long long)q * NSLOT;
-    if (!START) cw = cf[0];
+  double cw[QC];
+  double cj[KT][QC];
 #pragma unroll
-    for (int jj = 0; jj < KMAX; ++jj) cj[jj] = START ? 0.0 : cf[1 + jj];
+  for (int c = 0; c < QC; ++c) {
+    const int q = rhs_of<QC>(tid, c, nr);
+    const double* cf = d.coef + (long long)q * NSLOT;
+    cw[c] = START ? 1.0 : cf[0];
+#pragma unroll
+    for (int jj = 0; jj < KT; ++jj) cj[jj][c] = (START || jj >= nw) ? 0.0 : cf[1 + jj];
   }
 
-  double* X = lds;                                        // SRHT tile [R][nr]
-  double* acc = lds + (SK == SK_SRHT ? tile_elems : 0);   // sketch accumulator [s][nr]
+  double* X = lds;                                                   // SRHT tile (padded)
+  double* acc = lds + (SK == SK_SRHT ? padx(TILE) : 0);              // sketch accumulator [s][nr]
   const int snr = d.s * nr;
   for (int x = tid; x < snr; x += BLOCK) acc[x] = 0.0;
   __syncthreads();
 
-  double nrm = 0.0;
+  double nrm[QC];
+#pragma unroll
+  for (int c = 0; c < QC; ++c) nrm[c] = 0.0;
   for (int t = blockIdx.x; t < d.ntiles; t += d.nblk) {
-    const long long e0 = (long long)t * tile_elems;
-    for (int l = tid; l < tile_elems; l += BLOCK) {
-      const long long e = e0 + l;
-      double uu = 0.0;
-      int r = (int)(e >> d.lognrhs);
-      if (e < nel) {
-        double u;
-        if (START) {
-          u = d.b[e];
+    const long long e = ((long long)t << LT) + (long long)tid * EPT;
+    double uu[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) uu[j] = 0.0;
+    if (e < nel) {
+      double u[EPT];
+      if (START) {
+        get8(d.b, e, nel, u);
+      } else {
+        double w[EPT];
+        if (OP == OP_STENCIL) {
+          double c[EPT];
+          get8(src, e, nel, c);
+          stencil8(d, src, e, nel, c, w);
         } else {
-          double w;
-          if (OP == OP_STENCIL) w = stencil_apply(d, src, r, e);
-          else w = d.wbuf[e];
-          u = cw * w;
-#pragma unroll
-          for (int jj = 0; jj < KMAX; ++jj)
-            if (jj < nw) u -= cj[jj] * (double)V[(long long)(j0 + jj) * d.ldv + e];
+          get8(d.wbuf, e, nel, w);
         }
-        const T ut = (T)u;
-        dst[e] = ut;
-        uu = (double)ut;
-        nrm += uu * uu;
-        if (SK == SK_SPARSE) {
-          int rows[ZMAX];
-          unsigned long long sb;
-          sparse_sign_column(d.key_a, d.key_b, r, d.s, d.zeta, rows, &sb);
 #pragma unroll
-          for (int tt = 0; tt < ZMAX; ++tt)
-            if (tt < d.zeta) atomicAdd(&acc[rows[tt] * nr + q], ((sb >> tt) & 1ull) ? -uu : uu);
+        for (int j = 0; j < EPT; ++j) u[j] = cw[slot_of<QC>(j)] * w[j];
+#pragma unroll
+        for (int jj = 0; jj < KT; ++jj) {
+          if (jj < nw) {
+            double vj[EPT];
+            get8(V + (long long)(j0 + jj) * d.ldv, e, nel, vj);
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) u[j] -= cj[jj][slot_of<QC>(j)] * vj[j];
+          }
         }
       }
-      if (SK == SK_SRHT) {
-        const double sgn = (sm64_out(d.key_a, (unsigned long long)r) >> 63) ? -1.0 : 1.0;
-        X[l] = uu * sgn;
+      if (e + EPT <= nel) {
+        store8(dst + e, u, uu);
+      } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+          if (e + j < nel) {
+            const T ut = (T)u[j];
+            dst[e + j] = ut;
+            uu[j] = (double)ut;
+          }
+      }
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) nrm[slot_of<QC>(j)] += uu[j] * uu[j];
+      if (SK == SK_SPARSE) {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+          if (e + j < nel) {
+            const int r = (int)((e + j) >> d.lognrhs);
+            const int q = (int)((e + j) & (nr - 1));
+            int rows[ZMAX];
+            unsigned long long sb;
+            sparse_sign_column(d.key_a, d.key_b, r, d.s, d.zeta, rows, &sb);
+#pragma unroll
+            for (int tt = 0; tt < ZMAX; ++tt)
+              if (tt < d.zeta) atomicAdd(&acc[rows[tt] * nr + q], ((sb >> tt) & 1ull) ? -uu[j] : uu[j]);
+          }
+        }
       }
     }
     if (SK == SK_SRHT) {
-      __syncthreads();
-      // Walsh-Hadamard transform of the tile along rows (Sylvester order).
-      for (int h = 1; h < R; h <<= 1) {
-        for (int bi = tid; bi < (R >> 1) * nr; bi += BLOCK) {
-          const int qq = bi & (nr - 1);
-          const int pr = bi >> d.lognrhs;
-          const int lo = ((pr & ~(h - 1)) << 1) | (pr & (h - 1));
-          const int a = lo * nr + qq, bb = (lo + h) * nr + qq;
-          const double xa = X[a], xb = X[bb];
-          X[a] = xa + xb;
-          X[bb] = xa - xb;
-        }
-        __syncthreads();
+      // D signs, then the transform of the tile along rows
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const unsigned long long r = (unsigned long long)((e + j) >> d.lognrhs);
+        if (sm64_out(d.key_a, r) >> 63) uu[j] = -uu[j];
       }
+      fwht_tile<LT>(uu, X, d.lognrhs);
       // sampled rows r = (r_hi, r_lo): contribution (-1)^popcount(r_hi & t) * X[r_lo]
       for (int pq = tid; pq < snr; pq += BLOCK) {
         const int p = pq >> d.lognrhs, qq = pq & (nr - 1);
         const int rr = d.srht_rows[p];
         const int par = __popc((unsigned)(rr >> d.log_rows) & (unsigned)t) & 1;
-        const double v = X[(rr & (R - 1)) * nr + qq];
+        const double v = X[padx(((rr & (d.rows_per_tile - 1)) << d.lognrhs) + qq)];
         acc[pq] += par ? -v : v;
       }
       __syncthreads();
@@ -307,116 +634,166 @@ __global__ void __launch_bounds__(BLOCK) k_update(SolveDev d, int i) {
   __syncthreads();
   for (int pq = tid; pq < snr; pq += BLOCK) d.skpart[(long long)pq * d.nblk + blockIdx.x] = acc[pq];
 
-  nrm = wave_sum_rhs(nrm, nr);
-  if (lane < nr) nred[wv][lane] = nrm;
+  // norm partials per rhs
+  for (int q = 0; q < nr; ++q) {
+    double a = 0.0;
+#pragma unroll
+    for (int c = 0; c < QC; ++c)
+      if (rhs_of<QC>(tid, c, nr) == q) a += nrm[c];
+    a = wave_sum_all(a);
+    if (lane == 0) nred[wv][q] = a;
+  }
   __syncthreads();
-  if (tid < nr)
-    d.npart[(long long)blockIdx.x * nr + tid] = ((nred[0][tid] + nred[1][tid]) + nred[2][tid]) + nred[3][tid];
+  for (int q = tid; q < nr; q += BLOCK) {
+    double t = 0.0;
+    for (int w = 0; w < NW; ++w) t += nred[w][q];
+    d.npart[(long long)blockIdx.x * nr + q] = t;
+  }
 }
 
 // ------------------------------------------------------------------ combine
 // out = sum_j cf_j u_j with cf_j = beta c_j / eta_j (FP64 accumulation).
 template <typename T>
-__global__ void __launch_bounds__(BLOCK) k_combine(SolveDev d, const double* __restrict__ cf, int mmax,
-                                                   double* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_combine(SolveDev d, const double* __restrict__ cf, int mmax,
+                                                 double* __restrict__ out) {
   const T* __restrict__ V = (const T*)d.V;
   const long long nel = (long long)d.n * d.nrhs;
   const int nr = d.nrhs;
-  for (long long e = (long long)blockIdx.x * BLOCK + threadIdx.x; e < nel; e += (long long)gridDim.x * BLOCK) {
-    const int q = (int)(e & (nr - 1));
-    const double* c = cf + (long long)q * (d.m + 1);
-    double a = 0.0;
-    for (int j = 0; j < mmax; ++j) a += c[j] * (double)V[(long long)j * d.ldv + e];
-    out[e] = a;
+  for (long long e = ((long long)blockIdx.x * 256 + threadIdx.x) * EPT; e < nel;
+       e += (long long)gridDim.x * 256 * EPT) {
+    double a[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) a[j] = 0.0;
+    for (int jv = 0; jv < mmax; ++jv) {
+      double v[EPT];
+      get8(V + (long long)jv * d.ldv, e, nel, v);
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) a[j] += cf[(long long)((e + j) & (nr - 1)) * (d.m + 1) + jv] * v[j];
+    }
+    if (e + EPT <= nel) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        double2 o;
+        o.x = a[2 * h];
+        o.y = a[2 * h + 1];
+        *reinterpret_cast<double2*>(out + e + 2 * h) = o;
+      }
+    } else {
+      for (int j = 0; j < EPT; ++j)
+        if (e + j < nel) out[e + j] = a[j];
+    }
   }
 }
 
 // ------------------------------------------------------------------ host launchers
-template <typename T>
-static hipError_t launch_dots_t(const SolveDev& d, int i, hipStream_t st) {
-  if (d.op == OP_STENCIL)
-    hipLaunchKernelGGL((k_dots<T, OP_STENCIL>), dim3(d.nblk + d.nred), dim3(BLOCK), 0, st, d, i, d.nblk);
-  else
-    hipLaunchKernelGGL((k_dots<T, OP_CSR>), dim3(d.nblk + d.nred), dim3(BLOCK), 0, st, d, i, d.nblk);
+template <typename T, int LT, int QC, int KT>
+static hipError_t launch_dots_k(const SolveDev& d, int i, hipStream_t st, int nstream, int grid) {
+  const dim3 g(grid), b(1 << (LT - 3));
+  if (d.op == OP_STENCIL) hipLaunchKernelGGL((k_dots<T, OP_STENCIL, LT, QC, KT>), g, b, 0, st, d, i, nstream);
+  else hipLaunchKernelGGL((k_dots<T, OP_CSR, LT, QC, KT>), g, b, 0, st, d, i, nstream);
   return hipGetLastError();
 }
+template <typename T, int LT, int QC>
+static hipError_t launch_dots_q(const SolveDev& d, int i, hipStream_t st, int nstream, int grid) {
+  if (d.k <= 2) return launch_dots_k<T, LT, QC, 2>(d, i, st, nstream, grid);
+  if (d.k <= 4) return launch_dots_k<T, LT, QC, 4>(d, i, st, nstream, grid);
+  return launch_dots_k<T, LT, QC, 8>(d, i, st, nstream, grid);
+}
 
-template <typename T>
-static hipError_t launch_update_t(const SolveDev& d, int i, hipStream_t st, size_t lds_update) {
-  if (d.op == OP_STENCIL) {
-    if (d.sketch == SK_SRHT)
-      hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SRHT, false>), dim3(d.nblk), dim3(BLOCK), lds_update, st, d, i);
-    else
-      hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SPARSE, false>), dim3(d.nblk), dim3(BLOCK), lds_update, st, d, i);
+template <typename T, bool START, int LT, int QC, int KT>
+static hipError_t launch_update_k(const SolveDev& d, int i, hipStream_t st, size_t lds) {
+  const dim3 g(d.nblk), b(1 << (LT - 3));
+  if (d.op == OP_STENCIL || START) {
+    if (d.sketch == SK_SRHT) hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SRHT, START, LT, QC, KT>), g, b, lds, st, d, i);
+    else hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SPARSE, START, LT, QC, KT>), g, b, lds, st, d, i);
   } else {
-    if (d.sketch == SK_SRHT)
-      hipLaunchKernelGGL((k_update<T, OP_CSR, SK_SRHT, false>), dim3(d.nblk), dim3(BLOCK), lds_update, st, d, i);
-    else
-      hipLaunchKernelGGL((k_update<T, OP_CSR, SK_SPARSE, false>), dim3(d.nblk), dim3(BLOCK), lds_update, st, d, i);
+    if (d.sketch == SK_SRHT) hipLaunchKernelGGL((k_update<T, OP_CSR, SK_SRHT, START, LT, QC, KT>), g, b, lds, st, d, i);
+    else hipLaunchKernelGGL((k_update<T, OP_CSR, SK_SPARSE, START, LT, QC, KT>), g, b, lds, st, d, i);
   }
   return hipGetLastError();
 }
-
-template <typename T>
-static hipError_t launch_start_t(const SolveDev& d, hipStream_t st, size_t lds_update) {
-  if (d.sketch == SK_SRHT)
-    hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SRHT, true>), dim3(d.nblk), dim3(BLOCK), lds_update, st, d, 0);
-  else
-    hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SPARSE, true>), dim3(d.nblk), dim3(BLOCK), lds_update, st, d, 0);
-  return hipGetLastError();
+template <typename T, bool START, int LT, int QC>
+static hipError_t launch_update_q(const SolveDev& d, int i, hipStream_t st, size_t lds) {
+  if (START) return launch_update_k<T, START, LT, QC, 2>(d, i, st, lds);
+  if (d.k <= 2) return launch_update_k<T, START, LT, QC, 2>(d, i, st, lds);
+  if (d.k <= 4) return launch_update_k<T, START, LT, QC, 4>(d, i, st, lds);
+  return launch_update_k<T, START, LT, QC, 8>(d, i, st, lds);
 }
 
 template <typename T>
-static hipError_t launch_finish_t(const SolveDev& d, hipStream_t st) {
-  hipLaunchKernelGGL((k_dots<T, OP_STENCIL>), dim3(d.nred), dim3(BLOCK), 0, st, d, d.m + 1, 0);
-  return hipGetLastError();
+static hipError_t dots_t(const SolveDev& d, int i, hipStream_t st, int nstream, int grid) {
+  const bool q1 = d.nrhs == 1;
+  if (d.log_tile == 11)
+    return q1 ? launch_dots_q<T, 11, 1>(d, i, st, nstream, grid) : launch_dots_q<T, 11, 8>(d, i, st, nstream, grid);
+  return q1 ? launch_dots_q<T, 9, 1>(d, i, st, nstream, grid) : launch_dots_q<T, 9, 8>(d, i, st, nstream, grid);
 }
 
-template <typename T>
-static hipError_t set_lds_attr() {
+template <typename T, bool START>
+static hipError_t update_t(const SolveDev& d, int i, hipStream_t st, size_t lds) {
+  const bool q1 = d.nrhs == 1;
+  if (d.log_tile == 11)
+    return q1 ? launch_update_q<T, START, 11, 1>(d, i, st, lds) : launch_update_q<T, START, 11, 8>(d, i, st, lds);
+  return q1 ? launch_update_q<T, START, 9, 1>(d, i, st, lds) : launch_update_q<T, START, 9, 8>(d, i, st, lds);
+}
+
+template <typename T, int LT, int QC, int KT>
+static void set_lds_attr_k(hipError_t& e) {
   const int mx = 160 * 1024;
-  hipError_t e = hipSuccess;
-  auto f = [&](const void* k) { hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, mx); if (r != hipSuccess) e = r; };
-  f((const void*)k_update<T, OP_STENCIL, SK_SRHT, false>);
-  f((const void*)k_update<T, OP_STENCIL, SK_SPARSE, false>);
-  f((const void*)k_update<T, OP_CSR, SK_SRHT, false>);
-  f((const void*)k_update<T, OP_CSR, SK_SPARSE, false>);
-  f((const void*)k_update<T, OP_STENCIL, SK_SRHT, true>);
-  f((const void*)k_update<T, OP_STENCIL, SK_SPARSE, true>);
-  return e;
+  auto f = [&](const void* k) {
+    hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    if (r != hipSuccess) e = r;
+  };
+  f((const void*)k_update<T, OP_STENCIL, SK_SRHT, false, LT, QC, KT>);
+  f((const void*)k_update<T, OP_STENCIL, SK_SPARSE, false, LT, QC, KT>);
+  f((const void*)k_update<T, OP_CSR, SK_SRHT, false, LT, QC, KT>);
+  f((const void*)k_update<T, OP_CSR, SK_SPARSE, false, LT, QC, KT>);
+  if (KT == 2) {
+    f((const void*)k_update<T, OP_STENCIL, SK_SRHT, true, LT, QC, KT>);
+    f((const void*)k_update<T, OP_STENCIL, SK_SPARSE, true, LT, QC, KT>);
+  }
+}
+template <typename T, int LT, int QC>
+static void set_lds_attr_q(hipError_t& e) {
+  set_lds_attr_k<T, LT, QC, 2>(e);
+  set_lds_attr_k<T, LT, QC, 4>(e);
+  set_lds_attr_k<T, LT, QC, 8>(e);
 }
 
 hipError_t basis_set_attributes() {
-  hipError_t e = set_lds_attr<float>();
-  if (e != hipSuccess) return e;
-  return set_lds_attr<double>();
+  hipError_t e = hipSuccess;
+  set_lds_attr_q<float, 11, 1>(e);
+  set_lds_attr_q<float, 11, 8>(e);
+  set_lds_attr_q<float, 9, 1>(e);
+  set_lds_attr_q<float, 9, 8>(e);
+  set_lds_attr_q<double, 11, 1>(e);
+  set_lds_attr_q<double, 11, 8>(e);
+  set_lds_attr_q<double, 9, 1>(e);
+  set_lds_attr_q<double, 9, 8>(e);
+  return e;
 }
 
 hipError_t basis_start(const SolveDev& d, int esize, hipStream_t st, size_t lds) {
-  return esize == 4 ? launch_start_t<float>(d, st, lds) : launch_start_t<double>(d, st, lds);
+  return esize == 4 ? update_t<float, true>(d, 0, st, lds) : update_t<double, true>(d, 0, st, lds);
 }
 hipError_t basis_dots(const SolveDev& d, int esize, int i, hipStream_t st) {
-  return esize == 4 ? launch_dots_t<float>(d, i, st) : launch_dots_t<double>(d, i, st);
+  return esize == 4 ? dots_t<float>(d, i, st, d.nblk, d.nblk + d.nred) : dots_t<double>(d, i, st, d.nblk, d.nblk + d.nred);
 }
 hipError_t basis_update(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds) {
-  return esize == 4 ? launch_update_t<float>(d, i, st, lds) : launch_update_t<double>(d, i, st, lds);
+  return esize == 4 ? update_t<float, false>(d, i, st, lds) : update_t<double, false>(d, i, st, lds);
 }
 hipError_t basis_finish(const SolveDev& d, int esize, hipStream_t st) {
-  return esize == 4 ? launch_finish_t<float>(d, st) : launch_finish_t<double>(d, st);
+  return esize == 4 ? dots_t<float>(d, d.m + 1, st, 0, d.nred) : dots_t<double>(d, d.m + 1, st, 0, d.nred);
 }
 hipError_t basis_combine(const SolveDev& d, int esize, const double* cf, int mmax, double* out, hipStream_t st) {
   const long long nel = (long long)d.n * d.nrhs;
-  long long g = (nel + BLOCK - 1) / BLOCK;
-  if (g > 8192) g = 8192;
-  if (esize == 4) hipLaunchKernelGGL(k_combine<float>, dim3((unsigned)g), dim3(BLOCK), 0, st, d, cf, mmax, out);
-  else hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)g), dim3(BLOCK), 0, st, d, cf, mmax, out);
+  long long g = (nel + 256 * EPT - 1) / (256 * EPT);
+  if (g > 4096) g = 4096;
+  if (esize == 4) hipLaunchKernelGGL(k_combine<float>, dim3((unsigned)g), dim3(256), 0, st, d, cf, mmax, out);
+  else hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)g), dim3(256), 0, st, d, cf, mmax, out);
   return hipGetLastError();
 }
 
-}  // namespace fab
-
-namespace fab {
-
+// ------------------------------------------------------------------ small utility kernels
 __global__ void k_zero(unsigned long long* p, long long n8) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += (long long)gridDim.x * blockDim.x)
     p[i] = 0ull;

@@ -1,9 +1,12 @@
 // Small dense FP64 stages of the method, one workgroup per right-hand side:
 //
-//  k_lsq    normalise the sketched basis Theta V_{m+1}; Householder QR of
-//           Theta V_m; y = R^{-1} Q^T Theta v_{m+1} (sketch-and-solve of the
-//           least-squares problem eq. (7), Remark 3); the compression
-//           H_hat = H_m + h_{m+1,m} y e_m^T (eq. (6)).
+//  k_lsq    Householder QR of the sketched basis Theta V_{m+1} (its last
+//           column carried along gives Q^T Theta v_{m+1}); y = R_m^{-1} Q^T
+//           Theta v_{m+1} (sketch-and-solve of the least-squares problem
+//           eq. (7), Remark 3) by back substitution; the compression
+//           H_hat = H_m + h_{m+1,m} y e_m^T (eq. (6)).  The matrix is held in
+//           registers across the workgroup when s <= 448 and m + 1 <= 112,
+//           else it is factorised in global memory.
 //  k_fexp   exp(alpha H_hat) e_1 by scaling and squaring with a diagonal Pade
 //           approximant (Higham, SIAM J. Matrix Anal. Appl. 26 (2005)), the
 //           algorithm behind the expm the paper uses in Section 5.
@@ -99,6 +102,42 @@ __device__ void bgemm(int m, const double* __restrict__ A, const double* __restr
   __syncthreads();
 }
 
+// C = A * B for m <= 128 with B staged in LDS (Bl: m*m doubles) and A read
+// through the cache; thread (ti, tj) of a 16 x 16 grid owns an 8 x 8 block of C.
+__device__ void bgemm_small(int m, const double* __restrict__ A, const double* __restrict__ B,
+                            double* __restrict__ C, double* Bl) {
+  const int tid = threadIdx.x;
+  const long long mm = (long long)m * m;
+  for (long long x = tid; x < mm; x += DBLOCK) Bl[x] = B[x];
+  __syncthreads();
+  const int ti = tid & 15, tj = tid >> 4;
+  const int i0 = ti * 8, j0 = tj * 8;
+  if (i0 < m && j0 < m) {
+    double acc[8][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+    for (int k = 0; k < m; ++k) {
+      double av[8], bv[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) av[a] = (i0 + a < m) ? A[i0 + a + (long long)k * m] : 0.0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) bv[b] = (j0 + b < m) ? Bl[k + (long long)(j0 + b) * m] : 0.0;
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] += av[a] * bv[b];
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        if (i0 + a < m && j0 + b < m) C[i0 + a + (long long)(j0 + b) * m] = acc[a][b];
+  }
+  __syncthreads();
+}
+
 // ----------------------------------------------------------------- LU with partial pivoting
 // In place on A (m x m); piv[j] = row swapped with j.  Returns 1 if singular.
 __device__ int blu(int m, double* A, int* piv, double* shv, int* shi) {
@@ -149,6 +188,30 @@ __device__ int blu(int m, double* A, int* piv, double* shv, int* shi) {
   return singular;
 }
 
+// Solve (LU) x = b in place for one right-hand side, all threads sharing the
+// substitution (one barrier per pivot).
+__device__ void blu_solve1(int m, const double* LU, const int* piv, double* x) {
+  if (threadIdx.x == 0)
+    for (int j = 0; j < m; ++j) {
+      const int p = piv[j];
+      if (p != j) { const double t = x[j]; x[j] = x[p]; x[p] = t; }
+    }
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    const double xj = x[j];
+    __syncthreads();
+    for (int r = j + 1 + threadIdx.x; r < m; r += DBLOCK) x[r] -= LU[r + (long long)j * m] * xj;
+    __syncthreads();
+  }
+  for (int j = m - 1; j >= 0; --j) {
+    const double xj = x[j] / LU[j + (long long)j * m];
+    __syncthreads();
+    if (threadIdx.x == 0) x[j] = xj;
+    for (int r = threadIdx.x; r < j; r += DBLOCK) x[r] -= LU[r + (long long)j * m] * xj;
+    __syncthreads();
+  }
+}
+
 // Solve (LU) X = B in place for nb right-hand-side columns of B (ld m); one thread per column.
 __device__ void blu_solve(int m, const double* LU, const int* piv, double* B, int nb) {
   for (int c = threadIdx.x; c < nb; c += DBLOCK) {
@@ -173,41 +236,49 @@ __device__ void blu_solve(int m, const double* LU, const int* piv, double* B, in
 __device__ inline int* st_mused(const SolveDev& d, int q) { return d.status + 4 + 2 * q; }
 __device__ inline int* st_brk(const SolveDev& d, int q) { return d.status + 5 + 2 * q; }
 
-// ----------------------------------------------------------------- sketched least squares
-__global__ void __launch_bounds__(DBLOCK) k_lsq(SolveDev d, DenseDev g) {
-  const int q = blockIdx.x;
+// ----------------------------------------------------------------- sketched QR and least squares
+constexpr int LBLOCK = 512;          // 8 waves
+constexpr int LRS = 7;               // row slots per lane: rows lane + 64*rs  (s <= 448)
+constexpr int LCS = 14;              // column slots per wave: cols wave + 8*cs (m + 1 <= 112)
+
+// Householder QR of W (s x ncol, column-major, normalised sketch columns) held
+// in registers; on exit R (ncol-1 x ncol-1 upper, ld mu) and z = first mu
+// entries of the transformed last column are written to Rl / zl (LDS), and
+// |r_jj| extremes to rmm.
+__device__ void qr_registers(const double* __restrict__ S, const double* __restrict__ eta, int s, int ncol,
+                             double* vsh, double* Rl, double* zl, double* tau_sh, double* rmm) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  __shared__ double sh[8];
-  __shared__ double yv[MAXM];
-  const int m = d.m, s = d.s;
-  double* ws = g.base + (long long)q * g.stride;
-  double* W = ws + g.oW;
-  double* Hh = ws + g.oH;
-  double* info = ws + g.oInfo;
-  const int mu = *st_mused(d, q);
-  const int brk = *st_brk(d, q);
-  const double* S = d.S + (long long)q * s * (m + 1);
-  const double* eta = d.eta + (long long)q * (m + 1);
-  const double* H = d.H + (long long)q * (m + 1) * m;
-  const bool do_ls = (!brk) && mu > 0 && g.ls_mode != 2;
-  const int ncol = do_ls ? mu + 1 : 0;
-
-  for (long long x = tid; x < (long long)s * ncol; x += DBLOCK) {
-    const int c = (int)(x / s);
-    const double e = eta[c];
-    W[x] = e > 0.0 ? S[x] / e : 0.0;
+  const int mu = ncol - 1;
+  double a[LCS][LRS];
+#pragma unroll
+  for (int cs = 0; cs < LCS; ++cs) {
+    const int c = wv + 8 * cs;
+    const double e = c < ncol ? eta[c] : 0.0;
+    const double sc = e > 0.0 ? 1.0 / e : 0.0;
+#pragma unroll
+    for (int rs = 0; rs < LRS; ++rs) {
+      const int r = lane + 64 * rs;
+      a[cs][rs] = (c < ncol && r < s) ? S[(long long)c * s + r] * sc : 0.0;
+    }
   }
-  for (int x = tid; x < mu; x += DBLOCK) yv[x] = 0.0;
-  __syncthreads();
-
   double rmax = 0.0, rmin = 1e308;
-  if (do_ls) {
-    for (int j = 0; j < mu; ++j) {
-      double* wj = W + (long long)j * s;
-      double part = 0.0;
-      for (int r = j + tid; r < s; r += DBLOCK) part += wj[r] * wj[r];
-      const double n2 = bsum(part, sh);
-      const double x1 = wj[j];
+  for (int j = 0; j < mu; ++j) {
+    const int ow = j & 7, oc = j >> 3, jl = j & 63, js = j >> 6;
+    if (wv == ow) {
+      double part = 0.0, cand = 0.0;
+#pragma unroll
+      for (int cs = 0; cs < LCS; ++cs) {
+        if (cs == oc) {
+#pragma unroll
+          for (int rs = 0; rs < LRS; ++rs) {
+            const int r = lane + 64 * rs;
+            if (r >= j) part += a[cs][rs] * a[cs][rs];
+            if (rs == js) cand = a[cs][rs];
+          }
+        }
+      }
+      const double n2 = wsum(part);
+      const double x1 = __shfl(cand, jl, 64);
       double beta = 0.0, tau = 0.0, scal = 0.0;
       if (n2 > 0.0) {
         const double nrm = sqrt(n2);
@@ -215,48 +286,175 @@ __global__ void __launch_bounds__(DBLOCK) k_lsq(SolveDev d, DenseDev g) {
         tau = (beta - x1) / beta;
         scal = 1.0 / (x1 - beta);
       }
-      __syncthreads();
-      if (n2 > 0.0)
-        for (int r = j + 1 + tid; r < s; r += DBLOCK) wj[r] *= scal;
-      __syncthreads();
-      if (tid == 0) wj[j] = beta;
-      const double ab = fabs(beta);
-      rmax = fmax(rmax, ab);
-      rmin = fmin(rmin, ab);
-      if (n2 > 0.0) {
-        for (int c = j + 1 + wv; c < ncol; c += DBLOCK / 64) {
-          double* wc = W + (long long)c * s;
-          double dt = 0.0;
-          for (int r = j + 1 + lane; r < s; r += 64) dt += wj[r] * wc[r];
-          dt = wsum(dt) + wc[j];
-          dt *= tau;
-          if (lane == 0) wc[j] -= dt;
-          for (int r = j + 1 + lane; r < s; r += 64) wc[r] -= dt * wj[r];
+#pragma unroll
+      for (int cs = 0; cs < LCS; ++cs) {
+        if (cs == oc) {
+#pragma unroll
+          for (int rs = 0; rs < LRS; ++rs) {
+            const int r = lane + 64 * rs;
+            if (r < s) vsh[r] = r < j ? 0.0 : (r == j ? 1.0 : a[cs][rs] * scal);
+            if (r == j) a[cs][rs] = beta;
+            else if (r > j) a[cs][rs] = 0.0;
+          }
         }
       }
-      __syncthreads();
+      if (lane == 0) *tau_sh = tau;
+      rmax = fmax(rmax, fabs(beta));
+      rmin = fmin(rmin, fabs(beta));
     }
-    // back substitution R y = (Q^T Theta v_{m+1})[0:mu] by one wave
-    if (wv == 0) {
-      const double* z = W + (long long)mu * s;
-      for (int i = mu - 1; i >= 0; --i) {
-        double acc = 0.0;
-        for (int c = i + 1 + lane; c < mu; c += 64) acc += W[i + (long long)c * s] * yv[c];
-        acc = wsum(acc);
-        const double rii = W[i + (long long)i * s];
-        const double yi = rii != 0.0 ? (z[i] - acc) / rii : 0.0;
-        if (lane == 0) yv[i] = yi;
-        wave_order();
+    __syncthreads();
+    const double tau = *tau_sh;
+    double vr[LRS];
+#pragma unroll
+    for (int rs = 0; rs < LRS; ++rs) {
+      const int r = lane + 64 * rs;
+      vr[rs] = r < s ? vsh[r] : 0.0;
+    }
+#pragma unroll
+    for (int cs = 0; cs < LCS; ++cs) {
+      const int c = wv + 8 * cs;
+      if (c > j && c < ncol) {   // uniform per wave
+        double dt = 0.0;
+#pragma unroll
+        for (int rs = 0; rs < LRS; ++rs) dt += vr[rs] * a[cs][rs];
+        dt = tau * wsum(dt);
+#pragma unroll
+        for (int rs = 0; rs < LRS; ++rs) a[cs][rs] -= dt * vr[rs];
       }
     }
     __syncthreads();
   }
+  // R and z to LDS: entry (r, c) with r <= c (r < mu)
+#pragma unroll
+  for (int cs = 0; cs < LCS; ++cs) {
+    const int c = wv + 8 * cs;
+#pragma unroll
+    for (int rs = 0; rs < LRS; ++rs) {
+      const int r = lane + 64 * rs;
+      if (c < mu && r < mu) Rl[r + c * mu] = r <= c ? a[cs][rs] : 0.0;
+      if (c == mu && r < mu) zl[r] = a[cs][rs];
+    }
+  }
+  // |r_jj| extremes from the owner waves
+  if (lane == 0) {
+    rmm[2 * wv] = rmax;
+    rmm[2 * wv + 1] = rmin;
+  }
+  __syncthreads();
+}
+
+// Same factorisation with W in global memory (any s, m); R, z to Rg / zl.
+__device__ void qr_global(const double* __restrict__ S, const double* __restrict__ eta, int s, int ncol, double* W,
+                          double* zl, double* sh, double* rmm) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nth = blockDim.x, nwv = nth >> 6;
+  const int mu = ncol - 1;
+  for (long long x = tid; x < (long long)s * ncol; x += nth) {
+    const int c = (int)(x / s);
+    const double e = eta[c];
+    W[x] = e > 0.0 ? S[x] / e : 0.0;
+  }
+  __syncthreads();
+  double rmax = 0.0, rmin = 1e308;
+  for (int j = 0; j < mu; ++j) {
+    double* wj = W + (long long)j * s;
+    double part = 0.0;
+    for (int r = j + tid; r < s; r += nth) part += wj[r] * wj[r];
+    const double n2 = bsum(part, sh);
+    const double x1 = wj[j];
+    double beta = 0.0, tau = 0.0, scal = 0.0;
+    if (n2 > 0.0) {
+      const double nrm = sqrt(n2);
+      beta = x1 >= 0.0 ? -nrm : nrm;
+      tau = (beta - x1) / beta;
+      scal = 1.0 / (x1 - beta);
+    }
+    __syncthreads();
+    if (n2 > 0.0)
+      for (int r = j + 1 + tid; r < s; r += nth) wj[r] *= scal;
+    __syncthreads();
+    if (tid == 0) wj[j] = beta;
+    rmax = fmax(rmax, fabs(beta));
+    rmin = fmin(rmin, fabs(beta));
+    if (n2 > 0.0) {
+      for (int c = j + 1 + wv; c < ncol; c += nwv) {
+        double* wc = W + (long long)c * s;
+        double dt = 0.0;
+        for (int r = j + 1 + lane; r < s; r += 64) dt += wj[r] * wc[r];
+        dt = wsum(dt) + wc[j];
+        dt *= tau;
+        if (lane == 0) wc[j] -= dt;
+        for (int r = j + 1 + lane; r < s; r += 64) wc[r] -= dt * wj[r];
+      }
+    }
+    __syncthreads();
+  }
+  for (int r = tid; r < mu; r += nth) zl[r] = W[r + (long long)mu * s];
+  if (tid == 0) {
+    rmm[0] = rmax;
+    rmm[1] = rmin;
+    for (int w = 1; w < 8; ++w) { rmm[2 * w] = 0.0; rmm[2 * w + 1] = 1e308; }
+  }
+  __syncthreads();
+}
+
+// Dynamic LDS: vsh[448] + z[m+1] + (R[mu*mu] when mu <= 111).
+__global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  extern __shared__ double lsh[];
+  __shared__ double sh[16];
+  __shared__ double rmm[16];
+  __shared__ double tau_sh;
+  const int m = d.m, m1 = d.m + 1, s = d.s;
+  double* ws = g.base + (long long)q * g.stride;
+  double* Hh = ws + g.oH;
+  double* info = ws + g.oInfo;
+  const int mu = *st_mused(d, q);
+  const int brk = *st_brk(d, q);
+  const double* eta = d.eta + (long long)q * m1;
+  const double* H = d.H + (long long)q * m1 * m;
+  const double* S = d.S + (long long)q * s * m1;
+  const bool do_ls = (!brk) && mu > 0 && g.ls_mode != 2;
+  const bool in_regs = s <= 64 * LRS && mu + 1 <= 8 * LCS;
+  double* vsh = lsh;
+  double* z = vsh + 64 * LRS;
+  double* Rl = z + m1;
+  const double* Rm = Rl;
+  int ldr = mu;
+  double rmax = 0.0, rmin = 1e308;
+  if (do_ls) {
+    if (in_regs) {
+      qr_registers(S, eta, s, mu + 1, vsh, Rl, z, &tau_sh, rmm);
+    } else {
+      double* W = ws + g.oW;
+      qr_global(S, eta, s, mu + 1, W, z, sh, rmm);
+      Rm = W;
+      ldr = s;
+    }
+    for (int w = 0; w < 8; ++w) {
+      rmax = fmax(rmax, rmm[2 * w]);
+      rmin = fmin(rmin, rmm[2 * w + 1]);
+    }
+    // back substitution R y = z, one barrier per row
+    for (int i = mu - 1; i >= 0; --i) {
+      const double rii = Rm[i + (long long)i * ldr];
+      const double yi = rii != 0.0 ? z[i] / rii : 0.0;
+      __syncthreads();
+      for (int x = tid; x < i; x += LBLOCK) z[x] -= Rm[x + (long long)i * ldr] * yi;
+      if (tid == 0) z[i] = yi;
+      __syncthreads();
+    }
+  } else {
+    for (int x = tid; x < mu; x += LBLOCK) z[x] = 0.0;
+    __syncthreads();
+  }
   // H_hat = H_m + h_{m+1,m} y e_m^T (m_used x m_used, ld = mu)
-  const double hlast = (mu > 0 && !brk) ? H[(long long)(mu - 1) * (m + 1) + mu] : 0.0;
-  for (long long x = tid; x < (long long)mu * mu; x += DBLOCK) {
+  const double hlast = (mu > 0 && !brk) ? H[(long long)(mu - 1) * m1 + mu] : 0.0;
+  for (long long x = tid; x < (long long)mu * mu; x += LBLOCK) {
     const int r = (int)(x % mu), c = (int)(x / mu);
-    double v = H[(long long)c * (m + 1) + r];
-    if (c == mu - 1) v += hlast * yv[r];
+    double v = H[(long long)c * m1 + r];
+    if (c == mu - 1) v += hlast * z[r];
     Hh[x] = v;
   }
   if (tid == 0) {
@@ -266,7 +464,12 @@ __global__ void __launch_bounds__(DBLOCK) k_lsq(SolveDev d, DenseDev g) {
     info[INFO_FAIL] = 0.0;
   }
   double* yout = ws + g.oVec + 2 * (long long)m;
-  for (int x = tid; x < mu; x += DBLOCK) yout[x] = yv[x];
+  for (int x = tid; x < mu; x += LBLOCK) yout[x] = z[x];
+}
+
+size_t lsq_lds_bytes(int s, int m) {
+  const bool in_regs = s <= 64 * LRS && m + 1 <= 8 * LCS;
+  return (size_t)(64 * LRS + (m + 1) + (in_regs ? (size_t)m * m : 0)) * 8;
 }
 
 // ----------------------------------------------------------------- exp: Pade scaling and squaring
@@ -305,7 +508,13 @@ __global__ void __launch_bounds__(DBLOCK) k_fexp(SolveDev d, DenseDev g) {
   double cmax = 0.0;
   for (int cc = tid; cc < m; cc += DBLOCK) {
     double sacc = 0.0;
-    for (int r = 0; r < m; ++r) sacc += fabs(Hh[r + (long long)cc * m]);
+    for (int r0 = 0; r0 < m; r0 += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = r0 + u < m ? fabs(Hh[r0 + u + (long long)cc * m]) : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sacc += t[u];
+    }
     cmax = fmax(cmax, sacc);
   }
   for (int off = 32; off >= 1; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off, 64));
@@ -328,13 +537,18 @@ __global__ void __launch_bounds__(DBLOCK) k_fexp(SolveDev d, DenseDev g) {
 
   double cf[14];
   for (int j = 0; j <= 13; ++j) cf[j] = j <= qd ? pade_coef(qd, j) : 0.0;
+  extern __shared__ double lu_lds[];   // B staging of the small GEMM, later the LU factors
+  auto gemm = [&](const double* X, const double* Y, double* Z) {
+    if (m <= 128) bgemm_small(m, X, Y, Z, lu_lds);
+    else bgemm(m, X, Y, Z, As, Bs);
+  };
 
-  bgemm(m, A, A, A2, As, Bs);
-  if (qd >= 5) bgemm(m, A2, A2, A4, As, Bs);
-  if (qd >= 7) bgemm(m, A2, A4, A6, As, Bs);
+  gemm(A, A, A2);
+  if (qd >= 5) gemm(A2, A2, A4);
+  if (qd >= 7) gemm(A2, A4, A6);
   if (qd <= 9) {
     // T1 = sum_{odd j} c_j A^{j-1}, Vm = sum_{even j} c_j A^j ; A8 = A4*A4 when q = 9
-    if (qd == 9) bgemm(m, A4, A4, T2, As, Bs);
+    if (qd == 9) gemm(A4, A4, T2);
     for (long long x = tid; x < mm; x += DBLOCK) {
       const int r = (int)(x % m), cc = (int)(x / m);
       const double I = r == cc ? 1.0 : 0.0;
@@ -347,12 +561,12 @@ __global__ void __launch_bounds__(DBLOCK) k_fexp(SolveDev d, DenseDev g) {
       Vm[x] = v;
     }
     __syncthreads();
-    bgemm(m, A, T1, U, As, Bs);
+    gemm(A, T1, U);
   } else {
     for (long long x = tid; x < mm; x += DBLOCK)
       T1[x] = cf[13] * A6[x] + cf[11] * A4[x] + cf[9] * A2[x];
     __syncthreads();
-    bgemm(m, A6, T1, T2, As, Bs);
+    gemm(A6, T1, T2);
     for (long long x = tid; x < mm; x += DBLOCK) {
       const int r = (int)(x % m), cc = (int)(x / m);
       const double I = r == cc ? 1.0 : 0.0;
@@ -360,8 +574,8 @@ __global__ void __launch_bounds__(DBLOCK) k_fexp(SolveDev d, DenseDev g) {
       T1[x] = cf[12] * A6[x] + cf[10] * A4[x] + cf[8] * A2[x];
     }
     __syncthreads();
-    bgemm(m, A, T2, U, As, Bs);
-    bgemm(m, A6, T1, Vm, As, Bs);
+    gemm(A, T2, U);
+    gemm(A6, T1, Vm);
     for (long long x = tid; x < mm; x += DBLOCK) {
       const int r = (int)(x % m), cc = (int)(x / m);
       const double I = r == cc ? 1.0 : 0.0;
@@ -376,19 +590,30 @@ __global__ void __launch_bounds__(DBLOCK) k_fexp(SolveDev d, DenseDev g) {
     Vm[x] = v - u;
   }
   __syncthreads();
-  const int sing = blu(m, Vm, piv, sh, shi);
+  // LU of Q = V - U in LDS when it fits
+  double* LU = Vm;
+  if (m <= 128) {
+    for (long long x = tid; x < mm; x += DBLOCK) lu_lds[x] = Vm[x];
+    __syncthreads();
+    LU = lu_lds;
+  }
+  const int sing = blu(m, LU, piv, sh, shi);
   if (ssq == 0) {
     // X e_1 = Q^{-1} P e_1
-    for (int r = tid; r < m; r += DBLOCK) c[r] = T1[r];
+    double* xv = (m <= 128) ? nullptr : c;
+    __shared__ double xs_l[128];
+    if (m <= 128) xv = xs_l;
+    for (int r = tid; r < m; r += DBLOCK) xv[r] = T1[r];
     __syncthreads();
-    blu_solve(m, Vm, piv, c, 1);
+    blu_solve1(m, LU, piv, xv);
+    for (int r = tid; r < m; r += DBLOCK) c[r] = xv[r];
   } else {
-    blu_solve(m, Vm, piv, T1, m);   // T1 = X = r(A / 2^s)
+    blu_solve(m, LU, piv, T1, m);   // T1 = X = r(A / 2^s)
     // X^(2^s) e_1: repeated squaring of the matrix, then the first column
     double* Xa = T1;
     double* Xb = T2;
     for (int t = 0; t < ssq; ++t) {
-      bgemm(m, Xa, Xa, Xb, As, Bs);
+      gemm(Xa, Xa, Xb);
       double* tmp = Xa; Xa = Xb; Xb = tmp;
     }
     for (int r = tid; r < m; r += DBLOCK) c[r] = Xa[r];
@@ -753,9 +978,17 @@ __global__ void k_coef(SolveDev d, DenseDev g, double* cf) {
     cf[(long long)q * (m + 1) + j] = (j < mu && eta[j] > 0.0) ? beta * c[j] / eta[j] : 0.0;
 }
 
+hipError_t dense_set_attributes() {
+  hipError_t e = hipSuccess, r;
+  if ((r = hipFuncSetAttribute((const void*)k_lsq, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)) != hipSuccess) e = r;
+  if ((r = hipFuncSetAttribute((const void*)k_fexp, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)) != hipSuccess) e = r;
+  return e;
+}
+
 hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st) {
-  hipLaunchKernelGGL(k_lsq, dim3(d.nrhs), dim3(DBLOCK), 0, st, d, g);
-  if (g.fkind == 1) hipLaunchKernelGGL(k_fexp, dim3(d.nrhs), dim3(DBLOCK), 0, st, d, g);
+  hipLaunchKernelGGL(k_lsq, dim3(d.nrhs), dim3(LBLOCK), lsq_lds_bytes(d.s, d.m), st, d, g);
+  if (g.fkind == 1)
+    hipLaunchKernelGGL(k_fexp, dim3(d.nrhs), dim3(DBLOCK), d.m <= 128 ? (size_t)d.m * d.m * 8 : 0, st, d, g);
   else if (g.fkind == 2) hipLaunchKernelGGL(k_fpow, dim3(d.nrhs), dim3(64), 0, st, d, g);
   else hipLaunchKernelGGL(k_fpoly, dim3(d.nrhs), dim3(DBLOCK), 0, st, d, g);
   hipLaunchKernelGGL(k_coef, dim3(d.nrhs), dim3(256), 0, st, d, g, cf);

@@ -20,12 +20,15 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <set>
+#include <string>
+#include <tuple>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -43,6 +46,7 @@ hipError_t basis_combine(const SolveDev& d, int esize, const double* cf, int mma
 hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st);
 hipError_t zero_fill(void* p, size_t bytes, hipStream_t st);
 hipError_t srht_sample_rows(int* rows, long long npad, int s, unsigned long long key, hipStream_t st);
+hipError_t dense_set_attributes();
 }  // namespace fab
 
 using namespace fab;
@@ -144,13 +148,14 @@ struct Plan {
   fab_params p{};
   int esize = 4;
   // derived
-  int R = 0, logR = 0, ntiles = 0, nblk = 0, nred = 0;
+  int LT = 12, R = 0, logR = 0, ntiles = 0, nblk = 0, nred = 0;
+  long long ldv = 0;
   size_t lds_update = 0;
   size_t bytes = 0;
   // offsets in the workspace
   size_t oV, oW, oH, oEta, oWn, oCoef, oS, oPart, oNpart, oSk, oCnt, oStatus, oRows, oDense, oCf, oInfoHost;
   size_t dense_stride = 0;  // doubles per rhs
-  size_t oDW, oDH, oDM, oDVec, oDInfo;
+  size_t oDW, oDR, oDH, oDM, oDVec, oDInfo;
 };
 
 int ilog2(long long v) {
@@ -186,21 +191,26 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   if (f.kind == FAB_F_POLY) P.coef.assign(f.coef, f.coef + f.ncoef);
   P.p = p;
   P.esize = esize;
-  // tiles: R rows (power of two), R * nrhs <= TILE_ELEMS, aim for >= 512 tiles
-  int R = TILE_ELEMS / nrhs;
-  while (R > 64 && (n + R - 1) / R < 512) R >>= 1;
-  P.R = R;
-  P.logR = ilog2(R);
-  P.ntiles = (int)((n + R - 1) / R);
-  P.nblk = std::min(P.ntiles, 2048);
+  // tiles of 2^LT elements (rows x rhs): 2048 for large problems, 512 below
+  // 2^20 elements so that smaller problems still spread over many blocks
+  const long long nel = n * nrhs;
+  P.LT = nel >= (1LL << 20) ? 11 : 9;
+  const long long tile = 1LL << P.LT;
+  P.R = (int)(tile / nrhs);
+  P.logR = ilog2(P.R);
+  P.ntiles = (int)((nel + tile - 1) / tile);
+  P.nblk = std::min(P.ntiles, P.LT == 11 ? 512 : 2048);
   const long long snr = (long long)p.s * nrhs;
-  P.nred = (int)std::max<long long>(1, std::min<long long>((snr + 3) / 4, 64));
-  P.lds_update = (size_t)(snr + (p.sketch == FAB_SKETCH_SRHT ? (long long)R * nrhs : 0)) * 8;
+  const int waves_per_block = (int)(tile / 8 / 64) > 0 ? (int)(tile / 8 / 64) : 1;
+  P.nred = (int)std::max<long long>(1, std::min<long long>((snr + waves_per_block - 1) / waves_per_block, 128));
+  P.lds_update = (size_t)(snr + (p.sketch == FAB_SKETCH_SRHT ? tile + tile / 32 : 0)) * 8;
   if (P.lds_update > 160 * 1024) return FAB_EINVAL;
+  P.ldv = (nel + 63) & ~63LL;
   const int m = p.m, s = p.s;
   // dense workspace per rhs
   size_t o = 0;
   P.oDW = o; o += (size_t)s * (m + 1);
+  P.oDR = o; o += (size_t)(m + 1) * (m + 1);
   P.oDH = o; o += (size_t)m * m;
   P.oDM = o; o += (size_t)8 * m * m;
   P.oDVec = o; o += (size_t)8 * (m + 1);
@@ -209,7 +219,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   // workspace layout
   size_t w = 0;
   auto take = [&](size_t bytes) { size_t at = w; w = align256(w + bytes); return at; };
-  P.oV = take((size_t)(m + 1) * n * nrhs * esize);
+  P.oV = take((size_t)(m + 1) * P.ldv * esize);
   P.oW = A->op == OP_CSR ? take((size_t)n * nrhs * 8) : 0;
   P.oH = take((size_t)nrhs * (m + 1) * m * 8);
   P.oEta = take((size_t)nrhs * (m + 1) * 8);
@@ -221,7 +231,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   P.oSk = take((size_t)snr * P.nblk * 8);
   P.oCnt = take(256);
   P.oStatus = take((size_t)(4 + 2 * nrhs) * 4);
-  P.oRows = take((size_t)s * 4);
+  P.oRows = take(256);   // unused: sampled SRHT rows live in the context's cache
   P.oDense = take(P.dense_stride * nrhs * 8);
   P.oCf = take((size_t)nrhs * (m + 1) * 8);
   P.bytes = w;
@@ -274,7 +284,13 @@ struct fab_ctx_s {
   std::mutex mu;                 // arena + request table
   std::condition_variable cv;
   std::vector<hipStream_t> pool; // serving streams
+  std::vector<hipStream_t> pool_side;   // paired side streams (incremental QR)
+  std::vector<hipEvent_t> pool_ev;
   std::vector<int> pool_busy;
+  hipStream_t side = nullptr;    // side stream of the blocking path
+  hipEvent_t ev = nullptr;
+  // sampled SRHT rows per (padded length, s, seed), device arrays in the arena
+  std::map<std::tuple<long long, int, uint64_t>, int*> srht_cache;
   std::deque<uint64_t> queue;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
   uint64_t next_id = 1;
@@ -284,6 +300,19 @@ struct fab_ctx_s {
   double* host_info = nullptr;   // pinned staging for blocking solves
   std::mutex solve_mu;
   Prof prof;
+  // Replayable graphs of blocking solves, keyed by everything the launch
+  // sequence depends on (plan, pointers, profiling mask); small LRU.
+  struct GraphEntry {
+    std::string key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<std::pair<int, size_t>> marks;   // profiling event pairs recorded in the graph
+    size_t events_used = 0;
+    unsigned long long last_use = 0;
+  };
+  std::vector<GraphEntry> graphs;
+  unsigned long long graph_clock = 0;
+  bool use_graphs = true;
 };
 
 namespace {
@@ -301,10 +330,30 @@ struct Request {
   std::vector<fab_info> info;
 };
 
+// Sampled SRHT rows for (npad, s, seed): computed once on `st` (which the
+// caller then synchronises with) and cached in the arena.  Caller holds ctx->mu.
+const int* srht_rows_cached(fab_ctx ctx, long long npad, int s, uint64_t seed, hipStream_t st, int* rc) {
+  const auto key = std::make_tuple(npad, s, seed);
+  auto it = ctx->srht_cache.find(key);
+  if (it != ctx->srht_cache.end()) return it->second;
+  int* rows = (int*)ctx->arena.alloc((size_t)s * 4);
+  if (!rows) { *rc = FAB_ENOMEM; return nullptr; }
+  if (srht_sample_rows(rows, npad, s, sm64_out(seed, 2), st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    ctx->arena.release(rows);
+    *rc = FAB_EDEVICE;
+    return nullptr;
+  }
+  ctx->srht_cache[key] = rows;
+  return rows;
+}
+
 size_t host_info_doubles(int nrhs) { return (size_t)nrhs * NINFO + 4 + 2 * nrhs + 8; }
 
 // Enqueue the whole solve on `st`.  Host-visible results land in `hinfo` (pinned).
-int enqueue_solve(Plan& P, char* ws, hipStream_t st, double* hinfo, Prof* prof = nullptr) {
+// `side` runs the incremental sketched QR; `ev` orders it against `st`;
+// `rows` holds the sampled SRHT rows (cached per context).
+int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_t ev, const int* rows, double* hinfo,
+                  Prof* prof = nullptr) {
   const fab_params& p = P.p;
   fab_matrix A = P.A;
   const int m = p.m, s = p.s, nr = P.nrhs;
@@ -325,7 +374,7 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, double* hinfo, Prof* prof =
   d.col = A->col;
   d.val = A->val;
   d.V = ws + P.oV;
-  d.ldv = (long long)A->n * nr;
+  d.ldv = P.ldv;
   d.wbuf = A->op == OP_CSR ? (double*)(ws + P.oW) : nullptr;
   d.b = P.b;
   d.H = (double*)(ws + P.oH);
@@ -333,6 +382,7 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, double* hinfo, Prof* prof =
   d.wnorm = (double*)(ws + P.oWn);
   d.coef = (double*)(ws + P.oCoef);
   d.S = (double*)(ws + P.oS);
+  d.log_tile = P.LT;
   d.rows_per_tile = P.R;
   d.log_rows = P.logR;
   d.ntiles = P.ntiles;
@@ -344,7 +394,7 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, double* hinfo, Prof* prof =
   d.counter = (unsigned*)(ws + P.oCnt);
   d.status = (int*)(ws + P.oStatus);
   d.sketch = p.sketch == FAB_SKETCH_SRHT ? SK_SRHT : SK_SPARSE;
-  d.srht_rows = (const int*)(ws + P.oRows);
+  d.srht_rows = rows;
   if (d.sketch == SK_SRHT) {
     d.key_a = sm64_out(p.seed, 1);
     d.key_b = 0;
@@ -363,6 +413,7 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, double* hinfo, Prof* prof =
   g.stride = (long long)P.dense_stride;
   g.base = (double*)(ws + P.oDense);
   g.oW = (long long)P.oDW;
+  g.oR = (long long)P.oDR;
   g.oH = (long long)P.oDH;
   g.oM = (long long)P.oDM;
   g.oVec = (long long)P.oDVec;
@@ -379,9 +430,6 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, double* hinfo, Prof* prof =
   // zero the small state: H, eta, wnorm, coef, S, counter, status (contiguous from oH .. oRows)
   if ((e = zero_fill(ws + P.oH, P.oPart - P.oH, st)) != hipSuccess) return FAB_EDEVICE;
   if ((e = zero_fill(ws + P.oCnt, P.oRows - P.oCnt, st)) != hipSuccess) return FAB_EDEVICE;
-  if (d.sketch == SK_SRHT &&
-      srht_sample_rows((int*)(ws + P.oRows), 1LL << ilog2(A->n), s, sm64_out(p.seed, 2), st) != hipSuccess)
-    return FAB_EDEVICE;
   int open_cls = -1;
   auto B = [&](int cls) {
     if (prof && (prof->mask >> cls) & 1) { prof->begin(cls, st); open_cls = cls; }
@@ -484,7 +532,12 @@ void admit_locked(fab_ctx ctx) {
     r.stream_idx = si;
     ctx->pool_busy[si] = 1;
     hipSetDevice(ctx->device);
-    int rc = enqueue_solve(r.plan, ws, ctx->pool[si], r.host_info);
+    int rc = FAB_OK;
+    const int* rows = nullptr;
+    if (r.plan.p.sketch == FAB_SKETCH_SRHT)
+      rows = srht_rows_cached(ctx, 1LL << ilog2(r.plan.A->n), r.plan.p.s, r.plan.p.seed, ctx->pool[si], &rc);
+    if (rc == FAB_OK)
+      rc = enqueue_solve(r.plan, ws, ctx->pool[si], ctx->pool_side[si], ctx->pool_ev[si], rows, r.host_info);
     if (rc == FAB_OK && hipEventRecord(r.done_ev, ctx->pool[si]) != hipSuccess) rc = FAB_EDEVICE;
     if (rc != FAB_OK) {
       hipStreamSynchronize(ctx->pool[si]);
@@ -573,17 +626,33 @@ int fab_init(fab_ctx* out, int device, void* arena_dev_ptr, size_t arena_bytes, 
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return FAB_EDEVICE; }
     ctx->own_stream = true;
   }
+  (void)dense_set_attributes();
+  (void)hipGetLastError();
+  if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev, hipEventDisableTiming) != hipSuccess) {
+    delete ctx;
+    return FAB_EDEVICE;
+  }
   const int npool = 8;
   for (int i = 0; i < npool; ++i) {
-    hipStream_t s;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) { delete ctx; return FAB_EDEVICE; }
+    hipStream_t s, s2;
+    hipEvent_t e;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      delete ctx;
+      return FAB_EDEVICE;
+    }
     ctx->pool.push_back(s);
+    ctx->pool_side.push_back(s2);
+    ctx->pool_ev.push_back(e);
     ctx->pool_busy.push_back(0);
   }
   if (hipHostMalloc((void**)&ctx->host_info, host_info_doubles(32) * 8, hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return FAB_EDEVICE;
   }
+  if (const char* ev = std::getenv("FAB_NO_GRAPH")) ctx->use_graphs = ev[0] == '0';
   ctx->sched = std::thread(scheduler_main, ctx);
   *out = ctx;
   return FAB_OK;
@@ -672,12 +741,111 @@ int fab_create_matrix_csr(fab_ctx ctx, int64_t n, int64_t nnz, const int32_t* ro
 int fab_destroy_matrix(fab_matrix A) {
   if (!A) return FAB_EINVAL;
   fab_ctx ctx = A->ctx;
+  // lock order everywhere: solve_mu, then mu
+  std::lock_guard<std::mutex> slk(ctx->solve_mu);
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (A->refs.load() > 0) return FAB_EBUSY;
+  for (auto it = ctx->graphs.begin(); it != ctx->graphs.end();) {
+    fab_matrix gA;
+    std::memcpy(&gA, it->key.data(), sizeof(gA));
+    if (gA == A) {
+      hipGraphExecDestroy(it->exec);
+      hipGraphDestroy(it->graph);
+      it = ctx->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
   if (A->op == OP_CSR) ctx->arena.release(A->rowptr);
   ctx->matrices.erase(A);
   delete A;
   return FAB_OK;
+}
+
+static std::string graph_key(const Plan& P, const char* ws, const int* rows, const double* hinfo, int prof_mask,
+                             const fab_func& f) {
+  std::string k;
+  auto put = [&](const void* x, size_t n) { k.append((const char*)x, n); };
+  const void* ptrs[6] = {P.A, ws, P.b, P.out, rows, hinfo};
+  put(ptrs, sizeof(ptrs));
+  put(&P.nrhs, sizeof(int));
+  put(&P.esize, sizeof(int));
+  put(&P.p, sizeof(fab_params));
+  put(&prof_mask, sizeof(int));
+  put(&f.kind, sizeof(int));
+  put(&f.alpha, sizeof(double));
+  put(&f.sigma, sizeof(double));
+  put(&f.p, sizeof(double));
+  if (!P.coef.empty()) put(P.coef.data(), P.coef.size() * sizeof(double));
+  return k;
+}
+
+// Enqueue one blocking solve on ctx->stream: replay a cached graph of the
+// identical launch sequence when there is one, else capture (fork/join with
+// the side stream included) and instantiate it, falling back to direct
+// launches if capture is unavailable.
+static int launch_solve(fab_ctx ctx, Plan& P, char* ws, const int* rows, const fab_func& f) {
+  Prof* prof = ctx->prof.mask ? &ctx->prof : nullptr;
+  // event pairs recorded inside a replayed graph do not time the kernels, so
+  // timed (profiled) solves use direct launches of the same kernels
+  if (!ctx->use_graphs || prof) return enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, prof);
+  const std::string key = graph_key(P, ws, rows, ctx->host_info, ctx->prof.mask, f);
+  for (auto& g : ctx->graphs) {
+    if (g.key == key) {
+      g.last_use = ++ctx->graph_clock;
+      if (prof) {
+        prof->marks = g.marks;
+        prof->used = g.events_used;
+      }
+      return hipGraphLaunch(g.exec, ctx->stream) == hipSuccess ? FAB_OK : FAB_EDEVICE;
+    }
+  }
+  if (prof) {
+    // make sure every event the capture will use already exists
+    while (prof->pool.size() < (size_t)(4 * P.p.m + 16)) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) break;
+      prof->pool.push_back(e);
+    }
+  }
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->use_graphs = false;
+    return enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, prof);
+  }
+  int rc = enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, prof);
+  hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+  hipGraphExec_t exec = nullptr;
+  if (rc == FAB_OK && e == hipSuccess && graph) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (rc != FAB_OK || e != hipSuccess || !exec) {
+    (void)hipGetLastError();
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    ctx->use_graphs = false;
+    if (prof) { prof->marks.clear(); prof->used = 0; }
+    return enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, prof);
+  }
+  fab_ctx_s::GraphEntry ge;
+  ge.key = key;
+  ge.graph = graph;
+  ge.exec = exec;
+  if (prof) {
+    ge.marks = prof->marks;
+    ge.events_used = prof->used;
+  }
+  ge.last_use = ++ctx->graph_clock;
+  if (ctx->graphs.size() >= 8) {
+    auto lru = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                [](const fab_ctx_s::GraphEntry& a, const fab_ctx_s::GraphEntry& b) {
+                                  return a.last_use < b.last_use;
+                                });
+    hipGraphExecDestroy(lru->exec);
+    hipGraphDestroy(lru->graph);
+    ctx->graphs.erase(lru);
+  }
+  ctx->graphs.push_back(ge);
+  return hipGraphLaunch(exec, ctx->stream) == hipSuccess ? FAB_OK : FAB_EDEVICE;
 }
 
 static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, const fab_params* p,
@@ -704,7 +872,12 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
       ctx->cv.wait_for(lk, std::chrono::milliseconds(1));
     }
   }
-  rc = enqueue_solve(P, ws, ctx->stream, ctx->host_info, ctx->prof.mask ? &ctx->prof : nullptr);
+  const int* rows = nullptr;
+  if (P.p.sketch == FAB_SKETCH_SRHT) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    rows = srht_rows_cached(ctx, 1LL << ilog2(A->n), P.p.s, P.p.seed, ctx->stream, &rc);
+  }
+  if (rc == FAB_OK) rc = launch_solve(ctx, P, ws, rows, f);
   if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == FAB_OK) rc = FAB_EDEVICE;
   if (ctx->prof.mask) ctx->prof.harvest();
   std::vector<fab_info> fi;
@@ -860,8 +1033,23 @@ int fab_finalize(fab_ctx ctx) {
     hipStreamSynchronize(s);
     hipStreamDestroy(s);
   }
+  for (auto s : ctx->pool_side) {
+    hipStreamSynchronize(s);
+    hipStreamDestroy(s);
+  }
+  for (auto e : ctx->pool_ev) hipEventDestroy(e);
+  if (ctx->side) {
+    hipStreamSynchronize(ctx->side);
+    hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev) hipEventDestroy(ctx->ev);
   if (ctx->own_stream) hipStreamDestroy(ctx->stream);
   else hipStreamSynchronize(ctx->stream);
+  for (auto& g : ctx->graphs) {
+    hipGraphExecDestroy(g.exec);
+    hipGraphDestroy(g.graph);
+  }
+  ctx->graphs.clear();
   if (ctx->host_info) hipHostFree(ctx->host_info);
   for (auto ev : ctx->prof.pool) hipEventDestroy(ev);
   if (ctx->arena.owned) hipFree(ctx->arena.base);

@@ -272,3 +272,36 @@ def test_enomem_tiny_arena():
             c.solve(A, b, W.FuncSpec("exp", alpha=-1.0), make_params(50, 2, 120, "srht", 8, 1, "fp32"))
         assert e.value.code == ENOMEM
         A.destroy()
+
+
+# ------------------------------------------------------------------ graph replay equals direct launches
+def test_graph_replays_match_direct_launches():
+    import os
+
+    import torch
+
+    from paper_2212_12758_amd import Context, make_params
+
+    st = W.convdiff3d(40, 50.0)
+    b = _dev(W.rhs(st.n, 9))
+    f = W.FuncSpec("exp", alpha=-1e-3)
+    p = make_params(40, 4, 100, "srht", 8, 3, "fp32", "sketch")
+    os.environ["FAB_NO_GRAPH"] = "1"
+    try:
+        with Context(0, arena_bytes=1 << 30) as ce:
+            Ae = ce.matrix(st)
+            ref, _ = ce.solve(Ae, b, f, p)
+            ref = ref.cpu().numpy()
+            Ae.destroy()
+    finally:
+        del os.environ["FAB_NO_GRAPH"]
+    with Context(0, arena_bytes=1 << 30) as cg:
+        Ag = cg.matrix(st)
+        out = torch.empty_like(b)
+        for rep in range(5):
+            junk = torch.randn(1 << 20, device="cuda").sum()      # eager work between replays
+            torch.cuda.synchronize()
+            cg.solve(Ag, b, f, p, out)
+            assert np.array_equal(out.cpu().numpy(), ref), rep
+            assert float(junk) == float(junk)
+        Ag.destroy()
