@@ -52,10 +52,11 @@ struct SolveDev {
   int rows_per_tile, log_rows;   // R = rows per tile = 2^log_tile / nrhs
   int ntiles;            // ceil(n / R)
   int nblk;              // streaming blocks (tiles are strided over blocks)
-  int nred;              // sketch-reduction blocks appended to the dots kernel
+  int nred;              // sketch-reduction blocks (leading blocks of the update kernel)
   double* part;          // [nblk][nrhs][NSLOT]
   double* npart;         // [nblk][nrhs]
-  double* skpart;        // [s*nrhs][nblk]
+  double* skpart;        // two buffers [2][s*nrhs][nblk]: column c uses buffer c & 1
+  long long skstride;    // s*nrhs*nblk
   unsigned* counter;     // last-block ticket
   int* status;           // [0] m_used, [1] breakdown, [2] non-finite
   // sketch

@@ -233,6 +233,33 @@ __device__ inline void block_sums(const double* a, double* red /* [BLOCK/64][RC]
   __syncthreads();
 }
 
+// Reduce the per-block sketch partials of column `col` into S[:, col]: one
+// wave per (row, rhs), eight loads in flight per lane, fixed order.
+__device__ inline void reduce_sketch_column(const SolveDev& d, int col, int wid, int nwaves) {
+  const int lane = threadIdx.x & 63;
+  const int nr = d.nrhs;
+  const double* base = d.skpart + (long long)(col & 1) * d.skstride;
+  for (int rho = wid; rho < d.s * nr; rho += nwaves) {
+    double v = 0.0;
+    const double* p = base + (long long)rho * d.nblk;
+    for (int b0 = 0; b0 < d.nblk; b0 += 512) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int b = b0 + lane + 64 * u;
+        x[u] = b < d.nblk ? p[b] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += x[u];
+    }
+    v = wave_sum_all(v);
+    if (lane == 0) {
+      const int pr = rho >> d.lognrhs, qq = rho & (nr - 1);
+      d.S[(long long)qq * d.s * (d.m + 1) + (long long)col * d.s + pr] = v * d.sk_scale;
+    }
+  }
+}
+
 // element j of thread tid: accumulator slot and rhs
 template <int QC>
 __device__ inline int slot_of(int j) { return QC == 1 ? 0 : j; }
@@ -249,8 +276,6 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int n
   constexpr int RC = 10;
   if (d.status[0]) return;  // every rhs has broken down already
   __shared__ double red[NW * RC];
-  __shared__ double sums[NSLOT * 32 + 32];
-  __shared__ unsigned ticket;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nr = d.nrhs;
   const int j0 = i - d.k > 0 ? i - d.k : 0;
@@ -320,47 +345,38 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int n
     }
     __syncthreads();
     for (int x = tid; x < RS; x += BLOCK) d.part[(long long)blockIdx.x * RS + x] = pblk[x];
-  } else {
-    // reduce the sketch partials of column i-1: one wave per (row, rhs)
-    const int nwaves = (gridDim.x - nstream) * NW;
-    const int wid = (blockIdx.x - nstream) * NW + wv;
-    const int col = i - 1;
-    for (int rho = wid; rho < d.s * nr; rho += nwaves) {
-      double v = 0.0;
-      const double* p = d.skpart + (long long)rho * d.nblk;
-      for (int b0 = 0; b0 < d.nblk; b0 += 512) {
-        double x[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int b = b0 + lane + 64 * u;
-          x[u] = b < d.nblk ? p[b] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v += x[u];
-      }
-      v = wave_sum_all(v);
-      if (lane == 0) {
-        const int pr = rho >> d.lognrhs, qq = rho & (nr - 1);
-        d.S[(long long)qq * d.s * (d.m + 1) + (long long)col * d.s + pr] = v * d.sk_scale;
-      }
-    }
   }
+}
 
-  // ---- last block: scalar reduction in a fixed order.  The barrier makes
-  // every wave's partial stores complete in this XCD's L2; one thread then
-  // releases them device-wide and takes a ticket.  The last block acquires
-  // once before reading everybody's partials.
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    ticket = atomicAdd(d.counter, 1u);
+// ------------------------------------------------------------------ step scalars
+// Reduce, in a fixed order, the dot partials of pass 1 (part; when have_dots)
+// and the norm partials of u_{i-1} (npb), then form for every rhs: eta_{i-1},
+// the breakdown test, h_{j,i-1}, ||w_i|| and the update coefficients (into the
+// shared array cfl[q*NSLOT + .]).  Every block computes identical values; the
+// block with publish = true also stores the persistent state.
+template <int BLOCK>
+__device__ void step_scalars(const SolveDev& d, int i, bool have_dots, const double* __restrict__ npb, bool publish,
+                             double* red, double* sums, double* cfl) {
+  constexpr int RC = 10;
+  const int tid = threadIdx.x;
+  const int nr = d.nrhs;
+  const int m = d.m;
+  const int j0 = i - d.k > 0 ? i - d.k : 0;
+  const int nw = i - j0;
+  const int RS = NSLOT * nr;
+  // scalar state of the rhs handled by this thread, loaded with the partials
+  int brk_pre = 0;
+  double wprev_pre = 0.0;
+  double ej_pre[KMAX];
+#pragma unroll
+  for (int jj = 0; jj < KMAX; ++jj) ej_pre[jj] = 0.0;
+  if (tid < nr) {
+    brk_pre = *rhs_brk(d, tid);
+    wprev_pre = i >= 2 ? d.wnorm[(long long)tid * (m + 1) + i - 2] : 0.0;
+#pragma unroll
+    for (int jj = 0; jj < KMAX; ++jj)
+      if (jj < nw - 1) ej_pre[jj] = d.eta[(long long)tid * (m + 1) + j0 + jj];
   }
-  __syncthreads();
-  if (ticket != gridDim.x - 1) return;
-  if (tid == 0) __threadfence();
-  __syncthreads();
-
-  // rows 0..RS-1: dot partials (when nstream > 0); rows RS..RS+nr-1: norm partials of u_{i-1}
   const int RT = RS + nr;
   for (int r0 = 0; r0 < RT; r0 += RC) {
     double a[RC];
@@ -371,9 +387,9 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int n
       for (int c = 0; c < RC; ++c) {
         const int rr = r0 + c;
         if (rr < RS) {
-          if (b < nstream) a[c] += d.part[(long long)b * RS + rr];
+          if (have_dots) a[c] += d.part[(long long)b * RS + rr];
         } else if (rr < RT) {
-          a[c] += d.npart[(long long)b * nr + (rr - RS)];
+          a[c] += npb[(long long)b * nr + (rr - RS)];
         }
       }
     }
@@ -383,26 +399,22 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int n
   }
   __syncthreads();
 
-  const int m = d.m;
   for (int qq = tid; qq < nr; qq += BLOCK) {
     double* eta = d.eta + (long long)qq * (m + 1);
     double* H = d.H + (long long)qq * (m + 1) * m;
     double* wn = d.wnorm + (long long)qq * (m + 1);
-    double* cf = d.coef + (long long)qq * NSLOT;
-    int* mused = rhs_mused(d, qq);
-    int* brk = rhs_brk(d, qq);
-    // all loads first (one latency), then the scalar logic
-    const int brk0 = *brk;
-    const double wprev = i >= 2 ? wn[i - 2] : 0.0;
+    double* cf = cfl + qq * NSLOT;
+    const int brk0 = brk_pre;
+    const double wprev = wprev_pre;
     const double eta_prev = sqrt(sums[RS + qq]);  // ||u_{i-1}||, the newest window member
     double ej[KMAX];
 #pragma unroll
-    for (int jj = 0; jj < KMAX; ++jj) ej[jj] = (jj < nw - 1) ? eta[j0 + jj] : eta_prev;
-    eta[i - 1] = eta_prev;
-    int b = brk0, mu = -1;
+    for (int jj = 0; jj < KMAX; ++jj) ej[jj] = (jj < nw - 1) ? ej_pre[jj] : eta_prev;
+    int b = brk0, mu = -1, nonfinite = 0;
+    double hsub = -1.0;   // value for H[i-1, i-2] when >= 0
     if (!b) {
       if (!isfinite(eta_prev)) {
-        d.status[1] = 1;
+        nonfinite = 1;
         b = 1;
         mu = i - 1;
       } else if (i == 1) {
@@ -410,38 +422,58 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int n
       } else if (eta_prev <= 100.0 * d.unit_round * wprev) {
         b = 1;  // invariant subspace of dimension i-1
         mu = i - 1;
-        H[(long long)(i - 2) * (m + 1) + (i - 1)] = 0.0;
+        hsub = 0.0;
       } else {
-        H[(long long)(i - 2) * (m + 1) + (i - 1)] = eta_prev;
+        hsub = eta_prev;
       }
     }
-    if (b || nstream == 0) {
+    if (b || !have_dots) {
       for (int sl = 0; sl < NSLOT; ++sl) cf[sl] = 0.0;
       if (!b) mu = m;
     } else {
-      wn[i - 1] = sqrt(sums[KMAX * nr + qq]) / eta_prev;
       cf[0] = 1.0 / eta_prev;
 #pragma unroll
       for (int jj = 0; jj < KMAX; ++jj) {
         if (jj < nw) {
           const double h = sums[jj * nr + qq] / (ej[jj] * eta_prev);
-          H[(long long)(i - 1) * (m + 1) + (j0 + jj)] = h;
           cf[1 + jj] = h / ej[jj];
+          if (publish) H[(long long)(i - 1) * (m + 1) + (j0 + jj)] = h;
         } else {
           cf[1 + jj] = 0.0;
         }
       }
     }
-    if (b != brk0) *brk = b;
-    if (mu >= 0) *mused = mu;
+    if (publish) {
+      eta[i - 1] = eta_prev;
+      if (hsub >= 0.0) H[(long long)(i - 2) * (m + 1) + (i - 1)] = hsub;
+      if (!b && have_dots) wn[i - 1] = sqrt(sums[KMAX * nr + qq]) / eta_prev;
+      if (b != brk0) *rhs_brk(d, qq) = b;
+      if (mu >= 0) *rhs_mused(d, qq) = mu;
+      if (nonfinite) d.status[1] = 1;
+    }
+    cfl[32 * NSLOT + qq] = (double)b;   // breakdown flags after this step
   }
   __syncthreads();
-  if (tid == 0) {
+  if (publish && tid == 0) {
     int all = 1;
-    for (int qq = 0; qq < nr; ++qq) all &= *rhs_brk(d, qq);
+    for (int qq = 0; qq < nr; ++qq) all &= (cfl[32 * NSLOT + qq] != 0.0);
     d.status[0] = all;
-    *d.counter = 0u;
   }
+}
+
+// Finishing pass after the last update: eta_m, h_{m+1,m}, breakdown test of
+// u_m (block 0) and the sketch of the last column (all blocks).
+template <int LT>
+__global__ void __launch_bounds__(1 << (LT - 3)) k_finish(SolveDev d) {
+  constexpr int BLOCK = 1 << (LT - 3);
+  constexpr int NW = BLOCK / 64;
+  if (d.status[0]) return;
+  __shared__ double red[NW * 10];
+  __shared__ double sums[NSLOT * 32 + 32];
+  __shared__ double cfl[33 * NSLOT + 32];
+  const int i = d.m + 1;
+  reduce_sketch_column(d, i - 1, blockIdx.x * NW + (threadIdx.x >> 6), gridDim.x * NW);
+  if (blockIdx.x == 0) step_scalars<BLOCK>(d, i, false, d.npart + (long long)(d.m & 1) * d.nblk * d.nrhs, true, red, sums, cfl);
 }
 
 // ------------------------------------------------------------------ Walsh-Hadamard transform of a tile
@@ -524,6 +556,20 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   if (d.status[0]) return;
   extern __shared__ double lds[];
   __shared__ double nred[NW][32];
+  // leading blocks reduce the sketch partials of column i-1 (written by the
+  // previous update pass into the other buffer)
+  const int nlead = START ? 0 : d.nred;
+  if ((int)blockIdx.x < nlead) {
+    reduce_sketch_column(d, i - 1, blockIdx.x * NW + (threadIdx.x >> 6), nlead * NW);
+    return;
+  }
+  const int blk = blockIdx.x - nlead;
+  __shared__ double sred[NW * 10];
+  __shared__ double ssums[NSLOT * 32 + 32];
+  __shared__ double cfl[33 * NSLOT + 32];
+  if (!START) {
+    step_scalars<BLOCK>(d, i, true, d.npart + (long long)((i - 1) & 1) * d.nblk * d.nrhs, blk == 0, sred, ssums, cfl);
+  }
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nr = d.nrhs;
   const long long nel = (long long)d.n * nr;
@@ -538,7 +584,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
 #pragma unroll
   for (int c = 0; c < QC; ++c) {
     const int q = rhs_of<QC>(tid, c, nr);
-    const double* cf = d.coef + (long long)q * NSLOT;
+    const double* cf = cfl + q * NSLOT;
     cw[c] = START ? 1.0 : cf[0];
 #pragma unroll
     for (int jj = 0; jj < KT; ++jj) cj[jj][c] = (START || jj >= nw) ? 0.0 : cf[1 + jj];
@@ -547,13 +593,16 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   double* X = lds;                                                   // SRHT tile (padded)
   double* acc = lds + (SK == SK_SRHT ? padx(TILE) : 0);              // sketch accumulator [s][nr]
   const int snr = d.s * nr;
+  int* rows_l = (int*)(acc + snr);                                    // sampled SRHT rows
   for (int x = tid; x < snr; x += BLOCK) acc[x] = 0.0;
+  if (SK == SK_SRHT)
+    for (int x = tid; x < d.s; x += BLOCK) rows_l[x] = d.srht_rows[x];
   __syncthreads();
 
   double nrm[QC];
 #pragma unroll
   for (int c = 0; c < QC; ++c) nrm[c] = 0.0;
-  for (int t = blockIdx.x; t < d.ntiles; t += d.nblk) {
+  for (int t = blk; t < d.ntiles; t += d.nblk) {
     const long long e = ((long long)t << LT) + (long long)tid * EPT;
     double uu[EPT];
 #pragma unroll
@@ -623,7 +672,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
       // sampled rows r = (r_hi, r_lo): contribution (-1)^popcount(r_hi & t) * X[r_lo]
       for (int pq = tid; pq < snr; pq += BLOCK) {
         const int p = pq >> d.lognrhs, qq = pq & (nr - 1);
-        const int rr = d.srht_rows[p];
+        const int rr = rows_l[p];
         const int par = __popc((unsigned)(rr >> d.log_rows) & (unsigned)t) & 1;
         const double v = X[padx(((rr & (d.rows_per_tile - 1)) << d.lognrhs) + qq)];
         acc[pq] += par ? -v : v;
@@ -632,7 +681,8 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
     }
   }
   __syncthreads();
-  for (int pq = tid; pq < snr; pq += BLOCK) d.skpart[(long long)pq * d.nblk + blockIdx.x] = acc[pq];
+  double* skp = d.skpart + (long long)(i & 1) * d.skstride;
+  for (int pq = tid; pq < snr; pq += BLOCK) skp[(long long)pq * d.nblk + blk] = acc[pq];
 
   // norm partials per rhs
   for (int q = 0; q < nr; ++q) {
@@ -644,10 +694,11 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
     if (lane == 0) nred[wv][q] = a;
   }
   __syncthreads();
+  double* npw = d.npart + (long long)(i & 1) * d.nblk * nr;
   for (int q = tid; q < nr; q += BLOCK) {
     double t = 0.0;
     for (int w = 0; w < NW; ++w) t += nred[w][q];
-    d.npart[(long long)blockIdx.x * nr + q] = t;
+    npw[(long long)blk * nr + q] = t;
   }
 }
 
@@ -702,7 +753,7 @@ static hipError_t launch_dots_q(const SolveDev& d, int i, hipStream_t st, int ns
 
 template <typename T, bool START, int LT, int QC, int KT>
 static hipError_t launch_update_k(const SolveDev& d, int i, hipStream_t st, size_t lds) {
-  const dim3 g(d.nblk), b(1 << (LT - 3));
+  const dim3 g(d.nblk + (START ? 0 : d.nred)), b(1 << (LT - 3));
   if (d.op == OP_STENCIL || START) {
     if (d.sketch == SK_SRHT) hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SRHT, START, LT, QC, KT>), g, b, lds, st, d, i);
     else hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SPARSE, START, LT, QC, KT>), g, b, lds, st, d, i);
@@ -776,13 +827,16 @@ hipError_t basis_start(const SolveDev& d, int esize, hipStream_t st, size_t lds)
   return esize == 4 ? update_t<float, true>(d, 0, st, lds) : update_t<double, true>(d, 0, st, lds);
 }
 hipError_t basis_dots(const SolveDev& d, int esize, int i, hipStream_t st) {
-  return esize == 4 ? dots_t<float>(d, i, st, d.nblk, d.nblk + d.nred) : dots_t<double>(d, i, st, d.nblk, d.nblk + d.nred);
+  return esize == 4 ? dots_t<float>(d, i, st, d.nblk, d.nblk) : dots_t<double>(d, i, st, d.nblk, d.nblk);
 }
 hipError_t basis_update(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds) {
   return esize == 4 ? update_t<float, false>(d, i, st, lds) : update_t<double, false>(d, i, st, lds);
 }
 hipError_t basis_finish(const SolveDev& d, int esize, hipStream_t st) {
-  return esize == 4 ? dots_t<float>(d, d.m + 1, st, 0, d.nred) : dots_t<double>(d, d.m + 1, st, 0, d.nred);
+  (void)esize;
+  if (d.log_tile == 11) hipLaunchKernelGGL(k_finish<11>, dim3(d.nred), dim3(256), 0, st, d);
+  else hipLaunchKernelGGL(k_finish<9>, dim3(d.nred), dim3(64), 0, st, d);
+  return hipGetLastError();
 }
 hipError_t basis_combine(const SolveDev& d, int esize, const double* cf, int mmax, double* out, hipStream_t st) {
   const long long nel = (long long)d.n * d.nrhs;

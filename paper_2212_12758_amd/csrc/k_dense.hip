@@ -5,7 +5,7 @@
 //           Theta v_{m+1} (sketch-and-solve of the least-squares problem
 //           eq. (7), Remark 3) by back substitution; the compression
 //           H_hat = H_m + h_{m+1,m} y e_m^T (eq. (6)).  The matrix is held in
-//           registers across the workgroup when s <= 448 and m + 1 <= 112,
+//           registers across the workgroup when s <= 448 and m + 1 <= 104,
 //           else it is factorised in global memory.
 //  k_fexp   exp(alpha H_hat) e_1 by scaling and squaring with a diagonal Pade
 //           approximant (Higham, SIAM J. Matrix Anal. Appl. 26 (2005)), the
@@ -24,6 +24,7 @@
 namespace fab {
 
 constexpr int DBLOCK = 256;
+constexpr int LDS_M = 112;   // dense stages keep m x m operands in LDS up to this size
 constexpr int MAXM = 512;
 enum { INFO_KAPPA = 0, INFO_HLAST = 1, INFO_BETA = 2, INFO_FAIL = 3, INFO_NSQ = 4, INFO_SCHUR_IT = 5, INFO_NRM = 6 };
 
@@ -102,7 +103,7 @@ __device__ void bgemm(int m, const double* __restrict__ A, const double* __restr
   __syncthreads();
 }
 
-// C = A * B for m <= 128 with B staged in LDS (Bl: m*m doubles) and A read
+// C = A * B for m <= LDS_M with B staged in LDS (Bl: m*m doubles) and A read
 // through the cache; thread (ti, tj) of a 16 x 16 grid owns an 8 x 8 block of C.
 __device__ void bgemm_small(int m, const double* __restrict__ A, const double* __restrict__ B,
                             double* __restrict__ C, double* Bl) {
@@ -139,53 +140,73 @@ __device__ void bgemm_small(int m, const double* __restrict__ A, const double* _
 }
 
 // ----------------------------------------------------------------- LU with partial pivoting
-// In place on A (m x m); piv[j] = row swapped with j.  Returns 1 if singular.
-__device__ int blu(int m, double* A, int* piv, double* shv, int* shi) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  int singular = 0;
+// In place on A (m x m, ld m; LDS or global); piv[j] = row swapped with j.
+// Two barriers per pivot: wave 0 finds the pivot, snapshots the pivot row and
+// the old row j (tmp: 2m doubles) and forms the multipliers (lcol: m doubles);
+// then every thread applies the row swap and the rank-1 update together.
+// Returns 1 if a zero pivot occurred.
+__device__ int blu(int m, double* A, int* piv, double* tmp, double* lcol) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nth = blockDim.x;
+  double* prow = tmp;        // pivot row (columns j..m-1)
+  double* jrow = tmp + m;    // old row j
+  __shared__ int sp;
+  __shared__ int sing_sh;
+  if (tid == 0) sing_sh = 0;
   for (int j = 0; j < m; ++j) {
-    double best = -1.0;
-    int bi = j;
-    for (int r = j + tid; r < m; r += DBLOCK) {
-      const double v = fabs(A[r + (long long)j * m]);
-      if (v > best) { best = v; bi = r; }
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = j;
+      for (int r = j + lane; r < m; r += 64) {
+        const double v = fabs(A[r + (long long)j * m]);
+        if (v > best) { best = v; bi = r; }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      const int p = bi;
+      for (int c = j + lane; c < m; c += 64) {
+        prow[c] = A[p + (long long)c * m];
+        jrow[c] = A[j + (long long)c * m];
+      }
+      const double pv = A[p + (long long)j * m];
+      for (int r = j + 1 + lane; r < m; r += 64) {
+        const double ar = (r == p) ? A[j + (long long)j * m] : A[r + (long long)j * m];
+        lcol[r] = pv != 0.0 ? ar / pv : 0.0;
+      }
+      if (lane == 0) {
+        piv[j] = p;
+        sp = p;
+        if (pv == 0.0) sing_sh = 1;
+      }
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    if (lane == 0) { shv[wv] = best; shi[wv] = bi; }
     __syncthreads();
-    if (tid == 0) {
-      double b0 = shv[0];
-      int i0 = shi[0];
-      for (int w = 1; w < DBLOCK / 64; ++w)
-        if (shv[w] > b0 || (shv[w] == b0 && shi[w] < i0)) { b0 = shv[w]; i0 = shi[w]; }
-      shi[4] = i0;
-      piv[j] = i0;
-    }
-    __syncthreads();
-    const int p = shi[4];
-    if (p != j)
-      for (int c = tid; c < m; c += DBLOCK) {
+    const int p = sp;
+    if (p != j)   // the row swap also moves the multipliers already stored left of column j
+      for (int c = tid; c < j; c += nth) {
         const double t = A[j + (long long)c * m];
         A[j + (long long)c * m] = A[p + (long long)c * m];
         A[p + (long long)c * m] = t;
       }
-    __syncthreads();
-    const double pv = A[j + (long long)j * m];
-    if (pv == 0.0) { singular = 1; continue; }
-    for (int r = j + 1 + tid; r < m; r += DBLOCK) A[r + (long long)j * m] /= pv;
-    __syncthreads();
-    const int w = m - j - 1;
-    for (int x = tid; x < w * w; x += DBLOCK) {
-      const int r = j + 1 + x % w, c = j + 1 + x / w;
-      A[r + (long long)c * m] -= A[r + (long long)j * m] * A[j + (long long)c * m];
+    const int w = m - j;   // columns j..m-1, rows j..m-1
+    for (int x = tid; x < w * w; x += nth) {
+      const int r = j + x % w, c = j + x / w;
+      double v;
+      if (r == j) {
+        v = prow[c];                                    // new pivot row
+      } else if (c == j) {
+        v = lcol[r];                                    // multiplier
+      } else {
+        const double a = (r == p) ? jrow[c] : A[r + (long long)c * m];
+        v = a - lcol[r] * prow[c];
+      }
+      A[r + (long long)c * m] = v;
     }
     __syncthreads();
   }
-  return singular;
+  return sing_sh;
 }
 
 // Solve (LU) x = b in place for one right-hand side, all threads sharing the
@@ -239,7 +260,7 @@ __device__ inline int* st_brk(const SolveDev& d, int q) { return d.status + 5 + 
 // ----------------------------------------------------------------- sketched QR and least squares
 constexpr int LBLOCK = 512;          // 8 waves
 constexpr int LRS = 7;               // row slots per lane: rows lane + 64*rs  (s <= 448)
-constexpr int LCS = 14;              // column slots per wave: cols wave + 8*cs (m + 1 <= 112)
+constexpr int LCS = 13;              // column slots per wave: cols wave + 8*cs (m + 1 <= 104)
 
 // Householder QR of W (s x ncol, column-major, normalised sketch columns) held
 // in registers; on exit R (ncol-1 x ncol-1 upper, ld mu) and z = first mu
@@ -292,38 +313,56 @@ __device__ void qr_registers(const double* __restrict__ S, const double* __restr
 #pragma unroll
           for (int rs = 0; rs < LRS; ++rs) {
             const int r = lane + 64 * rs;
-            if (r < s) vsh[r] = r < j ? 0.0 : (r == j ? 1.0 : a[cs][rs] * scal);
+            if (r < s) vsh[(j & 1) * (64 * LRS) + r] = r < j ? 0.0 : (r == j ? 1.0 : a[cs][rs] * scal);
             if (r == j) a[cs][rs] = beta;
             else if (r > j) a[cs][rs] = 0.0;
           }
         }
       }
-      if (lane == 0) *tau_sh = tau;
+      if (lane == 0) tau_sh[j & 1] = tau;
       rmax = fmax(rmax, fabs(beta));
       rmin = fmin(rmin, fabs(beta));
     }
+    // one barrier per step: the reflector buffers alternate between steps
     __syncthreads();
-    const double tau = *tau_sh;
+    const double tau = tau_sh[j & 1];
+    const double* vj = vsh + (j & 1) * (64 * LRS);
     double vr[LRS];
 #pragma unroll
     for (int rs = 0; rs < LRS; ++rs) {
       const int r = lane + 64 * rs;
-      vr[rs] = r < s ? vsh[r] : 0.0;
+      vr[rs] = r < s ? vj[r] : 0.0;
     }
+    // column dots of a group of slots first, then one interleaved butterfly
+    // for the whole group (independent shuffle chains overlap)
+    constexpr int G = (LCS + 1) / 2;
 #pragma unroll
-    for (int cs = 0; cs < LCS; ++cs) {
-      const int c = wv + 8 * cs;
-      if (c > j && c < ncol) {   // uniform per wave
-        double dt = 0.0;
+    for (int g0 = 0; g0 < LCS; g0 += G) {
+      double dt[G];
 #pragma unroll
-        for (int rs = 0; rs < LRS; ++rs) dt += vr[rs] * a[cs][rs];
-        dt = tau * wsum(dt);
+      for (int u = 0; u < G; ++u) {
+        dt[u] = 0.0;
+        if (g0 + u < LCS) {
 #pragma unroll
-        for (int rs = 0; rs < LRS; ++rs) a[cs][rs] -= dt * vr[rs];
+          for (int rs = 0; rs < LRS; ++rs) dt[u] += vr[rs] * a[(g0 + u) < LCS ? g0 + u : 0][rs];
+        }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int u = 0; u < G; ++u) dt[u] += __shfl_xor(dt[u], off, 64);
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int c = wv + 8 * (g0 + u);
+        if (g0 + u < LCS && c > j && c < ncol) {
+          const double f = tau * dt[u];
+#pragma unroll
+          for (int rs = 0; rs < LRS; ++rs) a[(g0 + u) < LCS ? g0 + u : 0][rs] -= f * vr[rs];
+        }
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   // R and z to LDS: entry (r, c) with r <= c (r < mu)
 #pragma unroll
   for (int cs = 0; cs < LCS; ++cs) {
@@ -405,7 +444,7 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
   extern __shared__ double lsh[];
   __shared__ double sh[16];
   __shared__ double rmm[16];
-  __shared__ double tau_sh;
+  __shared__ double tau_sh[2];
   const int m = d.m, m1 = d.m + 1, s = d.s;
   double* ws = g.base + (long long)q * g.stride;
   double* Hh = ws + g.oH;
@@ -417,15 +456,15 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
   const double* S = d.S + (long long)q * s * m1;
   const bool do_ls = (!brk) && mu > 0 && g.ls_mode != 2;
   const bool in_regs = s <= 64 * LRS && mu + 1 <= 8 * LCS;
-  double* vsh = lsh;
-  double* z = vsh + 64 * LRS;
+  double* vsh = lsh;                    // two reflector buffers
+  double* z = vsh + 2 * 64 * LRS;
   double* Rl = z + m1;
   const double* Rm = Rl;
   int ldr = mu;
   double rmax = 0.0, rmin = 1e308;
   if (do_ls) {
     if (in_regs) {
-      qr_registers(S, eta, s, mu + 1, vsh, Rl, z, &tau_sh, rmm);
+      qr_registers(S, eta, s, mu + 1, vsh, Rl, z, tau_sh, rmm);
     } else {
       double* W = ws + g.oW;
       qr_global(S, eta, s, mu + 1, W, z, sh, rmm);
@@ -469,7 +508,7 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
 
 size_t lsq_lds_bytes(int s, int m) {
   const bool in_regs = s <= 64 * LRS && m + 1 <= 8 * LCS;
-  return (size_t)(64 * LRS + (m + 1) + (in_regs ? (size_t)m * m : 0)) * 8;
+  return (size_t)(2 * 64 * LRS + (m + 1) + (in_regs ? (size_t)m * m : 0)) * 8;
 }
 
 // ----------------------------------------------------------------- exp: Pade scaling and squaring
@@ -539,7 +578,7 @@ __global__ void __launch_bounds__(DBLOCK) k_fexp(SolveDev d, DenseDev g) {
   for (int j = 0; j <= 13; ++j) cf[j] = j <= qd ? pade_coef(qd, j) : 0.0;
   extern __shared__ double lu_lds[];   // B staging of the small GEMM, later the LU factors
   auto gemm = [&](const double* X, const double* Y, double* Z) {
-    if (m <= 128) bgemm_small(m, X, Y, Z, lu_lds);
+    if (m <= LDS_M) bgemm_small(m, X, Y, Z, lu_lds);
     else bgemm(m, X, Y, Z, As, Bs);
   };
 
@@ -592,17 +631,19 @@ __global__ void __launch_bounds__(DBLOCK) k_fexp(SolveDev d, DenseDev g) {
   __syncthreads();
   // LU of Q = V - U in LDS when it fits
   double* LU = Vm;
-  if (m <= 128) {
+  if (m <= LDS_M) {
     for (long long x = tid; x < mm; x += DBLOCK) lu_lds[x] = Vm[x];
     __syncthreads();
     LU = lu_lds;
   }
-  const int sing = blu(m, LU, piv, sh, shi);
+  __shared__ double lu_tmp[2 * MAXM];
+  __shared__ double lu_l[MAXM];
+  const int sing = blu(m, LU, piv, lu_tmp, lu_l);
   if (ssq == 0) {
     // X e_1 = Q^{-1} P e_1
-    double* xv = (m <= 128) ? nullptr : c;
-    __shared__ double xs_l[128];
-    if (m <= 128) xv = xs_l;
+    double* xv = (m <= LDS_M) ? nullptr : c;
+    __shared__ double xs_l[LDS_M];
+    if (m <= LDS_M) xv = xs_l;
     for (int r = tid; r < m; r += DBLOCK) xv[r] = T1[r];
     __syncthreads();
     blu_solve1(m, LU, piv, xv);
@@ -988,7 +1029,7 @@ hipError_t dense_set_attributes() {
 hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st) {
   hipLaunchKernelGGL(k_lsq, dim3(d.nrhs), dim3(LBLOCK), lsq_lds_bytes(d.s, d.m), st, d, g);
   if (g.fkind == 1)
-    hipLaunchKernelGGL(k_fexp, dim3(d.nrhs), dim3(DBLOCK), d.m <= 128 ? (size_t)d.m * d.m * 8 : 0, st, d, g);
+    hipLaunchKernelGGL(k_fexp, dim3(d.nrhs), dim3(DBLOCK), d.m <= LDS_M ? (size_t)d.m * d.m * 8 : 0, st, d, g);
   else if (g.fkind == 2) hipLaunchKernelGGL(k_fpow, dim3(d.nrhs), dim3(64), 0, st, d, g);
   else hipLaunchKernelGGL(k_fpoly, dim3(d.nrhs), dim3(DBLOCK), 0, st, d, g);
   hipLaunchKernelGGL(k_coef, dim3(d.nrhs), dim3(256), 0, st, d, g, cf);

@@ -203,7 +203,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   const long long snr = (long long)p.s * nrhs;
   const int waves_per_block = (int)(tile / 8 / 64) > 0 ? (int)(tile / 8 / 64) : 1;
   P.nred = (int)std::max<long long>(1, std::min<long long>((snr + waves_per_block - 1) / waves_per_block, 128));
-  P.lds_update = (size_t)(snr + (p.sketch == FAB_SKETCH_SRHT ? tile + tile / 32 : 0)) * 8;
+  P.lds_update = (size_t)(snr + (p.sketch == FAB_SKETCH_SRHT ? tile + tile / 32 : 0)) * 8 + (size_t)p.s * 4;
   if (P.lds_update > 160 * 1024) return FAB_EINVAL;
   P.ldv = (nel + 63) & ~63LL;
   const int m = p.m, s = p.s;
@@ -227,8 +227,8 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   P.oCoef = take((size_t)nrhs * NSLOT * 8);
   P.oS = take((size_t)nrhs * s * (m + 1) * 8);
   P.oPart = take((size_t)P.nblk * nrhs * NSLOT * 8);
-  P.oNpart = take((size_t)P.nblk * nrhs * 8);
-  P.oSk = take((size_t)snr * P.nblk * 8);
+  P.oNpart = take((size_t)2 * P.nblk * nrhs * 8);
+  P.oSk = take((size_t)2 * snr * P.nblk * 8);
   P.oCnt = take(256);
   P.oStatus = take((size_t)(4 + 2 * nrhs) * 4);
   P.oRows = take(256);   // unused: sampled SRHT rows live in the context's cache
@@ -391,6 +391,7 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
   d.part = (double*)(ws + P.oPart);
   d.npart = (double*)(ws + P.oNpart);
   d.skpart = (double*)(ws + P.oSk);
+  d.skstride = (long long)p.s * nr * P.nblk;
   d.counter = (unsigned*)(ws + P.oCnt);
   d.status = (int*)(ws + P.oStatus);
   d.sketch = p.sketch == FAB_SKETCH_SRHT ? SK_SRHT : SK_SPARSE;

@@ -305,3 +305,19 @@ def test_graph_replays_match_direct_launches():
             assert np.array_equal(out.cpu().numpy(), ref), rep
             assert float(junk) == float(junk)
         Ag.destroy()
+
+
+# ------------------------------------------------------------------ dense stages beyond the LDS/register sizes
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_large_m_global_memory_dense_path(ctx, prec, tol):
+    st = W.laplacian2d(72)
+    b = W.rhs(st.n, 13)
+    Aor = operators.as_matrix(st)
+    A = ctx.matrix(st)
+    for f in (W.FuncSpec("exp", alpha=-0.5), W.FuncSpec("exp", alpha=-6.0)):     # no squaring / squaring
+        w = W.Workload("big_m", st, 13, 1, f, m=120, k=2, s=250, sketch="sparse_sign", sketch_seed=8)
+        print(f"case lap2d 72^2 m=120 {prec} {f.alpha}", flush=True)
+        out, info = _solve(ctx, w, A, b, prec)
+        assert info[0]["m_used"] == 120
+        assert krylov.relerr(out, krylov.fm(Aor, b, f, w.m)) < tol
+    A.destroy()
