@@ -21,7 +21,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libfab.so")
 ARCH = os.environ.get("FAB_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["k_basis.hip", "k_dense.hip", "runtime.cpp"]
+SOURCES = ["k_basis_f32_stencil.hip", "k_basis_f32_csr.hip", "k_basis_f64_stencil.hip", "k_basis_f64_csr.hip",
+           "k_basis.hip", "k_dense.hip", "k_expm.hip", "runtime.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -48,7 +49,7 @@ def _compile(src: str, objdir: str) -> str:
     return obj
 
 
-def build(jobs: int = 4, verbose: bool = False) -> str:
+def build(jobs: int = 8, verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
@@ -65,5 +66,5 @@ def build(jobs: int = 4, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    jobs = int(sys.argv[sys.argv.index("--jobs") + 1]) if "--jobs" in sys.argv else 4
+    jobs = int(sys.argv[sys.argv.index("--jobs") + 1]) if "--jobs" in sys.argv else 8
     build(jobs, verbose=True)

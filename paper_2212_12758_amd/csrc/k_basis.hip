@@ -1,836 +1,48 @@
-// Streaming kernels of the k-truncated basis construction (Algorithm 2 of the
-// paper) with the sketch Theta (Section 2.1.1) fused into the pass that
-// writes each new basis vector.
-//
-// One step i (1 <= i <= m) builds column i-1 of the Hessenberg matrix and the
-// basis vector u_i with two passes over the rows:
-//
-//   k_dots   : w~ = A u_{i-1} (stencil or CSR), window dots d_j = u_j^T w~ for
-//              j in [max(0,i-k), i-1] and ||w~||^2, written as per-block partials.
-//              The last block to finish reduces the partials in a fixed order
-//              (plus the norm partials of u_{i-1} from the previous update
-//              pass) and writes h_{j,i-1} = d_j / (eta_j eta_{i-1}), the
-//              subdiagonal entry h_{i-1,i-2} = eta_{i-1}, and the update
-//              coefficients.  Extra blocks appended to the grid reduce the
-//              sketch partials of column i-1.
-//   k_update : u_i = w~/eta_{i-1} - sum_j (h_{j,i-1}/eta_j) u_j  (classical
-//              Gram-Schmidt against the window, which equals the printed
-//              modified Gram-Schmidt in exact arithmetic because the window
-//              is orthonormal), stored in the basis precision; ||u_i||^2 and
-//              Theta u_i are accumulated from the stored (rounded) values.
-//
-// Vectors are kept unnormalised (v_j = u_j / eta_j); every scale is applied
-// to scalars, never by an extra pass over the vectors.  All arithmetic on
-// vector elements is FP64 whatever the storage type.
-//
-// Work layout: tiles of TILE = 2^LT consecutive elements (rows x rhs); a
-// block of TILE/8 threads owns one tile at a time and each thread owns 8
-// consecutive elements, moved with 16-byte vector loads and stores.  Basis
-// columns start on 256-byte boundaries.  QC = 1 when there is one right-hand
-// side (one accumulator per quantity); QC = 8 otherwise (one per element).
-#include "fab_dev.h"
+// Dispatch of the streaming basis kernels (the kernel templates are in
+// k_basis.h, their variants are compiled per storage type and operator in
+// k_basis_<type>_<op>.hip), the closing step, the combination V c and small
+// utility kernels.
+#include "k_basis.h"
 
 namespace fab {
 
-constexpr int EPT = 8;   // elements per thread per tile
-
-// ------------------------------------------------------------------ 8-element memory helpers
-__device__ inline void load8(const float* __restrict__ p, double* v) {
-  const float4 a = *reinterpret_cast<const float4*>(p);
-  const float4 b = *reinterpret_cast<const float4*>(p + 4);
-  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-}
-__device__ inline void load8(const double* __restrict__ p, double* v) {
-#pragma unroll
-  for (int h = 0; h < 4; ++h) {
-    const double2 a = *reinterpret_cast<const double2*>(p + 2 * h);
-    v[2 * h] = a.x;
-    v[2 * h + 1] = a.y;
-  }
-}
-__device__ inline void store8(float* __restrict__ p, const double* v, double* rounded) {
-  float4 a, b;
-  a.x = (float)v[0]; a.y = (float)v[1]; a.z = (float)v[2]; a.w = (float)v[3];
-  b.x = (float)v[4]; b.y = (float)v[5]; b.z = (float)v[6]; b.w = (float)v[7];
-  *reinterpret_cast<float4*>(p) = a;
-  *reinterpret_cast<float4*>(p + 4) = b;
-  rounded[0] = a.x; rounded[1] = a.y; rounded[2] = a.z; rounded[3] = a.w;
-  rounded[4] = b.x; rounded[5] = b.y; rounded[6] = b.z; rounded[7] = b.w;
-}
-__device__ inline void store8(double* __restrict__ p, const double* v, double* rounded) {
-#pragma unroll
-  for (int h = 0; h < 4; ++h) {
-    double2 a;
-    a.x = v[2 * h];
-    a.y = v[2 * h + 1];
-    *reinterpret_cast<double2*>(p + 2 * h) = a;
-  }
-#pragma unroll
-  for (int j = 0; j < 8; ++j) rounded[j] = v[j];
-}
-template <typename T>
-__device__ inline double ldg1(const T* __restrict__ u, long long x, long long nel) {
-  return (x >= 0 && x < nel) ? (double)u[x] : 0.0;
-}
-template <typename T>
-constexpr int vec_align() { return 16 / (int)sizeof(T); }
-
-// u[e+off .. e+off+7]: vector load when aligned and in range, else guarded scalars.
-template <typename T>
-__device__ inline void fetch8(const T* __restrict__ u, long long e, long long off, long long nel, double* v) {
-  const long long a = e + off;
-  if ((off % vec_align<T>()) == 0 && a >= 0 && a + EPT <= nel) {
-    load8(u + a, v);
-  } else {
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) v[j] = ldg1(u, a + j, nel);
-  }
-}
-
-template <typename T>
-__device__ inline void get8(const T* __restrict__ p, long long e, long long nel, double* v) {
-  if (e + EPT <= nel) {
-    load8(p + e, v);
-  } else {
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) v[j] = ldg1(p, e + j, nel);
-  }
-}
-
-// Boundary masks of elements e..e+7 (row = element >> lognrhs): bit j of
-// mx0 is set when element j has an x-1 neighbour, mx1 for x+1, etc.
-struct Masks8 {
-  unsigned mx0, mx1, my0, my1, mz0, mz1;
-};
-__device__ inline Masks8 masks8(const SolveDev& d, long long e) {
-  const int r0 = (int)(e >> d.lognrhs);
-  int x = r0 % d.nx;
-  const int yz = r0 / d.nx;
-  int y = yz % d.ny;
-  int z = yz / d.ny;
-  int rp = r0;
-  Masks8 mk{0u, 0u, 0u, 0u, 0u, 0u};
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int r = (int)((e + j) >> d.lognrhs);
-    if (r != rp) {
-      rp = r;
-      if (++x == d.nx) {
-        x = 0;
-        if (++y == d.ny) { y = 0; ++z; }
-      }
-    }
-    mk.mx0 |= (unsigned)(x > 0) << j;
-    mk.mx1 |= (unsigned)(x < d.nx - 1) << j;
-    mk.my0 |= (unsigned)(y > 0) << j;
-    mk.my1 |= (unsigned)(y < d.ny - 1) << j;
-    mk.mz0 |= (unsigned)(z > 0) << j;
-    mk.mz1 |= (unsigned)(z < d.nz - 1) << j;
-  }
-  return mk;
-}
-
-// Values at e+j-S (DIR < 0) or e+j+S (DIR > 0), j = 0..7, for a shift S < 8
-// known at compile time: inside the group they are centre values.
-template <typename T, int S, int DIR>
-__device__ inline void shifted8(const T* __restrict__ u, long long e, long long nel, const double* c, double* nb) {
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int src = j + DIR * S;
-    nb[j] = (src >= 0 && src < EPT) ? c[src >= 0 && src < EPT ? src : 0] : ldg1(u, e + src, nel);
-  }
-}
-
-template <typename T, int DIR>
-__device__ inline void xneighbour8(const T* __restrict__ u, long long e, long long nel, int nr, const double* c,
-                                   double* nb) {
-  if (nr == 1) shifted8<T, 1, DIR>(u, e, nel, c, nb);
-  else if (nr == 2) shifted8<T, 2, DIR>(u, e, nel, c, nb);
-  else if (nr == 4) shifted8<T, 4, DIR>(u, e, nel, c, nb);
-  else fetch8(u, e, (long long)DIR * nr, nel, nb);
-}
-
-// w = A u at elements e..e+7 for the stencil operator; c holds u[e..e+7].
-template <typename T>
-__device__ inline void stencil8(const SolveDev& d, const T* __restrict__ u, long long e, long long nel,
-                                const double* c, double* w) {
-  const Masks8 mk = masks8(d, e);
-  const int nr = d.nrhs;
-  double nb[EPT];
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) w[j] = d.c[0] * c[j];
-  xneighbour8<T, -1>(u, e, nel, nr, c, nb);
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) w[j] += d.c[1] * (((mk.mx0 >> j) & 1u) ? nb[j] : 0.0);
-  xneighbour8<T, 1>(u, e, nel, nr, c, nb);
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) w[j] += d.c[2] * (((mk.mx1 >> j) & 1u) ? nb[j] : 0.0);
-  const long long sy = (long long)d.nx * nr;
-  fetch8(u, e, -sy, nel, nb);
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) w[j] += d.c[3] * (((mk.my0 >> j) & 1u) ? nb[j] : 0.0);
-  fetch8(u, e, sy, nel, nb);
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) w[j] += d.c[4] * (((mk.my1 >> j) & 1u) ? nb[j] : 0.0);
-  if (d.nz > 1) {
-    const long long sz = sy * d.ny;
-    fetch8(u, e, -sz, nel, nb);
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) w[j] += d.c[5] * (((mk.mz0 >> j) & 1u) ? nb[j] : 0.0);
-    fetch8(u, e, sz, nel, nb);
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) w[j] += d.c[6] * (((mk.mz1 >> j) & 1u) ? nb[j] : 0.0);
-  }
-}
-
-template <typename T>
-__device__ inline double csr_apply(const SolveDev& d, const T* __restrict__ u, int r, int q) {
-  const int p0 = d.rowptr[r], p1 = d.rowptr[r + 1];
-  double w = 0.0;
-  for (int p = p0; p < p1; ++p) w += (double)d.val[p] * (double)u[(long long)d.col[p] * d.nrhs + q];
-  return w;
-}
-
-template <typename T, int OP>
-__device__ inline void apply8(const SolveDev& d, const T* __restrict__ src, long long e, long long nel,
-                              const double* c, double* w) {
-  if (OP == OP_STENCIL) {
-    stencil8(d, src, e, nel, c, w);
-  } else {
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const long long x = e + j;
-      w[j] = x < nel ? csr_apply(d, src, (int)(x >> d.lognrhs), (int)(x & (d.nrhs - 1))) : 0.0;
-    }
-  }
-}
-
-__device__ inline double wave_sum_all(double v) {
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ inline int* rhs_mused(const SolveDev& d, int q) { return d.status + 4 + 2 * q; }
-__device__ inline int* rhs_brk(const SolveDev& d, int q) { return d.status + 5 + 2 * q; }
-
-// Fixed-order block-wide sums of RC values per thread; result in out[0..RC) for every thread.
-template <int BLOCK, int RC>
-__device__ inline void block_sums(const double* a, double* red /* [BLOCK/64][RC] */, double* out) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < RC; ++c) {
-    const double v = wave_sum_all(a[c]);
-    if (lane == 0) red[wv * RC + c] = v;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < RC; ++c) {
-    double t = 0.0;
-    for (int w = 0; w < BLOCK / 64; ++w) t += red[w * RC + c];
-    out[c] = t;
-  }
-  __syncthreads();
-}
-
-// Reduce the per-block sketch partials of column `col` into S[:, col]: one
-// wave per (row, rhs), eight loads in flight per lane, fixed order.
-__device__ inline void reduce_sketch_column(const SolveDev& d, int col, int wid, int nwaves) {
-  const int lane = threadIdx.x & 63;
-  const int nr = d.nrhs;
-  const double* base = d.skpart + (long long)(col & 1) * d.skstride;
-  for (int rho = wid; rho < d.s * nr; rho += nwaves) {
-    double v = 0.0;
-    const double* p = base + (long long)rho * d.nblk;
-    for (int b0 = 0; b0 < d.nblk; b0 += 512) {
-      double x[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int b = b0 + lane + 64 * u;
-        x[u] = b < d.nblk ? p[b] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v += x[u];
-    }
-    v = wave_sum_all(v);
-    if (lane == 0) {
-      const int pr = rho >> d.lognrhs, qq = rho & (nr - 1);
-      d.S[(long long)qq * d.s * (d.m + 1) + (long long)col * d.s + pr] = v * d.sk_scale;
-    }
-  }
-}
-
-// element j of thread tid: accumulator slot and rhs
-template <int QC>
-__device__ inline int slot_of(int j) { return QC == 1 ? 0 : j; }
-template <int QC>
-__device__ inline int rhs_of(int tid, int j, int nr) { return QC == 1 ? 0 : ((tid * EPT + j) & (nr - 1)); }
-
-// ------------------------------------------------------------------ pass 1
-// i in 1..m: dots for column i-1.  i == m+1 with nstream == 0: finishing pass
-// (norm of u_m, subdiagonal h_{m+1,m}, sketch column m).
-template <typename T, int OP, int LT, int QC, int KT>
-__global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int nstream) {
-  constexpr int BLOCK = 1 << (LT - 3);
-  constexpr int NW = BLOCK / 64;
-  constexpr int RC = 10;
-  if (d.status[0]) return;  // every rhs has broken down already
-  __shared__ double red[NW * RC];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int nr = d.nrhs;
-  const int j0 = i - d.k > 0 ? i - d.k : 0;
-  const int nw = i - j0;
-  const T* __restrict__ V = (const T*)d.V;
-  const int RS = NSLOT * nr;   // partial values per block: slot-major (sl * nr + q)
-
-  if ((int)blockIdx.x < nstream) {
-    double acc[NSLOT][QC];
-#pragma unroll
-    for (int sl = 0; sl < NSLOT; ++sl)
-#pragma unroll
-      for (int c = 0; c < QC; ++c) acc[sl][c] = 0.0;
-    const T* __restrict__ src = V + (long long)(i - 1) * d.ldv;
-    const long long nel = (long long)d.n * nr;
-    for (int t = blockIdx.x; t < d.ntiles; t += d.nblk) {
-      const long long e = ((long long)t << LT) + (long long)tid * EPT;
-      if (e >= nel) continue;
-      double c[EPT], w[EPT];
-      get8(src, e, nel, c);
-      apply8<T, OP>(d, src, e, nel, c, w);
-      if (OP == OP_CSR) {
-        if (e + EPT <= nel) {
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            double2 o;
-            o.x = w[2 * h];
-            o.y = w[2 * h + 1];
-            *reinterpret_cast<double2*>(d.wbuf + e + 2 * h) = o;
-          }
-        } else {
-          for (int j = 0; j < EPT; ++j)
-            if (e + j < nel) d.wbuf[e + j] = w[j];
-        }
-      }
-#pragma unroll
-      for (int jj = 0; jj < KT; ++jj) {
-        if (jj < nw) {
-          double uj[EPT];
-          if (jj == nw - 1) {
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) uj[j] = c[j];
-          } else {
-            get8(V + (long long)(j0 + jj) * d.ldv, e, nel, uj);
-          }
-#pragma unroll
-          for (int j = 0; j < EPT; ++j) acc[jj][slot_of<QC>(j)] += uj[j] * w[j];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) acc[KMAX][slot_of<QC>(j)] += w[j] * w[j];
-    }
-    // per (slot, rhs) block partials, fixed order
-    __shared__ double pblk[NSLOT * 32];
-    for (int q = 0; q < nr; ++q) {
-      double a[RC];
-#pragma unroll
-      for (int sl = 0; sl < RC; ++sl) a[sl] = 0.0;
-#pragma unroll
-      for (int sl = 0; sl < NSLOT; ++sl)
-#pragma unroll
-        for (int c = 0; c < QC; ++c)
-          if (rhs_of<QC>(tid, c, nr) == q) a[sl] += acc[sl][c];
-      double o[RC];
-      block_sums<BLOCK, RC>(a, red, o);
-      if (tid < NSLOT) pblk[tid * nr + q] = o[tid];
-    }
-    __syncthreads();
-    for (int x = tid; x < RS; x += BLOCK) d.part[(long long)blockIdx.x * RS + x] = pblk[x];
-  }
-}
-
-// ------------------------------------------------------------------ step scalars
-// Reduce, in a fixed order, the dot partials of pass 1 (part; when have_dots)
-// and the norm partials of u_{i-1} (npb), then form for every rhs: eta_{i-1},
-// the breakdown test, h_{j,i-1}, ||w_i|| and the update coefficients (into the
-// shared array cfl[q*NSLOT + .]).  Every block computes identical values; the
-// block with publish = true also stores the persistent state.
-template <int BLOCK>
-__device__ void step_scalars(const SolveDev& d, int i, bool have_dots, const double* __restrict__ npb, bool publish,
-                             double* red, double* sums, double* cfl) {
-  constexpr int RC = 10;
-  const int tid = threadIdx.x;
-  const int nr = d.nrhs;
-  const int m = d.m;
-  const int j0 = i - d.k > 0 ? i - d.k : 0;
-  const int nw = i - j0;
-  const int RS = NSLOT * nr;
-  // scalar state of the rhs handled by this thread, loaded with the partials
-  int brk_pre = 0;
-  double wprev_pre = 0.0;
-  double ej_pre[KMAX];
-#pragma unroll
-  for (int jj = 0; jj < KMAX; ++jj) ej_pre[jj] = 0.0;
-  if (tid < nr) {
-    brk_pre = *rhs_brk(d, tid);
-    wprev_pre = i >= 2 ? d.wnorm[(long long)tid * (m + 1) + i - 2] : 0.0;
-#pragma unroll
-    for (int jj = 0; jj < KMAX; ++jj)
-      if (jj < nw - 1) ej_pre[jj] = d.eta[(long long)tid * (m + 1) + j0 + jj];
-  }
-  const int RT = RS + nr;
-  for (int r0 = 0; r0 < RT; r0 += RC) {
-    double a[RC];
-#pragma unroll
-    for (int c = 0; c < RC; ++c) a[c] = 0.0;
-    for (int b = tid; b < d.nblk; b += BLOCK) {
-#pragma unroll
-      for (int c = 0; c < RC; ++c) {
-        const int rr = r0 + c;
-        if (rr < RS) {
-          if (have_dots) a[c] += d.part[(long long)b * RS + rr];
-        } else if (rr < RT) {
-          a[c] += npb[(long long)b * nr + (rr - RS)];
-        }
-      }
-    }
-    double o[RC];
-    block_sums<BLOCK, RC>(a, red, o);
-    if (tid < RC && r0 + tid < RT) sums[r0 + tid] = o[tid];
-  }
-  __syncthreads();
-
-  for (int qq = tid; qq < nr; qq += BLOCK) {
-    double* eta = d.eta + (long long)qq * (m + 1);
-    double* H = d.H + (long long)qq * (m + 1) * m;
-    double* wn = d.wnorm + (long long)qq * (m + 1);
-    double* cf = cfl + qq * NSLOT;
-    const int brk0 = brk_pre;
-    const double wprev = wprev_pre;
-    const double eta_prev = sqrt(sums[RS + qq]);  // ||u_{i-1}||, the newest window member
-    double ej[KMAX];
-#pragma unroll
-    for (int jj = 0; jj < KMAX; ++jj) ej[jj] = (jj < nw - 1) ? ej_pre[jj] : eta_prev;
-    int b = brk0, mu = -1, nonfinite = 0;
-    double hsub = -1.0;   // value for H[i-1, i-2] when >= 0
-    if (!b) {
-      if (!isfinite(eta_prev)) {
-        nonfinite = 1;
-        b = 1;
-        mu = i - 1;
-      } else if (i == 1) {
-        if (eta_prev == 0.0) { b = 1; mu = 0; }
-      } else if (eta_prev <= 100.0 * d.unit_round * wprev) {
-        b = 1;  // invariant subspace of dimension i-1
-        mu = i - 1;
-        hsub = 0.0;
-      } else {
-        hsub = eta_prev;
-      }
-    }
-    if (b || !have_dots) {
-      for (int sl = 0; sl < NSLOT; ++sl) cf[sl] = 0.0;
-      if (!b) mu = m;
-    } else {
-      cf[0] = 1.0 / eta_prev;
-#pragma unroll
-      for (int jj = 0; jj < KMAX; ++jj) {
-        if (jj < nw) {
-          const double h = sums[jj * nr + qq] / (ej[jj] * eta_prev);
-          cf[1 + jj] = h / ej[jj];
-          if (publish) H[(long long)(i - 1) * (m + 1) + (j0 + jj)] = h;
-        } else {
-          cf[1 + jj] = 0.0;
-        }
-      }
-    }
-    if (publish) {
-      eta[i - 1] = eta_prev;
-      if (hsub >= 0.0) H[(long long)(i - 2) * (m + 1) + (i - 1)] = hsub;
-      if (!b && have_dots) wn[i - 1] = sqrt(sums[KMAX * nr + qq]) / eta_prev;
-      if (b != brk0) *rhs_brk(d, qq) = b;
-      if (mu >= 0) *rhs_mused(d, qq) = mu;
-      if (nonfinite) d.status[1] = 1;
-    }
-    cfl[32 * NSLOT + qq] = (double)b;   // breakdown flags after this step
-  }
-  __syncthreads();
-  if (publish && tid == 0) {
-    int all = 1;
-    for (int qq = 0; qq < nr; ++qq) all &= (cfl[32 * NSLOT + qq] != 0.0);
-    d.status[0] = all;
-  }
-}
-
-// Finishing pass after the last update: eta_m, h_{m+1,m}, breakdown test of
-// u_m (block 0) and the sketch of the last column (all blocks).
-template <int LT>
-__global__ void __launch_bounds__(1 << (LT - 3)) k_finish(SolveDev d) {
-  constexpr int BLOCK = 1 << (LT - 3);
-  constexpr int NW = BLOCK / 64;
-  if (d.status[0]) return;
-  __shared__ double red[NW * 10];
-  __shared__ double sums[NSLOT * 32 + 32];
-  __shared__ double cfl[33 * NSLOT + 32];
-  const int i = d.m + 1;
-  reduce_sketch_column(d, i - 1, blockIdx.x * NW + (threadIdx.x >> 6), gridDim.x * NW);
-  if (blockIdx.x == 0) step_scalars<BLOCK>(d, i, false, d.npart + (long long)(d.m & 1) * d.nblk * d.nrhs, true, red, sums, cfl);
-}
-
-// ------------------------------------------------------------------ Walsh-Hadamard transform of a tile
-// X holds the tile (padded index padx(e) = e + e/32).  On entry each thread
-// holds its 8 consecutive elements in v (index bits 0..2); the transform acts
-// on index bits [lnr, LT) (the row bits of the tile), in three-bit phases:
-// registers hold three index bits, LDS transposes move between phases.  On
-// exit the transformed tile is in X.
-__device__ inline int padx(int e) { return e + (e >> 5); }
-
-__device__ inline void butterflies3_unused(double* v, int p, int lnr) {
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    if (p + b >= lnr) {
-#pragma unroll
-      for (int j = 0; j < EPT; ++j)
-        if (!(j & (1 << b))) {
-          const double x = v[j], y = v[j | (1 << b)];
-          v[j] = x + y;
-          v[j | (1 << b)] = x - y;
-        }
-    }
-  }
-}
-
-__device__ inline void butterflies_range(double* v, int pos, int lo, int hi) {
-  // stages on index bits [lo, hi) while registers hold bits pos, pos+1, pos+2
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    if (pos + b >= lo && pos + b < hi) {
-#pragma unroll
-      for (int j = 0; j < EPT; ++j)
-        if (!(j & (1 << b))) {
-          const double x = v[j], y = v[j | (1 << b)];
-          v[j] = x + y;
-          v[j | (1 << b)] = x - y;
-        }
-    }
-  }
-}
-
-template <int LT>
-__device__ inline void fwht_tile(double* v, double* X, int lnr) {
-  const int tid = threadIdx.x;
-  butterflies_range(v, 0, lnr, 3);
-  int cur = 0;
-#pragma unroll
-  for (int p = 3; p < LT; p += 3) {
-    const int pos = p + 3 <= LT ? p : LT - 3;   // a last partial phase reuses done bits
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int e = (tid & ((1 << cur) - 1)) | (j << cur) | ((tid >> cur) << (cur + 3));
-      X[padx(e)] = v[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int e = (tid & ((1 << pos) - 1)) | (j << pos) | ((tid >> pos) << (pos + 3));
-      v[j] = X[padx(e)];
-    }
-    __syncthreads();
-    cur = pos;
-    butterflies_range(v, pos, p > lnr ? p : lnr, p + 3 < LT ? p + 3 : LT);
-  }
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int e = (tid & ((1 << cur) - 1)) | (j << cur) | ((tid >> cur) << (cur + 3));
-    X[padx(e)] = v[j];
-  }
-  __syncthreads();
-}
-
-// ------------------------------------------------------------------ pass 2
-// START: u_0 = fl(b).  Otherwise u_i = cf0 * w~ - sum_j cf_{1+j} u_{j0+j}.
-template <typename T, int OP, int SK, bool START, int LT, int QC, int KT>
-__global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
-  constexpr int BLOCK = 1 << (LT - 3);
-  constexpr int TILE = 1 << LT;
-  constexpr int NW = BLOCK / 64;
-  if (d.status[0]) return;
-  extern __shared__ double lds[];
-  __shared__ double nred[NW][32];
-  // leading blocks reduce the sketch partials of column i-1 (written by the
-  // previous update pass into the other buffer)
-  const int nlead = START ? 0 : d.nred;
-  if ((int)blockIdx.x < nlead) {
-    reduce_sketch_column(d, i - 1, blockIdx.x * NW + (threadIdx.x >> 6), nlead * NW);
-    return;
-  }
-  const int blk = blockIdx.x - nlead;
-  __shared__ double sred[NW * 10];
-  __shared__ double ssums[NSLOT * 32 + 32];
-  __shared__ double cfl[33 * NSLOT + 32];
-  if (!START) {
-    step_scalars<BLOCK>(d, i, true, d.npart + (long long)((i - 1) & 1) * d.nblk * d.nrhs, blk == 0, sred, ssums, cfl);
-  }
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int nr = d.nrhs;
-  const long long nel = (long long)d.n * nr;
-  const int j0 = i - d.k > 0 ? i - d.k : 0;
-  const int nw = START ? 0 : i - j0;
-  T* __restrict__ V = (T*)d.V;
-  const T* __restrict__ src = START ? nullptr : V + (long long)(i - 1) * d.ldv;
-  T* __restrict__ dst = V + (long long)i * d.ldv;
-
-  double cw[QC];
-  double cj[KT][QC];
-#pragma unroll
-  for (int c = 0; c < QC; ++c) {
-    const int q = rhs_of<QC>(tid, c, nr);
-    const double* cf = cfl + q * NSLOT;
-    cw[c] = START ? 1.0 : cf[0];
-#pragma unroll
-    for (int jj = 0; jj < KT; ++jj) cj[jj][c] = (START || jj >= nw) ? 0.0 : cf[1 + jj];
-  }
-
-  double* X = lds;                                                   // SRHT tile (padded)
-  double* acc = lds + (SK == SK_SRHT ? padx(TILE) : 0);              // sketch accumulator [s][nr]
-  const int snr = d.s * nr;
-  int* rows_l = (int*)(acc + snr);                                    // sampled SRHT rows
-  for (int x = tid; x < snr; x += BLOCK) acc[x] = 0.0;
-  if (SK == SK_SRHT)
-    for (int x = tid; x < d.s; x += BLOCK) rows_l[x] = d.srht_rows[x];
-  __syncthreads();
-
-  double nrm[QC];
-#pragma unroll
-  for (int c = 0; c < QC; ++c) nrm[c] = 0.0;
-  for (int t = blk; t < d.ntiles; t += d.nblk) {
-    const long long e = ((long long)t << LT) + (long long)tid * EPT;
-    double uu[EPT];
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) uu[j] = 0.0;
-    if (e < nel) {
-      double u[EPT];
-      if (START) {
-        get8(d.b, e, nel, u);
-      } else {
-        double w[EPT];
-        if (OP == OP_STENCIL) {
-          double c[EPT];
-          get8(src, e, nel, c);
-          stencil8(d, src, e, nel, c, w);
-        } else {
-          get8(d.wbuf, e, nel, w);
-        }
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) u[j] = cw[slot_of<QC>(j)] * w[j];
-#pragma unroll
-        for (int jj = 0; jj < KT; ++jj) {
-          if (jj < nw) {
-            double vj[EPT];
-            get8(V + (long long)(j0 + jj) * d.ldv, e, nel, vj);
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) u[j] -= cj[jj][slot_of<QC>(j)] * vj[j];
-          }
-        }
-      }
-      if (e + EPT <= nel) {
-        store8(dst + e, u, uu);
-      } else {
-#pragma unroll
-        for (int j = 0; j < EPT; ++j)
-          if (e + j < nel) {
-            const T ut = (T)u[j];
-            dst[e + j] = ut;
-            uu[j] = (double)ut;
-          }
-      }
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) nrm[slot_of<QC>(j)] += uu[j] * uu[j];
-      if (SK == SK_SPARSE) {
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-          if (e + j < nel) {
-            const int r = (int)((e + j) >> d.lognrhs);
-            const int q = (int)((e + j) & (nr - 1));
-            int rows[ZMAX];
-            unsigned long long sb;
-            sparse_sign_column(d.key_a, d.key_b, r, d.s, d.zeta, rows, &sb);
-#pragma unroll
-            for (int tt = 0; tt < ZMAX; ++tt)
-              if (tt < d.zeta) atomicAdd(&acc[rows[tt] * nr + q], ((sb >> tt) & 1ull) ? -uu[j] : uu[j]);
-          }
-        }
-      }
-    }
-    if (SK == SK_SRHT) {
-      // D signs, then the transform of the tile along rows
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        const unsigned long long r = (unsigned long long)((e + j) >> d.lognrhs);
-        if (sm64_out(d.key_a, r) >> 63) uu[j] = -uu[j];
-      }
-      fwht_tile<LT>(uu, X, d.lognrhs);
-      // sampled rows r = (r_hi, r_lo): contribution (-1)^popcount(r_hi & t) * X[r_lo]
-      for (int pq = tid; pq < snr; pq += BLOCK) {
-        const int p = pq >> d.lognrhs, qq = pq & (nr - 1);
-        const int rr = rows_l[p];
-        const int par = __popc((unsigned)(rr >> d.log_rows) & (unsigned)t) & 1;
-        const double v = X[padx(((rr & (d.rows_per_tile - 1)) << d.lognrhs) + qq)];
-        acc[pq] += par ? -v : v;
-      }
-      __syncthreads();
-    }
-  }
-  __syncthreads();
-  double* skp = d.skpart + (long long)(i & 1) * d.skstride;
-  for (int pq = tid; pq < snr; pq += BLOCK) skp[(long long)pq * d.nblk + blk] = acc[pq];
-
-  // norm partials per rhs
-  for (int q = 0; q < nr; ++q) {
-    double a = 0.0;
-#pragma unroll
-    for (int c = 0; c < QC; ++c)
-      if (rhs_of<QC>(tid, c, nr) == q) a += nrm[c];
-    a = wave_sum_all(a);
-    if (lane == 0) nred[wv][q] = a;
-  }
-  __syncthreads();
-  double* npw = d.npart + (long long)(i & 1) * d.nblk * nr;
-  for (int q = tid; q < nr; q += BLOCK) {
-    double t = 0.0;
-    for (int w = 0; w < NW; ++w) t += nred[w][q];
-    npw[(long long)blk * nr + q] = t;
-  }
-}
-
-// ------------------------------------------------------------------ combine
-// out = sum_j cf_j u_j with cf_j = beta c_j / eta_j (FP64 accumulation).
-template <typename T>
-__global__ void __launch_bounds__(256) k_combine(SolveDev d, const double* __restrict__ cf, int mmax,
-                                                 double* __restrict__ out) {
-  const T* __restrict__ V = (const T*)d.V;
-  const long long nel = (long long)d.n * d.nrhs;
-  const int nr = d.nrhs;
-  for (long long e = ((long long)blockIdx.x * 256 + threadIdx.x) * EPT; e < nel;
-       e += (long long)gridDim.x * 256 * EPT) {
-    double a[EPT];
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) a[j] = 0.0;
-    for (int jv = 0; jv < mmax; ++jv) {
-      double v[EPT];
-      get8(V + (long long)jv * d.ldv, e, nel, v);
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) a[j] += cf[(long long)((e + j) & (nr - 1)) * (d.m + 1) + jv] * v[j];
-    }
-    if (e + EPT <= nel) {
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        double2 o;
-        o.x = a[2 * h];
-        o.y = a[2 * h + 1];
-        *reinterpret_cast<double2*>(out + e + 2 * h) = o;
-      }
-    } else {
-      for (int j = 0; j < EPT; ++j)
-        if (e + j < nel) out[e + j] = a[j];
-    }
-  }
-}
-
-// ------------------------------------------------------------------ host launchers
-template <typename T, int LT, int QC, int KT>
-static hipError_t launch_dots_k(const SolveDev& d, int i, hipStream_t st, int nstream, int grid) {
-  const dim3 g(grid), b(1 << (LT - 3));
-  if (d.op == OP_STENCIL) hipLaunchKernelGGL((k_dots<T, OP_STENCIL, LT, QC, KT>), g, b, 0, st, d, i, nstream);
-  else hipLaunchKernelGGL((k_dots<T, OP_CSR, LT, QC, KT>), g, b, 0, st, d, i, nstream);
-  return hipGetLastError();
-}
-template <typename T, int LT, int QC>
-static hipError_t launch_dots_q(const SolveDev& d, int i, hipStream_t st, int nstream, int grid) {
-  if (d.k <= 2) return launch_dots_k<T, LT, QC, 2>(d, i, st, nstream, grid);
-  if (d.k <= 4) return launch_dots_k<T, LT, QC, 4>(d, i, st, nstream, grid);
-  return launch_dots_k<T, LT, QC, 8>(d, i, st, nstream, grid);
-}
-
-template <typename T, bool START, int LT, int QC, int KT>
-static hipError_t launch_update_k(const SolveDev& d, int i, hipStream_t st, size_t lds) {
-  const dim3 g(d.nblk + (START ? 0 : d.nred)), b(1 << (LT - 3));
-  if (d.op == OP_STENCIL || START) {
-    if (d.sketch == SK_SRHT) hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SRHT, START, LT, QC, KT>), g, b, lds, st, d, i);
-    else hipLaunchKernelGGL((k_update<T, OP_STENCIL, SK_SPARSE, START, LT, QC, KT>), g, b, lds, st, d, i);
-  } else {
-    if (d.sketch == SK_SRHT) hipLaunchKernelGGL((k_update<T, OP_CSR, SK_SRHT, START, LT, QC, KT>), g, b, lds, st, d, i);
-    else hipLaunchKernelGGL((k_update<T, OP_CSR, SK_SPARSE, START, LT, QC, KT>), g, b, lds, st, d, i);
-  }
-  return hipGetLastError();
-}
-template <typename T, bool START, int LT, int QC>
-static hipError_t launch_update_q(const SolveDev& d, int i, hipStream_t st, size_t lds) {
-  if (START) return launch_update_k<T, START, LT, QC, 2>(d, i, st, lds);
-  if (d.k <= 2) return launch_update_k<T, START, LT, QC, 2>(d, i, st, lds);
-  if (d.k <= 4) return launch_update_k<T, START, LT, QC, 4>(d, i, st, lds);
-  return launch_update_k<T, START, LT, QC, 8>(d, i, st, lds);
-}
-
-template <typename T>
-static hipError_t dots_t(const SolveDev& d, int i, hipStream_t st, int nstream, int grid) {
-  const bool q1 = d.nrhs == 1;
-  if (d.log_tile == 11)
-    return q1 ? launch_dots_q<T, 11, 1>(d, i, st, nstream, grid) : launch_dots_q<T, 11, 8>(d, i, st, nstream, grid);
-  return q1 ? launch_dots_q<T, 9, 1>(d, i, st, nstream, grid) : launch_dots_q<T, 9, 8>(d, i, st, nstream, grid);
-}
-
-template <typename T, bool START>
-static hipError_t update_t(const SolveDev& d, int i, hipStream_t st, size_t lds) {
-  const bool q1 = d.nrhs == 1;
-  if (d.log_tile == 11)
-    return q1 ? launch_update_q<T, START, 11, 1>(d, i, st, lds) : launch_update_q<T, START, 11, 8>(d, i, st, lds);
-  return q1 ? launch_update_q<T, START, 9, 1>(d, i, st, lds) : launch_update_q<T, START, 9, 8>(d, i, st, lds);
-}
-
-template <typename T, int LT, int QC, int KT>
-static void set_lds_attr_k(hipError_t& e) {
-  const int mx = 160 * 1024;
-  auto f = [&](const void* k) {
-    hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    if (r != hipSuccess) e = r;
-  };
-  f((const void*)k_update<T, OP_STENCIL, SK_SRHT, false, LT, QC, KT>);
-  f((const void*)k_update<T, OP_STENCIL, SK_SPARSE, false, LT, QC, KT>);
-  f((const void*)k_update<T, OP_CSR, SK_SRHT, false, LT, QC, KT>);
-  f((const void*)k_update<T, OP_CSR, SK_SPARSE, false, LT, QC, KT>);
-  if (KT == 2) {
-    f((const void*)k_update<T, OP_STENCIL, SK_SRHT, true, LT, QC, KT>);
-    f((const void*)k_update<T, OP_STENCIL, SK_SPARSE, true, LT, QC, KT>);
-  }
-}
-template <typename T, int LT, int QC>
-static void set_lds_attr_q(hipError_t& e) {
-  set_lds_attr_k<T, LT, QC, 2>(e);
-  set_lds_attr_k<T, LT, QC, 4>(e);
-  set_lds_attr_k<T, LT, QC, 8>(e);
-}
+hipError_t basis_part_dots_f32_stencil(const SolveDev& d, int i, hipStream_t st, int nstream, int grid);
+hipError_t basis_part_update_f32_stencil(const SolveDev& d, int i, hipStream_t st, size_t lds);
+hipError_t basis_part_attributes_f32_stencil();
+hipError_t basis_part_start_f32_stencil(const SolveDev& d, hipStream_t st, size_t lds);
+hipError_t basis_part_dots_f32_csr(const SolveDev& d, int i, hipStream_t st, int nstream, int grid);
+hipError_t basis_part_update_f32_csr(const SolveDev& d, int i, hipStream_t st, size_t lds);
+hipError_t basis_part_attributes_f32_csr();
+hipError_t basis_part_dots_f64_stencil(const SolveDev& d, int i, hipStream_t st, int nstream, int grid);
+hipError_t basis_part_update_f64_stencil(const SolveDev& d, int i, hipStream_t st, size_t lds);
+hipError_t basis_part_attributes_f64_stencil();
+hipError_t basis_part_start_f64_stencil(const SolveDev& d, hipStream_t st, size_t lds);
+hipError_t basis_part_dots_f64_csr(const SolveDev& d, int i, hipStream_t st, int nstream, int grid);
+hipError_t basis_part_update_f64_csr(const SolveDev& d, int i, hipStream_t st, size_t lds);
+hipError_t basis_part_attributes_f64_csr();
 
 hipError_t basis_set_attributes() {
-  hipError_t e = hipSuccess;
-  set_lds_attr_q<float, 11, 1>(e);
-  set_lds_attr_q<float, 11, 8>(e);
-  set_lds_attr_q<float, 9, 1>(e);
-  set_lds_attr_q<float, 9, 8>(e);
-  set_lds_attr_q<double, 11, 1>(e);
-  set_lds_attr_q<double, 11, 8>(e);
-  set_lds_attr_q<double, 9, 1>(e);
-  set_lds_attr_q<double, 9, 8>(e);
+  hipError_t e = hipSuccess, r;
+  if ((r = basis_part_attributes_f32_stencil()) != hipSuccess) e = r;
+  if ((r = basis_part_attributes_f32_csr()) != hipSuccess) e = r;
+  if ((r = basis_part_attributes_f64_stencil()) != hipSuccess) e = r;
+  if ((r = basis_part_attributes_f64_csr()) != hipSuccess) e = r;
   return e;
 }
 
 hipError_t basis_start(const SolveDev& d, int esize, hipStream_t st, size_t lds) {
-  return esize == 4 ? update_t<float, true>(d, 0, st, lds) : update_t<double, true>(d, 0, st, lds);
+  return esize == 4 ? basis_part_start_f32_stencil(d, st, lds) : basis_part_start_f64_stencil(d, st, lds);
 }
 hipError_t basis_dots(const SolveDev& d, int esize, int i, hipStream_t st) {
-  return esize == 4 ? dots_t<float>(d, i, st, d.nblk, d.nblk) : dots_t<double>(d, i, st, d.nblk, d.nblk);
+  const bool csr = d.op == OP_CSR;
+  if (esize == 4)
+    return csr ? basis_part_dots_f32_csr(d, i, st, d.nblk, d.nblk) : basis_part_dots_f32_stencil(d, i, st, d.nblk, d.nblk);
+  return csr ? basis_part_dots_f64_csr(d, i, st, d.nblk, d.nblk) : basis_part_dots_f64_stencil(d, i, st, d.nblk, d.nblk);
 }
 hipError_t basis_update(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds) {
-  return esize == 4 ? update_t<float, false>(d, i, st, lds) : update_t<double, false>(d, i, st, lds);
+  const bool csr = d.op == OP_CSR;
+  if (esize == 4) return csr ? basis_part_update_f32_csr(d, i, st, lds) : basis_part_update_f32_stencil(d, i, st, lds);
+  return csr ? basis_part_update_f64_csr(d, i, st, lds) : basis_part_update_f64_stencil(d, i, st, lds);
 }
 hipError_t basis_finish(const SolveDev& d, int esize, hipStream_t st) {
   (void)esize;
@@ -888,3 +100,4 @@ hipError_t srht_sample_rows(int* rows, long long npad, int s, unsigned long long
 }
 
 }  // namespace fab
+

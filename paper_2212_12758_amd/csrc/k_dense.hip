@@ -7,9 +7,7 @@
 //           H_hat = H_m + h_{m+1,m} y e_m^T (eq. (6)).  The matrix is held in
 //           registers across the workgroup when s <= 448 and m + 1 <= 104,
 //           else it is factorised in global memory.
-//  k_fexp   exp(alpha H_hat) e_1 by scaling and squaring with a diagonal Pade
-//           approximant (Higham, SIAM J. Matrix Anal. Appl. 26 (2005)), the
-//           algorithm behind the expm the paper uses in Section 5.
+//  (exp(alpha H_hat) e_1 lives in k_expm.hip: multi-workgroup Pade products.)
 //  k_fpow   (H_hat + sigma I)^{+-1/2} e_1 through the real Schur decomposition
 //           (Francis double-shift QR, Golub & Van Loan Sec. 7.5) and the real
 //           quasi-triangular square root recurrence (Higham, Linear Algebra
@@ -23,8 +21,10 @@
 
 namespace fab {
 
+hipError_t exp_launch(const SolveDev& d, const DenseDev& g, hipStream_t st);
+hipError_t exp_set_attributes();
+
 constexpr int DBLOCK = 256;
-constexpr int LDS_M = 112;   // dense stages keep m x m operands in LDS up to this size
 constexpr int MAXM = 512;
 enum { INFO_KAPPA = 0, INFO_HLAST = 1, INFO_BETA = 2, INFO_FAIL = 3, INFO_NSQ = 4, INFO_SCHUR_IT = 5, INFO_NRM = 6 };
 
@@ -52,206 +52,6 @@ __device__ inline double bsum(double v, double* sh) {
   for (int w = 0; w < nwv; ++w) t += sh[w];
   __syncthreads();
   return t;
-}
-
-// ----------------------------------------------------------------- block GEMM
-// C = A * B, square m x m, col-major, ld = m; C must not alias A or B.
-__device__ void bgemm(int m, const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C,
-                      double* As, double* Bs) {  // As, Bs: 16*65 doubles each
-  const int tid = threadIdx.x;
-  const int tr = tid & 15, tc = tid >> 4;
-  for (int i0 = 0; i0 < m; i0 += 64) {
-    for (int j0 = 0; j0 < m; j0 += 64) {
-      double acc[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-      for (int k0 = 0; k0 < m; k0 += 16) {
-        for (int x = tid; x < 1024; x += DBLOCK) {
-          const int ii = x & 63, kk = x >> 6;
-          const int gi = i0 + ii, gk = k0 + kk;
-          As[kk * 65 + ii] = (gi < m && gk < m) ? A[gi + (long long)gk * m] : 0.0;
-          const int jj = x >> 4, kb = x & 15;
-          const int gj = j0 + jj, gkb = k0 + kb;
-          Bs[kb * 65 + jj] = (gj < m && gkb < m) ? B[gkb + (long long)gj * m] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < 16; ++kk) {
-          double av[4], bv[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) av[a] = As[kk * 65 + tr * 4 + a];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) bv[b] = Bs[kk * 65 + tc * 4 + b];
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int gi = i0 + tr * 4 + a, gj = j0 + tc * 4 + b;
-          if (gi < m && gj < m) C[gi + (long long)gj * m] = acc[a][b];
-        }
-    }
-  }
-  __syncthreads();
-}
-
-// C = A * B for m <= LDS_M with B staged in LDS (Bl: m*m doubles) and A read
-// through the cache; thread (ti, tj) of a 16 x 16 grid owns an 8 x 8 block of C.
-__device__ void bgemm_small(int m, const double* __restrict__ A, const double* __restrict__ B,
-                            double* __restrict__ C, double* Bl) {
-  const int tid = threadIdx.x;
-  const long long mm = (long long)m * m;
-  for (long long x = tid; x < mm; x += DBLOCK) Bl[x] = B[x];
-  __syncthreads();
-  const int ti = tid & 15, tj = tid >> 4;
-  const int i0 = ti * 8, j0 = tj * 8;
-  if (i0 < m && j0 < m) {
-    double acc[8][8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-      for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
-    for (int k = 0; k < m; ++k) {
-      double av[8], bv[8];
-#pragma unroll
-      for (int a = 0; a < 8; ++a) av[a] = (i0 + a < m) ? A[i0 + a + (long long)k * m] : 0.0;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) bv[b] = (j0 + b < m) ? Bl[k + (long long)(j0 + b) * m] : 0.0;
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int b = 0; b < 8; ++b) acc[a][b] += av[a] * bv[b];
-    }
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-      for (int b = 0; b < 8; ++b)
-        if (i0 + a < m && j0 + b < m) C[i0 + a + (long long)(j0 + b) * m] = acc[a][b];
-  }
-  __syncthreads();
-}
-
-// ----------------------------------------------------------------- LU with partial pivoting
-// In place on A (m x m, ld m; LDS or global); piv[j] = row swapped with j.
-// Two barriers per pivot: wave 0 finds the pivot, snapshots the pivot row and
-// the old row j (tmp: 2m doubles) and forms the multipliers (lcol: m doubles);
-// then every thread applies the row swap and the rank-1 update together.
-// Returns 1 if a zero pivot occurred.
-__device__ int blu(int m, double* A, int* piv, double* tmp, double* lcol) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int nth = blockDim.x;
-  double* prow = tmp;        // pivot row (columns j..m-1)
-  double* jrow = tmp + m;    // old row j
-  __shared__ int sp;
-  __shared__ int sing_sh;
-  if (tid == 0) sing_sh = 0;
-  for (int j = 0; j < m; ++j) {
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = j;
-      for (int r = j + lane; r < m; r += 64) {
-        const double v = fabs(A[r + (long long)j * m]);
-        if (v > best) { best = v; bi = r; }
-      }
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      const int p = bi;
-      for (int c = j + lane; c < m; c += 64) {
-        prow[c] = A[p + (long long)c * m];
-        jrow[c] = A[j + (long long)c * m];
-      }
-      const double pv = A[p + (long long)j * m];
-      for (int r = j + 1 + lane; r < m; r += 64) {
-        const double ar = (r == p) ? A[j + (long long)j * m] : A[r + (long long)j * m];
-        lcol[r] = pv != 0.0 ? ar / pv : 0.0;
-      }
-      if (lane == 0) {
-        piv[j] = p;
-        sp = p;
-        if (pv == 0.0) sing_sh = 1;
-      }
-    }
-    __syncthreads();
-    const int p = sp;
-    if (p != j)   // the row swap also moves the multipliers already stored left of column j
-      for (int c = tid; c < j; c += nth) {
-        const double t = A[j + (long long)c * m];
-        A[j + (long long)c * m] = A[p + (long long)c * m];
-        A[p + (long long)c * m] = t;
-      }
-    const int w = m - j;   // columns j..m-1, rows j..m-1
-    for (int x = tid; x < w * w; x += nth) {
-      const int r = j + x % w, c = j + x / w;
-      double v;
-      if (r == j) {
-        v = prow[c];                                    // new pivot row
-      } else if (c == j) {
-        v = lcol[r];                                    // multiplier
-      } else {
-        const double a = (r == p) ? jrow[c] : A[r + (long long)c * m];
-        v = a - lcol[r] * prow[c];
-      }
-      A[r + (long long)c * m] = v;
-    }
-    __syncthreads();
-  }
-  return sing_sh;
-}
-
-// Solve (LU) x = b in place for one right-hand side, all threads sharing the
-// substitution (one barrier per pivot).
-__device__ void blu_solve1(int m, const double* LU, const int* piv, double* x) {
-  if (threadIdx.x == 0)
-    for (int j = 0; j < m; ++j) {
-      const int p = piv[j];
-      if (p != j) { const double t = x[j]; x[j] = x[p]; x[p] = t; }
-    }
-  __syncthreads();
-  for (int j = 0; j < m; ++j) {
-    const double xj = x[j];
-    __syncthreads();
-    for (int r = j + 1 + threadIdx.x; r < m; r += DBLOCK) x[r] -= LU[r + (long long)j * m] * xj;
-    __syncthreads();
-  }
-  for (int j = m - 1; j >= 0; --j) {
-    const double xj = x[j] / LU[j + (long long)j * m];
-    __syncthreads();
-    if (threadIdx.x == 0) x[j] = xj;
-    for (int r = threadIdx.x; r < j; r += DBLOCK) x[r] -= LU[r + (long long)j * m] * xj;
-    __syncthreads();
-  }
-}
-
-// Solve (LU) X = B in place for nb right-hand-side columns of B (ld m); one thread per column.
-__device__ void blu_solve(int m, const double* LU, const int* piv, double* B, int nb) {
-  for (int c = threadIdx.x; c < nb; c += DBLOCK) {
-    double* x = B + (long long)c * m;
-    for (int j = 0; j < m; ++j) {
-      const int p = piv[j];
-      if (p != j) { const double t = x[j]; x[j] = x[p]; x[p] = t; }
-    }
-    for (int j = 0; j < m; ++j) {
-      const double xj = x[j];
-      for (int r = j + 1; r < m; ++r) x[r] -= LU[r + (long long)j * m] * xj;
-    }
-    for (int j = m - 1; j >= 0; --j) {
-      const double xj = x[j] / LU[j + (long long)j * m];
-      x[j] = xj;
-      for (int r = 0; r < j; ++r) x[r] -= LU[r + (long long)j * m] * xj;
-    }
-  }
-  __syncthreads();
 }
 
 __device__ inline int* st_mused(const SolveDev& d, int q) { return d.status + 4 + 2 * q; }
@@ -509,162 +309,6 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
 size_t lsq_lds_bytes(int s, int m) {
   const bool in_regs = s <= 64 * LRS && m + 1 <= 8 * LCS;
   return (size_t)(2 * 64 * LRS + (m + 1) + (in_regs ? (size_t)m * m : 0)) * 8;
-}
-
-// ----------------------------------------------------------------- exp: Pade scaling and squaring
-__device__ inline double pade_coef(int q, int j) {
-  // c_j = (2q-j)! q! / ((2q)! j! (q-j)!)
-  double c = 1.0;
-  for (int i = 0; i < j; ++i) c *= (double)(q - i) / (double)((2 * q - i) * (i + 1));
-  return c;
-}
-
-__global__ void __launch_bounds__(DBLOCK) k_fexp(SolveDev d, DenseDev g) {
-  const int q = blockIdx.x;
-  const int tid = threadIdx.x;
-  __shared__ double As[16 * 65], Bs[16 * 65];
-  __shared__ double sh[8];
-  __shared__ int shi[8];
-  __shared__ int piv[MAXM];
-  double* ws = g.base + (long long)q * g.stride;
-  const int mu = *st_mused(d, q);
-  double* c = ws + g.oVec;        // result f(H_hat) e_1
-  double* info = ws + g.oInfo;
-  if (mu == 0) return;
-  const int m = mu;
-  const long long mm = (long long)m * m;
-  double* A = ws + g.oM;          // alpha * H_hat (scaled)
-  double* A2 = A + mm;
-  double* A4 = A2 + mm;
-  double* A6 = A4 + mm;
-  double* U = A6 + mm;
-  double* Vm = U + mm;
-  double* T1 = Vm + mm;
-  double* T2 = T1 + mm;
-  const double* Hh = ws + g.oH;
-
-  // 1-norm of alpha*H_hat
-  double cmax = 0.0;
-  for (int cc = tid; cc < m; cc += DBLOCK) {
-    double sacc = 0.0;
-    for (int r0 = 0; r0 < m; r0 += 8) {
-      double t[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] = r0 + u < m ? fabs(Hh[r0 + u + (long long)cc * m]) : 0.0;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) sacc += t[u];
-    }
-    cmax = fmax(cmax, sacc);
-  }
-  for (int off = 32; off >= 1; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off, 64));
-  if ((tid & 63) == 0) sh[tid >> 6] = cmax;
-  __syncthreads();
-  double nrm = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3])) * fabs(g.alpha);
-  __syncthreads();
-
-  const double theta[5] = {1.495585217958292e-2, 2.539398330063230e-1, 9.504178996162932e-1,
-                           2.097847961257068e0, 5.371920351148152e0};
-  const int degs[5] = {3, 5, 7, 9, 13};
-  int qd = 13, ssq = 0;
-  for (int t = 0; t < 4; ++t)
-    if (nrm <= theta[t]) { qd = degs[t]; break; }
-  if (qd == 13 && nrm > theta[4]) ssq = (int)ceil(log2(nrm / theta[4]));
-  if (ssq < 0) ssq = 0;
-  const double scale = g.alpha * ldexp(1.0, -ssq);
-  for (long long x = tid; x < mm; x += DBLOCK) A[x] = scale * Hh[x];
-  __syncthreads();
-
-  double cf[14];
-  for (int j = 0; j <= 13; ++j) cf[j] = j <= qd ? pade_coef(qd, j) : 0.0;
-  extern __shared__ double lu_lds[];   // B staging of the small GEMM, later the LU factors
-  auto gemm = [&](const double* X, const double* Y, double* Z) {
-    if (m <= LDS_M) bgemm_small(m, X, Y, Z, lu_lds);
-    else bgemm(m, X, Y, Z, As, Bs);
-  };
-
-  gemm(A, A, A2);
-  if (qd >= 5) gemm(A2, A2, A4);
-  if (qd >= 7) gemm(A2, A4, A6);
-  if (qd <= 9) {
-    // T1 = sum_{odd j} c_j A^{j-1}, Vm = sum_{even j} c_j A^j ; A8 = A4*A4 when q = 9
-    if (qd == 9) gemm(A4, A4, T2);
-    for (long long x = tid; x < mm; x += DBLOCK) {
-      const int r = (int)(x % m), cc = (int)(x / m);
-      const double I = r == cc ? 1.0 : 0.0;
-      double u = cf[1] * I + cf[3] * A2[x];
-      double v = cf[0] * I + cf[2] * A2[x];
-      if (qd >= 5) { u += cf[5] * A4[x]; v += cf[4] * A4[x]; }
-      if (qd >= 7) { u += cf[7] * A6[x]; v += cf[6] * A6[x]; }
-      if (qd >= 9) { u += cf[9] * T2[x]; v += cf[8] * T2[x]; }
-      T1[x] = u;
-      Vm[x] = v;
-    }
-    __syncthreads();
-    gemm(A, T1, U);
-  } else {
-    for (long long x = tid; x < mm; x += DBLOCK)
-      T1[x] = cf[13] * A6[x] + cf[11] * A4[x] + cf[9] * A2[x];
-    __syncthreads();
-    gemm(A6, T1, T2);
-    for (long long x = tid; x < mm; x += DBLOCK) {
-      const int r = (int)(x % m), cc = (int)(x / m);
-      const double I = r == cc ? 1.0 : 0.0;
-      T2[x] += cf[7] * A6[x] + cf[5] * A4[x] + cf[3] * A2[x] + cf[1] * I;
-      T1[x] = cf[12] * A6[x] + cf[10] * A4[x] + cf[8] * A2[x];
-    }
-    __syncthreads();
-    gemm(A, T2, U);
-    gemm(A6, T1, Vm);
-    for (long long x = tid; x < mm; x += DBLOCK) {
-      const int r = (int)(x % m), cc = (int)(x / m);
-      const double I = r == cc ? 1.0 : 0.0;
-      Vm[x] += cf[6] * A6[x] + cf[4] * A4[x] + cf[2] * A2[x] + cf[0] * I;
-    }
-    __syncthreads();
-  }
-  // P = V + U (into T1), Q = V - U (into Vm)
-  for (long long x = tid; x < mm; x += DBLOCK) {
-    const double u = U[x], v = Vm[x];
-    T1[x] = v + u;
-    Vm[x] = v - u;
-  }
-  __syncthreads();
-  // LU of Q = V - U in LDS when it fits
-  double* LU = Vm;
-  if (m <= LDS_M) {
-    for (long long x = tid; x < mm; x += DBLOCK) lu_lds[x] = Vm[x];
-    __syncthreads();
-    LU = lu_lds;
-  }
-  __shared__ double lu_tmp[2 * MAXM];
-  __shared__ double lu_l[MAXM];
-  const int sing = blu(m, LU, piv, lu_tmp, lu_l);
-  if (ssq == 0) {
-    // X e_1 = Q^{-1} P e_1
-    double* xv = (m <= LDS_M) ? nullptr : c;
-    __shared__ double xs_l[LDS_M];
-    if (m <= LDS_M) xv = xs_l;
-    for (int r = tid; r < m; r += DBLOCK) xv[r] = T1[r];
-    __syncthreads();
-    blu_solve1(m, LU, piv, xv);
-    for (int r = tid; r < m; r += DBLOCK) c[r] = xv[r];
-  } else {
-    blu_solve(m, LU, piv, T1, m);   // T1 = X = r(A / 2^s)
-    // X^(2^s) e_1: repeated squaring of the matrix, then the first column
-    double* Xa = T1;
-    double* Xb = T2;
-    for (int t = 0; t < ssq; ++t) {
-      gemm(Xa, Xa, Xb);
-      double* tmp = Xa; Xa = Xb; Xb = tmp;
-    }
-    for (int r = tid; r < m; r += DBLOCK) c[r] = Xa[r];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    info[INFO_NSQ] = ssq;
-    info[INFO_NRM] = nrm;
-    if (sing) info[INFO_FAIL] = 1.0;
-  }
 }
 
 // ----------------------------------------------------------------- polynomial
@@ -1022,14 +666,14 @@ __global__ void k_coef(SolveDev d, DenseDev g, double* cf) {
 hipError_t dense_set_attributes() {
   hipError_t e = hipSuccess, r;
   if ((r = hipFuncSetAttribute((const void*)k_lsq, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)) != hipSuccess) e = r;
-  if ((r = hipFuncSetAttribute((const void*)k_fexp, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)) != hipSuccess) e = r;
+  if ((r = exp_set_attributes()) != hipSuccess) e = r;
   return e;
 }
 
 hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st) {
   hipLaunchKernelGGL(k_lsq, dim3(d.nrhs), dim3(LBLOCK), lsq_lds_bytes(d.s, d.m), st, d, g);
   if (g.fkind == 1)
-    hipLaunchKernelGGL(k_fexp, dim3(d.nrhs), dim3(DBLOCK), d.m <= LDS_M ? (size_t)d.m * d.m * 8 : 0, st, d, g);
+    (void)exp_launch(d, g, st);
   else if (g.fkind == 2) hipLaunchKernelGGL(k_fpow, dim3(d.nrhs), dim3(64), 0, st, d, g);
   else hipLaunchKernelGGL(k_fpoly, dim3(d.nrhs), dim3(DBLOCK), 0, st, d, g);
   hipLaunchKernelGGL(k_coef, dim3(d.nrhs), dim3(256), 0, st, d, g, cf);

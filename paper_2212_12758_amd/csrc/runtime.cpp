@@ -213,7 +213,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   P.oDR = o; o += (size_t)(m + 1) * (m + 1);
   P.oDH = o; o += (size_t)m * m;
   P.oDM = o; o += (size_t)8 * m * m;
-  P.oDVec = o; o += (size_t)8 * (m + 1);
+  P.oDVec = o; o += (size_t)8 * (m + 1) + 32;   // vectors c, y, ...; exp parameter block behind them
   P.oDInfo = o; o += NINFO;
   P.dense_stride = (o + 31) & ~size_t(31);
   // workspace layout
