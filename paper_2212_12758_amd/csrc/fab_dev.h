@@ -82,6 +82,54 @@ struct DenseDev {
   double coef[MAXCOEF];
 };
 
+// ---------------------------------------------------------------- wave helpers
+// Index of this thread's wave in the workgroup, marked wave-uniform so that
+// branches on it stay scalar.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// Value of a double in lane `lane` (wave-uniform index) of this wave.
+__device__ inline double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Back substitution U x = z for upper-triangular U (order n <= 64 R,
+// column-major, leading dimension ldu) by one wave: rows lane + 64 u stay in
+// registers and x_j is read from its owner lane, so no barrier is needed.  A
+// zero diagonal entry gives x_j = 0.  z and x may alias.
+template <int R>
+__device__ void wave_upper_solve(int n, const double* U, long long ldu, const double* z, double* x) {
+  const int lane = threadIdx.x & 63;
+  double y[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    y[u] = r < n ? z[r] : 0.0;
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    const int uj = j >> 6;
+    double src = y[0];
+#pragma unroll
+    for (int u = 1; u < R; ++u)
+      if (uj == u) src = y[u];
+    const double ujj = U[j + (long long)j * ldu];
+    const double xj = ujj != 0.0 ? readlane_d(src, j & 63) / ujj : 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int r = lane + 64 * u;
+      if (r == j) y[u] = xj;
+      else if (r < j) y[u] -= U[r + (long long)j * ldu] * xj;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    if (r < n) x[r] = y[u];
+  }
+}
+
 // ---------------------------------------------------------------- SplitMix64
 // Counter-based SplitMix64 (Steele, Lea & Flood 2014): out(key, i) is the
 // i-th output of the generator whose state starts at `key`; stream keys are

@@ -219,7 +219,7 @@ __device__ inline int* rhs_brk(const SolveDev& d, int q) { return d.status + 5 +
 // Fixed-order block-wide sums of RC values per thread; result in out[0..RC) for every thread.
 template <int BLOCK, int RC>
 __device__ inline void block_sums(const double* a, double* red /* [BLOCK/64][RC] */, double* out) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = wave_id();
 #pragma unroll
   for (int c = 0; c < RC; ++c) {
     const double v = wave_sum_all(a[c]);
@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int n
   constexpr int RC = 10;
   if (d.status[0]) return;  // every rhs has broken down already
   __shared__ double red[NW * RC];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = wave_id();
   const int nr = d.nrhs;
   const int j0 = i - d.k > 0 ? i - d.k : 0;
   const int nw = i - j0;
@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_finish(SolveDev d) {
   __shared__ double sums[NSLOT * 32 + 32];
   __shared__ double cfl[33 * NSLOT + 32];
   const int i = d.m + 1;
-  reduce_sketch_column(d, i - 1, blockIdx.x * NW + (threadIdx.x >> 6), gridDim.x * NW);
+  reduce_sketch_column(d, i - 1, blockIdx.x * NW + wave_id(), gridDim.x * NW);
   if (blockIdx.x == 0) step_scalars<BLOCK>(d, i, false, d.npart + (long long)(d.m & 1) * d.nblk * d.nrhs, true, red, sums, cfl);
 }
 
@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   // previous update pass into the other buffer)
   const int nlead = START ? 0 : d.nred;
   if ((int)blockIdx.x < nlead) {
-    reduce_sketch_column(d, i - 1, blockIdx.x * NW + (threadIdx.x >> 6), nlead * NW);
+    reduce_sketch_column(d, i - 1, blockIdx.x * NW + wave_id(), nlead * NW);
     return;
   }
   const int blk = blockIdx.x - nlead;
@@ -557,7 +557,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   if (!START) {
     step_scalars<BLOCK>(d, i, true, d.npart + (long long)((i - 1) & 1) * d.nblk * d.nrhs, blk == 0, sred, ssums, cfl);
   }
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = wave_id();
   const int nr = d.nrhs;
   const long long nel = (long long)d.n * nr;
   const int j0 = i - d.k > 0 ? i - d.k : 0;

@@ -42,7 +42,7 @@ __device__ inline double wsum(double v) {
 
 // block-wide sum; `sh` holds >= 4 doubles; every thread gets the result
 __device__ inline double bsum(double v, double* sh) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = wave_id();
   v = wsum(v);
   __syncthreads();
   if (lane == 0) sh[wv] = v;
@@ -68,7 +68,7 @@ constexpr int LCS = 13;              // column slots per wave: cols wave + 8*cs 
 // |r_jj| extremes to rmm.
 __device__ void qr_registers(const double* __restrict__ S, const double* __restrict__ eta, int s, int ncol,
                              double* vsh, double* Rl, double* zl, double* tau_sh, double* rmm) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = wave_id();
   const int mu = ncol - 1;
   double a[LCS][LRS];
 #pragma unroll
@@ -185,7 +185,7 @@ __device__ void qr_registers(const double* __restrict__ S, const double* __restr
 // Same factorisation with W in global memory (any s, m); R, z to Rg / zl.
 __device__ void qr_global(const double* __restrict__ S, const double* __restrict__ eta, int s, int ncol, double* W,
                           double* zl, double* sh, double* rmm) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = wave_id();
   const int nth = blockDim.x, nwv = nth >> 6;
   const int mu = ncol - 1;
   for (long long x = tid; x < (long long)s * ncol; x += nth) {
@@ -275,27 +275,26 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
       rmax = fmax(rmax, rmm[2 * w]);
       rmin = fmin(rmin, rmm[2 * w + 1]);
     }
-    // back substitution R y = z, one barrier per row
-    for (int i = mu - 1; i >= 0; --i) {
-      const double rii = Rm[i + (long long)i * ldr];
-      const double yi = rii != 0.0 ? z[i] / rii : 0.0;
-      __syncthreads();
-      for (int x = tid; x < i; x += LBLOCK) z[x] -= Rm[x + (long long)i * ldr] * yi;
-      if (tid == 0) z[i] = yi;
-      __syncthreads();
+    // back substitution R y = z by one wave (no barriers)
+    __syncthreads();
+    if (tid < 64) {
+      if (mu <= 128) wave_upper_solve<2>(mu, Rm, ldr, z, z);
+      else if (mu <= 256) wave_upper_solve<4>(mu, Rm, ldr, z, z);
+      else wave_upper_solve<8>(mu, Rm, ldr, z, z);
     }
+    __syncthreads();
   } else {
     for (int x = tid; x < mu; x += LBLOCK) z[x] = 0.0;
     __syncthreads();
   }
   // H_hat = H_m + h_{m+1,m} y e_m^T (m_used x m_used, ld = mu)
   const double hlast = (mu > 0 && !brk) ? H[(long long)(mu - 1) * m1 + mu] : 0.0;
-  for (long long x = tid; x < (long long)mu * mu; x += LBLOCK) {
-    const int r = (int)(x % mu), c = (int)(x / mu);
-    double v = H[(long long)c * m1 + r];
-    if (c == mu - 1) v += hlast * z[r];
-    Hh[x] = v;
-  }
+  for (int c = wave_id(); c < mu; c += LBLOCK / 64)
+    for (int r = tid & 63; r < mu; r += 64) {
+      double v = H[(long long)c * m1 + r];
+      if (c == mu - 1) v += hlast * z[r];
+      Hh[r + (long long)c * mu] = v;
+    }
   if (tid == 0) {
     info[INFO_KAPPA] = do_ls ? (rmin > 0.0 ? rmax / rmin : 1e308) : 1.0;
     info[INFO_HLAST] = hlast;

@@ -321,3 +321,4 @@ def test_large_m_global_memory_dense_path(ctx, prec, tol):
         assert info[0]["m_used"] == 120
         assert krylov.relerr(out, krylov.fm(Aor, b, f, w.m)) < tol
     A.destroy()
+
