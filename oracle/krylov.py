@@ -145,6 +145,45 @@ def nt(A, b: np.ndarray, f, m: int, k: int, sketch=None, ls: str = "sketch"):
     return out
 
 
+def estimates(res: dict, f, unit_round: float) -> dict:
+    """A-posteriori quantities of the dense tail for a result of ``nt``.
+
+    Norms are taken as ||R x||, which approximates ||V_m x|| through the
+    sketch (Section 2.1.1); R is the factor of Theta V_m (identity without a
+    least-squares solve):
+
+    * ls_gate  = ||R (c - c_0)|| / ||R c||, c_0 = f(H_m) e_1: how far the
+      least-squares column of eq. (6) moves the result (eq. (8) vs Algorithm 4);
+    * conv_est = ||R (c - [c_d; 0])|| / ||R c||, c_d from the compression at
+      order m_d = m - max(5, m // 10), whose sketched least-squares solution
+      R_d^{-1} R[:m_d, m_d] comes from the same factor;
+    * round_est = u sum_j |c_j| ||R e_j|| / ||R c|| (u: basis unit roundoff),
+      the first-order effect of rounding every stored basis vector on V_m c.
+    After a breakdown the result is exact and both quantities are 0.
+    """
+    mu = res["m_used"]
+    H = res["Hbar"]
+    c = res["c"]
+    have_r = "R" in res
+    R = res["R"][:mu, :mu] if have_r else np.eye(mu)
+    c0 = matfun.fmat_e1(f, H[:mu, :mu])
+    md = mu - max(5, mu // 10)
+    cd = np.zeros(mu)
+    if md >= 1:
+        yd = sl.solve_triangular(R[:md, :md], R[:md, md]) if have_r else np.zeros(md)
+        Hd = H[:md, :md].copy()
+        if not res["breakdown"]:
+            Hd[:, md - 1] += H[md, md - 1] * yd
+        cd[:md] = matfun.fmat_e1(f, Hd)
+    nc = np.linalg.norm(R @ c)
+    gate = np.linalg.norm(R @ (c - c0)) / nc
+    conv = np.linalg.norm(R @ (c - cd)) / nc if md >= 1 else np.inf
+    rnd = unit_round * float(np.abs(c) @ np.linalg.norm(R, axis=0)) / nc
+    if res["breakdown"]:
+        gate = conv = 0.0
+    return {"ls_gate": float(gate), "conv_est": float(conv), "round_est": float(rnd)}
+
+
 def sfom(A, b: np.ndarray, f, m: int, k: int, sketch) -> np.ndarray:
     """sFOM, eq. (9): V_m R^{-1} f(S^T Theta A V_m R^{-1}) S^T Theta b,
     with Theta V_m = S R and the basis from Algorithm 2."""

@@ -74,13 +74,58 @@ struct DenseDev {
   int m, s, nrhs;
   long long stride;      // doubles per rhs
   double* base;
-  long long oW, oR, oH, oM, oVec, oInfo;   // Q [s*(m+1)], R [(m+1)^2], H_hat [m*m], 8 scratch m*m, vectors, info
+  // per-rhs regions: Householder workspace [s*(m+1)], R [m*m], compressed
+  // matrices [3][m*m] (one per variant), scratch [9*m*m], vectors [8(m+1)+32], info
+  long long oW, oR, oH, oM, oVec, oInfo;
   int ls_mode;           // 1 sketch-and-solve, 2 none
   int fkind;             // 1 exp, 2 pow, 3 poly
+  int nvar;              // f evaluations per rhs: 1, or 3 with the a-posteriori estimates
   double alpha, sigma, p;
+  double unit_round;     // unit roundoff of the basis storage (rounding estimate)
   int ncoef;
   double coef[MAXCOEF];
 };
+
+// Per-rhs info block (NINFO doubles), copied to the host after every solve.
+enum {
+  INFO_KAPPA = 0,    // kappa(R) of the sketched basis (|r_jj| max / min)
+  INFO_HLAST = 1,    // h_{m+1,m}
+  INFO_BETA = 2,     // ||b||
+  INFO_FAIL = 3,     // 1: singular / non-finite small problem, 2: Schur iteration failed
+  INFO_NSQ = 4,      // exp: scaling steps
+  INFO_SCHUR_IT = 5, // pow: Schur sweeps; exp: Taylor degree
+  INFO_NRM = 6,      // exp: ||alpha H_hat||_1
+  INFO_MD = 8,       // order m_used - d of the convergence-check variant
+  INFO_GATE = 9,     // ||R (c_y - c_0)|| / ||R c_y||
+  INFO_ROUND = 10,   // u sum_j |c_j| ||R e_j|| / ||R c||
+  INFO_CONV = 11,    // ||R (c - [c_{m-d}; 0])|| / ||R c||
+  INFO_VFAIL = 12    // [12 + v]: failure of variant v's f evaluation
+};
+
+// The f evaluations of the dense tail.  Variant 0 is the result (H_hat of
+// order m_used); with the estimates, variant 1 is H_m without the
+// least-squares correction (the cheaper approximation, eq. (8)) and variant 2
+// the compression at order m_used - d.  Each has its matrix (ld = its order),
+// output vector and scratch.
+struct DenseVariant {
+  int dim;
+  const double* H;
+  double* c;
+  double* scratch;      // 3 m*m doubles
+  double* info;
+};
+__device__ inline DenseVariant dense_variant(const SolveDev& d, const DenseDev& g, int q, int v) {
+  double* ws = g.base + (long long)q * g.stride;
+  const long long mm = (long long)g.m * g.m;
+  DenseVariant r;
+  const int mu = d.status[4 + 2 * q];
+  r.dim = v == 2 ? (int)ws[g.oInfo + INFO_MD] : mu;
+  r.H = ws + g.oH + v * mm;
+  r.c = ws + g.oVec + (v == 0 ? 0 : (v == 1 ? 5 : 6) * (long long)(g.m + 1));
+  r.scratch = ws + g.oM + 3 * v * mm;
+  r.info = ws + g.oInfo;
+  return r;
+}
 
 // ---------------------------------------------------------------- wave helpers
 // Index of this thread's wave in the workgroup, marked wave-uniform so that

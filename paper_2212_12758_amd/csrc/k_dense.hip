@@ -26,7 +26,6 @@ hipError_t exp_set_attributes();
 
 constexpr int DBLOCK = 256;
 constexpr int MAXM = 512;
-enum { INFO_KAPPA = 0, INFO_HLAST = 1, INFO_BETA = 2, INFO_FAIL = 3, INFO_NSQ = 4, INFO_SCHUR_IT = 5, INFO_NRM = 6 };
 
 // Orders this wave's memory operations (LDS and global) without a workgroup
 // barrier; used inside sections that only one wave executes.
@@ -255,7 +254,7 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
   const double* H = d.H + (long long)q * m1 * m;
   const double* S = d.S + (long long)q * s * m1;
   const bool do_ls = (!brk) && mu > 0 && g.ls_mode != 2;
-  const bool in_regs = s <= 64 * LRS && mu + 1 <= 8 * LCS;
+  const bool in_regs = s <= 64 * LRS && m + 1 <= 8 * LCS;   // as planned (m_used <= m)
   double* vsh = lsh;                    // two reflector buffers
   double* z = vsh + 2 * 64 * LRS;
   double* Rl = z + m1;
@@ -295,11 +294,50 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
       if (c == mu - 1) v += hlast * z[r];
       Hh[r + (long long)c * mu] = v;
     }
+  // R_m for the estimates (ld m_used)
+  double* Rg = ws + g.oR;
+  if (do_ls)
+    for (int c = wave_id(); c < mu; c += LBLOCK / 64)
+      for (int r = tid & 63; r < mu; r += 64) Rg[r + (long long)c * mu] = r <= c ? Rm[r + (long long)c * ldr] : 0.0;
+  if (g.nvar == 3) {
+    // variant 1: H_m (no least-squares correction); variant 2: the
+    // compression at order md = m_used - max(5, m_used/10)
+    const long long mmf = (long long)m * m;
+    double* H1 = Hh + mmf;
+    double* H2 = Hh + 2 * mmf;
+    int md = mu - (mu / 10 > 5 ? mu / 10 : 5);
+    if (md < 1) md = 0;
+    for (int c = wave_id(); c < mu; c += LBLOCK / 64)
+      for (int r = tid & 63; r < mu; r += 64) H1[r + (long long)c * mu] = H[(long long)c * m1 + r];
+    double* z2 = z + m1 + (in_regs ? (long long)m * m : 0);
+    if (md >= 1) {
+      if (do_ls) {
+        if (tid < 64) {
+          // y' = R_md^{-1} R[0:md, md]: the sketched LS solution at order md
+          if (md <= 128) wave_upper_solve<2>(md, Rm, ldr, Rm + (long long)md * ldr, z2);
+          else if (md <= 256) wave_upper_solve<4>(md, Rm, ldr, Rm + (long long)md * ldr, z2);
+          else wave_upper_solve<8>(md, Rm, ldr, Rm + (long long)md * ldr, z2);
+        }
+      } else {
+        for (int x = tid; x < md; x += LBLOCK) z2[x] = 0.0;
+      }
+      __syncthreads();
+      const double hl2 = brk ? 0.0 : H[(long long)(md - 1) * m1 + md];
+      for (int c = wave_id(); c < md; c += LBLOCK / 64)
+        for (int r = tid & 63; r < md; r += 64) {
+          double v = H[(long long)c * m1 + r];
+          if (c == md - 1) v += hl2 * z2[r];
+          H2[r + (long long)c * md] = v;
+        }
+    }
+    if (tid == 0) info[INFO_MD] = md;
+  }
   if (tid == 0) {
     info[INFO_KAPPA] = do_ls ? (rmin > 0.0 ? rmax / rmin : 1e308) : 1.0;
     info[INFO_HLAST] = hlast;
     info[INFO_BETA] = eta[0];
     info[INFO_FAIL] = 0.0;
+    info[INFO_VFAIL + 1] = info[INFO_VFAIL + 2] = 0.0;
   }
   double* yout = ws + g.oVec + 2 * (long long)m;
   for (int x = tid; x < mu; x += LBLOCK) yout[x] = z[x];
@@ -307,20 +345,19 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
 
 size_t lsq_lds_bytes(int s, int m) {
   const bool in_regs = s <= 64 * LRS && m + 1 <= 8 * LCS;
-  return (size_t)(2 * 64 * LRS + (m + 1) + (in_regs ? (size_t)m * m : 0)) * 8;
+  return (size_t)(2 * 64 * LRS + 2 * (m + 1) + (in_regs ? (size_t)m * m : 0)) * 8;
 }
 
 // ----------------------------------------------------------------- polynomial
 __global__ void __launch_bounds__(DBLOCK) k_fpoly(SolveDev d, DenseDev g) {
   const int q = blockIdx.x;
   const int tid = threadIdx.x;
-  double* ws = g.base + (long long)q * g.stride;
-  const int mu = *st_mused(d, q);
-  if (mu == 0) return;
-  const int m = mu;
-  const double* Hh = ws + g.oH;
-  double* c = ws + g.oVec;
-  double* t = ws + g.oM;       // scratch vector
+  const DenseVariant dv = dense_variant(d, g, q, blockIdx.y);
+  if (dv.dim == 0) return;
+  const int m = dv.dim;
+  const double* Hh = dv.H;
+  double* c = dv.c;
+  double* t = dv.scratch;      // scratch vector
   for (int r = tid; r < m; r += DBLOCK) c[r] = 0.0;
   __syncthreads();
   for (int j = g.ncoef - 1; j >= 0; --j) {     // Horner: c <- H_hat c + coef_j e_1
@@ -518,17 +555,17 @@ __global__ void __launch_bounds__(64) k_fpow(SolveDev d, DenseDev g) {
   __shared__ int bstart[MAXM + 1];
   __shared__ double zt[MAXM];
   __shared__ double xs[MAXM];
-  double* ws = g.base + (long long)q * g.stride;
-  const int mu = *st_mused(d, q);
-  double* c = ws + g.oVec;
-  double* info = ws + g.oInfo;
-  if (mu == 0) return;
-  const int m = mu;
+  const int v = blockIdx.y;
+  const DenseVariant dv = dense_variant(d, g, q, v);
+  double* c = dv.c;
+  double* info = dv.info;
+  if (dv.dim == 0) return;
+  const int m = dv.dim;
   const long long mm = (long long)m * m;
-  double* T = ws + g.oM;
+  double* T = dv.scratch;
   double* Z = T + mm;
   double* R = Z + mm;
-  const double* Hh = ws + g.oH;
+  const double* Hh = dv.H;
   for (long long x = lane; x < mm; x += 64) {
     const int r = (int)(x % m), cc = (int)(x / m);
     T[x] = Hh[x] + (r == cc ? g.sigma : 0.0);
@@ -540,7 +577,7 @@ __global__ void __launch_bounds__(64) k_fpow(SolveDev d, DenseDev g) {
   const int sweeps = francis_schur(m, T, Z);
   __syncthreads();
   if (sweeps < 0) {
-    if (lane == 0) info[INFO_FAIL] = 2.0;
+    if (lane == 0) info[v == 0 ? INFO_FAIL : INFO_VFAIL + v] = 2.0;
     for (int r = lane; r < m; r += 64) c[r] = 0.0;
     return;
   }
@@ -646,7 +683,7 @@ __global__ void __launch_bounds__(64) k_fpow(SolveDev d, DenseDev g) {
     for (int cc = 0; cc < m; ++cc) a += Z[r + (long long)cc * m] * xs[cc];
     c[r] = a;
   }
-  if (lane == 0) info[INFO_SCHUR_IT] = sweeps;
+  if (lane == 0 && v == 0) info[INFO_SCHUR_IT] = sweeps;
 }
 
 // ----------------------------------------------------------------- combination weights
@@ -669,12 +706,83 @@ hipError_t dense_set_attributes() {
   return e;
 }
 
+// ----------------------------------------------------------------- a-posteriori estimates
+// With R the triangular factor of the sketched basis (||R x|| approximates
+// ||V x||, Section 2.1.1), per rhs:
+//   ls gate     ||R (c - c_0)|| / ||R c||     c_0 = f(H_m) e_1 (eq. (8)): how much
+//                                             the least-squares column moves the result
+//   convergence ||R (c - [c_{m-d}; 0])|| / ||R c||
+//   rounding    u sum_j |c_j| ||R e_j|| / ||R c||   (first-order effect of
+//               rounding every stored basis vector on V c)
+// Without a least-squares solve (breakdown, or no LS requested) R is replaced
+// by the identity.
+__global__ void __launch_bounds__(256) k_estimates(SolveDev d, DenseDev g) {
+  const int q = blockIdx.x, tid = threadIdx.x;
+  __shared__ double sh[16];
+  double* ws = g.base + (long long)q * g.stride;
+  double* info = ws + g.oInfo;
+  const int mu = *st_mused(d, q);
+  const int brk = *st_brk(d, q);
+  if (mu == 0) {
+    if (tid == 0) info[INFO_GATE] = info[INFO_ROUND] = info[INFO_CONV] = 0.0;
+    return;
+  }
+  const int md = (int)info[INFO_MD];
+  const bool have_r = !brk && g.ls_mode != 2;
+  const double* R = ws + g.oR;
+  const DenseVariant v0 = dense_variant(d, g, q, 0), v1 = dense_variant(d, g, q, 1), v2 = dense_variant(d, g, q, 2);
+  const double* c = v0.c;
+  const double* c0 = v1.c;
+  const double* cd = v2.c;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, sr = 0.0;
+  for (int r = tid; r < mu; r += 256) {
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0, cn = 0.0;
+    if (have_r) {
+      for (int k = r; k < mu; ++k) {
+        const double a = R[r + (long long)k * mu];
+        w0 += a * c[k];
+        w1 += a * (c[k] - c0[k]);
+        w2 += a * (c[k] - (k < md ? cd[k] : 0.0));
+      }
+      for (int k = 0; k <= r; ++k) cn += R[k + (long long)r * mu] * R[k + (long long)r * mu];
+      cn = sqrt(cn);
+    } else {
+      w0 = c[r];
+      w1 = c[r] - c0[r];
+      w2 = c[r] - (r < md ? cd[r] : 0.0);
+      cn = 1.0;
+    }
+    s0 += w0 * w0;
+    s1 += w1 * w1;
+    s2 += w2 * w2;
+    sr += fabs(c[r]) * cn;
+  }
+  s0 = bsum(s0, sh);
+  s1 = bsum(s1, sh);
+  s2 = bsum(s2, sh);
+  sr = bsum(sr, sh);
+  if (tid == 0) {
+    const double n0 = sqrt(s0);
+    const double inf = __builtin_huge_val();
+    double gate = n0 > 0.0 ? sqrt(s1) / n0 : (s1 > 0.0 ? inf : 0.0);
+    double conv = md >= 1 ? (n0 > 0.0 ? sqrt(s2) / n0 : inf) : inf;
+    if (brk) gate = conv = 0.0;   // invariant subspace: the result is exact
+    if (info[INFO_VFAIL + 1] != 0.0 || !isfinite(gate)) gate = inf;
+    if (info[INFO_VFAIL + 2] != 0.0 || !isfinite(conv)) conv = brk ? 0.0 : inf;
+    info[INFO_GATE] = gate;
+    info[INFO_ROUND] = n0 > 0.0 ? g.unit_round * sr / n0 : 0.0;
+    info[INFO_CONV] = conv;
+  }
+}
+
 hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st) {
   hipLaunchKernelGGL(k_lsq, dim3(d.nrhs), dim3(LBLOCK), lsq_lds_bytes(d.s, d.m), st, d, g);
+  const dim3 gv(d.nrhs, g.nvar);
   if (g.fkind == 1)
     (void)exp_launch(d, g, st);
-  else if (g.fkind == 2) hipLaunchKernelGGL(k_fpow, dim3(d.nrhs), dim3(64), 0, st, d, g);
-  else hipLaunchKernelGGL(k_fpoly, dim3(d.nrhs), dim3(DBLOCK), 0, st, d, g);
+  else if (g.fkind == 2) hipLaunchKernelGGL(k_fpow, gv, dim3(64), 0, st, d, g);
+  else hipLaunchKernelGGL(k_fpoly, gv, dim3(DBLOCK), 0, st, d, g);
+  if (g.nvar == 3) hipLaunchKernelGGL(k_estimates, dim3(d.nrhs), dim3(256), 0, st, d, g);
   hipLaunchKernelGGL(k_coef, dim3(d.nrhs), dim3(256), 0, st, d, g, cf);
   return hipGetLastError();
 }

@@ -25,8 +25,6 @@ constexpr double RHO_MAX = 4.0;    // scaled norm per step
 constexpr double TAYLOR_TOL = 1e-18;
 constexpr int KMAX_TAYLOR = 64;
 
-__device__ inline int exp_mused(const SolveDev& d, int q) { return d.status[4 + 2 * q]; }
-
 template <typename Ptr>
 __device__ __forceinline__ void taylor_action(int m, Ptr H, double alpha, double* xs, double* ts, double* part,
                                               double* out, double* info, double* red) {
@@ -89,23 +87,23 @@ __device__ __forceinline__ void taylor_action(int m, Ptr H, double alpha, double
   }
   for (int r = tid; r < m; r += 256) out[r] = xs[r];
   if (tid == 0) {
-    info[4] = S;     // scaling steps
-    info[5] = K;     // Taylor degree
-    info[6] = nrm;   // ||alpha H_hat||_1
+    info[INFO_NSQ] = S;        // scaling steps
+    info[INFO_SCHUR_IT] = K;   // Taylor degree
+    info[INFO_NRM] = nrm;      // ||alpha H_hat||_1
   }
 }
 
 }  // namespace
 
 __global__ void __launch_bounds__(256) k_exp_taylor(SolveDev d, DenseDev g) {
-  const int q = blockIdx.x, tid = threadIdx.x;
-  double* ws = g.base + (long long)q * g.stride;
-  const int m = exp_mused(d, q);
+  const int q = blockIdx.x, tid = threadIdx.x, v = blockIdx.y;
+  const DenseVariant dv = dense_variant(d, g, q, v);
+  const int m = dv.dim;
   if (m == 0) return;
   const long long mm = (long long)m * m;
-  const double* Hh = ws + g.oH;
-  double* c = ws + g.oVec;
-  double* info = ws + g.oInfo;
+  const double* Hh = dv.H;
+  double* c = dv.c;
+  double* info = v == 0 ? dv.info : dv.scratch;   // the variants' scalars are not reported
   extern __shared__ double h_lds[];
   __shared__ double xs[EMAXM], ts[EMAXM], part[2 * EMAXM];
   __shared__ double red[4];
@@ -122,7 +120,7 @@ __global__ void __launch_bounds__(256) k_exp_taylor(SolveDev d, DenseDev g) {
 size_t exp_lds_bytes(int m) { return m <= LDSM ? (size_t)m * m * 8 : 0; }
 
 hipError_t exp_launch(const SolveDev& d, const DenseDev& g, hipStream_t st) {
-  hipLaunchKernelGGL(k_exp_taylor, dim3(d.nrhs), dim3(256), exp_lds_bytes(d.m), st, d, g);
+  hipLaunchKernelGGL(k_exp_taylor, dim3(d.nrhs, g.nvar), dim3(256), exp_lds_bytes(d.m), st, d, g);
   return hipGetLastError();
 }
 

@@ -147,6 +147,7 @@ struct Plan {
   std::vector<double> coef;
   fab_params p{};
   int esize = 4;
+  int nvar = 1;                // dense f evaluations per rhs (3 with the a-posteriori estimates)
   // derived
   int LT = 12, R = 0, logR = 0, ntiles = 0, nblk = 0, nred = 0;
   long long ldv = 0;
@@ -191,6 +192,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   if (f.kind == FAB_F_POLY) P.coef.assign(f.coef, f.coef + f.ncoef);
   P.p = p;
   P.esize = esize;
+  P.nvar = (p.prec == FAB_PREC_AUTO || p.ls_mode == FAB_LS_AUTO) ? 3 : 1;
   // tiles of 2^LT elements (rows x rhs): 2048 for large problems, 512 below
   // 2^20 elements so that smaller problems still spread over many blocks
   const long long nel = n * nrhs;
@@ -211,8 +213,8 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   size_t o = 0;
   P.oDW = o; o += (size_t)s * (m + 1);
   P.oDR = o; o += (size_t)(m + 1) * (m + 1);
-  P.oDH = o; o += (size_t)m * m;
-  P.oDM = o; o += (size_t)8 * m * m;
+  P.oDH = o; o += (size_t)3 * m * m;     // one compressed matrix per variant
+  P.oDM = o; o += (size_t)9 * m * m;     // 3 m*m scratch per variant
   P.oDVec = o; o += (size_t)8 * (m + 1) + 32;   // vectors c, y, ...; exp parameter block behind them
   P.oDInfo = o; o += NINFO;
   P.dense_stride = (o + 31) & ~size_t(31);
@@ -328,6 +330,7 @@ struct Request {
   int status = FAB_OK;
   double t_submit = 0.0, t_done = 0.0;
   std::vector<fab_info> info;
+  int fell_back = 0;             // recomputed with an FP64 basis (FAB_PREC_AUTO)
 };
 
 // Sampled SRHT rows for (npad, s, seed): computed once on `st` (which the
@@ -420,6 +423,8 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
   g.oVec = (long long)P.oDVec;
   g.oInfo = (long long)P.oDInfo;
   g.ls_mode = p.ls_mode == FAB_LS_NONE ? 2 : 1;
+  g.nvar = P.nvar;
+  g.unit_round = d.unit_round;
   g.fkind = P.f.kind;
   g.alpha = P.f.alpha;
   g.sigma = P.f.sigma;
@@ -491,10 +496,14 @@ int collect_info(const Plan& P, const double* hinfo, std::vector<fab_info>& out)
     fi.h_last = in[1];
     fi.beta = in[2];
     fi.prec_used = P.esize == 4 ? FAB_PREC_FP32 : FAB_PREC_FP64;
-    fi.err_est = 0.0;
-    fi.ls_gate = 0.0;
-    fi.round_est = 0.0;
-    fi.conv_est = 0.0;
+    if (P.nvar == 3) {
+      fi.ls_gate = in[INFO_GATE];
+      fi.round_est = in[INFO_ROUND];
+      fi.conv_est = in[INFO_CONV];
+      fi.err_est = std::max(fi.ls_gate, fi.round_est);
+    } else {
+      fi.err_est = fi.ls_gate = fi.round_est = fi.conv_est = 0.0;
+    }
     fi.ls_iters = 0;
     fi.fell_back = 0;
     if (in[3] != 0.0) rc = FAB_ENUMERIC;
@@ -505,9 +514,42 @@ int collect_info(const Plan& P, const double* hinfo, std::vector<fab_info>& out)
 
 int esize_for(int prec) { return prec == FAB_PREC_FP64 ? 8 : 4; }
 
+// FAB_PREC_AUTO: an FP32-basis result is recomputed with an FP64 basis when
+// the basis-rounding estimate exceeds tol/4 or the FP32 run produced
+// non-finite values.
+bool needs_fp64_rerun(const Plan& P, int rc, const std::vector<fab_info>& fi) {
+  if (P.p.prec != FAB_PREC_AUTO || P.esize != 4) return false;
+  if (rc == FAB_ENUMERIC) return true;
+  if (rc != FAB_OK) return false;
+  for (const auto& x : fi)
+    if (!(x.round_est <= P.p.tol / 4)) return true;
+  return false;
+}
+
 // ---------------------------------------------------------------- scheduler
 void retire_locked(fab_ctx ctx, Request& r) {
   r.status = collect_info(r.plan, r.host_info, r.info);
+  if (!r.fell_back && needs_fp64_rerun(r.plan, r.status, r.info)) {
+    // FAB_PREC_AUTO: queue the request again, first in line, with an FP64 basis
+    Plan P2;
+    fab_func f2 = r.plan.f;
+    if (f2.kind == FAB_F_POLY) f2.coef = r.plan.coef.data();   // the caller's array may be gone
+    if (make_plan(r.plan.A, r.plan.nrhs, f2, &r.plan.p, 8, P2) == FAB_OK &&
+        ctx->arena.could_ever_fit(P2.bytes)) {
+      P2.b = r.plan.b;
+      P2.out = r.plan.out;
+      ctx->arena.release(r.ws);
+      r.ws = nullptr;
+      ctx->pool_busy[r.stream_idx] = 0;
+      r.plan = P2;
+      r.fell_back = 1;
+      r.state = 0;
+      ctx->queue.push_front(r.id);
+      return;
+    }
+  }
+  if (r.fell_back)
+    for (auto& fi : r.info) fi.fell_back = 1;
   r.t_done = now_us();
   for (auto& fi : r.info) fi.latency_us = r.t_done - r.t_submit;
   ctx->arena.release(r.ws);
@@ -855,34 +897,54 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
   const double t0 = now_us();
   std::lock_guard<std::mutex> slk(ctx->solve_mu);
   hipSetDevice(ctx->device);
-  int first_prec = p->prec == FAB_PREC_FP64 ? FAB_PREC_FP64 : FAB_PREC_FP32;
+  int esize = esize_for(p->prec == FAB_PREC_FP64 ? FAB_PREC_FP64 : FAB_PREC_FP32);
   Plan P;
-  int rc = make_plan(A, nrhs, f, p, esize_for(first_prec), P);
-  if (rc != FAB_OK) return rc;
-  P.b = b;
-  P.out = out;
-  char* ws = nullptr;
-  {
-    std::unique_lock<std::mutex> lk(ctx->mu);
-    if (!ctx->arena.could_ever_fit(P.bytes)) return FAB_ENOMEM;
-    while (!(ws = (char*)ctx->arena.alloc(P.bytes))) {
-      bool running = false;
-      for (auto& kv : ctx->reqs)
-        if (kv.second->state == 1) running = true;
-      if (!running) return FAB_ENOMEM;
-      ctx->cv.wait_for(lk, std::chrono::milliseconds(1));
-    }
-  }
-  const int* rows = nullptr;
-  if (P.p.sketch == FAB_SKETCH_SRHT) {
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    rows = srht_rows_cached(ctx, 1LL << ilog2(A->n), P.p.s, P.p.seed, ctx->stream, &rc);
-  }
-  if (rc == FAB_OK) rc = launch_solve(ctx, P, ws, rows, f);
-  if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == FAB_OK) rc = FAB_EDEVICE;
-  if (ctx->prof.mask) ctx->prof.harvest();
   std::vector<fab_info> fi;
-  if (rc == FAB_OK) rc = collect_info(P, ctx->host_info, fi);
+  char* ws = nullptr;
+  int rc = FAB_OK;
+  bool fell_back = false;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    rc = make_plan(A, nrhs, f, p, esize, P);
+    if (rc != FAB_OK) return rc;
+    P.b = b;
+    P.out = out;
+    {
+      std::unique_lock<std::mutex> lk(ctx->mu);
+      if (!ctx->arena.could_ever_fit(P.bytes)) return FAB_ENOMEM;
+      while (!(ws = (char*)ctx->arena.alloc(P.bytes))) {
+        bool running = false;
+        for (auto& kv : ctx->reqs)
+          if (kv.second->state == 1) running = true;
+        if (!running) return FAB_ENOMEM;
+        ctx->cv.wait_for(lk, std::chrono::milliseconds(1));
+      }
+    }
+    const int* rows = nullptr;
+    if (P.p.sketch == FAB_SKETCH_SRHT) {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      rows = srht_rows_cached(ctx, 1LL << ilog2(A->n), P.p.s, P.p.seed, ctx->stream, &rc);
+    }
+    if (rc == FAB_OK) rc = launch_solve(ctx, P, ws, rows, f);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == FAB_OK) rc = FAB_EDEVICE;
+    if (ctx->prof.mask) ctx->prof.harvest();
+    fi.clear();
+    if (rc == FAB_OK || rc == FAB_ENUMERIC) {
+      const int rc2 = collect_info(P, ctx->host_info, fi);
+      if (rc == FAB_OK) rc = rc2;
+    }
+    if (attempt == 0 && needs_fp64_rerun(P, rc, fi)) {
+      // FAB_PREC_AUTO: recompute the whole request with an FP64 basis
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->arena.release(ws);
+      ws = nullptr;
+      esize = 8;
+      fell_back = true;
+      continue;
+    }
+    break;
+  }
+  if (fell_back)
+    for (auto& x : fi) x.fell_back = 1;
   if (diag && (rc == FAB_OK || rc == FAB_ENUMERIC)) {
     const int m = P.p.m, s = P.p.s;
     for (int q = 0; q < nrhs; ++q) {

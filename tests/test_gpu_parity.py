@@ -322,3 +322,74 @@ def test_large_m_global_memory_dense_path(ctx, prec, tol):
         assert krylov.relerr(out, krylov.fm(Aor, b, f, w.m)) < tol
     A.destroy()
 
+
+
+# ------------------------------------------------------------------ a-posteriori estimates and the FP64 fallback
+def test_estimates_match_oracle_and_auto_precision(ctx):
+    from paper_2212_12758_amd import make_params
+
+    base = W.config("convdiff3d_128_exp", scale=24)
+    w = W.Workload(base.name, base.op, base.b_seed, 1, base.f, m=40, k=4, s=100, sketch="srht", sketch_seed=7)
+    print("case estimates convdiff N=24", flush=True)
+    Aor = operators.as_matrix(w.op)
+    b = W.rhs(w.n, w.b_seed)
+    A = ctx.matrix(w.op)
+    fm = krylov.fm(Aor, b, w.f, w.m)
+    # FP64 basis with the estimates (ls auto): the values follow their definitions
+    p64 = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, "fp64", "auto", 1e-10)
+    out, info = ctx.solve(A, _dev(b), w.f, p64)
+    ref, sk = _oracle(w, Aor, b)
+    est = krylov.estimates(ref, w.f, 2.0**-53)
+    for key in ("ls_gate", "conv_est", "round_est"):
+        assert info[0][key] == pytest.approx(est[key], rel=1e-6, abs=1e-15), key
+    assert info[0]["err_est"] == max(info[0]["ls_gate"], info[0]["round_est"])
+    assert krylov.relerr(out.cpu().numpy(), fm) < TOL64
+    # automatic precision, loose tolerance: the FP32 basis is accepted
+    pa = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, "auto", "auto", 1e-6)
+    out, info = ctx.solve(A, _dev(b), w.f, pa)
+    assert info[0]["fell_back"] == 0 and info[0]["prec_used"] == 1
+    assert info[0]["round_est"] <= 1e-6 / 4
+    assert krylov.relerr(out.cpu().numpy(), fm) < TOL32
+    # automatic precision, tolerance below FP32 rounding: recomputed with an FP64 basis
+    pt = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, "auto", "auto", 1e-11)
+    out, info = ctx.solve(A, _dev(b), w.f, pt)
+    assert info[0]["fell_back"] == 1 and info[0]["prec_used"] == 2
+    assert krylov.relerr(out.cpu().numpy(), fm) < TOL64
+    # the same through the serving path
+    outs = _dev(np.zeros(w.n))
+    req = ctx.submit(A, _dev(b), w.f, pt, outs)
+    info = req.wait()
+    assert info[0]["fell_back"] == 1 and info[0]["prec_used"] == 2
+    assert krylov.relerr(outs.cpu().numpy(), fm) < TOL64
+    A.destroy()
+
+
+def test_estimates_sqrt_variants_and_breakdown(ctx):
+    from paper_2212_12758_amd import make_params
+
+    st = W.laplacian2d(40, 37)
+    b = W.rhs(st.n, 11)
+    Aor = operators.as_matrix(st)
+    A = ctx.matrix(st)
+    f = W.FuncSpec("pow", sigma=1e-3, p=-0.5)
+    w = W.Workload("lap", st, 11, 1, f, m=30, k=2, s=70, sketch="sparse_sign", sketch_seed=4)
+    print("case estimates invsqrt", flush=True)
+    p = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, "fp64", "auto", 1e-10)
+    out, info = ctx.solve(A, _dev(b), f, p)
+    ref, sk = _oracle(w, Aor, b)
+    est = krylov.estimates(ref, f, 2.0**-53)
+    for key in ("ls_gate", "conv_est"):
+        assert info[0][key] == pytest.approx(est[key], rel=1e-5, abs=1e-14), key
+    # lucky breakdown: exact result, both estimates 0
+    d = np.repeat([0.5, 1.0, 2.0, 3.5, 5.0], 40)
+    M = sp.diags(d).tocsr()
+    bd = W.rhs(len(d), 3)
+    Ad = ctx.matrix((M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float32)))
+    fe = W.FuncSpec("exp", alpha=-0.3)
+    pd = make_params(12, 2, 40, "sparse_sign", 8, 2, "fp64", "auto", 1e-10)
+    out, info = ctx.solve(Ad, _dev(bd), fe, pd)
+    assert info[0]["breakdown"] == 1 and info[0]["m_used"] == 5
+    assert info[0]["ls_gate"] == 0.0 and info[0]["conv_est"] == 0.0
+    assert krylov.relerr(out.cpu().numpy(), closed_form.diagonal_fAb(d, fe, bd)) < 1e-12
+    Ad.destroy()
+    A.destroy()

@@ -338,3 +338,34 @@ def test_planted_transpose_slip_in_fm_is_caught():
     ref = closed_form.dense_fAb(A, EXP1, b)
     assert krylov.relerr(krylov.fm(sp.csr_matrix(A), b, EXP1, m), ref) < 1e-12
     assert krylov.relerr(wrong, ref) > 1e-6
+
+
+def test_estimates_definitions_pinned():
+    """a-posteriori quantities: the order-m_d variant equals the method run at
+    m_d (same basis prefix, leading block of the same QR factor); the gate is
+    exactly 0 without a least-squares column; the sketched norms agree with
+    the true norms of V_m x within the embedding distortion."""
+    st = W.convdiff3d(14, 50.0)
+    A = operators.as_matrix(st)
+    b = W.rhs(st.n, 21)
+    f = W.FuncSpec("exp", alpha=-2e-3)
+    m, k, s = 30, 3, 120
+    sk = sketch.Sketch("sparse_sign", st.n, s, 5, 8)
+    res = krylov.nt(A, b, f, m, k, sk, "sketch")
+    est = krylov.estimates(res, f, 2.0**-53)
+    md = m - max(5, m // 10)
+    res_d = krylov.nt(A, b, f, md, k, sk, "sketch")
+    R = res["R"]
+    c = res["c"]
+    cd = np.zeros(m)
+    cd[:md] = res_d["c"]
+    assert np.linalg.norm(R @ (c - cd)) / np.linalg.norm(R @ c) == pytest.approx(est["conv_est"], rel=1e-8)
+    V = res["V"][:m].T
+    true_conv = np.linalg.norm(V @ (c - cd)) / np.linalg.norm(V @ c)
+    assert true_conv / 3 <= est["conv_est"] <= 3 * true_conv
+    c0 = krylov.nt(A, b, f, m, k, sk, "none")["c"]
+    true_gate = np.linalg.norm(V @ (c - c0)) / np.linalg.norm(V @ c)
+    assert true_gate / 3 <= est["ls_gate"] <= 3 * true_gate
+    assert est["round_est"] >= 2.0**-53   # sum_j |c_j| ||R e_j|| >= ||R c||
+    none = krylov.nt(A, b, f, m, k, sk, "none")
+    assert krylov.estimates(none, f, 2.0**-24)["ls_gate"] == 0.0
