@@ -95,11 +95,24 @@ enum {
   INFO_NSQ = 4,      // exp: scaling steps
   INFO_SCHUR_IT = 5, // pow: Schur sweeps; exp: Taylor degree
   INFO_NRM = 6,      // exp: ||alpha H_hat||_1
+  INFO_LSQR_IT = 7,  // LSQR refinement iterations
   INFO_MD = 8,       // order m_used - d of the convergence-check variant
   INFO_GATE = 9,     // ||R (c_y - c_0)|| / ||R c_y||
   INFO_ROUND = 10,   // u sum_j |c_j| ||R e_j|| / ||R c||
   INFO_CONV = 11,    // ||R (c - [c_{m-d}; 0])|| / ||R c||
-  INFO_VFAIL = 12    // [12 + v]: failure of variant v's f evaluation
+  INFO_VFAIL = 12,   // [12 + v]: failure of variant v's f evaluation
+  INFO_LSQR_RATIO = 15   // last LSQR step relative to the solution (z-norm)
+};
+
+// LSQR refinement state (see k_lsqr.hip)
+struct LsqrDev {
+  double* u;             // [n][nrhs] FP64 LSQR vector (unnormalised)
+  double* part;          // [nblk][nrhs][m+1] per-block dots and norm
+  double* st;            // [nrhs][stride] per-rhs vectors and scalars
+  long long stride;
+  int* alldone;          // every rhs stopped: remaining launches return
+  int nblk, maxit;
+  double tol;            // stop when the step is below tol relative to z
 };
 
 // The f evaluations of the dense tail.  Variant 0 is the result (H_hat of

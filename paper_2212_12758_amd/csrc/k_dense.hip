@@ -338,6 +338,7 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
     info[INFO_BETA] = eta[0];
     info[INFO_FAIL] = 0.0;
     info[INFO_VFAIL + 1] = info[INFO_VFAIL + 2] = 0.0;
+    info[INFO_LSQR_IT] = info[INFO_LSQR_RATIO] = 0.0;
   }
   double* yout = ws + g.oVec + 2 * (long long)m;
   for (int x = tid; x < mu; x += LBLOCK) yout[x] = z[x];
@@ -773,6 +774,20 @@ __global__ void __launch_bounds__(256) k_estimates(SolveDev d, DenseDev g) {
     info[INFO_ROUND] = n0 > 0.0 ? g.unit_round * sr / n0 : 0.0;
     info[INFO_CONV] = conv;
   }
+}
+
+// After an LSQR refinement has rebuilt H_hat: f for the result only, the
+// estimates (against the variants of the first pass) and the weights.
+hipError_t dense_after_refine(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st) {
+  DenseDev g1 = g;
+  g1.nvar = 1;
+  if (g.fkind == 1)
+    (void)exp_launch(d, g1, st);
+  else if (g.fkind == 2) hipLaunchKernelGGL(k_fpow, dim3(d.nrhs, 1), dim3(64), 0, st, d, g1);
+  else hipLaunchKernelGGL(k_fpoly, dim3(d.nrhs, 1), dim3(DBLOCK), 0, st, d, g1);
+  if (g.nvar == 3) hipLaunchKernelGGL(k_estimates, dim3(d.nrhs), dim3(256), 0, st, d, g);
+  hipLaunchKernelGGL(k_coef, dim3(d.nrhs), dim3(256), 0, st, d, g, cf);
+  return hipGetLastError();
 }
 
 hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st) {

@@ -1,0 +1,321 @@
+// Refinement of the least-squares problem of the compression (eq. (7)) by
+// LSQR preconditioned with the triangular factor R of the sketched basis
+// (Blendenpik, the preconditioner Section 3.1.1 uses):
+//     min_z || V_m R^{-1} z - v_{m+1} ||_2,   started from z = 0,   y = R^{-1} z.
+// LSQR (Paige & Saunders, ACM TOMS 8 (1982)) in its standard form: the
+// operator M = V_m R^{-1} is applied as M p = sum_j (p_j / eta_j) u_j with
+// p = R^{-1} v (a pass over the basis), and M^T u = R^{-T} diag(1/eta) U^T u.
+//
+// One iteration = k_lsqr_pass (stream the basis once: form the new n-vector
+// u~ <- M v - (alpha/beta) u~ and, on the same tile, its dots with every
+// basis vector and its norm, as per-block partials) + k_lsqr_step (one
+// workgroup per rhs: reduce the partials in a fixed order, the triangular
+// solves with R and R^T, the LSQR recurrences, the stopping test and the
+// coefficients of the next pass).  The launch sequence has a fixed length;
+// once every rhs has stopped the remaining launches return immediately.
+#include "k_basis.h"
+
+namespace fab {
+
+namespace {
+
+// per-rhs state, stride lsqr_state_stride(m) doubles:
+//   [0, m1) v   [m1, 2m1) w   [2m1, 3m1) x   [3m1, 4m1) pass coefficients
+//   [4m1, 5m1) scratch   then scalars at 5m1 + k
+enum { LS_A = 0, LS_ALPHA, LS_BETA, LS_RHOBAR, LS_PHIBAR, LS_DONE, LS_ITERS, LS_RATIO, LS_NSCAL = 16 };
+
+// Solve U^T x = z (U upper triangular, column-major, leading dimension ldu)
+// by one wave: forward substitution with rows in registers.
+template <int R>
+__device__ void wave_upper_t_solve(int n, const double* U, long long ldu, const double* z, double* x) {
+  const int lane = threadIdx.x & 63;
+  double y[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    y[u] = r < n ? z[r] : 0.0;
+  }
+  for (int j = 0; j < n; ++j) {
+    const int uj = j >> 6;
+    double src = y[0];
+#pragma unroll
+    for (int u = 1; u < R; ++u)
+      if (uj == u) src = y[u];
+    const double ujj = U[j + (long long)j * ldu];
+    const double xj = ujj != 0.0 ? readlane_d(src, j & 63) / ujj : 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int r = lane + 64 * u;
+      if (r == j) y[u] = xj;
+      else if (r > j && r < n) y[u] -= U[j + (long long)r * ldu] * xj;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    if (r < n) x[r] = y[u];
+  }
+}
+
+__device__ void upper_solve_any(int n, const double* U, long long ldu, const double* z, double* x) {
+  if (n <= 128) wave_upper_solve<2>(n, U, ldu, z, x);
+  else if (n <= 256) wave_upper_solve<4>(n, U, ldu, z, x);
+  else wave_upper_solve<8>(n, U, ldu, z, x);
+}
+__device__ void upper_t_solve_any(int n, const double* U, long long ldu, const double* z, double* x) {
+  if (n <= 128) wave_upper_t_solve<2>(n, U, ldu, z, x);
+  else if (n <= 256) wave_upper_t_solve<4>(n, U, ldu, z, x);
+  else wave_upper_t_solve<8>(n, U, ldu, z, x);
+}
+
+__device__ inline double bsum256(double v, double* sh) {
+  v = wave_sum_all(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return t;
+}
+
+}  // namespace
+
+size_t lsqr_state_stride(int m) { return (size_t)5 * (m + 1) + LS_NSCAL; }
+size_t lsqr_pass_lds(int m, int nrhs) { return (size_t)4 * nrhs * (m + 1) * 8; }
+
+// Stream the basis once.  first: u~ = u_m / eta_m (the right-hand side
+// v_{m+1}); else u~ <- sum_j cf_j u_j - a u~.  Partials per block and rhs:
+// the dots u_j^T u~ (j < m) and ||u~||^2 (slot m).
+template <typename T>
+__global__ void __launch_bounds__(256) k_lsqr_pass(SolveDev d, LsqrDev L, int first) {
+  if (*L.alldone) return;
+  extern __shared__ double acc[];   // [wave][rhs][m+1]
+  const int tid = threadIdx.x, lane = tid & 63, wv = wave_id();
+  const int nr = d.nrhs, m = d.m, m1 = m + 1;
+  const T* __restrict__ V = (const T*)d.V;
+  const long long nel = (long long)d.n * nr;
+  for (int x = tid; x < 4 * nr * m1; x += 256) acc[x] = 0.0;
+  __syncthreads();
+  int rq[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) rq[j] = (tid * EPT + j) & (nr - 1);
+  for (long long e = ((long long)blockIdx.x * 256 + tid) * EPT; e - (long long)tid * EPT < nel;
+       e += (long long)gridDim.x * 256 * EPT) {
+    const bool live = e < nel;
+    double un[EPT];
+    if (live) {
+      if (first) {
+        get8(V + (long long)m * d.ldv, e, nel, un);
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) un[j] /= d.eta[(long long)rq[j] * m1 + m];
+      } else {
+        double old[EPT];
+        get8(L.u, e, nel, old);
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) un[j] = -L.st[(long long)rq[j] * L.stride + 5 * m1 + LS_A] * old[j];
+        for (int jv = 0; jv < m; ++jv) {
+          double v[EPT];
+          get8(V + (long long)jv * d.ldv, e, nel, v);
+#pragma unroll
+          for (int j = 0; j < EPT; ++j) un[j] += L.st[(long long)rq[j] * L.stride + 3 * m1 + jv] * v[j];
+        }
+      }
+      if (e + EPT <= nel) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          double2 o;
+          o.x = un[2 * h];
+          o.y = un[2 * h + 1];
+          *reinterpret_cast<double2*>(L.u + e + 2 * h) = o;
+        }
+      } else {
+        for (int j = 0; j < EPT; ++j)
+          if (e + j < nel) L.u[e + j] = un[j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) un[j] = 0.0;
+    }
+    // dots with the basis and the norm, reduced per wave into LDS slots
+    for (int jv = 0; jv <= m; ++jv) {
+      double v[EPT];
+      if (jv < m && live) get8(V + (long long)jv * d.ldv, e, nel, v);
+      else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) v[j] = jv == m ? un[j] : 0.0;
+      }
+      for (int q = 0; q < nr; ++q) {
+        double p = 0.0;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+          if (rq[j] == q) p += v[j] * un[j];
+        p = wave_sum_all(p);
+        if (lane == 0) acc[(wv * nr + q) * m1 + jv] += p;
+      }
+    }
+  }
+  __syncthreads();
+  for (int x = tid; x < nr * m1; x += 256)
+    L.part[(long long)blockIdx.x * nr * m1 + x] = (acc[x] + acc[nr * m1 + x]) + (acc[2 * nr * m1 + x] + acc[3 * nr * m1 + x]);
+}
+
+// One LSQR step per rhs (first: the initialisation).
+__global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrDev L, int first) {
+  if (*L.alldone) return;
+  const int q = blockIdx.x, tid = threadIdx.x;
+  __shared__ double sh[8];
+  const int nr = d.nrhs, m = d.m, m1 = m + 1;
+  double* st = L.st + (long long)q * L.stride;
+  double* v = st;
+  double* w = st + m1;
+  double* x = st + 2 * m1;
+  double* cf = st + 3 * m1;
+  double* tmp = st + 4 * m1;
+  double* sc = st + 5 * m1;
+  const int mu = d.status[4 + 2 * q];
+  const int brk = d.status[5 + 2 * q];
+  const double* ws = g.base + (long long)q * g.stride;
+  const double* R = ws + g.oR;                       // R_m, ld m_used
+  const double* eta = d.eta + (long long)q * m1;
+  if (first) {
+    if (tid == 0) {
+      sc[LS_DONE] = (brk || mu == 0 || g.ls_mode == 2) ? 1.0 : 0.0;
+      sc[LS_ITERS] = 0.0;
+      sc[LS_RATIO] = 0.0;
+    }
+    for (int j = tid; j < m1; j += 256) x[j] = 0.0;
+    __syncthreads();
+  }
+  if (sc[LS_DONE] != 0.0) return;
+  // reduce the pass partials in a fixed order
+  for (int j = tid; j <= mu; j += 256) {
+    const int slot = j < mu ? j : m;
+    double a = 0.0;
+    for (int b = 0; b < L.nblk; ++b) a += L.part[((long long)b * nr + q) * m1 + slot];
+    tmp[j] = a;
+  }
+  __syncthreads();
+  const double beta = sqrt(tmp[mu]);
+  // s = R^{-T} (d / eta) / beta  ->  cf (scratch)
+  for (int j = tid; j < mu; j += 256) cf[j] = beta > 0.0 ? tmp[j] / (eta[j] * beta) : 0.0;
+  __syncthreads();
+  if (tid < 64) upper_t_solve_any(mu, R, mu, cf, tmp);
+  __syncthreads();
+  // alpha v = s - beta v_old
+  double p2 = 0.0;
+  for (int j = tid; j < mu; j += 256) {
+    const double t = first ? tmp[j] : tmp[j] - beta * v[j];
+    tmp[j] = t;
+    p2 += t * t;
+  }
+  const double alpha = sqrt(bsum256(p2, sh));
+  for (int j = tid; j < mu; j += 256) v[j] = alpha > 0.0 ? tmp[j] / alpha : 0.0;
+  __syncthreads();
+  if (first) {
+    for (int j = tid; j < mu; j += 256) w[j] = v[j];
+    if (tid == 0) {
+      sc[LS_PHIBAR] = beta;
+      sc[LS_RHOBAR] = alpha;
+      if (!(beta > 0.0) || !(alpha > 0.0)) sc[LS_DONE] = 1.0;   // y = 0 solves it
+    }
+  } else {
+    const double rhobar = sc[LS_RHOBAR], phibar = sc[LS_PHIBAR];
+    const double rho = sqrt(rhobar * rhobar + beta * beta);
+    const double c = rho > 0.0 ? rhobar / rho : 1.0, s = rho > 0.0 ? beta / rho : 0.0;
+    const double theta = s * alpha, phi = c * phibar;
+    const double step = rho > 0.0 ? phi / rho : 0.0;
+    double dx2 = 0.0, x2 = 0.0;
+    for (int j = tid; j < mu; j += 256) {
+      const double dx = step * w[j];
+      x[j] += dx;
+      dx2 += dx * dx;
+      x2 += x[j] * x[j];
+      w[j] = v[j] - (rho > 0.0 ? theta / rho : 0.0) * w[j];
+    }
+    dx2 = bsum256(dx2, sh);
+    x2 = bsum256(x2, sh);
+    if (tid == 0) {
+      sc[LS_RHOBAR] = -c * alpha;
+      sc[LS_PHIBAR] = s * phibar;
+      sc[LS_ITERS] += 1.0;
+      const double ratio = x2 > 0.0 ? sqrt(dx2 / x2) : 0.0;
+      sc[LS_RATIO] = ratio;
+      if (ratio <= L.tol || sc[LS_ITERS] >= L.maxit || !(alpha > 0.0) || !(beta > 0.0)) sc[LS_DONE] = 1.0;
+    }
+  }
+  __syncthreads();
+  // coefficients of the next pass: cf = R^{-1} v / eta, a = alpha / beta
+  if (tid < 64) upper_solve_any(mu, R, mu, v, tmp);
+  __syncthreads();
+  for (int j = tid; j < m; j += 256) cf[j] = j < mu ? tmp[j] / eta[j] : 0.0;
+  if (tid == 0) sc[LS_A] = beta > 0.0 ? alpha / beta : 0.0;
+}
+
+// All rhs stopped?  (one thread; keeps the remaining launches empty)
+__global__ void k_lsqr_alldone(SolveDev d, LsqrDev L) {
+  if (threadIdx.x != 0 || *L.alldone) return;
+  const int m1 = d.m + 1;
+  int all = 1;
+  for (int q = 0; q < d.nrhs; ++q) all &= L.st[(long long)q * L.stride + 5 * m1 + LS_DONE] != 0.0;
+  *L.alldone = all;
+}
+
+// y = R^{-1} z, H_hat = H_m + h_{m+1,m} y e_m^T, iteration count to the info block.
+__global__ void __launch_bounds__(256) k_lsqr_finish(SolveDev d, DenseDev g, LsqrDev L) {
+  const int q = blockIdx.x, tid = threadIdx.x;
+  const int m = d.m, m1 = m + 1;
+  double* ws = g.base + (long long)q * g.stride;
+  const double* st = L.st + (long long)q * L.stride;
+  const double* sc = st + 5 * m1;
+  const int mu = d.status[4 + 2 * q];
+  const int brk = d.status[5 + 2 * q];
+  double* info = ws + g.oInfo;
+  if (tid == 0) {
+    info[INFO_LSQR_IT] = sc[LS_ITERS];
+    info[INFO_LSQR_RATIO] = sc[LS_RATIO];
+  }
+  if (brk || mu == 0 || g.ls_mode == 2) return;
+  __shared__ double y[512];
+  if (tid < 64) upper_solve_any(mu, ws + g.oR, mu, st + 2 * m1, y);
+  __syncthreads();
+  double* yout = ws + g.oVec + 2 * (long long)m;
+  for (int j = tid; j < mu; j += 256) yout[j] = y[j];
+  const double* H = d.H + (long long)q * m1 * m;
+  const double hlast = H[(long long)(mu - 1) * m1 + mu];
+  double* Hh = ws + g.oH;
+  for (int c = wave_id(); c < mu; c += 4)
+    for (int r = tid & 63; r < mu; r += 64) {
+      double val = H[(long long)c * m1 + r];
+      if (c == mu - 1) val += hlast * y[r];
+      Hh[r + (long long)c * mu] = val;
+    }
+}
+
+hipError_t lsqr_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st) {
+  const size_t lds = lsqr_pass_lds(d.m, d.nrhs);
+  auto pass = [&](int first) {
+    if (esize == 4) hipLaunchKernelGGL(k_lsqr_pass<float>, dim3(L.nblk), dim3(256), lds, st, d, L, first);
+    else hipLaunchKernelGGL(k_lsqr_pass<double>, dim3(L.nblk), dim3(256), lds, st, d, L, first);
+  };
+  pass(1);
+  hipLaunchKernelGGL(k_lsqr_step, dim3(d.nrhs), dim3(256), 0, st, d, g, L, 1);
+  hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
+  for (int it = 0; it < L.maxit; ++it) {
+    pass(0);
+    hipLaunchKernelGGL(k_lsqr_step, dim3(d.nrhs), dim3(256), 0, st, d, g, L, 0);
+    hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
+  }
+  hipLaunchKernelGGL(k_lsqr_finish, dim3(d.nrhs), dim3(256), 0, st, d, g, L);
+  return hipGetLastError();
+}
+
+hipError_t lsqr_set_attributes() {
+  hipError_t e = hipSuccess, r;
+  if ((r = hipFuncSetAttribute((const void*)k_lsqr_pass<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               120 * 1024)) != hipSuccess) e = r;
+  if ((r = hipFuncSetAttribute((const void*)k_lsqr_pass<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               120 * 1024)) != hipSuccess) e = r;
+  return e;
+}
+
+}  // namespace fab

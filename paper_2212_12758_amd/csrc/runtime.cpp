@@ -47,6 +47,11 @@ hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStrea
 hipError_t zero_fill(void* p, size_t bytes, hipStream_t st);
 hipError_t srht_sample_rows(int* rows, long long npad, int s, unsigned long long key, hipStream_t st);
 hipError_t dense_set_attributes();
+hipError_t dense_after_refine(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st);
+hipError_t lsqr_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st);
+hipError_t lsqr_set_attributes();
+size_t lsqr_state_stride(int m);
+size_t lsqr_pass_lds(int m, int nrhs);
 }  // namespace fab
 
 using namespace fab;
@@ -148,6 +153,9 @@ struct Plan {
   fab_params p{};
   int esize = 4;
   int nvar = 1;                // dense f evaluations per rhs (3 with the a-posteriori estimates)
+  bool lsqr = false;           // workspace for the LSQR refinement is planned
+  int lnblk = 0;               // LSQR pass blocks
+  size_t oLu = 0, oLpart = 0, oLst = 0, oLflag = 0;
   // derived
   int LT = 12, R = 0, logR = 0, ntiles = 0, nblk = 0, nred = 0;
   long long ldv = 0;
@@ -236,6 +244,19 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   P.oRows = take(256);   // unused: sampled SRHT rows live in the context's cache
   P.oDense = take(P.dense_stride * nrhs * 8);
   P.oCf = take((size_t)nrhs * (m + 1) * 8);
+  // LSQR refinement (FAB_LS_AUTO when the gate fails, FAB_LS_LSQR always)
+  if (p.ls_mode == FAB_LS_AUTO || p.ls_mode == FAB_LS_LSQR) {
+    const bool fits = lsqr_pass_lds(m, nrhs) <= 120 * 1024;
+    if (!fits && p.ls_mode == FAB_LS_LSQR) return FAB_EINVAL;
+    if (fits) {
+      P.lsqr = true;
+      P.lnblk = (int)std::min<long long>((nel + 2047) / 2048, 512);
+      P.oLu = take((size_t)nel * 8);
+      P.oLpart = take((size_t)P.lnblk * nrhs * (m + 1) * 8);
+      P.oLst = take((size_t)nrhs * lsqr_state_stride(m) * 8);
+      P.oLflag = take(256);
+    }
+  }
   P.bytes = w;
   return FAB_OK;
 }
@@ -331,6 +352,7 @@ struct Request {
   double t_submit = 0.0, t_done = 0.0;
   std::vector<fab_info> info;
   int fell_back = 0;             // recomputed with an FP64 basis (FAB_PREC_AUTO)
+  int refined = 0;               // least-squares refinement enqueued
 };
 
 // Sampled SRHT rows for (npad, s, seed): computed once on `st` (which the
@@ -355,12 +377,12 @@ size_t host_info_doubles(int nrhs) { return (size_t)nrhs * NINFO + 4 + 2 * nrhs 
 // Enqueue the whole solve on `st`.  Host-visible results land in `hinfo` (pinned).
 // `side` runs the incremental sketched QR; `ev` orders it against `st`;
 // `rows` holds the sampled SRHT rows (cached per context).
-int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_t ev, const int* rows, double* hinfo,
-                  Prof* prof = nullptr) {
+// Kernel descriptors of a planned request in its workspace.
+void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev& g) {
   const fab_params& p = P.p;
   fab_matrix A = P.A;
   const int m = p.m, s = p.s, nr = P.nrhs;
-  SolveDev d{};
+  d = SolveDev{};
   d.n = A->n;
   d.nrhs = nr;
   d.lognrhs = ilog2(nr);
@@ -410,7 +432,7 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
   }
   d.unit_round = P.esize == 4 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
 
-  DenseDev g{};
+  g = DenseDev{};
   g.m = m;
   g.s = s;
   g.nrhs = nr;
@@ -432,6 +454,14 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
   g.ncoef = (int)P.coef.size();
   for (size_t i = 0; i < P.coef.size(); ++i) g.coef[i] = P.coef[i];
 
+}
+
+int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_t ev, const int* rows, double* hinfo,
+                  Prof* prof = nullptr) {
+  const int m = P.p.m, nr = P.nrhs;
+  SolveDev d;
+  DenseDev g;
+  build_descs(P, ws, rows, d, g);
   hipError_t e;
   // zero the small state: H, eta, wnorm, coef, S, counter, status (contiguous from oH .. oRows)
   if ((e = zero_fill(ws + P.oH, P.oPart - P.oH, st)) != hipSuccess) return FAB_EDEVICE;
@@ -504,7 +534,9 @@ int collect_info(const Plan& P, const double* hinfo, std::vector<fab_info>& out)
     } else {
       fi.err_est = fi.ls_gate = fi.round_est = fi.conv_est = 0.0;
     }
-    fi.ls_iters = 0;
+    fi.ls_iters = (int)in[INFO_LSQR_IT];
+    // refined: the least-squares part of the error is the last LSQR step
+    if (fi.ls_iters > 0) fi.err_est = std::max(in[INFO_LSQR_RATIO], fi.round_est);
     fi.fell_back = 0;
     if (in[3] != 0.0) rc = FAB_ENUMERIC;
     if (!std::isfinite(fi.beta)) rc = FAB_ENUMERIC;
@@ -513,6 +545,46 @@ int collect_info(const Plan& P, const double* hinfo, std::vector<fab_info>& out)
 }
 
 int esize_for(int prec) { return prec == FAB_PREC_FP64 ? 8 : 4; }
+
+// LSQR refinement of the least squares (FAB_LS_LSQR always; FAB_LS_AUTO when
+// the gate ||R (c_y - c_0)|| / ||R c_y|| exceeds tol/10), then f, the
+// estimates, the weights and the combination again, and the info copy.
+int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* hinfo) {
+  SolveDev d;
+  DenseDev g;
+  build_descs(P, ws, rows, d, g);
+  LsqrDev L{};
+  L.u = (double*)(ws + P.oLu);
+  L.part = (double*)(ws + P.oLpart);
+  L.st = (double*)(ws + P.oLst);
+  L.stride = (long long)lsqr_state_stride(P.p.m);
+  L.alldone = (int*)(ws + P.oLflag);
+  L.nblk = P.lnblk;
+  L.maxit = 32;
+  L.tol = P.p.tol / 10;
+  if (zero_fill(ws + P.oLflag, 256, st) != hipSuccess) return FAB_EDEVICE;
+  if (lsqr_launch(d, g, L, P.esize, st) != hipSuccess) return FAB_EDEVICE;
+  double* cf = (double*)(ws + P.oCf);
+  if (dense_after_refine(d, g, cf, st) != hipSuccess) return FAB_EDEVICE;
+  if (basis_combine(d, P.esize, cf, P.p.m, P.out, st) != hipSuccess) return FAB_EDEVICE;
+  const int nr = P.nrhs;
+  for (int q = 0; q < nr; ++q)
+    if (hipMemcpyAsync(hinfo + (size_t)q * NINFO, g.base + (size_t)q * P.dense_stride + P.oDInfo, NINFO * 8,
+                       hipMemcpyDeviceToHost, st) != hipSuccess)
+      return FAB_EDEVICE;
+  if (hipMemcpyAsync(hinfo + (size_t)nr * NINFO, d.status, (size_t)(4 + 2 * nr) * 4, hipMemcpyDeviceToHost, st) !=
+      hipSuccess)
+    return FAB_EDEVICE;
+  return FAB_OK;
+}
+
+bool needs_refine(const Plan& P, int rc, const std::vector<fab_info>& fi) {
+  if (rc != FAB_OK || !P.lsqr) return false;
+  if (P.p.ls_mode == FAB_LS_LSQR) return true;
+  for (const auto& x : fi)
+    if (!x.breakdown && !(x.ls_gate <= P.p.tol / 10)) return true;
+  return false;
+}
 
 // FAB_PREC_AUTO: an FP32-basis result is recomputed with an FP64 basis when
 // the basis-rounding estimate exceeds tol/4 or the FP32 run produced
@@ -547,6 +619,15 @@ void retire_locked(fab_ctx ctx, Request& r) {
       ctx->queue.push_front(r.id);
       return;
     }
+  }
+  if (!r.refined && needs_refine(r.plan, r.status, r.info)) {
+    // least-squares refinement on the request's stream; retired when it ends
+    r.refined = 1;
+    const hipStream_t st = ctx->pool[r.stream_idx];
+    if (enqueue_refine(r.plan, r.ws, st, nullptr, r.host_info) == FAB_OK && hipEventRecord(r.done_ev, st) == hipSuccess)
+      return;
+    hipStreamSynchronize(st);
+    r.status = FAB_EDEVICE;
   }
   if (r.fell_back)
     for (auto& fi : r.info) fi.fell_back = 1;
@@ -670,6 +751,7 @@ int fab_init(fab_ctx* out, int device, void* arena_dev_ptr, size_t arena_bytes, 
     ctx->own_stream = true;
   }
   (void)dense_set_attributes();
+  (void)lsqr_set_attributes();
   (void)hipGetLastError();
   if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev, hipEventDisableTiming) != hipSuccess) {
@@ -942,6 +1024,11 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
       continue;
     }
     break;
+  }
+  if (needs_refine(P, rc, fi)) {
+    rc = enqueue_refine(P, ws, ctx->stream, nullptr, ctx->host_info);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == FAB_OK) rc = FAB_EDEVICE;
+    if (rc == FAB_OK) rc = collect_info(P, ctx->host_info, fi);
   }
   if (fell_back)
     for (auto& x : fi) x.fell_back = 1;

@@ -374,8 +374,11 @@ def test_estimates_sqrt_variants_and_breakdown(ctx):
     f = W.FuncSpec("pow", sigma=1e-3, p=-0.5)
     w = W.Workload("lap", st, 11, 1, f, m=30, k=2, s=70, sketch="sparse_sign", sketch_seed=4)
     print("case estimates invsqrt", flush=True)
-    p = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, "fp64", "auto", 1e-10)
+    # tolerance loose enough that the gate passes: no refinement, the
+    # estimates of the sketch-and-solve result are reported
+    p = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, "fp64", "auto", 1.0)
     out, info = ctx.solve(A, _dev(b), f, p)
+    assert info[0]["ls_iters"] == 0
     ref, sk = _oracle(w, Aor, b)
     est = krylov.estimates(ref, f, 2.0**-53)
     for key in ("ls_gate", "conv_est"):
@@ -392,4 +395,42 @@ def test_estimates_sqrt_variants_and_breakdown(ctx):
     assert info[0]["ls_gate"] == 0.0 and info[0]["conv_est"] == 0.0
     assert krylov.relerr(out.cpu().numpy(), closed_form.diagonal_fAb(d, fe, bd)) < 1e-12
     Ad.destroy()
+    A.destroy()
+
+
+# ------------------------------------------------------------------ LSQR refinement of the least squares
+def test_lsqr_refinement_recovers_exact_least_squares(ctx):
+    """Unconverged inverse square root: sketch-and-solve moves the result by
+    ~1e-2 from f_m, the exact least-squares solution reaches f_m (Lemma 2);
+    the preconditioned LSQR refinement (AUTO after the gate, or forced) must
+    close that gap, through the blocking and the serving path alike."""
+    from paper_2212_12758_amd import make_params
+
+    st = W.laplacian2d(64)
+    b = W.rhs(st.n, 5)
+    f = W.FuncSpec("pow", sigma=1e-3, p=-0.5)
+    m = 60
+    w = W.Workload("lap64", st, 5, 1, f, m=m, k=2, s=2 * (m + 1), sketch="sparse_sign", sketch_seed=9)
+    print("case lsqr lap64 invsqrt", flush=True)
+    Aor = operators.as_matrix(st)
+    A = ctx.matrix(st)
+    fm = krylov.fm(Aor, b, f, m)
+    ref_sk, _ = _oracle(w, Aor, b)
+    out_sk, info_sk = _solve(ctx, w, A, b, "fp64", ls="sketch")
+    assert krylov.relerr(out_sk, ref_sk["f"]) < 1e-9
+    err_sk = krylov.relerr(out_sk, fm)
+    assert err_sk > 1e-3
+    for ls in ("auto", "lsqr"):
+        p = make_params(m, 2, w.s, "sparse_sign", 8, 9, "fp64", ls, 1e-8)
+        out, info = ctx.solve(A, _dev(b), f, p)
+        out = out.cpu().numpy()
+        assert info[0]["ls_iters"] >= 1, ls
+        assert krylov.relerr(out, fm) < 1e-6, (ls, krylov.relerr(out, fm))
+        assert krylov.relerr(out, fm) < 1e-3 * err_sk
+    outs = _dev(np.zeros(st.n))
+    p = make_params(m, 2, w.s, "sparse_sign", 8, 9, "fp64", "auto", 1e-8)
+    info_s = ctx.submit(A, _dev(b), f, p, outs).wait()
+    out_b, info_b = ctx.solve(A, _dev(b), f, p)
+    assert info_s[0]["ls_iters"] == info_b[0]["ls_iters"] >= 1
+    assert np.array_equal(outs.cpu().numpy(), out_b.cpu().numpy())
     A.destroy()
