@@ -50,6 +50,69 @@ def algorithmic_bytes(n, nrhs, m, k, esize):
             "solve": dots + update + start + combine}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_update_convdiff3d_128_exp.json")
+KERNEL_SOURCES = ["paper_2212_12758_amd/csrc/k_basis.h", "paper_2212_12758_amd/csrc/k_basis_part.inc",
+                  "paper_2212_12758_amd/csrc/fab_dev.h"]
+CALIBRATION_BYTES = 4 << 28   # the 1 GiB copy of --calibrate-copy
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_update launch from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return t["bytes_per_launch"] if t.get("source_sha256") == kernel_source_hash() else None
+
+
+def _pmc_rows(d, counter):
+    import csv
+    import glob
+
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection*.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def summarize_pmc(fetch_dir, write_dir):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of k_update, each scaled by
+    the same counter on a copy kernel of known size (the 1 GiB copy of
+    --calibrate-copy), written to the traffic summary read by measured_traffic()."""
+    out = {"kernel": "k_update<float, stencil, SRHT, 11, 1, 4> (steps after the first)",
+           "workload": "convdiff3d_128_exp", "source_sha256": kernel_source_hash()}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = _pmc_rows(d, counter)
+        copies = [v for k, v in rows if "copyBuffer" in k]
+        upd = [v for k, v in rows if "k_update<float, 0, 1, false, 11, 1, 4>" in k]
+        if not copies or not upd:
+            raise SystemExit(f"{counter}: no calibration copy or k_update dispatches in {d}")
+        cal = max(copies)
+        factor = CALIBRATION_BYTES / (cal * 1024.0)
+        out[key] = {"counter": counter, "calibration_copy_kib": cal, "factor": factor,
+                    "k_update_mean_kib": sum(upd) / len(upd), "dispatches": len(upd),
+                    "bytes_per_launch": factor * 1024.0 * sum(upd) / len(upd)}
+    out["bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -66,7 +129,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-basis comparison run")
+    ap.add_argument("--prec", default="auto", choices=["auto", "fp32", "fp64"],
+                    help="basis precision policy (auto: FP32 + estimates + FP64 fallback)")
+    ap.add_argument("--ls", default="auto", choices=["auto", "sketch", "none", "lsqr"],
+                    help="least-squares policy (auto: sketch-and-solve + gate + LSQR refinement)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU: turn two rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE outputs into the traffic summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the solve is not sharded "
                                    "across GPUs (see DESIGN.md for how it would shard)", "n_gpus": args.gpus}))
@@ -85,8 +159,14 @@ def main():
     A = ctx.matrix(w.op)
     bd = torch.from_numpy(b).cuda()
     out = torch.empty_like(bd)
-    p32 = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, "fp32", "sketch", 1e-6)
-    p64 = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, "fp64", "sketch", 1e-10)
+    p32 = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, args.prec, args.ls, 1e-6)
+    p64 = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, "fp64", args.ls, 1e-10)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ab32 = algorithmic_bytes(n, 1, w.m, w.k, 4)
 
     for _ in range(args.warmup):
@@ -159,14 +239,17 @@ def main():
             "n": n, "f": "exp(-1e-3 A)", "m": w.m, "k": w.k, "s": w.s, "sketch": "srht", "basis": "fp32",
             "accumulate": "fp64", "ls": "sketch-and-solve",
             "relerr_vs_oracle": relerr, "meets_tol": (relerr is not None and relerr <= 1e-6) or None,
-            "m_used": info[0]["m_used"],
+            "m_used": info[0]["m_used"], "prec_policy": args.prec, "ls_policy": args.ls,
+            "prec_used": {1: "fp32", 2: "fp64"}.get(info[0]["prec_used"]), "fell_back": info[0]["fell_back"],
+            "ls_iters": info[0]["ls_iters"], "err_est": info[0]["err_est"], "ls_gate": info[0]["ls_gate"],
+            "round_est": info[0]["round_est"], "conv_est": info[0]["conv_est"],
             "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
             "hbm_algorithmic_GBps": ab32["solve"] * value / 1e9,
             "fp64_basis_solves_per_s": fp64_rate,
             "fp32_over_fp64": (value / fp64_rate) if fp64_rate else None,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": measured_traffic(),
                      "kernel": "k_update (Gram-Schmidt update + norm + fused SRHT)",
                      "bytes_per_launch": ab32["update_per_launch"], "mean_launch_us": upd_ms * 1e3,
                      "launches": nlaunch, "timing": "HIP events around each launch, direct launches, "

@@ -235,30 +235,53 @@ __device__ inline void block_sums(const double* a, double* red /* [BLOCK/64][RC]
   __syncthreads();
 }
 
-// Reduce the per-block sketch partials of column `col` into S[:, col]: one
-// wave per (row, rhs), eight loads in flight per lane, fixed order.
-__device__ inline void reduce_sketch_column(const SolveDev& d, int col, int wid, int nwaves) {
-  const int lane = threadIdx.x & 63;
+// Reduce the per-block sketch partials of column `col` into S[:, col].
+// Sketch partials of one column: layout [row / 8][block][row % 8] (rows =
+// sketch row x rhs), so that a block stores whole 64-byte lines and a
+// reducing wave loads 8 blocks x 8 rows per instruction.  One workgroup per
+// group of 8 rows: its waves split the blocks, lanes (block % 8, row % 8)
+// accumulate in a fixed order, then a butterfly over the block bits and a
+// fixed-order sum over the waves.
+template <int BLOCK>
+__device__ void reduce_sketch_column(const SolveDev& d, int col, int g0, int gstride) {
+  constexpr int NW = BLOCK / 64;
+  __shared__ double rs_red[NW * 8];
+  const int lane = threadIdx.x & 63, wv = wave_id();
   const int nr = d.nrhs;
+  const int snr = d.s * nr;
+  const int ngroups = (snr + 7) >> 3;
   const double* base = d.skpart + (long long)(col & 1) * d.skstride;
-  for (int rho = wid; rho < d.s * nr; rho += nwaves) {
+  const int chunk = (d.nblk + NW - 1) / NW;
+  const int b_lo = wv * chunk, b_hi = b_lo + chunk < d.nblk ? b_lo + chunk : d.nblk;
+  const int bsub = lane >> 3, rr = lane & 7;
+  for (int g = g0; g < ngroups; g += gstride) {
+    const double* p = base + (long long)g * d.nblk * 8;
     double v = 0.0;
-    const double* p = base + (long long)rho * d.nblk;
-    for (int b0 = 0; b0 < d.nblk; b0 += 512) {
+    for (int b0 = b_lo; b0 < b_hi; b0 += 64) {
       double x[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int b = b0 + lane + 64 * u;
-        x[u] = b < d.nblk ? p[b] : 0.0;
+        const int b = b0 + 8 * u + bsub;
+        x[u] = b < b_hi ? p[(long long)b * 8 + rr] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) v += x[u];
     }
-    v = wave_sum_all(v);
-    if (lane == 0) {
-      const int pr = rho >> d.lognrhs, qq = rho & (nr - 1);
-      d.S[(long long)qq * d.s * (d.m + 1) + (long long)col * d.s + pr] = v * d.sk_scale;
+    v += __shfl_xor(v, 8, 64);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (lane < 8) rs_red[wv * 8 + lane] = v;
+    __syncthreads();
+    if (threadIdx.x < 8) {
+      double t = 0.0;
+      for (int w = 0; w < NW; ++w) t += rs_red[w * 8 + threadIdx.x];
+      const int rho = g * 8 + (int)threadIdx.x;
+      if (rho < snr) {
+        const int pr = rho >> d.lognrhs, qq = rho & (nr - 1);
+        d.S[(long long)qq * d.s * (d.m + 1) + (long long)col * d.s + pr] = t * d.sk_scale;
+      }
     }
+    __syncthreads();
   }
 }
 
@@ -474,7 +497,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_finish(SolveDev d) {
   __shared__ double sums[NSLOT * 32 + 32];
   __shared__ double cfl[33 * NSLOT + 32];
   const int i = d.m + 1;
-  reduce_sketch_column(d, i - 1, blockIdx.x * NW + wave_id(), gridDim.x * NW);
+  reduce_sketch_column<BLOCK>(d, i - 1, blockIdx.x, gridDim.x);
   if (blockIdx.x == 0) step_scalars<BLOCK>(d, i, false, d.npart + (long long)(d.m & 1) * d.nblk * d.nrhs, true, red, sums, cfl);
 }
 
@@ -547,7 +570,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   // previous update pass into the other buffer)
   const int nlead = START ? 0 : d.nred;
   if ((int)blockIdx.x < nlead) {
-    reduce_sketch_column(d, i - 1, blockIdx.x * NW + wave_id(), nlead * NW);
+    reduce_sketch_column<BLOCK>(d, i - 1, blockIdx.x, nlead);
     return;
   }
   const int blk = blockIdx.x - nlead;
@@ -669,7 +692,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   }
   __syncthreads();
   double* skp = d.skpart + (long long)(i & 1) * d.skstride;
-  for (int pq = tid; pq < snr; pq += BLOCK) skp[(long long)pq * d.nblk + blk] = acc[pq];
+  for (int pq = tid; pq < snr; pq += BLOCK) skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = acc[pq];
 
   // norm partials per rhs
   for (int q = 0; q < nr; ++q) {

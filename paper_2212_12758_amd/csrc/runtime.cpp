@@ -211,8 +211,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   P.ntiles = (int)((nel + tile - 1) / tile);
   P.nblk = std::min(P.ntiles, P.LT == 11 ? 512 : 2048);
   const long long snr = (long long)p.s * nrhs;
-  const int waves_per_block = (int)(tile / 8 / 64) > 0 ? (int)(tile / 8 / 64) : 1;
-  P.nred = (int)std::max<long long>(1, std::min<long long>((snr + waves_per_block - 1) / waves_per_block, 128));
+  P.nred = (int)std::max<long long>(1, std::min<long long>((snr + 7) / 8, 128));   // one per 8 sketch rows
   P.lds_update = (size_t)(snr + (p.sketch == FAB_SKETCH_SRHT ? tile + tile / 32 : 0)) * 8 + (size_t)p.s * 4;
   if (P.lds_update > 160 * 1024) return FAB_EINVAL;
   P.ldv = (nel + 63) & ~63LL;
@@ -238,7 +237,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   P.oS = take((size_t)nrhs * s * (m + 1) * 8);
   P.oPart = take((size_t)P.nblk * nrhs * NSLOT * 8);
   P.oNpart = take((size_t)2 * P.nblk * nrhs * 8);
-  P.oSk = take((size_t)2 * snr * P.nblk * 8);
+  P.oSk = take((size_t)2 * ((snr + 7) & ~7LL) * P.nblk * 8);
   P.oCnt = take(256);
   P.oStatus = take((size_t)(4 + 2 * nrhs) * 4);
   P.oRows = take(256);   // unused: sampled SRHT rows live in the context's cache
@@ -416,7 +415,7 @@ void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev
   d.part = (double*)(ws + P.oPart);
   d.npart = (double*)(ws + P.oNpart);
   d.skpart = (double*)(ws + P.oSk);
-  d.skstride = (long long)p.s * nr * P.nblk;
+  d.skstride = (((long long)p.s * nr + 7) & ~7LL) * P.nblk;
   d.counter = (unsigned*)(ws + P.oCnt);
   d.status = (int*)(ws + P.oStatus);
   d.sketch = p.sketch == FAB_SKETCH_SRHT ? SK_SRHT : SK_SPARSE;
