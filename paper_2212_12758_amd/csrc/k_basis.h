@@ -186,6 +186,67 @@ __device__ inline void stencil8(const SolveDev& d, const T* __restrict__ u, long
   }
 }
 
+// Branch-free w = A u at e..e+7 when the y stride n_x*nrhs keeps vector loads
+// aligned and nrhs is 1 or a multiple of 8: every load is issued
+// unconditionally and the boundary conditions are applied to the values, so
+// the loads of a tile overlap.  Neighbour addresses are clamped into
+// [0, nel); a clamped value is always masked out when the 8 elements share
+// their grid row (n_x a multiple of 8, or nrhs >= 8), otherwise the caller
+// restricts this path to tiles whose neighbourhood lies inside [0, nel)
+// (stencil_reach).  In 2D the z offsets are 0 (the centre again, masked out).
+template <typename T>
+__device__ inline void stencil8_fast(const SolveDev& d, const T* __restrict__ u, long long e, const double* c,
+                                     double* w) {
+  const Masks8 mk = masks8(d, e);
+  const int nr = d.nrhs;
+  const long long sy = (long long)d.nx * nr, sz = d.nz > 1 ? sy * d.ny : 0;
+  double xm[EPT], xp[EPT], ym[EPT], yp[EPT], zm[EPT], zp[EPT];
+  const long long nel = (long long)d.n * nr;
+  load8(u + (e >= sy ? e - sy : e), ym);
+  load8(u + (e + sy + EPT <= nel ? e + sy : e), yp);
+  load8(u + (e >= sz ? e - sz : e), zm);
+  load8(u + (e + sz + EPT <= nel ? e + sz : e), zp);
+  if (nr == 1) {
+    const double l = (double)u[e >= 1 ? e - 1 : e];
+    const double r = (double)u[e + EPT < nel ? e + EPT : e];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      xm[j] = j == 0 ? l : c[j > 0 ? j - 1 : 0];
+      xp[j] = j == EPT - 1 ? r : c[j < EPT - 1 ? j + 1 : 0];
+    }
+  } else {
+    load8(u + (e >= nr ? e - nr : e), xm);
+    load8(u + (e + nr + EPT <= nel ? e + nr : e), xp);
+  }
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    double a = d.c[0] * c[j];
+    a += d.c[1] * (((mk.mx0 >> j) & 1u) ? xm[j] : 0.0);
+    a += d.c[2] * (((mk.mx1 >> j) & 1u) ? xp[j] : 0.0);
+    a += d.c[3] * (((mk.my0 >> j) & 1u) ? ym[j] : 0.0);
+    a += d.c[4] * (((mk.my1 >> j) & 1u) ? yp[j] : 0.0);
+    a += d.c[5] * (((mk.mz0 >> j) & 1u) ? zm[j] : 0.0);
+    a += d.c[6] * (((mk.mz1 >> j) & 1u) ? zp[j] : 0.0);
+    w[j] = a;
+  }
+}
+
+template <typename T>
+__device__ inline bool stencil_fast_ok(const SolveDev& d) {
+  return d.op == OP_STENCIL && (d.nrhs == 1 || d.nrhs >= 8) && ((long long)d.nx * d.nrhs) % vec_align<T>() == 0;
+}
+
+// Tiles [lo, hi) with lo >= reach and hi + reach <= nel may use
+// stencil8_fast: 0 when groups of 8 elements share their grid row (every
+// full tile qualifies), else the largest neighbour offset.
+__device__ inline long long stencil_reach(const SolveDev& d) {
+  if (d.nrhs >= 8 || d.nx % EPT == 0) return 0;
+  const long long sy = (long long)d.nx * d.nrhs;
+  const long long sz = d.nz > 1 ? sy * d.ny : 0;
+  long long r = sy > sz ? sy : sz;
+  return r > d.nrhs ? r : d.nrhs;
+}
+
 template <typename T>
 __device__ inline double csr_apply(const SolveDev& d, const T* __restrict__ u, int r, int q) {
   const int p0 = d.rowptr[r], p1 = d.rowptr[r + 1];
@@ -316,8 +377,28 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int n
       for (int c = 0; c < QC; ++c) acc[sl][c] = 0.0;
     const T* __restrict__ src = V + (long long)(i - 1) * d.ldv;
     const long long nel = (long long)d.n * nr;
+    const bool fast_ok = OP == OP_STENCIL && nw == KT && stencil_fast_ok<T>(d);
+    const long long reach = stencil_reach(d);
     for (int t = blockIdx.x; t < d.ntiles; t += d.nblk) {
       const long long e = ((long long)t << LT) + (long long)tid * EPT;
+      if (fast_ok && ((long long)t << LT) >= reach && (((long long)t + 1) << LT) + reach <= nel) {
+        // interior tile, full window: all loads first, no branches
+        double c[EPT], w[EPT], win[KT > 1 ? KT - 1 : 1][EPT];
+        load8(src + e, c);
+#pragma unroll
+        for (int jj = 0; jj < KT - 1; ++jj) load8(V + (long long)(j0 + jj) * d.ldv + e, win[jj]);
+        stencil8_fast(d, src, e, c, w);
+#pragma unroll
+        for (int jj = 0; jj < KT - 1; ++jj)
+#pragma unroll
+          for (int j = 0; j < EPT; ++j) acc[jj][slot_of<QC>(j)] += win[jj][j] * w[j];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+          acc[KT - 1][slot_of<QC>(j)] += c[j] * w[j];
+          acc[KMAX][slot_of<QC>(j)] += w[j] * w[j];
+        }
+        continue;
+      }
       if (e >= nel) continue;
       double c[EPT], w[EPT];
       get8(src, e, nel, c);
@@ -612,6 +693,8 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   double nrm[QC];
 #pragma unroll
   for (int c = 0; c < QC; ++c) nrm[c] = 0.0;
+  const bool fast_ok = !START && OP == OP_STENCIL && nw == KT && stencil_fast_ok<T>(d);
+  const long long reach = stencil_reach(d);
   for (int t = blk; t < d.ntiles; t += d.nblk) {
     const long long e = ((long long)t << LT) + (long long)tid * EPT;
     double uu[EPT];
@@ -621,6 +704,22 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
       double u[EPT];
       if (START) {
         get8(d.b, e, nel, u);
+      } else if (fast_ok && ((long long)t << LT) >= reach && (((long long)t + 1) << LT) + reach <= nel) {
+        // interior tile, full window: all loads first, no branches
+        double c[EPT], w[EPT], win[KT > 1 ? KT - 1 : 1][EPT];
+        load8(src + e, c);
+#pragma unroll
+        for (int jj = 0; jj < KT - 1; ++jj) load8(V + (long long)(j0 + jj) * d.ldv + e, win[jj]);
+        stencil8_fast(d, src, e, c, w);
+        // same order of operations as the general path below
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) u[j] = cw[slot_of<QC>(j)] * w[j];
+#pragma unroll
+        for (int jj = 0; jj < KT - 1; ++jj)
+#pragma unroll
+          for (int j = 0; j < EPT; ++j) u[j] -= cj[jj][slot_of<QC>(j)] * win[jj][j];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) u[j] -= cj[KT - 1][slot_of<QC>(j)] * c[j];
       } else {
         double w[EPT];
         if (OP == OP_STENCIL) {
