@@ -133,10 +133,14 @@ __device__ void qr_registers(const double* __restrict__ S, const double* __restr
       vr[rs] = r < s ? vj[r] : 0.0;
     }
     // column dots of a group of slots first, then one interleaved butterfly
-    // for the whole group (independent shuffle chains overlap)
+    // for the whole group (independent shuffle chains overlap).  Only the
+    // slots of this wave right of column j are live (wv is wave-uniform, so
+    // the tests below are scalar branches): finished columns and padding
+    // skip their reductions.
     constexpr int G = (LCS + 1) / 2;
 #pragma unroll
     for (int g0 = 0; g0 < LCS; g0 += G) {
+      if (wv + 8 * (g0 + G - 1) <= j || wv + 8 * g0 >= ncol) continue;   // no live slot in the group
       double dt[G];
 #pragma unroll
       for (int u = 0; u < G; ++u) {
@@ -149,7 +153,10 @@ __device__ void qr_registers(const double* __restrict__ S, const double* __restr
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1)
 #pragma unroll
-        for (int u = 0; u < G; ++u) dt[u] += __shfl_xor(dt[u], off, 64);
+        for (int u = 0; u < G; ++u) {
+          const int c = wv + 8 * (g0 + u);
+          if (g0 + u < LCS && c > j && c < ncol) dt[u] += __shfl_xor(dt[u], off, 64);
+        }
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         const int c = wv + 8 * (g0 + u);
