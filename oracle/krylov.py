@@ -145,6 +145,58 @@ def nt(A, b: np.ndarray, f, m: int, k: int, sketch=None, ls: str = "sketch"):
     return out
 
 
+def sketched_gs_basis(A, b: np.ndarray, m: int, sketch):
+    """Algorithm 1: the basis whose sketch Theta V is kept orthonormal.
+
+    Each new vector w = A v_{i-1} is sketched (p = Theta w), one classical
+    Gram-Schmidt step on the sketch gives r = S^T p, s = p - S r and
+    r_ii = ||s||, and the same coefficients act on the vectors:
+    v_i = (w - V r) / r_ii.  Returns V (rows v_0..v_mu), Hbar (the columns
+    2..m+1 of R), r_11 = ||Theta b||, S = Theta V (columns), m_used and the
+    breakdown flag (r_ii <= 100 eps ||p||: the subspace is invariant).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    p = sketch.apply(b)
+    r11 = float(np.linalg.norm(p))
+    V = np.zeros((m + 1, n))
+    S = np.zeros((p.size, m + 1))
+    H = np.zeros((m + 1, m))
+    if r11 == 0.0:
+        return V[:1], H[:1, :0], 0.0, S[:, :1], 0, True
+    V[0] = b / r11
+    S[:, 0] = p / r11
+    for i in range(1, m + 1):
+        w = A @ V[i - 1]
+        p = sketch.apply(w)
+        r = S[:, :i].T @ p
+        sv = p - S[:, :i] @ r
+        rii = float(np.linalg.norm(sv))
+        H[:i, i - 1] = r
+        if rii <= _breakdown_tol() * np.linalg.norm(p):
+            return V[:i], H[: i + 1, :i], r11, S[:, :i], i, True
+        H[i, i - 1] = rii
+        S[:, i] = sv / rii
+        V[i] = (w - V[:i].T @ r) / rii
+    return V, H, r11, S, m, False
+
+
+def sgs(A, b: np.ndarray, f, m: int, sketch) -> dict:
+    """Algorithm 3 with the least-squares problem of line 2 solved exactly
+    (the limit of its LSQR iteration): y = argmin ||V_m z - v_{m+1}||, result
+    r_11 V_m f(H_m + h_{m+1,m} y e_m^T) e_1."""
+    V, Hbar, r11, S, mu, brk = sketched_gs_basis(A, b, m, sketch)
+    y = np.zeros(mu)
+    if not brk and mu > 0:
+        y = np.linalg.lstsq(V[:mu].T, V[mu], rcond=None)[0]
+    Hhat = Hbar[:mu, :mu].copy()
+    if not brk and mu > 0:
+        Hhat[:, mu - 1] += Hbar[mu, mu - 1] * y
+    c = matfun.fmat_e1(f, Hhat) if mu > 0 else np.zeros(0)
+    return {"V": V, "Hbar": Hbar, "r11": r11, "S": S, "m_used": mu, "breakdown": brk, "y": y, "Hhat": Hhat,
+            "c": c, "f": r11 * (V[:mu].T @ c) if mu > 0 else np.zeros_like(np.asarray(b, float))}
+
+
 def estimates(res: dict, f, unit_round: float) -> dict:
     """A-posteriori quantities of the dense tail for a result of ``nt``.
 

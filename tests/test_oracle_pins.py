@@ -369,3 +369,31 @@ def test_estimates_definitions_pinned():
     assert est["round_est"] >= 2.0**-53   # sum_j |c_j| ||R e_j|| >= ||R c||
     none = krylov.nt(A, b, f, m, k, sk, "none")
     assert krylov.estimates(none, f, 2.0**-24)["ls_gate"] == 0.0
+
+
+def test_sketched_gs_basis_algorithm1_pinned():
+    """Algorithm 1: the sketch of the basis is orthonormal, the Arnoldi-like
+    relation (eq. (3)) holds, r_11 = ||Theta b||, and with the exact
+    least-squares solution Algorithm 3 returns f_m (Lemma 2) - checked
+    against the full Arnoldi approximation and a dense brute force."""
+    st = W.convdiff3d(10, 50.0)
+    A = operators.as_matrix(st)
+    b = W.rhs(st.n, 7)
+    sk = sketch.Sketch("srht", st.n, 120, 3, 8)
+    m = 30
+    V, H, r11, S, mu, brk = krylov.sketched_gs_basis(A, b, m, sk)
+    assert mu == m and not brk
+    # one classical Gram-Schmidt step per column (as printed): orthonormal to O(kappa u)
+    assert np.abs(S.T @ S - np.eye(m + 1)).max() < 1e-7
+    assert np.allclose(sk.apply(V.T), S, atol=1e-11)
+    assert r11 == pytest.approx(np.linalg.norm(sk.apply(b)), rel=1e-14)
+    rel = np.linalg.norm(A @ V[:m].T - V.T @ H) / np.linalg.norm(A @ V[:m].T)
+    assert rel < 1e-12
+    f = W.FuncSpec("exp", alpha=-2e-3)
+    out = krylov.sgs(A, b, f, m, sk)
+    fm = krylov.fm(A, b, f, m)
+    assert krylov.relerr(out["f"], fm) < 1e-10
+    # a planted slip (coefficients not scaled by r_ii) breaks the relation
+    Hbad = H.copy()
+    Hbad[m, m - 1] *= 1.01
+    assert np.linalg.norm(A @ V[:m].T - V.T @ Hbad) / np.linalg.norm(A @ V[:m].T) > 1e-6
