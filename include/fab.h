@@ -90,9 +90,19 @@ enum fab_ls_mode {
                                  with Blendenpik, Section 3.1.1)                            */
 };
 
+/* Construction of the basis. */
+enum fab_basis {
+  FAB_BASIS_TRUNCATED = 0,    /* k-truncated orthogonalisation (Algorithm 2)              */
+  FAB_BASIS_SKETCHED_GS = 1   /* Gram-Schmidt on the sketch (Algorithm 1): Theta V_{m+1} is
+                                 orthonormal, v_i = (A v_{i-1} - V_{i-1} r_i) / r_ii; with
+                                 FAB_LS_AUTO the least squares are always refined by LSQR,
+                                 which gives Algorithm 3                                    */
+};
+
 typedef struct {
-  int m;              /* Krylov dimension, 1 <= m < n                             */
-  int k;              /* truncation window, 1 <= k <= 8 (Algorithm 2)             */
+  int m;              /* Krylov dimension, 1 <= m < n (m <= 500)                  */
+  int k;              /* truncation window, 1 <= k <= 8 (Algorithm 2; ignored by
+                         FAB_BASIS_SKETCHED_GS)                                    */
   int s;              /* sketch rows, m < s <= min(8192, padded n)                */
   int sketch;         /* enum fab_sketch_kind                                     */
   int zeta;           /* sparse-sign nonzeros per column, 1 <= zeta <= min(s,16)  */
@@ -100,6 +110,7 @@ typedef struct {
   int prec;           /* enum fab_prec                                            */
   int ls_mode;        /* enum fab_ls_mode                                         */
   double tol;         /* target relative accuracy for AUTO policies (e.g. 1e-6)    */
+  int basis;          /* enum fab_basis; 0 (a zero-initialised struct) = truncated  */
 } fab_params;
 
 /* Per right-hand side diagnostics. */
@@ -199,11 +210,14 @@ int fab_wait(fab_ctx ctx, fab_request req, fab_info* info);
  * blocking solves on this context record a HIP event pair on the context's
  * stream around every launch and accumulate the elapsed times per class:      */
 enum fab_kernel_class {
-  FAB_K_DOTS = 0,     /* matvec + window dots + reductions (one per Krylov step)  */
-  FAB_K_UPDATE = 1,   /* Gram-Schmidt update + norm + fused sketch (one per step) */
+  FAB_K_DOTS = 0,     /* matvec + window dots + reductions (one per Krylov step);
+                         sketched-GS basis: matvec + sketch partials              */
+  FAB_K_UPDATE = 1,   /* Gram-Schmidt update + norm + fused sketch (one per step);
+                         sketched-GS basis: u_i = w - V_{i-1} r_i                  */
   FAB_K_COMBINE = 2,  /* out = beta V_m c                                          */
   FAB_K_DENSE = 3,    /* sketched QR / least squares, f(H_hat) e_1, weights         */
-  FAB_K_OTHER = 4,    /* first vector, final reduction                             */
+  FAB_K_OTHER = 4,    /* first vector, final reduction; sketched-GS basis: sketch
+                         reduction and the Gram-Schmidt step on the sketch        */
   FAB_K_NCLASS = 5
 };
 /* Time the classes whose bit (1 << class) is set in class_mask; 0 disables.

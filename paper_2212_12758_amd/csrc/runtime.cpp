@@ -50,6 +50,11 @@ hipError_t dense_set_attributes();
 hipError_t dense_after_refine(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st);
 hipError_t lsqr_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st);
 hipError_t lsqr_set_attributes();
+hipError_t bg_apply(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds);
+hipError_t bg_reduce(const SolveDev& d, int col, hipStream_t st);
+hipError_t bg_gs(const SolveDev& d, double* cf, int i, hipStream_t st);
+hipError_t bg_update(const SolveDev& d, int esize, const double* cf, int i, hipStream_t st);
+hipError_t bg_set_attributes();
 size_t lsqr_state_stride(int m);
 size_t lsqr_pass_lds(int m, int nrhs);
 }  // namespace fab
@@ -154,6 +159,8 @@ struct Plan {
   int esize = 4;
   int nvar = 1;                // dense f evaluations per rhs (3 with the a-posteriori estimates)
   bool lsqr = false;           // workspace for the LSQR refinement is planned
+  bool bg = false;             // basis by Gram-Schmidt on the sketch (Algorithm 1)
+  size_t oBgCf = 0;            // its update weights [nrhs][m+2]
   int lnblk = 0;               // LSQR pass blocks
   size_t oLu = 0, oLpart = 0, oLst = 0, oLflag = 0;
   // derived
@@ -181,7 +188,9 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   const long long n = A->n;
   if (nrhs < 1 || nrhs > 32 || (nrhs & (nrhs - 1))) return FAB_EINVAL;
   if (p.m < 1 || p.m >= n || p.m > 500) return FAB_EINVAL;
-  if (p.k < 1 || p.k > KMAX) return FAB_EINVAL;
+  if (p.basis != FAB_BASIS_TRUNCATED && p.basis != FAB_BASIS_SKETCHED_GS) return FAB_EINVAL;
+  const bool bg = p.basis == FAB_BASIS_SKETCHED_GS;
+  if (!bg && (p.k < 1 || p.k > KMAX)) return FAB_EINVAL;
   if (p.sketch != FAB_SKETCH_SRHT && p.sketch != FAB_SKETCH_SPARSE_SIGN) return FAB_EINVAL;
   const long long npad = 1LL << ilog2(n);
   if (p.s <= p.m || p.s > 8192 || p.s > npad) return FAB_EINVAL;
@@ -199,6 +208,8 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   P.f = f;
   if (f.kind == FAB_F_POLY) P.coef.assign(f.coef, f.coef + f.ncoef);
   P.p = p;
+  if (bg) P.p.k = 1;   // the window is not used
+  P.bg = bg;
   P.esize = esize;
   P.nvar = (p.prec == FAB_PREC_AUTO || p.ls_mode == FAB_LS_AUTO) ? 3 : 1;
   // tiles of 2^LT elements (rows x rhs): 2048 for large problems, 512 below
@@ -243,10 +254,13 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   P.oRows = take(256);   // unused: sampled SRHT rows live in the context's cache
   P.oDense = take(P.dense_stride * nrhs * 8);
   P.oCf = take((size_t)nrhs * (m + 1) * 8);
+  if (bg) P.oBgCf = take((size_t)nrhs * (m + 2) * 8);
   // LSQR refinement (FAB_LS_AUTO when the gate fails, FAB_LS_LSQR always)
   if (p.ls_mode == FAB_LS_AUTO || p.ls_mode == FAB_LS_LSQR) {
     const bool fits = lsqr_pass_lds(m, nrhs) <= 120 * 1024;
-    if (!fits && p.ls_mode == FAB_LS_LSQR) return FAB_EINVAL;
+    // Algorithm 3 needs the refinement: the sketched problem is trivial for
+    // a sketch-orthonormal basis
+    if (!fits && (p.ls_mode == FAB_LS_LSQR || bg)) return FAB_EINVAL;
     if (fits) {
       P.lsqr = true;
       P.lnblk = (int)std::min<long long>((nel + 2047) / 2048, 512);
@@ -476,7 +490,27 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
   e = basis_start(d, P.esize, st, P.lds_update);
   E();
   if (e != hipSuccess) return FAB_EDEVICE;
-  for (int i = 1; i <= m; ++i) {
+  if (P.bg) {
+    double* bcf = (double*)(ws + P.oBgCf);
+    for (int i = 0; i <= m && e == hipSuccess; ++i) {
+      if (i > 0) {
+        B(FAB_K_DOTS);
+        e = bg_apply(d, P.esize, i, st, P.lds_update);
+        E();
+        if (e != hipSuccess) break;
+      }
+      B(FAB_K_OTHER);
+      e = bg_reduce(d, i, st);
+      if (e == hipSuccess) e = bg_gs(d, bcf, i, st);
+      E();
+      if (e != hipSuccess || i == 0) continue;
+      B(FAB_K_UPDATE);
+      e = bg_update(d, P.esize, bcf, i, st);
+      E();
+    }
+    if (e != hipSuccess) return FAB_EDEVICE;
+  }
+  for (int i = 1; i <= m && !P.bg; ++i) {
     B(FAB_K_DOTS);
     e = basis_dots(d, P.esize, i, st);
     E();
@@ -486,10 +520,12 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
     E();
     if (e != hipSuccess) return FAB_EDEVICE;
   }
-  B(FAB_K_OTHER);
-  e = basis_finish(d, P.esize, st);
-  E();
-  if (e != hipSuccess) return FAB_EDEVICE;
+  if (!P.bg) {
+    B(FAB_K_OTHER);
+    e = basis_finish(d, P.esize, st);
+    E();
+    if (e != hipSuccess) return FAB_EDEVICE;
+  }
   double* cf = (double*)(ws + P.oCf);
   B(FAB_K_DENSE);
   e = dense_tail(d, g, cf, st);
@@ -579,7 +615,7 @@ int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* h
 
 bool needs_refine(const Plan& P, int rc, const std::vector<fab_info>& fi) {
   if (rc != FAB_OK || !P.lsqr) return false;
-  if (P.p.ls_mode == FAB_LS_LSQR) return true;
+  if (P.p.ls_mode == FAB_LS_LSQR || P.bg) return true;
   for (const auto& x : fi)
     if (!x.breakdown && !(x.ls_gate <= P.p.tol / 10)) return true;
   return false;
@@ -751,6 +787,7 @@ int fab_init(fab_ctx* out, int device, void* arena_dev_ptr, size_t arena_bytes, 
   }
   (void)dense_set_attributes();
   (void)lsqr_set_attributes();
+  (void)bg_set_attributes();
   (void)hipGetLastError();
   if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev, hipEventDisableTiming) != hipSuccess) {

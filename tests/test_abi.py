@@ -38,8 +38,39 @@ def test_library_exports_every_declared_symbol():
 def test_binding_marshalling_matches_header_struct_sizes():
     from paper_2212_12758_amd import fab
 
-    # fab_params: 5 ints, u64 seed, 2 ints, double tol -> 48 bytes with natural alignment
-    assert ctypes.sizeof(fab.fab_params) == 48
+    # fab_params: 5 ints, u64 seed, 2 ints, double tol, int basis -> 56 bytes with natural alignment
+    assert ctypes.sizeof(fab.fab_params) == 56
+    assert fab.fab_params.basis.offset == 48
     # fab_info: 7 doubles, 5 ints (+4 padding), 1 double -> 88 bytes
     assert ctypes.sizeof(fab.fab_info) == 88
     assert ctypes.sizeof(fab.fab_func) == 48
+
+
+def test_binding_struct_layouts_match_the_c_header(tmp_path):
+    """Sizes and offsets the C compiler gives the header's structs equal the binding's."""
+    import shutil
+    import subprocess
+
+    from paper_2212_12758_amd import fab
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = {"fab_params": fab.fab_params, "fab_info": fab.fab_info, "fab_func": fab.fab_func,
+              "fab_diag": fab.fab_diag}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fab.h"', "int main(void) {"]
+    for name, st in fields.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in st._fields_:
+            lines.append(f'  printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for name, st in fields.items():
+        assert int(got[name]) == ctypes.sizeof(st), name
+        for fname, _ in st._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(st, fname).offset, (name, fname)

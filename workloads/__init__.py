@@ -144,7 +144,8 @@ class Workload:
         return len(self.op[0]) - 1
 
 
-CONFIG_NAMES = ("lap2d_100_exp", "convdiff3d_128_exp", "rgg_2p20_invsqrt", "convdiff3d_256_exp_8rhs")
+CONFIG_NAMES = ("lap2d_100_exp", "convdiff3d_128_exp", "rgg_2p20_invsqrt", "convdiff3d_256_exp_8rhs",
+                "lap3d_80_invsqrt")
 
 
 def config(name: str, scale: int | None = None) -> Workload:
@@ -167,4 +168,12 @@ def config(name: str, scale: int | None = None) -> Workload:
         N = 256 if scale is None else scale
         return Workload(name, convdiff3d(N, 100.0), 50, 8, FuncSpec("exp", alpha=-1e-3),
                         m=200, k=4, s=800, sketch="srht", sketch_seed=5)
+    if name == "lap3d_80_invsqrt":
+        # timing workload of the sketched Gram-Schmidt basis (Section 5.1.4):
+        # A^{-1/2} b for the 3D Laplacian with N = 80 (n = 512000), a sketch of
+        # floor(1.05 m) rows
+        N = 80 if scale is None else scale
+        m = 120
+        return Workload(name, laplacian3d(N), 8, 1, FuncSpec("pow", sigma=0.0, p=-0.5),
+                        m=m, k=2, s=int(math.floor(1.05 * m)), sketch="srht", sketch_seed=8)
     raise KeyError(name)
