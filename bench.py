@@ -18,6 +18,15 @@ Prints one JSON line.  Besides the contract fields it carries
 and in config: relative error of the timed result against that oracle,
 p50/p99 latency, algorithmic HBM GB/s of the whole solve, and the FP64-basis
 rate of the same method (the plain FP64 GPU path).
+
+--workload lap3d_80_invsqrt times the sketched Gram-Schmidt basis
+(Algorithm 3) on the paper's timing problem instead: A^{-1/2} b for the 3D
+Laplacian with N = 80 (n = 512,000), m = 120, an SRHT sketch of
+floor(1.05 m) = 126 rows, LSQR for the least squares.  By default the
+Gram-Schmidt step on the sketch runs twice (--basis sketched_gs2): with so
+few sketch rows one pass leaves Theta V far from orthonormal.  Its dominant
+kernel is the update u_i = w - V_{i-1} r_i, its oracle Algorithm 3 with the
+exact least-squares solution; it also reports the error against Arnoldi's f_m.
 """
 import argparse
 import json
@@ -30,6 +39,23 @@ sys.path.insert(0, ROOT)
 
 METRIC = "f(A)b solves/s at relerr≤1e-6 vs FP64 oracle; HBM GB/s; p50/p99 latency"
 HBM_PEAK_GBPS = 8000.0
+
+
+def algorithmic_bytes_bg(n, nrhs, m, esize, lsqr_iters):
+    """Bytes per solve and per kernel class for the sketched Gram-Schmidt basis
+    (stencil operator).  Step i (1..m): the apply pass reads u_{i-1}; the
+    update reads u_0..u_{i-1} (the stencil source among them) and writes u_i.
+    Start: read b, write u_0.  LSQR: per iteration one product with V_m and
+    one with V_m^T (m vectors each) plus about 6 FP64 vectors of its own.
+    Combine: read m vectors, write the FP64 result."""
+    vec = n * nrhs * esize
+    apply_ = m * vec
+    update = sum(i + 1 for i in range(1, m + 1)) * vec
+    start = n * nrhs * 8 + vec
+    lsqr = lsqr_iters * (2 * m * vec + 6 * n * nrhs * 8)
+    combine = m * vec + n * nrhs * 8
+    return {"dots_per_launch": apply_ / m, "update_per_launch": update / m,
+            "solve": apply_ + update + start + lsqr + combine}
 
 
 def algorithmic_bytes(n, nrhs, m, k, esize):
@@ -50,31 +76,50 @@ def algorithmic_bytes(n, nrhs, m, k, esize):
             "solve": dots + update + start + combine}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_update_convdiff3d_128_exp.json")
-KERNEL_SOURCES = ["paper_2212_12758_amd/csrc/k_basis.h", "paper_2212_12758_amd/csrc/k_basis_part.inc",
-                  "paper_2212_12758_amd/csrc/fab_dev.h"]
+# Per workload: the basis it is timed with, its dominant kernel (the name
+# rocprofv3 reports for the FP32 variant), the counter summary of that kernel
+# and the sources that define it (a summary counts only while they are unchanged).
+CSRC = "paper_2212_12758_amd/csrc/"
+BENCH = {
+    "convdiff3d_128_exp": {
+        "basis": "truncated",
+        "kernel": "k_update (Gram-Schmidt update + norm + fused SRHT)",
+        "pmc_kernel": "k_update<float, 0, 1, false, 11, 1, 4>",
+        "traffic_file": os.path.join(ROOT, "profiles", "traffic_k_update_convdiff3d_128_exp.json"),
+        "sources": [CSRC + "k_basis.h", CSRC + "k_basis_part.inc", CSRC + "fab_dev.h"],
+        "operator": "3D upwind convection-diffusion 7-point 128^3, Pe=50", "f": "exp(-1e-3 A)",
+    },
+    "lap3d_80_invsqrt": {
+        "basis": "sketched_gs2",
+        "kernel": "k_bg_update (u_i = w - V_{i-1} r_i over all previous vectors)",
+        "pmc_kernel": "k_bg_update<float, 0, true>",
+        "traffic_file": os.path.join(ROOT, "profiles", "traffic_k_bg_update_lap3d_80_invsqrt.json"),
+        "sources": [CSRC + "k_bg.hip", CSRC + "k_basis.h", CSRC + "fab_dev.h"],
+        "operator": "3D Laplacian 7-point 80^3 (T_N = tridiag(-1, 2, -1))", "f": "A^{-1/2}",
+    },
+}
 CALIBRATION_BYTES = 4 << 28   # the 1 GiB copy of --calibrate-copy
 
 
-def kernel_source_hash():
+def kernel_source_hash(workload="convdiff3d_128_exp"):
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in BENCH[workload]["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per k_update launch from the committed counter summary, or
-    None when the kernel sources changed since the counters were taken."""
+def measured_traffic(workload="convdiff3d_128_exp"):
+    """HBM bytes per launch of the workload's dominant kernel from the committed
+    counter summary, or None when its sources changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(BENCH[workload]["traffic_file"]) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    return t["bytes_per_launch"] if t.get("source_sha256") == kernel_source_hash() else None
+    return t["bytes_per_launch"] if t.get("source_sha256") == kernel_source_hash(workload) else None
 
 
 def _pmc_rows(d, counter):
@@ -90,25 +135,26 @@ def _pmc_rows(d, counter):
     return rows
 
 
-def summarize_pmc(fetch_dir, write_dir):
-    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of k_update, each scaled by
-    the same counter on a copy kernel of known size (the 1 GiB copy of
-    --calibrate-copy), written to the traffic summary read by measured_traffic()."""
-    out = {"kernel": "k_update<float, stencil, SRHT, 11, 1, 4> (steps after the first)",
-           "workload": "convdiff3d_128_exp", "source_sha256": kernel_source_hash()}
+def summarize_pmc(fetch_dir, write_dir, workload="convdiff3d_128_exp"):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the workload's dominant
+    kernel, each scaled by the same counter on a copy kernel of known size (the
+    1 GiB copy of --calibrate-copy), written to the traffic summary read by
+    measured_traffic()."""
+    cfg = BENCH[workload]
+    out = {"kernel": cfg["pmc_kernel"], "workload": workload, "source_sha256": kernel_source_hash(workload)}
     for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = _pmc_rows(d, counter)
         copies = [v for k, v in rows if "copyBuffer" in k]
-        upd = [v for k, v in rows if "k_update<float, 0, 1, false, 11, 1, 4>" in k]
+        upd = [v for k, v in rows if cfg["pmc_kernel"] in k]
         if not copies or not upd:
-            raise SystemExit(f"{counter}: no calibration copy or k_update dispatches in {d}")
+            raise SystemExit(f"{counter}: no calibration copy or {cfg['pmc_kernel']} dispatches in {d}")
         cal = max(copies)
         factor = CALIBRATION_BYTES / (cal * 1024.0)
         out[key] = {"counter": counter, "calibration_copy_kib": cal, "factor": factor,
-                    "k_update_mean_kib": sum(upd) / len(upd), "dispatches": len(upd),
+                    "kernel_mean_kib": sum(upd) / len(upd), "dispatches": len(upd),
                     "bytes_per_launch": factor * 1024.0 * sum(upd) / len(upd)}
     out["bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(cfg["traffic_file"], "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
 
@@ -137,9 +183,14 @@ def main():
                     help="first run one 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no GPU: turn two rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE outputs into the traffic summary")
+    ap.add_argument("--basis", default=None, choices=["truncated", "sketched_gs", "sketched_gs2"],
+                    help="basis construction (default: the workload's)")
+    ap.add_argument("--workload", default="convdiff3d_128_exp", choices=sorted(BENCH),
+                    help="convdiff3d_128_exp (headline, truncated basis) or lap3d_80_invsqrt (sketched "
+                         "Gram-Schmidt basis, Algorithm 3)")
     args = ap.parse_args()
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc)
+        summarize_pmc(*args.summarize_pmc, workload=args.workload)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the solve is not sharded "
@@ -152,25 +203,28 @@ def main():
     import workloads as W
     from paper_2212_12758_amd import Context, make_params
 
-    w = W.config("convdiff3d_128_exp")
+    cfg = BENCH[args.workload]
+    basis = args.basis or cfg["basis"]
+    bg = basis != "truncated"
+    w = W.config(args.workload)
     n = w.n
     b = W.rhs(n, w.b_seed)
     ctx = Context(0, arena_bytes=6 << 30)
     A = ctx.matrix(w.op)
     bd = torch.from_numpy(b).cuda()
     out = torch.empty_like(bd)
-    p32 = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, args.prec, args.ls, 1e-6)
-    p64 = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, "fp64", args.ls, 1e-10)
+    p32 = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, args.prec, args.ls, 1e-6, basis=basis)
+    p64 = make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, "fp64", args.ls, 1e-10, basis=basis)
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    ab32 = algorithmic_bytes(n, 1, w.m, w.k, 4)
 
+    info = None
     for _ in range(args.warmup):
-        ctx.solve(A, bd, w.f, p32, out)
+        _, info = ctx.solve(A, bd, w.f, p32, out)
     # timed region: K complete solves (replayed HIP graphs of the launch sequence)
     lat = []
     torch.cuda.synchronize()
@@ -184,6 +238,11 @@ def main():
     elapsed = t1 - t0
     value = args.steps / elapsed
     res32 = out.cpu().numpy()
+    esize = 8 if info[0]["prec_used"] == 2 else 4
+    if bg:
+        ab32 = algorithmic_bytes_bg(n, 1, w.m, esize, info[0]["ls_iters"])
+    else:
+        ab32 = algorithmic_bytes(n, 1, w.m, w.k, esize)
 
     # kernel timing region: the same K solves with direct launches and a HIP
     # event pair around every launch of the dominant kernel on its stream
@@ -217,28 +276,39 @@ def main():
 
     cpu = None
     relerr = None
+    relerr_fm = None
     if not args.no_cpu_baseline:
         from oracle import krylov, operators
+        from oracle import sketch as osk
 
         Aor = operators.as_matrix(w.op)
         c0 = time.perf_counter()
-        ref = krylov.fm(Aor, b, w.f, w.m)
+        if bg:
+            sk = osk.Sketch(w.sketch, n, w.s, w.sketch_seed, w.zeta)
+            ref = krylov.sgs(Aor, b, w.f, w.m, sk, passes=2 if basis == "sketched_gs2" else 1)["f"]
+            what = (f"Algorithm 3 with the exact least squares (FP64, numpy/scipy, "
+                    f"{'two' if basis == 'sketched_gs2' else 'one'} Gram-Schmidt pass(es) on the sketch)")
+        else:
+            ref = krylov.fm(Aor, b, w.f, w.m)
+            what = "f_m by full Arnoldi (FP64, numpy/scipy)"
         tcpu = time.perf_counter() - c0
         relerr = krylov.relerr(res32, ref)
+        if bg:
+            relerr_fm = krylov.relerr(res32, krylov.fm(Aor, b, w.f, w.m))
         cpu = {"value": 1.0 / tcpu, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
-               "sample": f"one full solve of the same workload: f_m by full Arnoldi (FP64, numpy/scipy) "
-                         f"at n={n}, m={w.m}, {tcpu:.1f} s"}
+               "sample": f"one full solve of the same workload: {what} at n={n}, m={w.m}, {tcpu:.1f} s"}
 
     lat_ms = np.array(lat) * 1e3
     line = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if esize == 4 else "f64", "data": "synthetic",
         "config": {
-            "workload": "convdiff3d_128_exp", "operator": "3D upwind convection-diffusion 7-point 128^3, Pe=50",
-            "n": n, "f": "exp(-1e-3 A)", "m": w.m, "k": w.k, "s": w.s, "sketch": "srht", "basis": "fp32",
-            "accumulate": "fp64", "ls": "sketch-and-solve",
-            "relerr_vs_oracle": relerr, "meets_tol": (relerr is not None and relerr <= 1e-6) or None,
+            "workload": args.workload, "operator": cfg["operator"],
+            "n": n, "f": cfg["f"], "m": w.m, "k": None if bg else w.k, "s": w.s, "sketch": w.sketch,
+            "basis": basis, "storage": "fp32" if esize == 4 else "fp64",
+            "accumulate": "fp64", "relerr_vs_oracle": relerr,
+            "meets_tol": (relerr is not None and relerr <= 1e-6) or None,
             "m_used": info[0]["m_used"], "prec_policy": args.prec, "ls_policy": args.ls,
             "prec_used": {1: "fp32", 2: "fp64"}.get(info[0]["prec_used"]), "fell_back": info[0]["fell_back"],
             "ls_iters": info[0]["ls_iters"], "err_est": info[0]["err_est"], "ls_gate": info[0]["ls_gate"],
@@ -249,8 +319,9 @@ def main():
             "fp32_over_fp64": (value / fp64_rate) if fp64_rate else None,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": measured_traffic(),
-                     "kernel": "k_update (Gram-Schmidt update + norm + fused SRHT)",
+                     "frac": (achieved / HBM_PEAK_GBPS) if achieved else None,
+                     "traffic": measured_traffic(args.workload),
+                     "kernel": cfg["kernel"],
                      "bytes_per_launch": ab32["update_per_launch"], "mean_launch_us": upd_ms * 1e3,
                      "launches": nlaunch, "timing": "HIP events around each launch, direct launches, "
                      f"{args.steps} solves ({1e3 * prof_elapsed / args.steps:.2f} ms/solve in that region)",
@@ -258,6 +329,8 @@ def main():
                      "dots_kernel_GBps": ab32["dots_per_launch"] / (dots_us * 1e-6) / 1e9 if dots_us > 0 else None},
         "cpu_baseline": cpu,
     }
+    if bg:
+        line["config"]["relerr_vs_arnoldi_fm"] = relerr_fm
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -93,10 +93,14 @@ enum fab_ls_mode {
 /* Construction of the basis. */
 enum fab_basis {
   FAB_BASIS_TRUNCATED = 0,    /* k-truncated orthogonalisation (Algorithm 2)              */
-  FAB_BASIS_SKETCHED_GS = 1   /* Gram-Schmidt on the sketch (Algorithm 1): Theta V_{m+1} is
+  FAB_BASIS_SKETCHED_GS = 1,  /* Gram-Schmidt on the sketch (Algorithm 1): Theta V_{m+1} is
                                  orthonormal, v_i = (A v_{i-1} - V_{i-1} r_i) / r_ii; with
                                  FAB_LS_AUTO the least squares are always refined by LSQR,
                                  which gives Algorithm 3                                    */
+  FAB_BASIS_SKETCHED_GS2 = 2  /* as FAB_BASIS_SKETCHED_GS with the Gram-Schmidt step on the
+                                 sketch repeated once on its residual (r_i = r' + r''; not in
+                                 the paper): same long-vector work, Theta V stays orthonormal
+                                 to rounding when s is close to m                         */
 };
 
 typedef struct {
@@ -111,6 +115,9 @@ typedef struct {
   int ls_mode;        /* enum fab_ls_mode                                         */
   double tol;         /* target relative accuracy for AUTO policies (e.g. 1e-6)    */
   int basis;          /* enum fab_basis; 0 (a zero-initialised struct) = truncated  */
+  int ls_maxit;       /* LSQR iteration limit, 0..1024; 0 = default: 32 for the
+                         truncated basis (Blendenpik-preconditioned), 128 for the
+                         sketched Gram-Schmidt bases (unpreconditioned)          */
 } fab_params;
 
 /* Per right-hand side diagnostics. */

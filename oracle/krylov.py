@@ -145,7 +145,7 @@ def nt(A, b: np.ndarray, f, m: int, k: int, sketch=None, ls: str = "sketch"):
     return out
 
 
-def sketched_gs_basis(A, b: np.ndarray, m: int, sketch):
+def sketched_gs_basis(A, b: np.ndarray, m: int, sketch, passes: int = 1):
     """Algorithm 1: the basis whose sketch Theta V is kept orthonormal.
 
     Each new vector w = A v_{i-1} is sketched (p = Theta w), one classical
@@ -154,6 +154,12 @@ def sketched_gs_basis(A, b: np.ndarray, m: int, sketch):
     v_i = (w - V r) / r_ii.  Returns V (rows v_0..v_mu), Hbar (the columns
     2..m+1 of R), r_11 = ||Theta b||, S = Theta V (columns), m_used and the
     breakdown flag (r_ii <= 100 eps ||p||: the subspace is invariant).
+
+    passes = 2 is not in the paper: the Gram-Schmidt step on the sketch is
+    repeated once on its own residual (r = r' + r'', s = p - S r' - S r''),
+    which leaves exact arithmetic unchanged (S is orthonormal, so r'' = 0)
+    but keeps S orthonormal to rounding where one pass loses it (sketches
+    with s close to m).  parity unpinned by the paper; pinned by invariants.
     """
     b = np.asarray(b, dtype=np.float64)
     n = b.size
@@ -171,6 +177,10 @@ def sketched_gs_basis(A, b: np.ndarray, m: int, sketch):
         p = sketch.apply(w)
         r = S[:, :i].T @ p
         sv = p - S[:, :i] @ r
+        for _ in range(passes - 1):
+            r2 = S[:, :i].T @ sv
+            sv = sv - S[:, :i] @ r2
+            r = r + r2
         rii = float(np.linalg.norm(sv))
         H[:i, i - 1] = r
         if rii <= _breakdown_tol() * np.linalg.norm(p):
@@ -181,11 +191,12 @@ def sketched_gs_basis(A, b: np.ndarray, m: int, sketch):
     return V, H, r11, S, m, False
 
 
-def sgs(A, b: np.ndarray, f, m: int, sketch) -> dict:
-    """Algorithm 3 with the least-squares problem of line 2 solved exactly
-    (the limit of its LSQR iteration): y = argmin ||V_m z - v_{m+1}||, result
-    r_11 V_m f(H_m + h_{m+1,m} y e_m^T) e_1."""
-    V, Hbar, r11, S, mu, brk = sketched_gs_basis(A, b, m, sketch)
+def sgs(A, b: np.ndarray, f, m: int, sketch, passes: int = 1) -> dict:
+    """Algorithm 3 with the least-squares problem of its second step solved
+    exactly (the limit of its LSQR iteration): y = argmin ||V_m z - v_{m+1}||,
+    result r_11 V_m f(H_m + h_{m+1,m} y e_m^T) e_1.  ``passes`` as in
+    sketched_gs_basis."""
+    V, Hbar, r11, S, mu, brk = sketched_gs_basis(A, b, m, sketch, passes)
     y = np.zeros(mu)
     if not brk and mu > 0:
         y = np.linalg.lstsq(V[:mu].T, V[mu], rcond=None)[0]

@@ -10,7 +10,8 @@
 //   k_bg_reduce : fixed-order reduction of those partials into S[:, i].
 //   k_bg_gs     : one workgroup per right-hand side: p = S[:, i] / eta_{i-1}
 //                 (= Theta A v_{i-1}), r_j = s_j^T p for j < i, the sketch
-//                 residual p - S_{i-1} r, r_ii = its norm, the breakdown test
+//                 residual p - S_{i-1} r (optionally a second pass on it),
+//                 r_ii = its norm, the breakdown test
 //                 r_ii <= 100 u ||p||, the Hessenberg column (r; r_ii), and
 //                 the update weights 1/eta_{i-1} and r_j / eta_j.
 //   k_bg_update : u_i = w~ / eta_{i-1} - sum_{j<i} (r_j / eta_j) u_j, so that
@@ -133,9 +134,13 @@ __device__ inline double gs_block_sum(double v, double* red) {
 
 // ------------------------------------------------------------------ small Gram-Schmidt on the sketch
 // cf: [nrhs][m+2] update weights (cf[0] = 1/eta_{i-1}, cf[1+j] = r_j/eta_j).
-__global__ void __launch_bounds__(GS_BLOCK) k_bg_gs(SolveDev d, double* __restrict__ cfall, int i) {
-  extern __shared__ double psh[];      // p, s values
+// passes = 2 repeats the step on its own residual and adds the coefficients
+// (r = r' + r''), which keeps S orthonormal to rounding when one classical
+// pass does not; the long vectors still see one update with the total r.
+__global__ void __launch_bounds__(GS_BLOCK) k_bg_gs(SolveDev d, double* __restrict__ cfall, int i, int passes) {
+  extern __shared__ double psh[];      // p, then the residual (s values)
   __shared__ double csh[512];          // r_j / eta_j
+  __shared__ double cnew[512];         // this pass's coefficients
   __shared__ double red[GS_BLOCK / 64];
   const int q = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = wave_id();
   const int m = d.m, m1 = d.m + 1, s = d.s;
@@ -174,25 +179,32 @@ __global__ void __launch_bounds__(GS_BLOCK) k_bg_gs(SolveDev d, double* __restri
     a += v * v;
   }
   const double pn = sqrt(gs_block_sum(a, red));   // includes the barrier after psh is written
-  // r_j = s_j^T p with s_j = S[:, j] / eta_j: one wave per column
-  for (int j = wv; j < i; j += GS_BLOCK / 64) {
-    const double* Sj = S + (long long)j * s;
-    double t = 0.0;
-    for (int r = lane; r < s; r += 64) t += Sj[r] * psh[r];
-    t = wave_sum_all(t);
-    if (lane == 0) csh[j] = t / (eta[j] * eta[j]);   // r_j / eta_j
-  }
-  __syncthreads();
-  // sketch residual p - sum_j r_j s_j, stored as Theta u_i
-  double b2 = 0.0;
-  for (int r = tid; r < s; r += GS_BLOCK) {
-    double v = psh[r];
+  for (int j = tid; j < i; j += GS_BLOCK) csh[j] = 0.0;
+  double rii = 0.0;
+  for (int pass = 0; pass < passes; ++pass) {
+    // coefficients s_j^T x of the current vector x (p, then the residual),
+    // s_j = S[:, j] / eta_j: one wave per column, stored as r_j / eta_j
+    for (int j = wv; j < i; j += GS_BLOCK / 64) {
+      const double* Sj = S + (long long)j * s;
+      double t = 0.0;
+      for (int r = lane; r < s; r += 64) t += Sj[r] * psh[r];
+      t = wave_sum_all(t);
+      if (lane == 0) cnew[j] = t / (eta[j] * eta[j]);
+    }
+    __syncthreads();
+    // residual x - sum_j r_j s_j (each thread its own rows)
+    double b2 = 0.0;
+    for (int r = tid; r < s; r += GS_BLOCK) {
+      double v = psh[r];
 #pragma unroll 8
-    for (int j = 0; j < i; ++j) v -= csh[j] * S[(long long)j * s + r];
-    Si[r] = v;
-    b2 += v * v;
+      for (int j = 0; j < i; ++j) v -= cnew[j] * S[(long long)j * s + r];
+      psh[r] = v;
+      b2 += v * v;
+    }
+    for (int j = tid; j < i; j += GS_BLOCK) csh[j] += cnew[j];
+    rii = sqrt(gs_block_sum(b2, red));   // barriers: psh, csh complete before the next pass
   }
-  const double rii = sqrt(gs_block_sum(b2, red));
+  for (int r = tid; r < s; r += GS_BLOCK) Si[r] = psh[r];   // Theta u_i
   const bool nonfinite = !isfinite(pn) || !isfinite(rii);
   const bool brk = nonfinite || rii <= 100.0 * d.unit_round * pn;
   for (int j = tid; j < i; j += GS_BLOCK) {
@@ -320,10 +332,11 @@ hipError_t bg_reduce(const SolveDev& d, int col, hipStream_t st) {
   return hipGetLastError();
 }
 
-// i = 0: r_11 = ||Theta b||; i >= 1: the Gram-Schmidt step of column i.
-hipError_t bg_gs(const SolveDev& d, double* cf, int i, hipStream_t st) {
-  if (d.s > GS_MAXS || d.m + 1 > 512) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_bg_gs, dim3(d.nrhs), dim3(GS_BLOCK), (size_t)d.s * 8, st, d, cf, i);
+// i = 0: r_11 = ||Theta b||; i >= 1: the Gram-Schmidt step of column i
+// (passes = 1 as in Algorithm 1, 2 with the step repeated).
+hipError_t bg_gs(const SolveDev& d, double* cf, int i, int passes, hipStream_t st) {
+  if (d.s > GS_MAXS || d.m + 1 > 512 || passes < 1 || passes > 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bg_gs, dim3(d.nrhs), dim3(GS_BLOCK), (size_t)d.s * 8, st, d, cf, i, passes);
   return hipGetLastError();
 }
 

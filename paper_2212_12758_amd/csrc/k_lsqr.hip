@@ -291,22 +291,44 @@ __global__ void __launch_bounds__(256) k_lsqr_finish(SolveDev d, DenseDev g, Lsq
     }
 }
 
-hipError_t lsqr_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st) {
+namespace {
+void lsqr_pass_launch(const SolveDev& d, const LsqrDev& L, int esize, hipStream_t st, int first) {
   const size_t lds = lsqr_pass_lds(d.m, d.nrhs);
-  auto pass = [&](int first) {
-    if (esize == 4) hipLaunchKernelGGL(k_lsqr_pass<float>, dim3(L.nblk), dim3(256), lds, st, d, L, first);
-    else hipLaunchKernelGGL(k_lsqr_pass<double>, dim3(L.nblk), dim3(256), lds, st, d, L, first);
-  };
-  pass(1);
+  if (esize == 4) hipLaunchKernelGGL(k_lsqr_pass<float>, dim3(L.nblk), dim3(256), lds, st, d, L, first);
+  else hipLaunchKernelGGL(k_lsqr_pass<double>, dim3(L.nblk), dim3(256), lds, st, d, L, first);
+}
+}  // namespace
+
+// Initialisation (u = v_{m+1}, first bidiagonalisation step).
+hipError_t lsqr_begin(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st) {
+  lsqr_pass_launch(d, L, esize, st, 1);
   hipLaunchKernelGGL(k_lsqr_step, dim3(d.nrhs), dim3(256), 0, st, d, g, L, 1);
   hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
-  for (int it = 0; it < L.maxit; ++it) {
-    pass(0);
+  return hipGetLastError();
+}
+
+// `count` further iterations; launches after every right-hand side stopped return at once.
+hipError_t lsqr_iterate(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st,
+                        int count) {
+  for (int it = 0; it < count; ++it) {
+    lsqr_pass_launch(d, L, esize, st, 0);
     hipLaunchKernelGGL(k_lsqr_step, dim3(d.nrhs), dim3(256), 0, st, d, g, L, 0);
     hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
   }
+  return hipGetLastError();
+}
+
+hipError_t lsqr_end(const SolveDev& d, const DenseDev& g, const LsqrDev& L, hipStream_t st) {
   hipLaunchKernelGGL(k_lsqr_finish, dim3(d.nrhs), dim3(256), 0, st, d, g, L);
   return hipGetLastError();
+}
+
+// The whole refinement as one fixed-length launch sequence (L.maxit iterations).
+hipError_t lsqr_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st) {
+  hipError_t e = lsqr_begin(d, g, L, esize, st);
+  if (e == hipSuccess) e = lsqr_iterate(d, g, L, esize, st, L.maxit);
+  if (e == hipSuccess) e = lsqr_end(d, g, L, st);
+  return e;
 }
 
 hipError_t lsqr_set_attributes() {

@@ -49,10 +49,14 @@ hipError_t srht_sample_rows(int* rows, long long npad, int s, unsigned long long
 hipError_t dense_set_attributes();
 hipError_t dense_after_refine(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st);
 hipError_t lsqr_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st);
+hipError_t lsqr_begin(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st);
+hipError_t lsqr_iterate(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st,
+                        int count);
+hipError_t lsqr_end(const SolveDev& d, const DenseDev& g, const LsqrDev& L, hipStream_t st);
 hipError_t lsqr_set_attributes();
 hipError_t bg_apply(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds);
 hipError_t bg_reduce(const SolveDev& d, int col, hipStream_t st);
-hipError_t bg_gs(const SolveDev& d, double* cf, int i, hipStream_t st);
+hipError_t bg_gs(const SolveDev& d, double* cf, int i, int passes, hipStream_t st);
 hipError_t bg_update(const SolveDev& d, int esize, const double* cf, int i, hipStream_t st);
 hipError_t bg_set_attributes();
 size_t lsqr_state_stride(int m);
@@ -188,8 +192,10 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   const long long n = A->n;
   if (nrhs < 1 || nrhs > 32 || (nrhs & (nrhs - 1))) return FAB_EINVAL;
   if (p.m < 1 || p.m >= n || p.m > 500) return FAB_EINVAL;
-  if (p.basis != FAB_BASIS_TRUNCATED && p.basis != FAB_BASIS_SKETCHED_GS) return FAB_EINVAL;
-  const bool bg = p.basis == FAB_BASIS_SKETCHED_GS;
+  if (p.basis != FAB_BASIS_TRUNCATED && p.basis != FAB_BASIS_SKETCHED_GS && p.basis != FAB_BASIS_SKETCHED_GS2)
+    return FAB_EINVAL;
+  const bool bg = p.basis != FAB_BASIS_TRUNCATED;
+  if (p.ls_maxit < 0 || p.ls_maxit > 1024) return FAB_EINVAL;
   if (!bg && (p.k < 1 || p.k > KMAX)) return FAB_EINVAL;
   if (p.sketch != FAB_SKETCH_SRHT && p.sketch != FAB_SKETCH_SPARSE_SIGN) return FAB_EINVAL;
   const long long npad = 1LL << ilog2(n);
@@ -334,6 +340,7 @@ struct fab_ctx_s {
   bool stop = false;
   std::set<fab_matrix> matrices;
   double* host_info = nullptr;   // pinned staging for blocking solves
+  int* host_flag = nullptr;      // pinned: LSQR stop flag of blocking solves
   std::mutex solve_mu;
   Prof prof;
   // Replayable graphs of blocking solves, keyed by everything the launch
@@ -501,7 +508,7 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
       }
       B(FAB_K_OTHER);
       e = bg_reduce(d, i, st);
-      if (e == hipSuccess) e = bg_gs(d, bcf, i, st);
+      if (e == hipSuccess) e = bg_gs(d, bcf, i, P.p.basis == FAB_BASIS_SKETCHED_GS2 ? 2 : 1, st);
       E();
       if (e != hipSuccess || i == 0) continue;
       B(FAB_K_UPDATE);
@@ -582,9 +589,14 @@ int collect_info(const Plan& P, const double* hinfo, std::vector<fab_info>& out)
 int esize_for(int prec) { return prec == FAB_PREC_FP64 ? 8 : 4; }
 
 // LSQR refinement of the least squares (FAB_LS_LSQR always; FAB_LS_AUTO when
-// the gate ||R (c_y - c_0)|| / ||R c_y|| exceeds tol/10), then f, the
-// estimates, the weights and the combination again, and the info copy.
-int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* hinfo) {
+// the gate ||R (c_y - c_0)|| / ||R c_y|| exceeds tol/10, or always with a
+// sketched Gram-Schmidt basis), then f, the estimates, the weights and the
+// combination again, and the info copy.  With `host_flag` (pinned; blocking
+// solves) the iterations are issued in chunks and the stream is synchronised
+// after each to stop issuing once every right-hand side has stopped; without
+// it (served requests) the whole fixed-length sequence is enqueued.  Both
+// stop at the same iteration: the device flag decides.
+int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* hinfo, int* host_flag = nullptr) {
   SolveDev d;
   DenseDev g;
   build_descs(P, ws, rows, d, g);
@@ -595,10 +607,24 @@ int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* h
   L.stride = (long long)lsqr_state_stride(P.p.m);
   L.alldone = (int*)(ws + P.oLflag);
   L.nblk = P.lnblk;
-  L.maxit = 32;
+  L.maxit = P.p.ls_maxit > 0 ? P.p.ls_maxit : (P.bg ? 128 : 32);
   L.tol = P.p.tol / 10;
   if (zero_fill(ws + P.oLflag, 256, st) != hipSuccess) return FAB_EDEVICE;
-  if (lsqr_launch(d, g, L, P.esize, st) != hipSuccess) return FAB_EDEVICE;
+  if (!host_flag) {
+    if (lsqr_launch(d, g, L, P.esize, st) != hipSuccess) return FAB_EDEVICE;
+  } else {
+    constexpr int CHUNK = 16;
+    if (lsqr_begin(d, g, L, P.esize, st) != hipSuccess) return FAB_EDEVICE;
+    for (int it = 0; it < L.maxit; it += CHUNK) {
+      if (lsqr_iterate(d, g, L, P.esize, st, std::min(CHUNK, L.maxit - it)) != hipSuccess) return FAB_EDEVICE;
+      *host_flag = 0;
+      if (hipMemcpyAsync(host_flag, L.alldone, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return FAB_EDEVICE;
+      if (*host_flag) break;
+    }
+    if (lsqr_end(d, g, L, st) != hipSuccess) return FAB_EDEVICE;
+  }
   double* cf = (double*)(ws + P.oCf);
   if (dense_after_refine(d, g, cf, st) != hipSuccess) return FAB_EDEVICE;
   if (basis_combine(d, P.esize, cf, P.p.m, P.out, st) != hipSuccess) return FAB_EDEVICE;
@@ -809,7 +835,8 @@ int fab_init(fab_ctx* out, int device, void* arena_dev_ptr, size_t arena_bytes, 
     ctx->pool_ev.push_back(e);
     ctx->pool_busy.push_back(0);
   }
-  if (hipHostMalloc((void**)&ctx->host_info, host_info_doubles(32) * 8, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&ctx->host_info, host_info_doubles(32) * 8, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->host_flag, 256, hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return FAB_EDEVICE;
   }
@@ -1062,7 +1089,7 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
     break;
   }
   if (needs_refine(P, rc, fi)) {
-    rc = enqueue_refine(P, ws, ctx->stream, nullptr, ctx->host_info);
+    rc = enqueue_refine(P, ws, ctx->stream, nullptr, ctx->host_info, ctx->host_flag);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == FAB_OK) rc = FAB_EDEVICE;
     if (rc == FAB_OK) rc = collect_info(P, ctx->host_info, fi);
   }
@@ -1237,6 +1264,7 @@ int fab_finalize(fab_ctx ctx) {
   }
   ctx->graphs.clear();
   if (ctx->host_info) hipHostFree(ctx->host_info);
+  if (ctx->host_flag) hipHostFree(ctx->host_flag);
   for (auto ev : ctx->prof.pool) hipEventDestroy(ev);
   if (ctx->arena.owned) hipFree(ctx->arena.base);
   delete ctx;

@@ -18,7 +18,7 @@ F_EXP, F_POW, F_POLY = 1, 2, 3
 SKETCH_SRHT, SKETCH_SPARSE_SIGN = 1, 2
 PREC_FP32, PREC_FP64, PREC_AUTO = 1, 2, 3
 LS_AUTO, LS_SKETCH, LS_NONE, LS_LSQR = 0, 1, 2, 3
-BASIS_TRUNCATED, BASIS_SKETCHED_GS = 0, 1
+BASIS_TRUNCATED, BASIS_SKETCHED_GS, BASIS_SKETCHED_GS2 = 0, 1, 2
 
 
 class fab_func(C.Structure):
@@ -29,7 +29,7 @@ class fab_func(C.Structure):
 class fab_params(C.Structure):
     _fields_ = [("m", C.c_int), ("k", C.c_int), ("s", C.c_int), ("sketch", C.c_int), ("zeta", C.c_int),
                 ("seed", C.c_uint64), ("prec", C.c_int), ("ls_mode", C.c_int), ("tol", C.c_double),
-                ("basis", C.c_int)]
+                ("basis", C.c_int), ("ls_maxit", C.c_int)]
 
 
 class fab_info(C.Structure):
@@ -103,14 +103,15 @@ def make_func(f) -> tuple:
 
 
 def make_params(m, k, s, sketch="srht", zeta=8, seed=0, prec="fp32", ls_mode="sketch", tol=1e-6,
-                basis="truncated") -> fab_params:
+                basis="truncated", ls_maxit=0) -> fab_params:
     sk = {"srht": SKETCH_SRHT, "sparse_sign": SKETCH_SPARSE_SIGN}[sketch] if isinstance(sketch, str) else sketch
     pr = {"fp32": PREC_FP32, "fp64": PREC_FP64, "auto": PREC_AUTO}[prec] if isinstance(prec, str) else prec
     ls = {"auto": LS_AUTO, "sketch": LS_SKETCH, "none": LS_NONE, "lsqr": LS_LSQR}[ls_mode] \
         if isinstance(ls_mode, str) else ls_mode
-    bs = {"truncated": BASIS_TRUNCATED, "sketched_gs": BASIS_SKETCHED_GS}[basis] if isinstance(basis, str) else basis
+    bs = {"truncated": BASIS_TRUNCATED, "sketched_gs": BASIS_SKETCHED_GS,
+          "sketched_gs2": BASIS_SKETCHED_GS2}[basis] if isinstance(basis, str) else basis
     return fab_params(int(m), int(k), int(s), sk, int(zeta), int(seed) & ((1 << 64) - 1), pr, ls, float(tol),
-                      int(bs))
+                      int(bs), int(ls_maxit))
 
 
 class Matrix:

@@ -38,9 +38,9 @@ def test_library_exports_every_declared_symbol():
 def test_binding_marshalling_matches_header_struct_sizes():
     from paper_2212_12758_amd import fab
 
-    # fab_params: 5 ints, u64 seed, 2 ints, double tol, int basis -> 56 bytes with natural alignment
+    # fab_params: 5 ints, u64 seed, 2 ints, double tol, 2 ints -> 56 bytes with natural alignment
     assert ctypes.sizeof(fab.fab_params) == 56
-    assert fab.fab_params.basis.offset == 48
+    assert fab.fab_params.basis.offset == 48 and fab.fab_params.ls_maxit.offset == 52
     # fab_info: 7 doubles, 5 ints (+4 padding), 1 double -> 88 bytes
     assert ctypes.sizeof(fab.fab_info) == 88
     assert ctypes.sizeof(fab.fab_func) == 48

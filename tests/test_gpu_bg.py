@@ -36,10 +36,10 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
 
 
-def _p(w, prec, ls="lsqr", tol=1e-12, m=None):
+def _p(w, prec, ls="lsqr", tol=1e-12, m=None, basis="sketched_gs"):
     from paper_2212_12758_amd import make_params
 
-    return make_params(m or w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, prec, ls, tol, basis="sketched_gs")
+    return make_params(m or w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, prec, ls, tol, basis=basis)
 
 
 def _sk(w):
@@ -119,6 +119,38 @@ def test_bg_lap3d_invsqrt_small_sketch(ctx):
     A.destroy()
 
 
+# ------------------------------------------------------------------ the repeated Gram-Schmidt step on the sketch
+def test_bg2_keeps_sketch_orthonormal_with_small_sketch(ctx):
+    """s = 63 rows for m = 60: one pass loses the orthonormality of Theta V
+    (the oracle alone reaches 3e-2), the repeated step keeps it to rounding;
+    its result is the Arnoldi approximation f_m (exact least squares, here
+    LSQR to convergence)."""
+    st = W.laplacian3d(16)
+    b = W.rhs(st.n, 4)
+    m, s = 60, 63
+    f = W.FuncSpec("pow", sigma=0.0, p=-0.5)
+    w = W.Workload("lap3d16", st, 4, 1, f, m=m, k=2, s=s, sketch="srht", sketch_seed=5)
+    Aor = operators.as_matrix(st)
+    sk = _sk(w)
+    ref = krylov.sgs(Aor, b, f, m, sk, passes=2)
+    fm = krylov.fm(Aor, b, f, m)
+    A = ctx.matrix(st)
+    print("case bg2 lap3d16 fp64", flush=True)
+    out, info, dg = ctx.solve(A, _dev(b), f, _p(w, "fp64", basis="sketched_gs2"), diag=True)
+    out = out.cpu().numpy()
+    assert info[0]["m_used"] == m and info[0]["breakdown"] == 0
+    SV = dg["sv"]
+    assert np.abs(SV.T @ SV - np.eye(m + 1)).max() < 1e-12
+    H = ref["Hbar"]
+    assert np.abs(dg["hbar"][:21, :20] - H[:21, :20]).max() <= 1e-9 * np.abs(H).max()
+    assert krylov.relerr(out, ref["f"]) < 1e-8
+    assert krylov.relerr(out, fm) < 1e-8
+    print("case bg2 lap3d16 fp32", flush=True)
+    out32, info32 = ctx.solve(A, _dev(b), f, _p(w, "fp32", tol=1e-8, basis="sketched_gs2"))
+    assert krylov.relerr(out32.cpu().numpy(), fm) < 1e-5
+    A.destroy()
+
+
 # ------------------------------------------------------------------ invariant subspace
 def test_bg_lucky_breakdown(ctx):
     d = np.repeat([0.5, 1.0, 2.0, 3.5, 5.0], 200)
@@ -192,6 +224,6 @@ def test_bg_invalid_basis(ctx):
     b = _dev(W.rhs(st.n, 1))
     f = W.FuncSpec("exp", alpha=-1.0)
     with pytest.raises(FabError) as e:
-        ctx.solve(A, b, f, make_params(20, 2, 60, "srht", 8, 1, "fp64", "lsqr", basis=2))
+        ctx.solve(A, b, f, make_params(20, 2, 60, "srht", 8, 1, "fp64", "lsqr", basis=3))
     assert e.value.code == EINVAL
     A.destroy()

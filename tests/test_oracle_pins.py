@@ -397,3 +397,34 @@ def test_sketched_gs_basis_algorithm1_pinned():
     Hbad = H.copy()
     Hbad[m, m - 1] *= 1.01
     assert np.linalg.norm(A @ V[:m].T - V.T @ Hbad) / np.linalg.norm(A @ V[:m].T) > 1e-6
+
+
+def test_sketched_gs_two_passes_pinned():
+    """The repeated Gram-Schmidt step on the sketch (not in the paper) keeps
+    Theta V orthonormal to rounding where one pass loses it (s = 63 rows for
+    m = 60 on a 3D Laplacian), spans the same Krylov subspace (Arnoldi-like
+    relation, same f_m with the exact least squares) and agrees with one pass
+    where that pass is accurate."""
+    st = W.laplacian3d(16)
+    A = operators.as_matrix(st)
+    b = W.rhs(st.n, 4)
+    m, s = 60, 63
+    sk = sketch.Sketch("srht", st.n, s, 5, 8)
+    _, _, _, S1, _, _ = krylov.sketched_gs_basis(A, b, m, sk, passes=1)
+    V, H, r11, S, mu, brk = krylov.sketched_gs_basis(A, b, m, sk, passes=2)
+    assert mu == m and not brk
+    assert np.abs(S1.T @ S1 - np.eye(m + 1)).max() > 1e-3        # one pass: lost
+    assert np.abs(S.T @ S - np.eye(m + 1)).max() < 1e-13         # two passes: kept
+    assert np.abs(sk.apply(V.T) - S).max() < 1e-6
+    rel = np.linalg.norm(A @ V[:m].T - V.T @ H) / np.linalg.norm(A @ V[:m].T)
+    assert rel < 1e-12
+    f = W.FuncSpec("pow", sigma=0.0, p=-0.5)
+    assert krylov.relerr(krylov.sgs(A, b, f, m, sk, passes=2)["f"], krylov.fm(A, b, f, m)) < 1e-11
+    # a well-conditioned sketch: both passes give the same Hessenberg matrix
+    st2 = W.convdiff3d(10, 50.0)
+    A2 = operators.as_matrix(st2)
+    b2 = W.rhs(st2.n, 7)
+    sk2 = sketch.Sketch("srht", st2.n, 120, 3, 8)
+    H1 = krylov.sketched_gs_basis(A2, b2, 20, sk2, passes=1)[1]
+    H2 = krylov.sketched_gs_basis(A2, b2, 20, sk2, passes=2)[1]
+    assert np.abs(H1 - H2).max() < 1e-9 * np.abs(H1).max()
