@@ -31,6 +31,11 @@ namespace {
 
 constexpr int GS_BLOCK = 256;
 constexpr int GS_MAXS = 8192;
+constexpr size_t GS_LDS_MAX = 150 * 1024;
+// Dynamic LDS of the Gram-Schmidt step: p (s values), plus the sketch columns
+// S[:, 0..m-1] when they fit (every access of the step is then an LDS access).
+size_t gs_lds_staged(int s, int m) { return (size_t)s * (m + 1) * 8; }
+bool gs_staged(int s, int m) { return gs_lds_staged(s, m) <= GS_LDS_MAX; }
 
 // ------------------------------------------------------------------ pass 1
 template <typename T, int OP, int SK, int LT>
@@ -137,8 +142,9 @@ __device__ inline double gs_block_sum(double v, double* red) {
 // passes = 2 repeats the step on its own residual and adds the coefficients
 // (r = r' + r''), which keeps S orthonormal to rounding when one classical
 // pass does not; the long vectors still see one update with the total r.
+template <bool STAGED>
 __global__ void __launch_bounds__(GS_BLOCK) k_bg_gs(SolveDev d, double* __restrict__ cfall, int i, int passes) {
-  extern __shared__ double psh[];      // p, then the residual (s values)
+  extern __shared__ double psh[];      // p, then the residual (s values); staged: S[:, 0..i-1] behind it
   __shared__ double csh[512];          // r_j / eta_j
   __shared__ double cnew[512];         // this pass's coefficients
   __shared__ double red[GS_BLOCK / 64];
@@ -178,18 +184,31 @@ __global__ void __launch_bounds__(GS_BLOCK) k_bg_gs(SolveDev d, double* __restri
     psh[r] = v;
     a += v * v;
   }
-  const double pn = sqrt(gs_block_sum(a, red));   // includes the barrier after psh is written
+  // columns 0..i-1: their LDS copy (STAGED, a compile-time choice so that
+  // the accesses compile to LDS loads) or global memory
+  if (STAGED)
+    for (long long x = tid; x < (long long)i * s; x += GS_BLOCK) psh[s + x] = S[x];
+  const double* Sc = STAGED ? (const double*)(psh + s) : (const double*)S;
+  const double pn = sqrt(gs_block_sum(a, red));   // includes the barrier after psh (and Sl) is written
   for (int j = tid; j < i; j += GS_BLOCK) csh[j] = 0.0;
   double rii = 0.0;
   for (int pass = 0; pass < passes; ++pass) {
     // coefficients s_j^T x of the current vector x (p, then the residual),
     // s_j = S[:, j] / eta_j: one wave per column, stored as r_j / eta_j
-    for (int j = wv; j < i; j += GS_BLOCK / 64) {
-      const double* Sj = S + (long long)j * s;
-      double t = 0.0;
-      for (int r = lane; r < s; r += 64) t += Sj[r] * psh[r];
-      t = wave_sum_all(t);
-      if (lane == 0) cnew[j] = t / (eta[j] * eta[j]);
+    // (four columns per wave at a time, so that their loads overlap)
+    for (int j0 = 4 * wv; j0 < i; j0 += 4 * (GS_BLOCK / 64)) {
+      double t[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int r = lane; r < s; r += 64) {
+        const double x = psh[r];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (j0 + u < i) t[u] += Sc[(long long)(j0 + u) * s + r] * x;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double tu = wave_sum_all(t[u]);
+        if (lane == 0 && j0 + u < i) cnew[j0 + u] = tu / (eta[j0 + u] * eta[j0 + u]);
+      }
     }
     __syncthreads();
     // residual x - sum_j r_j s_j (each thread its own rows)
@@ -197,7 +216,7 @@ __global__ void __launch_bounds__(GS_BLOCK) k_bg_gs(SolveDev d, double* __restri
     for (int r = tid; r < s; r += GS_BLOCK) {
       double v = psh[r];
 #pragma unroll 8
-      for (int j = 0; j < i; ++j) v -= cnew[j] * S[(long long)j * s + r];
+      for (int j = 0; j < i; ++j) v -= cnew[j] * Sc[(long long)j * s + r];
       psh[r] = v;
       b2 += v * v;
     }
@@ -336,7 +355,10 @@ hipError_t bg_reduce(const SolveDev& d, int col, hipStream_t st) {
 // (passes = 1 as in Algorithm 1, 2 with the step repeated).
 hipError_t bg_gs(const SolveDev& d, double* cf, int i, int passes, hipStream_t st) {
   if (d.s > GS_MAXS || d.m + 1 > 512 || passes < 1 || passes > 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_bg_gs, dim3(d.nrhs), dim3(GS_BLOCK), (size_t)d.s * 8, st, d, cf, i, passes);
+  if (gs_staged(d.s, d.m))
+    hipLaunchKernelGGL(k_bg_gs<true>, dim3(d.nrhs), dim3(GS_BLOCK), gs_lds_staged(d.s, d.m), st, d, cf, i, passes);
+  else
+    hipLaunchKernelGGL(k_bg_gs<false>, dim3(d.nrhs), dim3(GS_BLOCK), (size_t)d.s * 8, st, d, cf, i, passes);
   return hipGetLastError();
 }
 
@@ -352,8 +374,10 @@ hipError_t bg_set_attributes() {
   attr_t<float, OP_CSR>(e);
   attr_t<double, OP_STENCIL>(e);
   attr_t<double, OP_CSR>(e);
-  const hipError_t r =
-      hipFuncSetAttribute((const void*)k_bg_gs, hipFuncAttributeMaxDynamicSharedMemorySize, GS_MAXS * 8);
+  hipError_t r = hipFuncSetAttribute((const void*)k_bg_gs<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)GS_LDS_MAX);
+  if (r != hipSuccess) e = r;
+  r = hipFuncSetAttribute((const void*)k_bg_gs<false>, hipFuncAttributeMaxDynamicSharedMemorySize, GS_MAXS * 8);
   if (r != hipSuccess) e = r;
   return e;
 }

@@ -81,6 +81,10 @@ __device__ inline double bsum256(double v, double* sh) {
 }  // namespace
 
 size_t lsqr_state_stride(int m) { return (size_t)5 * (m + 1) + LS_NSCAL; }
+// R_m is staged in LDS by the step kernel up to this order (its triangular
+// solves are sequential in the column index, so each access is latency-bound)
+constexpr int STEP_LDS_M = 140;
+size_t lsqr_step_lds(int m) { return m <= STEP_LDS_M ? (size_t)m * m * 8 : 0; }
 size_t lsqr_pass_lds(int m, int nrhs) { return (size_t)4 * nrhs * (m + 1) * 8; }
 
 // Stream the basis once.  first: u~ = u_m / eta_m (the right-hand side
@@ -113,7 +117,19 @@ __global__ void __launch_bounds__(256) k_lsqr_pass(SolveDev d, LsqrDev L, int fi
         get8(L.u, e, nel, old);
 #pragma unroll
         for (int j = 0; j < EPT; ++j) un[j] = -L.st[(long long)rq[j] * L.stride + 5 * m1 + LS_A] * old[j];
-        for (int jv = 0; jv < m; ++jv) {
+        int jv = 0;
+        if (e + EPT <= nel) {
+          for (; jv + 4 <= m; jv += 4) {
+            double v[4][EPT];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) load8(V + (long long)(jv + u) * d.ldv + e, v[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int j = 0; j < EPT; ++j) un[j] += L.st[(long long)rq[j] * L.stride + 3 * m1 + jv + u] * v[u][j];
+          }
+        }
+        for (; jv < m; ++jv) {
           double v[EPT];
           get8(V + (long long)jv * d.ldv, e, nel, v);
 #pragma unroll
@@ -137,20 +153,34 @@ __global__ void __launch_bounds__(256) k_lsqr_pass(SolveDev d, LsqrDev L, int fi
       for (int j = 0; j < EPT; ++j) un[j] = 0.0;
     }
     // dots with the basis and the norm, reduced per wave into LDS slots
-    for (int jv = 0; jv <= m; ++jv) {
-      double v[EPT];
-      if (jv < m && live) get8(V + (long long)jv * d.ldv, e, nel, v);
-      else {
+    // (full chunks: four basis vectors per round, loads issued together)
+    const bool full = e + EPT <= nel;
+    for (int jv0 = 0; jv0 <= m; jv0 += 4) {
+      double v[4][EPT];
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) v[j] = jv == m ? un[j] : 0.0;
+      for (int u = 0; u < 4; ++u) {
+        const int jv = jv0 + u;
+        if (jv < m && full) {
+          load8(V + (long long)jv * d.ldv + e, v[u]);
+        } else if (jv < m && live) {
+          get8(V + (long long)jv * d.ldv, e, nel, v[u]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < EPT; ++j) v[u][j] = jv == m ? un[j] : 0.0;
+        }
       }
-      for (int q = 0; q < nr; ++q) {
-        double p = 0.0;
 #pragma unroll
-        for (int j = 0; j < EPT; ++j)
-          if (rq[j] == q) p += v[j] * un[j];
-        p = wave_sum_all(p);
-        if (lane == 0) acc[(wv * nr + q) * m1 + jv] += p;
+      for (int u = 0; u < 4; ++u) {
+        const int jv = jv0 + u;
+        if (jv > m) break;
+        for (int q = 0; q < nr; ++q) {
+          double p = 0.0;
+#pragma unroll
+          for (int j = 0; j < EPT; ++j)
+            if (rq[j] == q) p += v[u][j] * un[j];
+          p = wave_sum_all(p);
+          if (lane == 0) acc[(wv * nr + q) * m1 + jv] += p;
+        }
       }
     }
   }
@@ -159,10 +189,13 @@ __global__ void __launch_bounds__(256) k_lsqr_pass(SolveDev d, LsqrDev L, int fi
     L.part[(long long)blockIdx.x * nr * m1 + x] = (acc[x] + acc[nr * m1 + x]) + (acc[2 * nr * m1 + x] + acc[3 * nr * m1 + x]);
 }
 
-// One LSQR step per rhs (first: the initialisation).
+// One LSQR step per rhs (first: the initialisation).  RL: R_m is copied to
+// LDS (a compile-time choice, so that its accesses compile to LDS loads).
+template <bool RL>
 __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrDev L, int first) {
   if (*L.alldone) return;
   const int q = blockIdx.x, tid = threadIdx.x;
+  extern __shared__ double rlds[];
   __shared__ double sh[8];
   const int nr = d.nrhs, m = d.m, m1 = m + 1;
   double* st = L.st + (long long)q * L.stride;
@@ -175,7 +208,7 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
   const int mu = d.status[4 + 2 * q];
   const int brk = d.status[5 + 2 * q];
   const double* ws = g.base + (long long)q * g.stride;
-  const double* R = ws + g.oR;                       // R_m, ld m_used
+  const double* Rg = ws + g.oR;                      // R_m, ld m_used
   const double* eta = d.eta + (long long)q * m1;
   if (first) {
     if (tid == 0) {
@@ -187,12 +220,29 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
     __syncthreads();
   }
   if (sc[LS_DONE] != 0.0) return;
-  // reduce the pass partials in a fixed order
-  for (int j = tid; j <= mu; j += 256) {
-    const int slot = j < mu ? j : m;
-    double a = 0.0;
-    for (int b = 0; b < L.nblk; ++b) a += L.part[((long long)b * nr + q) * m1 + slot];
-    tmp[j] = a;
+  if (RL)
+    for (int x = tid; x < mu * mu; x += 256) rlds[x] = Rg[x];   // visible after the barrier below
+  const double* R = RL ? (const double*)rlds : Rg;
+  // reduce the pass partials in a fixed order: a wave per group of four
+  // slots, lanes over the blocks (so the loads of a slot group overlap)
+  {
+    const int lane = tid & 63, wv = wave_id();
+    for (int j0 = 4 * wv; j0 <= mu; j0 += 16) {
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int b = lane; b < L.nblk; b += 64) {
+        const double* pb = L.part + ((long long)b * nr + q) * m1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = j0 + u;
+          if (j <= mu) a[u] += pb[j < mu ? j : m];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double t = wave_sum_all(a[u]);
+        if (lane == 0 && j0 + u <= mu) tmp[j0 + u] = t;
+      }
+    }
   }
   __syncthreads();
   const double beta = sqrt(tmp[mu]);
@@ -292,6 +342,12 @@ __global__ void __launch_bounds__(256) k_lsqr_finish(SolveDev d, DenseDev g, Lsq
 }
 
 namespace {
+void step_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, hipStream_t st, int first) {
+  if (d.m <= STEP_LDS_M)
+    hipLaunchKernelGGL(k_lsqr_step<true>, dim3(d.nrhs), dim3(256), lsqr_step_lds(d.m), st, d, g, L, first);
+  else
+    hipLaunchKernelGGL(k_lsqr_step<false>, dim3(d.nrhs), dim3(256), 0, st, d, g, L, first);
+}
 void lsqr_pass_launch(const SolveDev& d, const LsqrDev& L, int esize, hipStream_t st, int first) {
   const size_t lds = lsqr_pass_lds(d.m, d.nrhs);
   if (esize == 4) hipLaunchKernelGGL(k_lsqr_pass<float>, dim3(L.nblk), dim3(256), lds, st, d, L, first);
@@ -302,7 +358,7 @@ void lsqr_pass_launch(const SolveDev& d, const LsqrDev& L, int esize, hipStream_
 // Initialisation (u = v_{m+1}, first bidiagonalisation step).
 hipError_t lsqr_begin(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st) {
   lsqr_pass_launch(d, L, esize, st, 1);
-  hipLaunchKernelGGL(k_lsqr_step, dim3(d.nrhs), dim3(256), 0, st, d, g, L, 1);
+  step_launch(d, g, L, st, 1);
   hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
   return hipGetLastError();
 }
@@ -312,7 +368,7 @@ hipError_t lsqr_iterate(const SolveDev& d, const DenseDev& g, const LsqrDev& L, 
                         int count) {
   for (int it = 0; it < count; ++it) {
     lsqr_pass_launch(d, L, esize, st, 0);
-    hipLaunchKernelGGL(k_lsqr_step, dim3(d.nrhs), dim3(256), 0, st, d, g, L, 0);
+    step_launch(d, g, L, st, 0);
     hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
   }
   return hipGetLastError();
@@ -337,6 +393,8 @@ hipError_t lsqr_set_attributes() {
                                120 * 1024)) != hipSuccess) e = r;
   if ((r = hipFuncSetAttribute((const void*)k_lsqr_pass<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                120 * 1024)) != hipSuccess) e = r;
+  if ((r = hipFuncSetAttribute((const void*)k_lsqr_step<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lsqr_step_lds(STEP_LDS_M))) != hipSuccess) e = r;
   return e;
 }
 
