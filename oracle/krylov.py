@@ -11,6 +11,9 @@ Plain, slow FP64 implementations of the paper's definitions and algorithms:
                          eq. (8)); the least-squares problem is solved exactly,
                          by sketch-and-solve (Remark 3) or skipped.
 * ``sfom``               the sFOM approximation, eq. (9).
+* ``sketched_gs_basis``  Algorithm 1; ``sgs`` Algorithm 3 (exact least squares).
+* ``whitened_basis``     Algorithm 2 with whitening, continued by Algorithm 1
+                         (Section 2.1.2); ``whitened`` its f(A)b.
 
 Readings of the printed Algorithm 2 (typographical slips in the inner loop):
 the update subtracts h_{j,i-1} v_j (the coefficient just computed times the
@@ -189,6 +192,96 @@ def sketched_gs_basis(A, b: np.ndarray, m: int, sketch, passes: int = 1):
         S[:, i] = sv / rii
         V[i] = (w - V[:i].T @ r) / rii
     return V, H, r11, S, m, False
+
+
+def sketch_condition(SV: np.ndarray) -> float:
+    """kappa_1(R) = ||R||_1 ||R^{-1}||_1 of the triangular factor of the
+    sketched basis SV (Theta V_i): the quantity the condition estimate of the
+    whitening test (Section 5.1.3, threshold 1000) estimates; R has the same
+    2-norm condition number as SV."""
+    R = np.linalg.qr(SV, mode="r")
+    Rinv = sl.solve_triangular(R, np.eye(R.shape[0]))
+    return float(np.linalg.norm(R, 1) * np.linalg.norm(Rinv, 1))
+
+
+def whitened_basis(A, b: np.ndarray, m: int, k: int, sketch, thresh: float = 1000.0, every: int = 5):
+    """Algorithm 2 with whitening (Section 2.1.2), continued by Algorithm 1.
+
+    Before step i (i a multiple of ``every``, i >= 2) the sketch of the basis
+    built so far, Theta V_i (columns v_0..v_{i-1}), is tested: if
+    kappa_1(R) > thresh, with Theta V_i = Q R (R with positive diagonal),
+    the basis is whitened, V_i <- V_i R^{-1}, Hbar_{i-1} <- R_i Hbar_{i-1}
+    R_{i-1}^{-1}, its sketch becomes Q, and every later step is a step of
+    Algorithm 1 on that sketch.  b = beta v_0 becomes beta R_00 v~_0, so the
+    scale of the result is beta R_00.  Without a trigger this is Algorithm 2.
+
+    Returns (V, Hbar, scale, S = Theta V, m_used, breakdown, whitened_at),
+    whitened_at = 0 when the basis was never whitened.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    V = np.zeros((m + 1, n))
+    H = np.zeros((m + 1, m))
+    beta = float(np.linalg.norm(b))
+    p0 = sketch.apply(b)
+    S = np.zeros((p0.size, m + 1))
+    if beta == 0.0:
+        return V[:1], H[:1, :0], 0.0, S[:, :1], 0, True, 0
+    V[0] = b / beta
+    S[:, 0] = p0 / beta
+    white = 0
+    for i in range(1, m + 1):
+        if not white and i % every == 0 and i >= 2 and sketch_condition(S[:, :i]) > thresh:
+            Q, R = np.linalg.qr(S[:, :i], mode="reduced")
+            sg = np.sign(np.diag(R))
+            sg[sg == 0] = 1.0
+            Q, R = Q * sg, R * sg[:, None]
+            V[:i] = sl.solve_triangular(R.T, V[:i], lower=True)        # rows of V_i R^{-1}
+            H[:i, : i - 1] = R @ H[:i, : i - 1] @ np.linalg.inv(R[: i - 1, : i - 1])
+            S[:, :i] = Q
+            beta = beta * R[0, 0]
+            white = i
+        w = A @ V[i - 1]
+        if not white:
+            wn = np.linalg.norm(w)
+            for j in range(max(0, i - k), i):
+                H[j, i - 1] = V[j] @ w
+                w = w - H[j, i - 1] * V[j]
+            H[i, i - 1] = np.linalg.norm(w)
+            if H[i, i - 1] <= _breakdown_tol() * wn:
+                H[i, i - 1] = 0.0
+                return V[:i], H[: i + 1, :i], beta, S[:, :i], i, True, white
+            V[i] = w / H[i, i - 1]
+            S[:, i] = sketch.apply(V[i])
+        else:
+            p = sketch.apply(w)
+            r = S[:, :i].T @ p
+            sv = p - S[:, :i] @ r
+            rii = float(np.linalg.norm(sv))
+            H[:i, i - 1] = r
+            if rii <= _breakdown_tol() * np.linalg.norm(p):
+                return V[:i], H[: i + 1, :i], beta, S[:, :i], i, True, white
+            H[i, i - 1] = rii
+            S[:, i] = sv / rii
+            V[i] = (w - V[:i].T @ r) / rii
+    return V, H, beta, S, m, False, white
+
+
+def whitened(A, b: np.ndarray, f, m: int, k: int, sketch, thresh: float = 1000.0, every: int = 5) -> dict:
+    """f(A)b from the whitened basis with the exact least-squares solution of
+    eq. (7) (the limit of the LSQR iteration the basis is paired with):
+    scale V_m f(H_m + h_{m+1,m} y e_m^T) e_1."""
+    V, Hbar, scale, S, mu, brk, white = whitened_basis(A, b, m, k, sketch, thresh, every)
+    y = np.zeros(mu)
+    if not brk and mu > 0:
+        y = np.linalg.lstsq(V[:mu].T, V[mu], rcond=None)[0]
+    Hhat = Hbar[:mu, :mu].copy()
+    if not brk and mu > 0:
+        Hhat[:, mu - 1] += Hbar[mu, mu - 1] * y
+    c = matfun.fmat_e1(f, Hhat) if mu > 0 else np.zeros(0)
+    return {"V": V, "Hbar": Hbar, "scale": scale, "S": S, "m_used": mu, "breakdown": brk, "whitened_at": white,
+            "y": y, "Hhat": Hhat, "c": c,
+            "f": scale * (V[:mu].T @ c) if mu > 0 else np.zeros_like(np.asarray(b, float))}
 
 
 def sgs(A, b: np.ndarray, f, m: int, sketch, passes: int = 1) -> dict:

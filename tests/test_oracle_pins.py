@@ -428,3 +428,52 @@ def test_sketched_gs_two_passes_pinned():
     H1 = krylov.sketched_gs_basis(A2, b2, 20, sk2, passes=1)[1]
     H2 = krylov.sketched_gs_basis(A2, b2, 20, sk2, passes=2)[1]
     assert np.abs(H1 - H2).max() < 1e-9 * np.abs(H1).max()
+
+
+def test_whitening_pinned():
+    """Whitening (Section 2.1.2): on a graph Laplacian where the truncated
+    basis alone loses its conditioning (the exact least-squares result of
+    Algorithm 4 is then 10% off f_m), the whitened basis continued by
+    Algorithm 1 stays well conditioned, satisfies the Arnoldi-like relation
+    (eq. (3)) and gives f_m.  Without a trigger it is Algorithm 2; whitening
+    forced at the last step gives Algorithm 1 (the equivalence of Remark 1)."""
+    n, m, k = 4096, 120, 2
+    op = W.rgg_laplacian(n, seed=3)
+    A = operators.as_matrix(op)
+    b = W.rhs(n, 3)
+    f = W.FuncSpec("pow", sigma=1e-3, p=-0.5)
+    sk = sketch.Sketch("sparse_sign", n, 2 * m, 3, 8)
+    fm = krylov.fm(A, b, f, m)
+    res = krylov.whitened(A, b, f, m, k, sk)
+    assert res["whitened_at"] == 90 and res["m_used"] == m
+    V, H = res["V"], res["Hbar"]
+    sv = np.linalg.svd(V.T, compute_uv=False)
+    assert sv[0] / sv[-1] < 100
+    assert np.linalg.norm(A @ V[:m].T - V.T @ H) / np.linalg.norm(A @ V[:m].T) < 1e-12
+    assert krylov.relerr(res["f"], fm) < 1e-10
+    assert krylov.relerr(krylov.nt(A, b, f, m, k, sk, "exact")["f"], fm) > 1e-2
+    # the sketch condition is kappa_1 of the triangular factor (a library routine)
+    SV = sk.apply(krylov.truncated_arnoldi(A, b, 40, k)[0].T)
+    Rq = np.linalg.qr(SV, mode="r")
+    assert krylov.sketch_condition(SV) == pytest.approx(np.linalg.cond(Rq, 1), rel=1e-10)
+    # no trigger: Algorithm 2
+    st = W.convdiff3d(10, 50.0)
+    A2 = operators.as_matrix(st)
+    b2 = W.rhs(st.n, 7)
+    sk2 = sketch.Sketch("srht", st.n, 120, 3, 8)
+    Vn, Hn, beta, *_ = krylov.truncated_arnoldi(A2, b2, 30, 2)
+    Vw, Hw, scale, _, _, _, at = krylov.whitened_basis(A2, b2, 30, 2, sk2, thresh=np.inf)
+    assert at == 0 and scale == beta
+    assert np.abs(Hw - Hn).max() == 0.0 and np.abs(Vw - Vn).max() == 0.0
+    # whitening forced before the last step: Algorithm 1 (Remark 1)
+    Vg, Hg, r11, Sg, *_ = krylov.sketched_gs_basis(A2, b2, 30, sk2)
+    Vw, Hw, scale, Sw, _, _, at = krylov.whitened_basis(A2, b2, 30, 2, sk2, thresh=0.0, every=30)
+    assert at == 30
+    assert scale == pytest.approx(r11, rel=1e-12)
+    assert np.abs(Hw - Hg).max() < 1e-9 * np.abs(Hg).max()
+    assert np.abs(Vw - Vg).max() < 1e-9
+    # a planted slip (H not transformed by R) breaks the relation
+    Vb, Hb, *_ = krylov.whitened_basis(A, b, m, k, sk)
+    Hbad = Hb.copy()
+    Hbad[:5, :4] *= 1.001
+    assert np.linalg.norm(A @ Vb[:m].T - Vb.T @ Hbad) / np.linalg.norm(A @ Vb[:m].T) > 1e-6
