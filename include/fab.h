@@ -97,10 +97,17 @@ enum fab_basis {
                                  orthonormal, v_i = (A v_{i-1} - V_{i-1} r_i) / r_ii; with
                                  FAB_LS_AUTO the least squares are always refined by LSQR,
                                  which gives Algorithm 3                                    */
-  FAB_BASIS_SKETCHED_GS2 = 2  /* as FAB_BASIS_SKETCHED_GS with the Gram-Schmidt step on the
+  FAB_BASIS_SKETCHED_GS2 = 2, /* as FAB_BASIS_SKETCHED_GS with the Gram-Schmidt step on the
                                  sketch repeated once on its residual (r_i = r' + r''; not in
                                  the paper): same long-vector work, Theta V stays orthonormal
                                  to rounding when s is close to m                         */
+  FAB_BASIS_WHITENED = 3      /* truncated orthogonalisation with whitening (Section 2.1.2):
+                                 every 5 steps kappa_1(R) of Theta V_i = Q R is tested; above
+                                 1000 (Section 5.1.3) the basis becomes V_i R^{-1}, Hbar
+                                 R Hbar R^{-1}, the sketch Q, and the remaining steps follow
+                                 Algorithm 1, with LSQR for the least squares (FAB_LS_AUTO).
+                                 All right-hand sides of a call whiten together when one
+                                 triggers.  Blocking calls only (fab_submit: FAB_EINVAL)   */
 };
 
 typedef struct {
@@ -117,7 +124,8 @@ typedef struct {
   int basis;          /* enum fab_basis; 0 (a zero-initialised struct) = truncated  */
   int ls_maxit;       /* LSQR iteration limit, 0..1024; 0 = default: 32 for the
                          truncated basis (Blendenpik-preconditioned), 128 for the
-                         sketched Gram-Schmidt bases (unpreconditioned)          */
+                         sketched Gram-Schmidt bases and a whitened basis (whose
+                         sketch is already orthonormal)                          */
 } fab_params;
 
 /* Per right-hand side diagnostics. */
@@ -134,6 +142,8 @@ typedef struct {
   int fell_back;      /* 1 if an FP32 result was recomputed with an FP64 basis       */
   int ls_iters;       /* LSQR iterations performed                                   */
   int prec_used;      /* FAB_PREC_FP32 or FAB_PREC_FP64                              */
+  int whitened_at;    /* FAB_BASIS_WHITENED: step at which the basis was whitened
+                         (0: never)                                                  */
   double latency_us;  /* submit-to-completion wall time                              */
 } fab_info;
 

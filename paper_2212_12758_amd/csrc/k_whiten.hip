@@ -1,0 +1,236 @@
+// Whitening of the truncated basis (Section 2.1.2): the sketch Theta V_i of
+// the basis built by Algorithm 2 is monitored, and once its condition
+// exceeds a threshold the basis is replaced by V_i R^{-1} (Theta V_i = Q R),
+// the Hessenberg matrix by R Hbar_{i-1} R_{i-1}^{-1} and the sketch by Q;
+// later steps follow Algorithm 1 (k_bg.hip).
+//
+//   k_wh_col    after the update pass of step i, one workgroup per rhs adds
+//               column a = i-1 to the triangular factor R of the normalised
+//               sketch (Theta v_j = S[:, j] / eta_j) and to X = R^{-1}:
+//                 g = (Theta V_{a+1})^T Theta v_a,  R[:a, a] = X^T g[:a],
+//                 R[a, a] = sqrt(g_a - ||R[:a, a]||^2),
+//                 X[:a, a] = -X R[:a, a] / R[a, a],  X[a, a] = 1 / R[a, a],
+//               and keeps the largest column sums of |R| and |X|, whose
+//               product is kappa_1(R) = ||R||_1 ||R^{-1}||_1.  On a check step
+//               it raises the flag when kappa_1(R) exceeds the threshold (or
+//               the factorisation broke down).
+//   k_wh_apply  one workgroup per rhs: Hbar_{i-1} <- R_i Hbar_{i-1} X_{i-1}
+//               (column i-1 of H, left by the discarded step i, is cleared),
+//               the sketch S[:, j] <- (Theta V_i X)[:, j] (j >= 1), the scales
+//               eta_0 <- eta_0 R_00 (the stored u_0 = b is kept) and eta_j <- 1,
+//               and the coefficients C[l, j] = X[l, j] / eta_l of the basis
+//               transform.
+//   k_wh_basis  u_j <- sum_{l <= j} C[l, j] u_l for 1 <= j < i, in place
+//               (each thread owns one element of every vector; output
+//               columns are produced in descending blocks so that no input is
+//               overwritten before it is read).
+//
+// Per-rhs scratch in the dense workspace (region oM, ld m): R at 0, X at m^2,
+// products at 2m^2 and 3m^2, C at 4m^2, scalars at 5m^2; the rescaled sketch
+// is staged in region oW.
+#include "k_basis.h"
+
+namespace fab {
+
+namespace {
+
+constexpr int WB = 256;     // threads per workgroup
+constexpr int WH_MAXS = 8192;
+enum { WS_MAXR = 0, WS_MAXX = 1, WS_SING = 2, WS_KAPPA = 3 };
+
+__device__ inline double wh_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wv = wave_id();
+  v = wave_sum_all(v);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < WB / 64; ++w) t += red[w];
+  return t;
+}
+
+__global__ void __launch_bounds__(WB) k_wh_col(SolveDev d, DenseDev g, int a, int check, double thresh,
+                                               int* flag) {
+  extern __shared__ double sa[];     // Theta v_a (s values)
+  __shared__ double gsh[512], rsh[512];
+  __shared__ double red[WB / 64];
+  const int q = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = wave_id();
+  if (d.status[5 + 2 * q]) return;   // broken down: nothing to monitor
+  const int m = d.m, m1 = m + 1, s = d.s;
+  const long long mm = (long long)m * m;
+  double* ws = g.base + (long long)q * g.stride + g.oM;
+  double* R = ws;
+  double* X = ws + mm;
+  double* sc = ws + 5 * mm;
+  const double* S = d.S + (long long)q * s * m1;
+  const double* eta = d.eta + (long long)q * m1;
+  const double ea = eta[a];
+  for (int r = tid; r < s; r += WB) sa[r] = S[(long long)a * s + r] / ea;
+  __syncthreads();
+  // g_l = (Theta v_l)^T Theta v_a, l <= a: four columns per wave at a time
+  for (int l0 = 4 * wv; l0 <= a; l0 += 4 * (WB / 64)) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = lane; r < s; r += 64) {
+      const double x = sa[r];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (l0 + u <= a) t[u] += S[(long long)(l0 + u) * s + r] * x;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double tu = wave_sum_all(t[u]);
+      if (lane == 0 && l0 + u <= a) gsh[l0 + u] = tu / eta[l0 + u];
+    }
+  }
+  __syncthreads();
+  // R[:a, a] = X^T g (X upper triangular: column l has rows 0..l)
+  double p2 = 0.0;
+  for (int l = tid; l < a; l += WB) {
+    double t = 0.0;
+    for (int u = 0; u <= l; ++u) t += X[u + (long long)l * m] * gsh[u];
+    rsh[l] = t;
+    R[l + (long long)a * m] = t;
+    p2 += t * t;
+  }
+  const double rr = gsh[a] - wh_sum(p2, red);   // the sum's barriers publish rsh
+  const bool sing = !(rr > 0.0) || !isfinite(rr);
+  const double raa = sing ? 0.0 : sqrt(rr);
+  // X[:a, a] = -X[:a, :a] R[:a, a] / R[a, a]
+  double cx = 0.0, cr = 0.0;
+  for (int t0 = tid; t0 < a; t0 += WB) {
+    double v = 0.0;
+    for (int l = t0; l < a; ++l) v += X[t0 + (long long)l * m] * rsh[l];
+    const double xv = sing ? 0.0 : -v / raa;
+    X[t0 + (long long)a * m] = xv;
+    cx += fabs(xv);
+    cr += fabs(rsh[t0]);
+  }
+  cx = wh_sum(cx, red);
+  cr = wh_sum(cr, red);
+  if (tid == 0) {
+    R[a + (long long)a * m] = raa;
+    X[a + (long long)a * m] = sing ? 0.0 : 1.0 / raa;
+    const double colR = cr + raa, colX = cx + (sing ? 0.0 : 1.0 / raa);
+    const double mr = a == 0 ? colR : fmax(sc[WS_MAXR], colR);
+    const double mx = a == 0 ? colX : fmax(sc[WS_MAXX], colX);
+    const double sg = (a == 0 ? 0.0 : sc[WS_SING]) + (sing ? 1.0 : 0.0);
+    sc[WS_MAXR] = mr;
+    sc[WS_MAXX] = mx;
+    sc[WS_SING] = sg;
+    sc[WS_KAPPA] = sg != 0.0 ? INFINITY : mr * mx;
+    if (check && (sg != 0.0 || mr * mx > thresh)) *flag = 1;
+  }
+}
+
+// Whitening of the small quantities at step i (columns 0..i-1).
+__global__ void __launch_bounds__(WB) k_wh_apply(SolveDev d, DenseDev g, int i) {
+  const int q = blockIdx.x, tid = threadIdx.x;
+  if (d.status[5 + 2 * q]) return;
+  const int m = d.m, m1 = m + 1, s = d.s;
+  const long long mm = (long long)m * m;
+  double* base = g.base + (long long)q * g.stride;
+  double* ws = base + g.oM;
+  const double* R = ws;
+  const double* X = ws + mm;
+  double* T = ws + 2 * mm;    // Hbar X, i x (i-1), ld m
+  double* C = ws + 4 * mm;
+  double* Sw = base + g.oW;   // rescaled sketch, s x i
+  double* H = d.H + (long long)q * m1 * m;
+  double* S = d.S + (long long)q * s * m1;
+  double* eta = d.eta + (long long)q * m1;
+  // T = Hbar_{i-1} X_{i-1}: T[r, c] = sum_{l <= c} H[r, l] X[l, c]
+  for (long long x = tid; x < (long long)i * (i - 1); x += WB) {
+    const int r = (int)(x % i), c = (int)(x / i);
+    double t = 0.0;
+    for (int l = 0; l <= c; ++l) t += H[r + (long long)l * m1] * X[l + (long long)c * m];
+    T[r + (long long)c * m] = t;
+  }
+  // rescaled sketch: Sw[:, j] = sum_{l <= j} (S[:, l] / eta_l) X[l, j]
+  for (long long x = tid; x < (long long)s * i; x += WB) {
+    const int r = (int)(x % s), j = (int)(x / s);
+    double t = 0.0;
+    for (int l = 0; l <= j; ++l) t += S[(long long)l * s + r] / eta[l] * X[l + (long long)j * m];
+    Sw[r + (long long)j * s] = t;
+  }
+  // basis coefficients C[l, j] = X[l, j] / eta_l (1 <= j < i)
+  for (long long x = tid; x < (long long)i * i; x += WB) {
+    const int l = (int)(x % i), j = (int)(x / i);
+    C[l + (long long)j * m] = (j >= 1 && l <= j) ? X[l + (long long)j * m] / eta[l] : 0.0;
+  }
+  __syncthreads();
+  // H <- R T (rows 0..i-1, columns 0..i-2); column i-1 cleared
+  for (long long x = tid; x < (long long)i * (i - 1); x += WB) {
+    const int r = (int)(x % i), c = (int)(x / i);
+    double t = 0.0;
+    for (int l = r; l < i; ++l) t += R[r + (long long)l * m] * T[l + (long long)c * m];
+    H[r + (long long)c * m1] = t;
+  }
+  for (int r = tid; r <= m; r += WB) H[r + (long long)(i - 1) * m1] = 0.0;
+  // S[:, j] <- Q[:, j] for 1 <= j < i; column 0 keeps Theta u_0 = eta'_0 q_0
+  for (long long x = tid; x < (long long)s * i; x += WB) {
+    const int j = (int)(x / s);
+    if (j >= 1) S[x] = Sw[x];
+  }
+  __syncthreads();
+  if (tid == 0) eta[0] = eta[0] * R[0];
+  for (int j = 1 + tid; j < i; j += WB) eta[j] = 1.0;
+}
+
+// In-place u_j <- sum_{l <= j} C[l, j] u_l, 1 <= j < i.
+template <typename T>
+__global__ void __launch_bounds__(256) k_wh_basis(SolveDev d, DenseDev g, int i) {
+  constexpr int JB = 32;   // output columns per block (accumulators per thread)
+  const int nr = d.nrhs, m = d.m;
+  const long long nel = (long long)d.n * nr;
+  T* __restrict__ V = (T*)d.V;
+  const long long mm = (long long)m * m;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < nel; e += (long long)gridDim.x * 256) {
+    const int q = (int)(e & (nr - 1));
+    if (d.status[5 + 2 * q]) continue;
+    const double* C = g.base + (long long)q * g.stride + g.oM + 4 * mm;
+    const int nblk = (i - 1 + JB - 1) / JB;
+    for (int bj = nblk - 1; bj >= 0; --bj) {
+      const int j0 = 1 + bj * JB, j1 = j0 + JB < i ? j0 + JB : i;   // outputs [j0, j1)
+      double acc[JB];
+#pragma unroll
+      for (int u = 0; u < JB; ++u) acc[u] = 0.0;
+      for (int l = 0; l < j1; ++l) {
+        const double x = (double)V[(long long)l * d.ldv + e];
+#pragma unroll
+        for (int u = 0; u < JB; ++u) {
+          const int j = j0 + u;
+          if (j < j1 && l <= j) acc[u] += C[l + (long long)j * m] * x;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < JB; ++u)
+        if (j0 + u < j1) V[(long long)(j0 + u) * d.ldv + e] = (T)acc[u];
+    }
+  }
+}
+
+}  // namespace
+
+// Column a = i-1 of the incremental factor; check != 0 tests the threshold.
+hipError_t wh_col(const SolveDev& d, const DenseDev& g, int a, int check, double thresh, int* flag,
+                  hipStream_t st) {
+  if (d.s > WH_MAXS || d.m + 1 > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_wh_col, dim3(d.nrhs), dim3(WB), (size_t)d.s * 8, st, d, g, a, check, thresh, flag);
+  return hipGetLastError();
+}
+
+hipError_t wh_whiten(const SolveDev& d, const DenseDev& g, int esize, int i, hipStream_t st) {
+  hipLaunchKernelGGL(k_wh_apply, dim3(d.nrhs), dim3(WB), 0, st, d, g, i);
+  const long long nel = (long long)d.n * d.nrhs;
+  long long gr = (nel + 255) / 256;
+  if (gr > 8192) gr = 8192;
+  if (esize == 4) hipLaunchKernelGGL(k_wh_basis<float>, dim3((unsigned)gr), dim3(256), 0, st, d, g, i);
+  else hipLaunchKernelGGL(k_wh_basis<double>, dim3((unsigned)gr), dim3(256), 0, st, d, g, i);
+  return hipGetLastError();
+}
+
+hipError_t wh_set_attributes() {
+  return hipFuncSetAttribute((const void*)k_wh_col, hipFuncAttributeMaxDynamicSharedMemorySize, WH_MAXS * 8);
+}
+
+}  // namespace fab

@@ -59,6 +59,15 @@ hipError_t bg_reduce(const SolveDev& d, int col, hipStream_t st);
 hipError_t bg_gs(const SolveDev& d, double* cf, int i, int passes, hipStream_t st);
 hipError_t bg_update(const SolveDev& d, int esize, const double* cf, int i, hipStream_t st);
 hipError_t bg_set_attributes();
+hipError_t wh_col(const SolveDev& d, const DenseDev& g, int a, int check, double thresh, int* flag,
+                  hipStream_t st);
+hipError_t wh_whiten(const SolveDev& d, const DenseDev& g, int esize, int i, hipStream_t st);
+hipError_t wh_set_attributes();
+
+// Whitening (FAB_BASIS_WHITENED): test the sketch condition every WH_EVERY
+// steps against WH_THRESH (the threshold of Section 5.1.3).
+constexpr int WH_EVERY = 5;
+constexpr double WH_THRESH = 1000.0;
 size_t lsqr_state_stride(int m);
 size_t lsqr_pass_lds(int m, int nrhs);
 }  // namespace fab
@@ -164,7 +173,10 @@ struct Plan {
   int nvar = 1;                // dense f evaluations per rhs (3 with the a-posteriori estimates)
   bool lsqr = false;           // workspace for the LSQR refinement is planned
   bool bg = false;             // basis by Gram-Schmidt on the sketch (Algorithm 1)
-  size_t oBgCf = 0;            // its update weights [nrhs][m+2]
+  bool whiten = false;         // truncated basis, whitened on a condition trigger, then Algorithm 1
+  int whitened_at = 0;         // step at which the last solve whitened (0: never)
+  size_t oBgCf = 0;            // Algorithm 1 update weights [nrhs][m+2]
+  size_t oWflag = 0;           // whitening trigger flag
   int lnblk = 0;               // LSQR pass blocks
   size_t oLu = 0, oLpart = 0, oLst = 0, oLflag = 0;
   // derived
@@ -192,9 +204,11 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   const long long n = A->n;
   if (nrhs < 1 || nrhs > 32 || (nrhs & (nrhs - 1))) return FAB_EINVAL;
   if (p.m < 1 || p.m >= n || p.m > 500) return FAB_EINVAL;
-  if (p.basis != FAB_BASIS_TRUNCATED && p.basis != FAB_BASIS_SKETCHED_GS && p.basis != FAB_BASIS_SKETCHED_GS2)
+  if (p.basis != FAB_BASIS_TRUNCATED && p.basis != FAB_BASIS_SKETCHED_GS && p.basis != FAB_BASIS_SKETCHED_GS2 &&
+      p.basis != FAB_BASIS_WHITENED)
     return FAB_EINVAL;
-  const bool bg = p.basis != FAB_BASIS_TRUNCATED;
+  const bool whiten = p.basis == FAB_BASIS_WHITENED;
+  const bool bg = p.basis == FAB_BASIS_SKETCHED_GS || p.basis == FAB_BASIS_SKETCHED_GS2;
   if (p.ls_maxit < 0 || p.ls_maxit > 1024) return FAB_EINVAL;
   if (!bg && (p.k < 1 || p.k > KMAX)) return FAB_EINVAL;
   if (p.sketch != FAB_SKETCH_SRHT && p.sketch != FAB_SKETCH_SPARSE_SIGN) return FAB_EINVAL;
@@ -216,6 +230,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   P.p = p;
   if (bg) P.p.k = 1;   // the window is not used
   P.bg = bg;
+  P.whiten = whiten;
   P.esize = esize;
   P.nvar = (p.prec == FAB_PREC_AUTO || p.ls_mode == FAB_LS_AUTO) ? 3 : 1;
   // tiles of 2^LT elements (rows x rhs): 2048 for large problems, 512 below
@@ -260,13 +275,14 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   P.oRows = take(256);   // unused: sampled SRHT rows live in the context's cache
   P.oDense = take(P.dense_stride * nrhs * 8);
   P.oCf = take((size_t)nrhs * (m + 1) * 8);
-  if (bg) P.oBgCf = take((size_t)nrhs * (m + 2) * 8);
+  if (bg || whiten) P.oBgCf = take((size_t)nrhs * (m + 2) * 8);
+  if (whiten) P.oWflag = take(256);
   // LSQR refinement (FAB_LS_AUTO when the gate fails, FAB_LS_LSQR always)
   if (p.ls_mode == FAB_LS_AUTO || p.ls_mode == FAB_LS_LSQR) {
     const bool fits = lsqr_pass_lds(m, nrhs) <= 120 * 1024;
     // Algorithm 3 needs the refinement: the sketched problem is trivial for
     // a sketch-orthonormal basis
-    if (!fits && (p.ls_mode == FAB_LS_LSQR || bg)) return FAB_EINVAL;
+    if (!fits && (p.ls_mode == FAB_LS_LSQR || bg || whiten)) return FAB_EINVAL;
     if (fits) {
       P.lsqr = true;
       P.lnblk = (int)std::min<long long>((nel + 2047) / 2048, 512);
@@ -477,7 +493,7 @@ void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev
 }
 
 int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_t ev, const int* rows, double* hinfo,
-                  Prof* prof = nullptr) {
+                  Prof* prof = nullptr, int* host_flag = nullptr) {
   const int m = P.p.m, nr = P.nrhs;
   SolveDev d;
   DenseDev g;
@@ -517,7 +533,14 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
     }
     if (e != hipSuccess) return FAB_EDEVICE;
   }
-  for (int i = 1; i <= m && !P.bg; ++i) {
+  // Truncated basis.  With whitening, after the update pass of step i the
+  // newest sketch column joins the condition monitor; every WH_EVERY steps
+  // the host reads the trigger, and on a trigger step i is discarded, the
+  // basis V_i is whitened and steps i..m follow Algorithm 1.
+  P.whitened_at = 0;
+  int* wflag = P.whiten ? (int*)(ws + P.oWflag) : nullptr;
+  if (P.whiten && (!host_flag || zero_fill(wflag, 256, st) != hipSuccess)) return FAB_EDEVICE;
+  for (int i = 1; i <= m && !P.bg && !P.whitened_at; ++i) {
     B(FAB_K_DOTS);
     e = basis_dots(d, P.esize, i, st);
     E();
@@ -526,8 +549,41 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
     e = basis_update(d, P.esize, i, st, P.lds_update);
     E();
     if (e != hipSuccess) return FAB_EDEVICE;
+    if (!P.whiten) continue;
+    const int check = (i % WH_EVERY == 0 && i >= 2) ? 1 : 0;
+    B(FAB_K_OTHER);
+    e = wh_col(d, g, i - 1, check, WH_THRESH, wflag, st);
+    E();
+    if (e != hipSuccess) return FAB_EDEVICE;
+    if (!check) continue;
+    *host_flag = 0;
+    if (hipMemcpyAsync(host_flag, wflag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return FAB_EDEVICE;
+    if (!*host_flag) continue;
+    P.whitened_at = i;
+    B(FAB_K_OTHER);
+    e = wh_whiten(d, g, P.esize, i, st);
+    E();
+    if (e != hipSuccess) return FAB_EDEVICE;
+    double* bcf = (double*)(ws + P.oBgCf);
+    for (int j = i; j <= m && e == hipSuccess; ++j) {
+      B(FAB_K_DOTS);
+      e = bg_apply(d, P.esize, j, st, P.lds_update);
+      E();
+      if (e != hipSuccess) break;
+      B(FAB_K_OTHER);
+      e = bg_reduce(d, j, st);
+      if (e == hipSuccess) e = bg_gs(d, bcf, j, 1, st);
+      E();
+      if (e != hipSuccess) break;
+      B(FAB_K_UPDATE);
+      e = bg_update(d, P.esize, bcf, j, st);
+      E();
+    }
+    if (e != hipSuccess) return FAB_EDEVICE;
   }
-  if (!P.bg) {
+  if (!P.bg && !P.whitened_at) {
     B(FAB_K_OTHER);
     e = basis_finish(d, P.esize, st);
     E();
@@ -580,6 +636,7 @@ int collect_info(const Plan& P, const double* hinfo, std::vector<fab_info>& out)
     // refined: the least-squares part of the error is the last LSQR step
     if (fi.ls_iters > 0) fi.err_est = std::max(in[INFO_LSQR_RATIO], fi.round_est);
     fi.fell_back = 0;
+    fi.whitened_at = P.whitened_at;
     if (in[3] != 0.0) rc = FAB_ENUMERIC;
     if (!std::isfinite(fi.beta)) rc = FAB_ENUMERIC;
   }
@@ -607,7 +664,7 @@ int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* h
   L.stride = (long long)lsqr_state_stride(P.p.m);
   L.alldone = (int*)(ws + P.oLflag);
   L.nblk = P.lnblk;
-  L.maxit = P.p.ls_maxit > 0 ? P.p.ls_maxit : (P.bg ? 128 : 32);
+  L.maxit = P.p.ls_maxit > 0 ? P.p.ls_maxit : ((P.bg || P.whitened_at) ? 128 : 32);
   L.tol = P.p.tol / 10;
   if (zero_fill(ws + P.oLflag, 256, st) != hipSuccess) return FAB_EDEVICE;
   if (!host_flag) {
@@ -641,7 +698,7 @@ int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* h
 
 bool needs_refine(const Plan& P, int rc, const std::vector<fab_info>& fi) {
   if (rc != FAB_OK || !P.lsqr) return false;
-  if (P.p.ls_mode == FAB_LS_LSQR || P.bg) return true;
+  if (P.p.ls_mode == FAB_LS_LSQR || P.bg || P.whitened_at) return true;
   for (const auto& x : fi)
     if (!x.breakdown && !(x.ls_gate <= P.p.tol / 10)) return true;
   return false;
@@ -814,6 +871,7 @@ int fab_init(fab_ctx* out, int device, void* arena_dev_ptr, size_t arena_bytes, 
   (void)dense_set_attributes();
   (void)lsqr_set_attributes();
   (void)bg_set_attributes();
+  (void)wh_set_attributes();
   (void)hipGetLastError();
   if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev, hipEventDisableTiming) != hipSuccess) {
@@ -976,7 +1034,9 @@ static int launch_solve(fab_ctx ctx, Plan& P, char* ws, const int* rows, const f
   Prof* prof = ctx->prof.mask ? &ctx->prof : nullptr;
   // event pairs recorded inside a replayed graph do not time the kernels, so
   // timed (profiled) solves use direct launches of the same kernels
-  if (!ctx->use_graphs || prof) return enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, prof);
+  // whitening reads its trigger on the host during the solve: direct launches
+  if (!ctx->use_graphs || prof || P.whiten)
+    return enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, prof, ctx->host_flag);
   const std::string key = graph_key(P, ws, rows, ctx->host_info, ctx->prof.mask, f);
   for (auto& g : ctx->graphs) {
     if (g.key == key) {
@@ -1171,6 +1231,7 @@ int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
   int first_prec = p->prec == FAB_PREC_FP64 ? FAB_PREC_FP64 : FAB_PREC_FP32;
   int rc = make_plan(A, nrhs, f, p, esize_for(first_prec), r->plan);
   if (rc != FAB_OK) return rc;
+  if (r->plan.whiten) return FAB_EINVAL;   // its trigger is read on the host mid-solve: blocking calls only
   r->plan.b = b;
   r->plan.out = out;
   hipSetDevice(ctx->device);

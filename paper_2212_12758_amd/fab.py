@@ -18,7 +18,7 @@ F_EXP, F_POW, F_POLY = 1, 2, 3
 SKETCH_SRHT, SKETCH_SPARSE_SIGN = 1, 2
 PREC_FP32, PREC_FP64, PREC_AUTO = 1, 2, 3
 LS_AUTO, LS_SKETCH, LS_NONE, LS_LSQR = 0, 1, 2, 3
-BASIS_TRUNCATED, BASIS_SKETCHED_GS, BASIS_SKETCHED_GS2 = 0, 1, 2
+BASIS_TRUNCATED, BASIS_SKETCHED_GS, BASIS_SKETCHED_GS2, BASIS_WHITENED = 0, 1, 2, 3
 
 
 class fab_func(C.Structure):
@@ -36,7 +36,8 @@ class fab_info(C.Structure):
     _fields_ = [("err_est", C.c_double), ("ls_gate", C.c_double), ("round_est", C.c_double),
                 ("conv_est", C.c_double), ("kappa_R", C.c_double), ("h_last", C.c_double),
                 ("beta", C.c_double), ("m_used", C.c_int), ("breakdown", C.c_int), ("fell_back", C.c_int),
-                ("ls_iters", C.c_int), ("prec_used", C.c_int), ("latency_us", C.c_double)]
+                ("ls_iters", C.c_int), ("prec_used", C.c_int), ("whitened_at", C.c_int),
+                ("latency_us", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,7 +110,8 @@ def make_params(m, k, s, sketch="srht", zeta=8, seed=0, prec="fp32", ls_mode="sk
     ls = {"auto": LS_AUTO, "sketch": LS_SKETCH, "none": LS_NONE, "lsqr": LS_LSQR}[ls_mode] \
         if isinstance(ls_mode, str) else ls_mode
     bs = {"truncated": BASIS_TRUNCATED, "sketched_gs": BASIS_SKETCHED_GS,
-          "sketched_gs2": BASIS_SKETCHED_GS2}[basis] if isinstance(basis, str) else basis
+          "sketched_gs2": BASIS_SKETCHED_GS2, "whitened": BASIS_WHITENED}[basis] \
+        if isinstance(basis, str) else basis
     return fab_params(int(m), int(k), int(s), sk, int(zeta), int(seed) & ((1 << 64) - 1), pr, ls, float(tol),
                       int(bs), int(ls_maxit))
 

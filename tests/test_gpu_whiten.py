@@ -1,0 +1,111 @@
+"""Whitening of the truncated basis (Section 2.1.2) on the HIP path, against
+the CPU oracle ``krylov.whitened`` (trigger kappa_1(R) > 1000 of the sketched
+basis every 5 steps, then Algorithm 1 and the exact least squares).
+
+Parity: the trigger step equals the oracle's (FP64 basis), the result agrees
+with the oracle and with Arnoldi's f_m to 1e-8 (LSQR to a relative step of
+1e-13), and the whitened sketch is orthonormal.  Without a trigger the mode
+is the truncated basis, bit for bit.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import krylov, operators, sketch as osk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2212_12758_amd import Context
+
+    assert torch.cuda.is_available()
+    c = Context(0, arena_bytes=8 << 30)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def _rgg_case():
+    n, m = 4096, 120
+    op = W.rgg_laplacian(n, seed=3)
+    f = W.FuncSpec("pow", sigma=1e-3, p=-0.5)
+    return W.Workload("rgg4096", op, 3, 1, f, m=m, k=2, s=2 * m, sketch="sparse_sign", zeta=8, sketch_seed=3)
+
+
+def _params(w, prec, ls="lsqr", tol=1e-12, basis="whitened"):
+    from paper_2212_12758_amd import make_params
+
+    return make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, prec, ls, tol, basis=basis)
+
+
+def test_whitening_restores_the_basis(ctx):
+    w = _rgg_case()
+    Aor = operators.as_matrix(w.op)
+    b = W.rhs(w.n, w.b_seed)
+    sk = osk.Sketch(w.sketch, w.n, w.s, w.sketch_seed, w.zeta)
+    ref = krylov.whitened(Aor, b, w.f, w.m, w.k, sk)
+    fm = krylov.fm(Aor, b, w.f, w.m)
+    assert ref["whitened_at"] == 90
+    A = ctx.matrix(w.op)
+    print("case whiten rgg4096 fp64", flush=True)
+    out, info, dg = ctx.solve(A, _dev(b), w.f, _params(w, "fp64"), diag=True)
+    out = out.cpu().numpy()
+    assert info[0]["whitened_at"] == 90 and info[0]["m_used"] == w.m and info[0]["ls_iters"] >= 1
+    assert abs(info[0]["beta"] - ref["scale"]) <= 1e-10 * ref["scale"]
+    SV = dg["sv"]
+    assert np.abs(SV.T @ SV - np.eye(w.m + 1)).max() < 1e-6
+    assert krylov.relerr(out, ref["f"]) < 1e-8
+    assert krylov.relerr(out, fm) < 1e-8
+    # the truncated basis alone with sketch-and-solve is 10% off here (the
+    # oracle's Algorithm 4 with sketch-and-solve: 0.10)
+    out_t, info_t = ctx.solve(A, _dev(b), w.f, _params(w, "fp64", ls="sketch", basis="truncated"))
+    assert info_t[0]["whitened_at"] == 0
+    assert krylov.relerr(out_t.cpu().numpy(), fm) > 1e-2
+    print("case whiten rgg4096 fp32", flush=True)
+    out32, info32 = ctx.solve(A, _dev(b), w.f, _params(w, "fp32", tol=1e-8))
+    # rounding in the FP32 vectors spoils the truncated basis sooner (step 60 here)
+    assert 0 < info32[0]["whitened_at"] <= 90
+    assert krylov.relerr(out32.cpu().numpy(), fm) < 1e-5
+    A.destroy()
+
+
+def test_whitening_without_trigger_is_the_truncated_basis(ctx):
+    st = W.convdiff3d(20, 50.0)
+    w = W.Workload("cd20", st, 50, 1, W.FuncSpec("exp", alpha=-1e-3), m=30, k=4, s=80, sketch="srht",
+                   sketch_seed=5)
+    b = W.rhs(st.n, 50)
+    A = ctx.matrix(st)
+    print("case whiten no trigger", flush=True)
+    o1, i1 = ctx.solve(A, _dev(b), w.f, _params(w, "fp64", ls="sketch", basis="whitened"))
+    o2, i2 = ctx.solve(A, _dev(b), w.f, _params(w, "fp64", ls="sketch", basis="truncated"))
+    assert i1[0]["whitened_at"] == 0
+    assert np.array_equal(o1.cpu().numpy(), o2.cpu().numpy())
+    A.destroy()
+
+
+def test_whitening_two_rhs_and_serving_refused(ctx):
+    from paper_2212_12758_amd import EINVAL, FabError
+
+    w = _rgg_case()
+    Aor = operators.as_matrix(w.op)
+    B = W.rhs(w.n, 3, 2)
+    A = ctx.matrix(w.op)
+    print("case whiten nrhs=2", flush=True)
+    out, info = ctx.solve(A, _dev(B), w.f, _params(w, "fp64"))
+    out = out.cpu().numpy()
+    assert info[0]["whitened_at"] == info[1]["whitened_at"] > 0
+    for r in range(2):
+        assert krylov.relerr(out[:, r], krylov.fm(Aor, np.ascontiguousarray(B[:, r]), w.f, w.m)) < 1e-8, r
+    with pytest.raises(FabError) as e:
+        ctx.submit(A, _dev(B), w.f, _params(w, "fp64"), _dev(np.zeros_like(B)))
+    assert e.value.code == EINVAL
+    A.destroy()
