@@ -785,24 +785,26 @@ __global__ void __launch_bounds__(256) k_estimates(SolveDev d, DenseDev g) {
 
 // After an LSQR refinement has rebuilt H_hat: f for the result only, the
 // estimates (against the variants of the first pass) and the weights.
-hipError_t dense_after_refine(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st) {
+hipError_t fsqrt_launch(const SolveDev& d, const DenseDev& g, double* fq, hipStream_t st);
+
+hipError_t dense_after_refine(const SolveDev& d, const DenseDev& g, double* cf, double* fq, hipStream_t st) {
   DenseDev g1 = g;
   g1.nvar = 1;
   if (g.fkind == 1)
     (void)exp_launch(d, g1, st);
-  else if (g.fkind == 2) hipLaunchKernelGGL(k_fpow, dim3(d.nrhs, 1), dim3(64), 0, st, d, g1);
+  else if (g.fkind == 2) (void)fsqrt_launch(d, g1, fq, st);
   else hipLaunchKernelGGL(k_fpoly, dim3(d.nrhs, 1), dim3(DBLOCK), 0, st, d, g1);
   if (g.nvar == 3) hipLaunchKernelGGL(k_estimates, dim3(d.nrhs), dim3(256), 0, st, d, g);
   hipLaunchKernelGGL(k_coef, dim3(d.nrhs), dim3(256), 0, st, d, g, cf);
   return hipGetLastError();
 }
 
-hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st) {
+hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, double* fq, hipStream_t st) {
   hipLaunchKernelGGL(k_lsq, dim3(d.nrhs), dim3(LBLOCK), lsq_lds_bytes(d.s, d.m), st, d, g);
   const dim3 gv(d.nrhs, g.nvar);
   if (g.fkind == 1)
     (void)exp_launch(d, g, st);
-  else if (g.fkind == 2) hipLaunchKernelGGL(k_fpow, gv, dim3(64), 0, st, d, g);
+  else if (g.fkind == 2) (void)fsqrt_launch(d, g, fq, st);
   else hipLaunchKernelGGL(k_fpoly, gv, dim3(DBLOCK), 0, st, d, g);
   if (g.nvar == 3) hipLaunchKernelGGL(k_estimates, dim3(d.nrhs), dim3(256), 0, st, d, g);
   hipLaunchKernelGGL(k_coef, dim3(d.nrhs), dim3(256), 0, st, d, g, cf);

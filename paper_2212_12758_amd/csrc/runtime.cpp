@@ -43,11 +43,12 @@ hipError_t basis_dots(const SolveDev& d, int esize, int i, hipStream_t st);
 hipError_t basis_update(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds);
 hipError_t basis_finish(const SolveDev& d, int esize, hipStream_t st);
 hipError_t basis_combine(const SolveDev& d, int esize, const double* cf, int mmax, double* out, hipStream_t st);
-hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st);
+hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, double* fq, hipStream_t st);
+size_t fsqrt_partials_doubles(int m, int nrhs);
 hipError_t zero_fill(void* p, size_t bytes, hipStream_t st);
 hipError_t srht_sample_rows(int* rows, long long npad, int s, unsigned long long key, hipStream_t st);
 hipError_t dense_set_attributes();
-hipError_t dense_after_refine(const SolveDev& d, const DenseDev& g, double* cf, hipStream_t st);
+hipError_t dense_after_refine(const SolveDev& d, const DenseDev& g, double* cf, double* fq, hipStream_t st);
 hipError_t lsqr_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st);
 hipError_t lsqr_begin(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st);
 hipError_t lsqr_iterate(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st,
@@ -176,6 +177,7 @@ struct Plan {
   bool whiten = false;         // truncated basis, whitened on a condition trigger, then Algorithm 1
   int whitened_at = 0;         // step at which the last solve whitened (0: never)
   size_t oBgCf = 0;            // Algorithm 1 update weights [nrhs][m+2]
+  size_t oFq = 0;              // quadrature partial sums of the square root (FAB_F_POW)
   size_t oWflag = 0;           // whitening trigger flag
   int lnblk = 0;               // LSQR pass blocks
   size_t oLu = 0, oLpart = 0, oLst = 0, oLflag = 0;
@@ -277,6 +279,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   P.oCf = take((size_t)nrhs * (m + 1) * 8);
   if (bg || whiten) P.oBgCf = take((size_t)nrhs * (m + 2) * 8);
   if (whiten) P.oWflag = take(256);
+  if (f.kind == FAB_F_POW) P.oFq = take(fsqrt_partials_doubles(m, nrhs) * 8);
   // LSQR refinement (FAB_LS_AUTO when the gate fails, FAB_LS_LSQR always)
   if (p.ls_mode == FAB_LS_AUTO || p.ls_mode == FAB_LS_LSQR) {
     const bool fits = lsqr_pass_lds(m, nrhs) <= 120 * 1024;
@@ -591,7 +594,7 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
   }
   double* cf = (double*)(ws + P.oCf);
   B(FAB_K_DENSE);
-  e = dense_tail(d, g, cf, st);
+  e = dense_tail(d, g, cf, (double*)(ws + P.oFq), st);
   E();
   if (e != hipSuccess) return FAB_EDEVICE;
   B(FAB_K_COMBINE);
@@ -683,7 +686,7 @@ int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* h
     if (lsqr_end(d, g, L, st) != hipSuccess) return FAB_EDEVICE;
   }
   double* cf = (double*)(ws + P.oCf);
-  if (dense_after_refine(d, g, cf, st) != hipSuccess) return FAB_EDEVICE;
+  if (dense_after_refine(d, g, cf, (double*)(ws + P.oFq), st) != hipSuccess) return FAB_EDEVICE;
   if (basis_combine(d, P.esize, cf, P.p.m, P.out, st) != hipSuccess) return FAB_EDEVICE;
   const int nr = P.nrhs;
   for (int q = 0; q < nr; ++q)

@@ -224,6 +224,6 @@ def test_bg_invalid_basis(ctx):
     b = _dev(W.rhs(st.n, 1))
     f = W.FuncSpec("exp", alpha=-1.0)
     with pytest.raises(FabError) as e:
-        ctx.solve(A, b, f, make_params(20, 2, 60, "srht", 8, 1, "fp64", "lsqr", basis=3))
+        ctx.solve(A, b, f, make_params(20, 2, 60, "srht", 8, 1, "fp64", "lsqr", basis=4))
     assert e.value.code == EINVAL
     A.destroy()
