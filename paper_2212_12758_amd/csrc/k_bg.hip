@@ -186,8 +186,19 @@ __global__ void __launch_bounds__(GS_BLOCK) k_bg_gs(SolveDev d, double* __restri
   }
   // columns 0..i-1: their LDS copy (STAGED, a compile-time choice so that
   // the accesses compile to LDS loads) or global memory
-  if (STAGED)
-    for (long long x = tid; x < (long long)i * s; x += GS_BLOCK) psh[s + x] = S[x];
+  if (STAGED) {
+    // eight loads in flight per thread
+    const long long n2 = (long long)i * s;
+    long long x = tid;
+    for (; x + 7 * GS_BLOCK < n2; x += 8 * GS_BLOCK) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = S[x + u * GS_BLOCK];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) psh[s + x + u * GS_BLOCK] = t[u];
+    }
+    for (; x < n2; x += GS_BLOCK) psh[s + x] = S[x];
+  }
   const double* Sc = STAGED ? (const double*)(psh + s) : (const double*)S;
   const double pn = sqrt(gs_block_sum(a, red));   // includes the barrier after psh (and Sl) is written
   for (int j = tid; j < i; j += GS_BLOCK) csh[j] = 0.0;

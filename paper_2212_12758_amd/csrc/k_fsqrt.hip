@@ -30,6 +30,7 @@ namespace fab {
 namespace {
 
 constexpr int FS_MAXR = 8;        // rows per lane: order <= 512
+constexpr int FS_LDS_M = 128;     // H staged in LDS up to this order
 constexpr int FS_BLOCKS = 64;     // node blocks per (rhs, variant)
 constexpr int FS_WAVES = 4;       // waves (nodes at a time) per block
 constexpr int FS_MAXN = 2048;     // node cap
@@ -48,7 +49,9 @@ __device__ inline double wsum64(double v) {
 
 // x = (B + tau I)^{-1} e_1 for the upper Hessenberg B = H + sigma I (order m,
 // ld m), rows r = lane + 64 u in x[u].  Returns false when T_00 = 0.
+template <int RR>
 __device__ bool hess_shifted_solve(int m, const double* __restrict__ H, double shift, double* x) {
+  constexpr int FS_MAXR = RR;   // rows per lane in this instantiation
   const int lane = threadIdx.x & 63;
   double cur[FS_MAXR], cs[FS_MAXR], sn[FS_MAXR];
 #pragma unroll
@@ -127,7 +130,24 @@ __device__ inline double* fs_partials(double* fq, int m, int q, int v) {
   return fq + ((long long)q * 3 + v) * FS_BLOCKS * (m + 1);
 }
 
+// Copy the m x m matrix to LDS with eight loads in flight per thread.
+__device__ inline void fs_stage(const double* __restrict__ H, double* Hl, int m, int nthreads) {
+  const long long n2 = (long long)m * m;
+  long long x = threadIdx.x;
+  for (; x + 7LL * nthreads < n2; x += 8LL * nthreads) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = H[x + u * nthreads];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Hl[x + u * nthreads] = t[u];
+  }
+  for (; x < n2; x += nthreads) Hl[x] = H[x];
+}
+
+template <int RR, bool STAGED>
 __global__ void __launch_bounds__(64) k_fs_setup(SolveDev d, DenseDev g, double* fq) {
+  constexpr int FS_MAXR = RR;
+  extern __shared__ double hl[];
   const int q = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
   const DenseVariant dv = dense_variant(d, g, q, v);
   const int m = dv.dim;
@@ -136,11 +156,16 @@ __global__ void __launch_bounds__(64) k_fs_setup(SolveDev d, DenseDev g, double*
     if (lane == 0) P->n = 0;
     return;
   }
+  if (STAGED) {
+    fs_stage(dv.H, hl, m, 64);
+    __syncthreads();
+  }
+  const double* H = STAGED ? (const double*)hl : dv.H;
   // ||B||_1
   double cmax = 0.0;
   for (int c = lane; c < m; c += 64) {
     double a = 0.0;
-    for (int r = 0; r < m; ++r) a += fabs(dv.H[r + (long long)c * m] + (r == c ? g.sigma : 0.0));
+    for (int r = 0; r < m; ++r) a += fabs(H[r + (long long)c * m] + (r == c ? g.sigma : 0.0));
     cmax = fmax(cmax, a);
   }
   for (int off = 32; off >= 1; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off, 64));
@@ -148,7 +173,7 @@ __global__ void __launch_bounds__(64) k_fs_setup(SolveDev d, DenseDev g, double*
   double u_lo;
   if (g.p < 0.0) {
     double x[FS_MAXR];
-    const bool ok = hess_shifted_solve(m, dv.H, g.sigma, x);
+    const bool ok = hess_shifted_solve<RR>(m, H, g.sigma, x);
     double n2 = 0.0;
 #pragma unroll
     for (int u = 0; u < FS_MAXR; ++u) n2 += x[u] * x[u];
@@ -173,13 +198,21 @@ __global__ void __launch_bounds__(64) k_fs_setup(SolveDev d, DenseDev g, double*
   }
 }
 
+template <int RR, bool STAGED>
 __global__ void __launch_bounds__(64 * FS_WAVES) k_fs_nodes(SolveDev d, DenseDev g, double* fq) {
+  constexpr int FS_MAXR = RR;
+  extern __shared__ double hl[];
   const int q = blockIdx.x, v = blockIdx.y, blk = blockIdx.z;
   const int lane = threadIdx.x & 63, wv = wave_id();
   const DenseVariant dv = dense_variant(d, g, q, v);
   const int m = dv.dim;
   const FsParams P = *(const FsParams*)dv.scratch;
   __shared__ double red[FS_WAVES][FS_MAXR * 64];
+  if (STAGED && m > 0 && P.n > blk * FS_WAVES) {
+    fs_stage(dv.H, hl, m, 64 * FS_WAVES);
+    __syncthreads();
+  }
+  const double* H = STAGED ? (const double*)hl : dv.H;
   double acc[FS_MAXR];
 #pragma unroll
   for (int u = 0; u < FS_MAXR; ++u) acc[u] = 0.0;
@@ -188,7 +221,7 @@ __global__ void __launch_bounds__(64 * FS_WAVES) k_fs_nodes(SolveDev d, DenseDev
       const double uj = P.u_lo + j * P.h;
       const double et = exp(uj);
       double x[FS_MAXR];
-      hess_shifted_solve(m, dv.H, g.sigma + et * et, x);
+      hess_shifted_solve<RR>(m, H, g.sigma + et * et, x);
       if (g.p > 0.0) {
         // B x: rows over lanes, x_c read from the lane that holds it
         double y[FS_MAXR];
@@ -204,7 +237,7 @@ __global__ void __launch_bounds__(64 * FS_WAVES) k_fs_nodes(SolveDev d, DenseDev
 #pragma unroll
           for (int u = 0; u < FS_MAXR; ++u) {
             const int r = lane + 64 * u;
-            if (r < m && r <= c + 1) y[u] += (dv.H[r + (long long)c * m] + (r == c ? g.sigma : 0.0)) * xc;
+            if (r < m && r <= c + 1) y[u] += (H[r + (long long)c * m] + (r == c ? g.sigma : 0.0)) * xc;
           }
         }
 #pragma unroll
@@ -260,13 +293,36 @@ __global__ void __launch_bounds__(256) k_fs_sum(SolveDev d, DenseDev g, double* 
 
 size_t fsqrt_partials_doubles(int m, int nrhs) { return (size_t)nrhs * 3 * FS_BLOCKS * (m + 1); }
 
+namespace {
+// The planned order d.m bounds every variant's order: it picks the rows per
+// lane and whether H fits in LDS.
+template <int RR, bool STAGED>
+void fs_launch_t(const SolveDev& d, const DenseDev& g, double* fq, hipStream_t st) {
+  const size_t lds = STAGED ? (size_t)d.m * d.m * 8 : 0;
+  hipLaunchKernelGGL((k_fs_setup<RR, STAGED>), dim3(d.nrhs, g.nvar), dim3(64), lds, st, d, g, fq);
+  hipLaunchKernelGGL((k_fs_nodes<RR, STAGED>), dim3(d.nrhs, g.nvar, FS_BLOCKS), dim3(64 * FS_WAVES), lds, st, d, g,
+                     fq);
+}
+}  // namespace
+
 hipError_t fsqrt_launch(const SolveDev& d, const DenseDev& g, double* fq, hipStream_t st) {
   if (d.m > 64 * FS_MAXR) return hipErrorInvalidValue;
-  const dim3 gv(d.nrhs, g.nvar);
-  hipLaunchKernelGGL(k_fs_setup, gv, dim3(64), 0, st, d, g, fq);
-  hipLaunchKernelGGL(k_fs_nodes, dim3(d.nrhs, g.nvar, FS_BLOCKS), dim3(64 * FS_WAVES), 0, st, d, g, fq);
-  hipLaunchKernelGGL(k_fs_sum, gv, dim3(256), 0, st, d, g, fq);
+  if (d.m <= 64) fs_launch_t<1, true>(d, g, fq, st);
+  else if (d.m <= FS_LDS_M) fs_launch_t<2, true>(d, g, fq, st);
+  else if (d.m <= 256) fs_launch_t<4, false>(d, g, fq, st);
+  else fs_launch_t<8, false>(d, g, fq, st);
+  hipLaunchKernelGGL(k_fs_sum, dim3(d.nrhs, g.nvar), dim3(256), 0, st, d, g, fq);
   return hipGetLastError();
+}
+
+hipError_t fsqrt_set_attributes() {
+  hipError_t e = hipSuccess, r;
+  const int lds = FS_LDS_M * FS_LDS_M * 8;
+  const void* ks[4] = {(const void*)k_fs_setup<1, true>, (const void*)k_fs_setup<2, true>,
+                       (const void*)k_fs_nodes<1, true>, (const void*)k_fs_nodes<2, true>};
+  for (const void* k : ks)
+    if ((r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess) e = r;
+  return e;
 }
 
 }  // namespace fab

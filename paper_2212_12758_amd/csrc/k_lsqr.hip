@@ -90,7 +90,7 @@ size_t lsqr_pass_lds(int m, int nrhs) { return (size_t)4 * nrhs * (m + 1) * 8; }
 // Stream the basis once.  first: u~ = u_m / eta_m (the right-hand side
 // v_{m+1}); else u~ <- sum_j cf_j u_j - a u~.  Partials per block and rhs:
 // the dots u_j^T u~ (j < m) and ||u~||^2 (slot m).
-template <typename T>
+template <typename T, bool NR1>
 __global__ void __launch_bounds__(256) k_lsqr_pass(SolveDev d, LsqrDev L, int first) {
   if (*L.alldone) return;
   extern __shared__ double acc[];   // [wave][rhs][m+1]
@@ -100,9 +100,9 @@ __global__ void __launch_bounds__(256) k_lsqr_pass(SolveDev d, LsqrDev L, int fi
   const long long nel = (long long)d.n * nr;
   for (int x = tid; x < 4 * nr * m1; x += 256) acc[x] = 0.0;
   __syncthreads();
-  int rq[EPT];
+  int rq[EPT];   // rhs of each element (0 with one rhs: the coefficients are then uniform)
 #pragma unroll
-  for (int j = 0; j < EPT; ++j) rq[j] = (tid * EPT + j) & (nr - 1);
+  for (int j = 0; j < EPT; ++j) rq[j] = NR1 ? 0 : (tid * EPT + j) & (nr - 1);
   for (long long e = ((long long)blockIdx.x * 256 + tid) * EPT; e - (long long)tid * EPT < nel;
        e += (long long)gridDim.x * 256 * EPT) {
     const bool live = e < nel;
@@ -220,31 +220,53 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
     __syncthreads();
   }
   if (sc[LS_DONE] != 0.0) return;
-  if (RL)
-    for (int x = tid; x < mu * mu; x += 256) rlds[x] = Rg[x];   // visible after the barrier below
+  if (RL) {
+    // eight loads in flight per thread (visible after the barrier below)
+    const int n2 = mu * mu;
+    int x = tid;
+    for (; x + 7 * 256 < n2; x += 8 * 256) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = Rg[x + u * 256];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) rlds[x + u * 256] = t[u];
+    }
+    for (; x < n2; x += 256) rlds[x] = Rg[x];
+  }
   const double* R = RL ? (const double*)rlds : Rg;
-  // reduce the pass partials in a fixed order: a wave per group of four
-  // slots, lanes over the blocks (so the loads of a slot group overlap)
+  // reduce the pass partials in a fixed order: thread (group g, slot j)
+  // sums blocks [g nb / G, (g+1) nb / G) in order, eight loads in flight,
+  // then the G group sums are added in order
   {
-    const int lane = tid & 63, wv = wave_id();
-    for (int j0 = 4 * wv; j0 <= mu; j0 += 16) {
-      double a[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int b = lane; b < L.nblk; b += 64) {
-        const double* pb = L.part + ((long long)b * nr + q) * m1;
+    __shared__ double gsum[256];
+    const int ns = mu + 1;
+    const int G = ns >= 256 ? 1 : 256 / ns;
+    for (int j0 = 0; j0 < ns; j0 += 256 / G) {
+      const int j = j0 + tid % (256 / G), grp = tid / (256 / G);
+      double a = 0.0;
+      if (j < ns && grp < G) {
+        const int slot = j < mu ? j : m;
+        const int b0 = (int)((long long)grp * L.nblk / G), b1 = (int)((long long)(grp + 1) * L.nblk / G);
+        int b = b0;
+        for (; b + 8 <= b1; b += 8) {
+          double t[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int j = j0 + u;
-          if (j <= mu) a[u] += pb[j < mu ? j : m];
+          for (int u = 0; u < 8; ++u) t[u] = L.part[((long long)(b + u) * nr + q) * m1 + slot];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a += t[u];
         }
+        for (; b < b1; ++b) a += L.part[((long long)b * nr + q) * m1 + slot];
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double t = wave_sum_all(a[u]);
-        if (lane == 0 && j0 + u <= mu) tmp[j0 + u] = t;
+      gsum[tid] = a;
+      __syncthreads();
+      if (tid < 256 / G && j0 + tid < ns) {
+        double t = 0.0;
+        for (int gg = 0; gg < G; ++gg) t += gsum[gg * (256 / G) + tid];
+        tmp[j0 + tid] = t;
       }
+      __syncthreads();
     }
   }
-  __syncthreads();
   const double beta = sqrt(tmp[mu]);
   // s = R^{-T} (d / eta) / beta  ->  cf (scratch)
   for (int j = tid; j < mu; j += 256) cf[j] = beta > 0.0 ? tmp[j] / (eta[j] * beta) : 0.0;
@@ -342,6 +364,11 @@ __global__ void __launch_bounds__(256) k_lsqr_finish(SolveDev d, DenseDev g, Lsq
 }
 
 namespace {
+template <typename T>
+void pass_launch_t(const SolveDev& d, const LsqrDev& L, hipStream_t st, int first, size_t lds) {
+  if (d.nrhs == 1) hipLaunchKernelGGL((k_lsqr_pass<T, true>), dim3(L.nblk), dim3(256), lds, st, d, L, first);
+  else hipLaunchKernelGGL((k_lsqr_pass<T, false>), dim3(L.nblk), dim3(256), lds, st, d, L, first);
+}
 void step_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, hipStream_t st, int first) {
   if (d.m <= STEP_LDS_M)
     hipLaunchKernelGGL(k_lsqr_step<true>, dim3(d.nrhs), dim3(256), lsqr_step_lds(d.m), st, d, g, L, first);
@@ -350,8 +377,8 @@ void step_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, hipStre
 }
 void lsqr_pass_launch(const SolveDev& d, const LsqrDev& L, int esize, hipStream_t st, int first) {
   const size_t lds = lsqr_pass_lds(d.m, d.nrhs);
-  if (esize == 4) hipLaunchKernelGGL(k_lsqr_pass<float>, dim3(L.nblk), dim3(256), lds, st, d, L, first);
-  else hipLaunchKernelGGL(k_lsqr_pass<double>, dim3(L.nblk), dim3(256), lds, st, d, L, first);
+  if (esize == 4) pass_launch_t<float>(d, L, st, first, lds);
+  else pass_launch_t<double>(d, L, st, first, lds);
 }
 }  // namespace
 
@@ -389,10 +416,10 @@ hipError_t lsqr_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, i
 
 hipError_t lsqr_set_attributes() {
   hipError_t e = hipSuccess, r;
-  if ((r = hipFuncSetAttribute((const void*)k_lsqr_pass<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               120 * 1024)) != hipSuccess) e = r;
-  if ((r = hipFuncSetAttribute((const void*)k_lsqr_pass<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               120 * 1024)) != hipSuccess) e = r;
+  const void* passes[4] = {(const void*)k_lsqr_pass<float, true>, (const void*)k_lsqr_pass<float, false>,
+                           (const void*)k_lsqr_pass<double, true>, (const void*)k_lsqr_pass<double, false>};
+  for (const void* k : passes)
+    if ((r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024)) != hipSuccess) e = r;
   if ((r = hipFuncSetAttribute((const void*)k_lsqr_step<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lsqr_step_lds(STEP_LDS_M))) != hipSuccess) e = r;
   return e;

@@ -45,6 +45,7 @@ hipError_t basis_finish(const SolveDev& d, int esize, hipStream_t st);
 hipError_t basis_combine(const SolveDev& d, int esize, const double* cf, int mmax, double* out, hipStream_t st);
 hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, double* fq, hipStream_t st);
 size_t fsqrt_partials_doubles(int m, int nrhs);
+hipError_t fsqrt_set_attributes();
 hipError_t zero_fill(void* p, size_t bytes, hipStream_t st);
 hipError_t srht_sample_rows(int* rows, long long npad, int s, unsigned long long key, hipStream_t st);
 hipError_t dense_set_attributes();
@@ -875,6 +876,7 @@ int fab_init(fab_ctx* out, int device, void* arena_dev_ptr, size_t arena_bytes, 
   (void)lsqr_set_attributes();
   (void)bg_set_attributes();
   (void)wh_set_attributes();
+  (void)fsqrt_set_attributes();
   (void)hipGetLastError();
   if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev, hipEventDisableTiming) != hipSuccess) {
