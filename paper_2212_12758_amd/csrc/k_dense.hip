@@ -8,10 +8,7 @@
 //           registers across the workgroup when s <= 448 and m + 1 <= 104,
 //           else it is factorised in global memory.
 //  (exp(alpha H_hat) e_1 lives in k_expm.hip: multi-workgroup Pade products.)
-//  k_fpow   (H_hat + sigma I)^{+-1/2} e_1 through the real Schur decomposition
-//           (Francis double-shift QR, Golub & Van Loan Sec. 7.5) and the real
-//           quasi-triangular square root recurrence (Higham, Linear Algebra
-//           Appl. 88/89 (1987)), the method of the sqrtm the paper uses.
+//  ((H_hat + sigma I)^{+-1/2} e_1 lives in k_fsqrt.hip: resolvent quadrature.)
 //  k_fpoly  sum_j coef_j H_hat^j e_1 (polynomial test functions).
 //  k_coef   combination weights beta c_j / eta_j for the final V c.
 //
@@ -378,320 +375,6 @@ __global__ void __launch_bounds__(DBLOCK) k_fpoly(SolveDev d, DenseDev g) {
     for (int r = tid; r < m; r += DBLOCK) c[r] = t[r];
     __syncthreads();
   }
-}
-
-// ----------------------------------------------------------------- real Schur + square root
-// One wave.  T (m x m, ld m) is overwritten by its real Schur form Z^T T Z
-// (quasi upper triangular, 1x1 and 2x2 diagonal blocks); Z accumulates.
-// Returns the number of QR sweeps, or -1 if it failed to converge.
-__device__ inline void house3(double x, double y, double z, double* v1, double* v2, double* tau) {
-  // reflector P = I - tau v v^T with v = (1, v1, v2), P (x,y,z)^T = (beta,0,0)^T
-  const double n = sqrt(x * x + y * y + z * z);
-  if (n == 0.0 || (y == 0.0 && z == 0.0)) { *v1 = 0.0; *v2 = 0.0; *tau = 0.0; return; }
-  const double beta = x >= 0.0 ? -n : n;
-  const double sc = 1.0 / (x - beta);
-  *v1 = y * sc;
-  *v2 = z * sc;
-  *tau = (beta - x) / beta;
-}
-
-__device__ int francis_schur(int m, double* T, double* Z) {
-  const int lane = threadIdx.x & 63;
-  const double eps = 2.220446049250313e-16;
-  int sweeps = 0;
-  int hi = m - 1;
-  int its = 0;
-  const int maxit = 60 * (m > 10 ? m : 10);
-  while (hi >= 0) {
-    if (sweeps > maxit) return -1;
-    // deflation search: largest l <= hi with negligible subdiagonal T[l, l-1]
-    int l = 0;
-    for (int base = hi; base > 0; base -= 64) {
-      const int ll = base - lane;
-      bool neg = false;
-      if (ll >= 1) {
-        const double sub = fabs(T[ll + (long long)(ll - 1) * m]);
-        double tst = fabs(T[ll - 1 + (long long)(ll - 1) * m]) + fabs(T[ll + (long long)ll * m]);
-        if (tst == 0.0) tst = 1.0;
-        neg = sub <= eps * tst;
-      }
-      const unsigned long long bal = __ballot(neg);
-      if (bal) { l = base - (__ffsll((long long)bal) - 1); break; }
-    }
-    if (l > 0 && lane == 0) T[l + (long long)(l - 1) * m] = 0.0;
-    wave_order();
-    if (l >= hi - 1) { hi = l - 1; its = 0; continue; }   // 1x1 or 2x2 block deflated
-    ++its;
-    ++sweeps;
-    // double shift from the trailing 2x2 of the active block (exceptional at 10, 20)
-    double sh, tp;
-    const double a11 = T[hi - 1 + (long long)(hi - 1) * m], a12 = T[hi - 1 + (long long)hi * m];
-    const double a21 = T[hi + (long long)(hi - 1) * m], a22 = T[hi + (long long)hi * m];
-    if (its % 10 == 0) {
-      const double w = fabs(a21) + fabs(T[hi - 1 + (long long)(hi - 2) * m]);
-      sh = 1.5 * w;
-      tp = w * w;
-    } else {
-      sh = a11 + a22;
-      tp = a11 * a22 - a12 * a21;
-    }
-    const double h00 = T[l + (long long)l * m], h01 = T[l + (long long)(l + 1) * m];
-    const double h10 = T[l + 1 + (long long)l * m], h11 = T[l + 1 + (long long)(l + 1) * m];
-    const double h21 = T[l + 2 + (long long)(l + 1) * m];
-    double x = h00 * h00 + h01 * h10 - sh * h00 + tp;
-    double y = h10 * (h00 + h11 - sh);
-    double z = h10 * h21;
-    for (int kk = l; kk <= hi - 2; ++kk) {
-      double v1, v2, tau;
-      house3(x, y, z, &v1, &v2, &tau);
-      if (tau != 0.0) {
-        const int c0 = kk > l ? kk - 1 : l;
-        // rows kk..kk+2, columns c0..m-1
-        for (int cc = c0 + lane; cc < m; cc += 64) {
-          double* col = T + (long long)cc * m;
-          const double sdot = tau * (col[kk] + v1 * col[kk + 1] + v2 * col[kk + 2]);
-          col[kk] -= sdot;
-          col[kk + 1] -= sdot * v1;
-          col[kk + 2] -= sdot * v2;
-        }
-        wave_order();
-        // columns kk..kk+2, rows 0..min(kk+3, hi)
-        const int rlim = kk + 3 < hi ? kk + 3 : hi;
-        for (int r = lane; r <= rlim; r += 64) {
-          double* p0 = T + r + (long long)kk * m;
-          const double sdot = tau * (p0[0] + v1 * p0[m] + v2 * p0[2 * (long long)m]);
-          p0[0] -= sdot;
-          p0[m] -= sdot * v1;
-          p0[2 * (long long)m] -= sdot * v2;
-        }
-        for (int r = lane; r < m; r += 64) {
-          double* p0 = Z + r + (long long)kk * m;
-          const double sdot = tau * (p0[0] + v1 * p0[m] + v2 * p0[2 * (long long)m]);
-          p0[0] -= sdot;
-          p0[m] -= sdot * v1;
-          p0[2 * (long long)m] -= sdot * v2;
-        }
-        wave_order();
-        if (kk > l && lane == 0) {  // entries annihilated by the reflector
-          T[kk + 1 + (long long)(kk - 1) * m] = 0.0;
-          T[kk + 2 + (long long)(kk - 1) * m] = 0.0;
-        }
-        wave_order();
-      }
-      x = T[kk + 1 + (long long)kk * m];
-      y = T[kk + 2 + (long long)kk * m];
-      if (kk < hi - 2) z = T[kk + 3 + (long long)kk * m];
-    }
-    // final 2x2 reflector on rows/cols hi-1, hi
-    {
-      const double n = sqrt(x * x + y * y);
-      if (n != 0.0 && y != 0.0) {
-        const double beta = x >= 0.0 ? -n : n;
-        const double v1 = y / (x - beta);
-        const double tau = (beta - x) / beta;
-        const int kk = hi - 1;
-        for (int cc = kk - 1 + lane; cc < m; cc += 64) {
-          double* col = T + (long long)cc * m;
-          const double sdot = tau * (col[kk] + v1 * col[kk + 1]);
-          col[kk] -= sdot;
-          col[kk + 1] -= sdot * v1;
-        }
-        wave_order();
-        for (int r = lane; r <= hi; r += 64) {
-          double* p0 = T + r + (long long)kk * m;
-          const double sdot = tau * (p0[0] + v1 * p0[m]);
-          p0[0] -= sdot;
-          p0[m] -= sdot * v1;
-        }
-        for (int r = lane; r < m; r += 64) {
-          double* p0 = Z + r + (long long)kk * m;
-          const double sdot = tau * (p0[0] + v1 * p0[m]);
-          p0[0] -= sdot;
-          p0[m] -= sdot * v1;
-        }
-        wave_order();
-        if (lane == 0) T[kk + 1 + (long long)(kk - 1) * m] = 0.0;
-        wave_order();
-      }
-    }
-  }
-  return sweeps;
-}
-
-// square root of a 1x1 or 2x2 diagonal block: R = a I + (T - theta I)/(2a),
-// a^2 = (theta + sqrt(det T))/2 (principal branch for blocks off the closed
-// negative axis); a 1x1 block is sqrt(t).
-__device__ inline void block_sqrt(int p, const double* t, double* r) {  // t, r: 2x2 col-major (p=1 uses [0])
-  if (p == 1) { r[0] = sqrt(t[0]); return; }
-  const double th = 0.5 * (t[0] + t[3]);
-  const double det = t[0] * t[3] - t[1] * t[2];
-  const double a = sqrt(0.5 * (th + sqrt(det)));
-  const double i2a = 0.5 / a;
-  r[0] = a + (t[0] - th) * i2a;
-  r[1] = t[1] * i2a;
-  r[2] = t[2] * i2a;
-  r[3] = a + (t[3] - th) * i2a;
-}
-
-// Solve A x = b for n <= 4 by Gaussian elimination with partial pivoting.
-__device__ inline void small_solve(int n, double* A, double* b) {  // A n x n col-major (ld 4)
-  for (int j = 0; j < n; ++j) {
-    int p = j;
-    for (int r = j + 1; r < n; ++r)
-      if (fabs(A[r + 4 * j]) > fabs(A[p + 4 * j])) p = r;
-    if (p != j) {
-      for (int c = 0; c < n; ++c) { const double t = A[j + 4 * c]; A[j + 4 * c] = A[p + 4 * c]; A[p + 4 * c] = t; }
-      const double t = b[j]; b[j] = b[p]; b[p] = t;
-    }
-    const double pv = A[j + 4 * j];
-    for (int r = j + 1; r < n; ++r) {
-      const double f = A[r + 4 * j] / pv;
-      for (int c = j; c < n; ++c) A[r + 4 * c] -= f * A[j + 4 * c];
-      b[r] -= f * b[j];
-    }
-  }
-  for (int j = n - 1; j >= 0; --j) {
-    double a = b[j];
-    for (int c = j + 1; c < n; ++c) a -= A[j + 4 * c] * b[c];
-    b[j] = a / A[j + 4 * j];
-  }
-}
-
-__global__ void __launch_bounds__(64) k_fpow(SolveDev d, DenseDev g) {
-  const int q = blockIdx.x;
-  const int lane = threadIdx.x;
-  __shared__ int bstart[MAXM + 1];
-  __shared__ double zt[MAXM];
-  __shared__ double xs[MAXM];
-  const int v = blockIdx.y;
-  const DenseVariant dv = dense_variant(d, g, q, v);
-  double* c = dv.c;
-  double* info = dv.info;
-  if (dv.dim == 0) return;
-  const int m = dv.dim;
-  const long long mm = (long long)m * m;
-  double* T = dv.scratch;
-  double* Z = T + mm;
-  double* R = Z + mm;
-  const double* Hh = dv.H;
-  for (long long x = lane; x < mm; x += 64) {
-    const int r = (int)(x % m), cc = (int)(x / m);
-    T[x] = Hh[x] + (r == cc ? g.sigma : 0.0);
-    Z[x] = r == cc ? 1.0 : 0.0;
-    R[x] = 0.0;
-  }
-  wave_order();
-  __syncthreads();
-  const int sweeps = francis_schur(m, T, Z);
-  __syncthreads();
-  if (sweeps < 0) {
-    if (lane == 0) info[v == 0 ? INFO_FAIL : INFO_VFAIL + v] = 2.0;
-    for (int r = lane; r < m; r += 64) c[r] = 0.0;
-    return;
-  }
-  // diagonal block structure
-  if (lane == 0) {
-    int nb = 0, i = 0;
-    while (i < m) {
-      bstart[nb++] = i;
-      i += (i + 1 < m && T[i + 1 + (long long)i * m] != 0.0) ? 2 : 1;
-    }
-    bstart[nb] = m;
-    bstart[MAXM] = nb;
-  }
-  __syncthreads();
-  const int nb = bstart[MAXM];
-  // block-column recurrence R_jj = sqrt(T_jj); R_ii X + X R_jj = T_ij - sum_k R_ik R_kj
-  for (int bj = 0; bj < nb; ++bj) {
-    const int j0 = bstart[bj], pj = bstart[bj + 1] - j0;
-    if (lane == 0) {
-      double tb[4], rb[4];
-      tb[0] = T[j0 + (long long)j0 * m];
-      if (pj == 2) {
-        tb[1] = T[j0 + 1 + (long long)j0 * m];
-        tb[2] = T[j0 + (long long)(j0 + 1) * m];
-        tb[3] = T[j0 + 1 + (long long)(j0 + 1) * m];
-      }
-      block_sqrt(pj, tb, rb);
-      R[j0 + (long long)j0 * m] = rb[0];
-      if (pj == 2) {
-        R[j0 + 1 + (long long)j0 * m] = rb[1];
-        R[j0 + (long long)(j0 + 1) * m] = rb[2];
-        R[j0 + 1 + (long long)(j0 + 1) * m] = rb[3];
-      }
-    }
-    wave_order();
-    __syncthreads();
-    for (int bi = bj - 1; bi >= 0; --bi) {
-      const int i0 = bstart[bi], pi = bstart[bi + 1] - i0;
-      const int k0 = i0 + pi;  // sum over k in [k0, j0)
-      double cvals[4];
-      for (int a = 0; a < pi; ++a)
-        for (int b = 0; b < pj; ++b) {
-          double acc = 0.0;
-          for (int kk = k0 + lane; kk < j0; kk += 64)
-            acc += R[i0 + a + (long long)kk * m] * R[kk + (long long)(j0 + b) * m];
-          acc = wsum(acc);
-          cvals[a + 2 * b] = T[i0 + a + (long long)(j0 + b) * m] - acc;
-        }
-      if (lane == 0) {
-        // (I_pj (x) R_ii + R_jj^T (x) I_pi) vec(X) = vec(C)
-        double Ab[16];
-        double rhs[4];
-        const int nn = pi * pj;
-        for (int x = 0; x < 16; ++x) Ab[x] = 0.0;
-        for (int b = 0; b < pj; ++b)
-          for (int a = 0; a < pi; ++a) {
-            const int row = a + pi * b;
-            rhs[row] = cvals[a + 2 * b];
-            for (int a2 = 0; a2 < pi; ++a2) Ab[row + 4 * (a2 + pi * b)] += R[i0 + a + (long long)(i0 + a2) * m];
-            for (int b2 = 0; b2 < pj; ++b2) Ab[row + 4 * (a + pi * b2)] += R[j0 + b2 + (long long)(j0 + b) * m];
-          }
-        small_solve(nn, Ab, rhs);
-        for (int b = 0; b < pj; ++b)
-          for (int a = 0; a < pi; ++a) R[i0 + a + (long long)(j0 + b) * m] = rhs[a + pi * b];
-      }
-      wave_order();
-      __syncthreads();
-    }
-  }
-  // zt = Z^T e_1 (first row of Z)
-  for (int r = lane; r < m; r += 64) zt[r] = Z[(long long)r * m];
-  __syncthreads();
-  if (g.p > 0.0) {
-    // c = Z (R zt)
-    for (int r = lane; r < m; r += 64) {
-      double a = 0.0;
-      for (int cc = 0; cc < m; ++cc) a += R[r + (long long)cc * m] * zt[cc];
-      xs[r] = a;
-    }
-  } else {
-    // R x = zt, block back substitution
-    for (int bi = nb - 1; bi >= 0; --bi) {
-      const int i0 = bstart[bi], pi = bstart[bi + 1] - i0;
-      double rv[2];
-      for (int a = 0; a < pi; ++a) {
-        double acc = 0.0;
-        for (int cc = i0 + pi + lane; cc < m; cc += 64) acc += R[i0 + a + (long long)cc * m] * xs[cc];
-        rv[a] = zt[i0 + a] - wsum(acc);
-      }
-      if (lane == 0) {
-        double Ab[16];
-        for (int a = 0; a < pi; ++a)
-          for (int a2 = 0; a2 < pi; ++a2) Ab[a + 4 * a2] = R[i0 + a + (long long)(i0 + a2) * m];
-        small_solve(pi, Ab, rv);
-        for (int a = 0; a < pi; ++a) xs[i0 + a] = rv[a];
-      }
-      __syncthreads();
-    }
-  }
-  __syncthreads();
-  for (int r = lane; r < m; r += 64) {
-    double a = 0.0;
-    for (int cc = 0; cc < m; ++cc) a += Z[r + (long long)cc * m] * xs[cc];
-    c[r] = a;
-  }
-  if (lane == 0 && v == 0) info[INFO_SCHUR_IT] = sweeps;
 }
 
 // ----------------------------------------------------------------- combination weights

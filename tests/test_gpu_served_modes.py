@@ -1,0 +1,65 @@
+"""The cheap approximations as served modes: Algorithm 5 (y = 0, eq. (8);
+FAB_LS_NONE) and sketch-and-solve (Remark 3; FAB_LS_SKETCH), which equals
+sFOM (eq. (9)).  Blocking and served (fab_submit) calls against the oracle's
+Algorithms 4/5 and sFOM on a nonsymmetric operator, where the truncated
+basis is not orthonormal and the three results differ; served results must
+equal blocking ones bit for bit, also when the two modes run concurrently."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import krylov, operators, sketch as osk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2212_12758_amd import Context
+
+    assert torch.cuda.is_available()
+    c = Context(0, arena_bytes=4 << 30)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def test_served_algorithm5_and_sfom(ctx):
+    from paper_2212_12758_amd import make_params
+
+    st = W.convdiff3d(20, 50.0)
+    b = W.rhs(st.n, 61)
+    f = W.FuncSpec("exp", alpha=-3e-2)   # ||alpha A|| = 30: not converged at m = 20
+    m, k, s = 20, 2, 80
+    Aor = operators.as_matrix(st)
+    sk = osk.Sketch("srht", st.n, s, 6, 8)
+    ref_none = krylov.nt(Aor, b, f, m, k, sk, "none")["f"]
+    ref_sk = krylov.nt(Aor, b, f, m, k, sk, "sketch")["f"]
+    ref_sfom = krylov.sfom(Aor, b, f, m, k, sk)
+    assert krylov.relerr(ref_sk, ref_sfom) < 1e-10          # Remark 3
+    assert krylov.relerr(ref_none, ref_sk) > 1e-4            # the modes differ here (1.4e-3)
+    A = ctx.matrix(st)
+    outs = {}
+    for ls, ref in (("none", ref_none), ("sketch", ref_sk)):
+        print(f"case served mode {ls}", flush=True)
+        p = make_params(m, k, s, "srht", 8, 6, "fp64", ls)
+        out, info = ctx.solve(A, _dev(b), f, p)
+        out = out.cpu().numpy()
+        assert krylov.relerr(out, ref) < 1e-10, ls
+        outs[ls] = out
+    # served, both modes in flight at once
+    reqs = []
+    for ls in ("none", "sketch", "none", "sketch"):
+        o = _dev(np.zeros(st.n))
+        reqs.append((ls, o, ctx.submit(A, _dev(b), f, make_params(m, k, s, "srht", 8, 6, "fp64", ls), o)))
+    for ls, o, r in reqs:
+        r.wait()
+        assert np.array_equal(o.cpu().numpy(), outs[ls]), ls
+    A.destroy()
