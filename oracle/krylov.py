@@ -14,6 +14,7 @@ Plain, slow FP64 implementations of the paper's definitions and algorithms:
 * ``sketched_gs_basis``  Algorithm 1; ``sgs`` Algorithm 3 (exact least squares).
 * ``whitened_basis``     Algorithm 2 with whitening, continued by Algorithm 1
                          (Section 2.1.2); ``whitened`` its f(A)b.
+* ``sign_fAb``           sign(A)b = (A^2)^{-1/2}(A b) (Section 5.1.3).
 
 Readings of the printed Algorithm 2 (typographical slips in the inner loop):
 the update subtracts h_{j,i-1} v_j (the coefficient just computed times the
@@ -350,6 +351,27 @@ def sfom(A, b: np.ndarray, f, m: int, k: int, sketch) -> np.ndarray:
     M = S.T @ SAV @ np.linalg.inv(R)
     z = matfun.fmat(f, M) @ (S.T @ sketch.apply(np.asarray(b, dtype=np.float64)))
     return Vm @ sl.solve_triangular(R, z)
+
+
+def square_operator(A):
+    """A^2 as a sparse matrix whose values are rounded to FP32: the operator
+    the sign function is evaluated with (CSR values are FP32 in the library;
+    A^2 of an integer stencil is exact)."""
+    import scipy.sparse as sps
+
+    A2 = sps.csr_matrix(A @ A)
+    A2.data = A2.data.astype(np.float32).astype(np.float64)
+    return A2
+
+
+def sign_fAb(A, b: np.ndarray, m: int, k: int, sketch=None, ls: str = "sketch") -> dict:
+    """sign(A) b = (A^2)^{-1/2} (A b) (Section 5.1.3, after Higham's
+    Chapter 5): the method of ``nt`` applied to the operator A^2 (FP32
+    values, ``square_operator``), the start vector A b and f(z) = z^{-1/2}."""
+    from types import SimpleNamespace
+
+    f = SimpleNamespace(kind="pow", sigma=0.0, p=-0.5, alpha=0.0, coef=())
+    return nt(square_operator(A), A @ np.asarray(b, dtype=np.float64), f, m, k, sketch, ls)
 
 
 def relerr(x: np.ndarray, ref: np.ndarray) -> float:

@@ -477,3 +477,40 @@ def test_whitening_pinned():
     Hbad = Hb.copy()
     Hbad[:5, :4] *= 1.001
     assert np.linalg.norm(A @ Vb[:m].T - Vb.T @ Hbad) / np.linalg.norm(A @ Vb[:m].T) > 1e-6
+
+
+def test_sign_function_pinned():
+    """sign(A) b = (A^2)^{-1/2} (A b).  On a diagonal operator with entries
+    k/4 of both signs (squares exact in FP32 and distinct) the Krylov space of
+    A^2 is invariant after 8 steps, so the method at m = 8 returns
+    sign(d) * b; applying it twice returns b.  On a shifted (indefinite) 2D
+    Laplacian the full-Arnoldi form of the same formula approaches the DST
+    closed form S sign(lambda) S b as m grows."""
+    import scipy.fft as sfft
+
+    d = np.repeat([-3.0, -2.0, -1.5, -0.75, 0.5, 1.25, 2.5, 3.25], 100)
+    A = sp.diags(d).tocsr()
+    b = W.rhs(d.size, 4)
+    # m = 8: the degree of the minimal polynomial of A^2 for A b, so the
+    # compression is exact (Section 3's exactness at that degree)
+    res = krylov.sign_fAb(A, b, 8, 2, ls="none")
+    assert krylov.relerr(res["f"], np.sign(d) * b) < 1e-13
+    twice = krylov.sign_fAb(A, res["f"], 8, 2, ls="none")["f"]
+    assert krylov.relerr(twice, b) < 1e-13
+    # a planted slip (z^{-1/2} applied to A instead of A^2 through a shift) fails
+    f = W.FuncSpec("pow", sigma=0.0, p=-0.5)
+    wrong = krylov.nt(A @ A + 0.5 * sp.identity(d.size), A @ b, f, 8, 2, None, "none")["f"]
+    assert krylov.relerr(wrong, np.sign(d) * b) > 1e-3
+    # shifted Laplacian: A^2 of the integer stencil is exact in FP32
+    N, shift = 8, 1.3
+    st = W.Stencil(2, N, N, 1, (4.0 - shift, -1.0, -1.0, -1.0, -1.0, 0.0, 0.0))
+    L = operators.as_matrix(st)
+    st0 = W.Stencil(2, N, N, 1, (4.0, -1.0, -1.0, -1.0, -1.0, 0.0, 0.0))
+    L0 = operators.as_matrix(st0)
+    assert np.abs(krylov.square_operator(L0) - L0 @ L0).max() == 0.0
+    bl = W.rhs(st.n, 4)
+    lam = closed_form.laplacian_eigs(W.laplacian2d(N)) - shift
+    ref = sfft.dstn(sfft.dstn(bl.reshape(N, N), type=1, norm="ortho") * np.sign(lam), type=1, norm="ortho").ravel()
+    e30 = krylov.relerr(krylov.fm(krylov.square_operator(L), L @ bl, f, 30), ref)
+    e45 = krylov.relerr(krylov.fm(krylov.square_operator(L), L @ bl, f, 45), ref)
+    assert e45 < 1e-5 and e45 < 1e-2 * e30
