@@ -61,7 +61,13 @@ enum fab_status {
 enum fab_func_kind {
   FAB_F_EXP = 1,      /* f(z) = exp(alpha z)                                      */
   FAB_F_POW = 2,      /* f(z) = (z + sigma)^p, p = +1/2 or -1/2 (principal branch) */
-  FAB_F_POLY = 3      /* f(z) = sum_j coef[j] z^j (test hook: exact for deg <= m-1) */
+  FAB_F_POLY = 3,     /* f(z) = sum_j coef[j] z^j (test hook: exact for deg <= m-1) */
+  FAB_F_SIGN = 4      /* f(z) = sign(Re z), computed as (A^2)^{-1/2} (A b) (Section 5.1.3):
+                         the method runs on the operator A^2 (formed once per matrix as
+                         CSR with FP32 values, exact for integer stencils, and kept until
+                         the matrix is destroyed) from the start vector A b, with
+                         f(z) = z^{-1/2}; m, k, s, ... apply to that solve; info.beta
+                         is ||A b||.  alpha, sigma, p are ignored.                   */
 };
 typedef struct {
   int kind;

@@ -314,6 +314,20 @@ __global__ void __launch_bounds__(256) k_bg_update(SolveDev d, const double* __r
   }
 }
 
+// y = A x for FP64 vectors [n][nrhs] (the start vector A b of the sign function).
+template <int OP>
+__global__ void __launch_bounds__(256) k_apply_op(SolveDev d, const double* __restrict__ x, double* __restrict__ y) {
+  const long long nel = (long long)d.n * d.nrhs;
+  for (long long e = ((long long)blockIdx.x * 256 + threadIdx.x) * EPT; e < nel;
+       e += (long long)gridDim.x * 256 * EPT) {
+    double c[EPT], w[EPT];
+    get8(x, e, nel, c);
+    apply8<double, OP>(d, x, e, nel, c, w);
+    for (int j = 0; j < EPT; ++j)
+      if (e + j < nel) y[e + j] = w[j];
+  }
+}
+
 template <typename T, int OP>
 hipError_t apply_t(const SolveDev& d, int i, hipStream_t st, size_t lds) {
   const dim3 g(d.nblk);
@@ -355,6 +369,15 @@ hipError_t bg_apply(const SolveDev& d, int esize, int i, hipStream_t st, size_t 
   const bool csr = d.op == OP_CSR;
   if (esize == 4) return csr ? apply_t<float, OP_CSR>(d, i, st, lds) : apply_t<float, OP_STENCIL>(d, i, st, lds);
   return csr ? apply_t<double, OP_CSR>(d, i, st, lds) : apply_t<double, OP_STENCIL>(d, i, st, lds);
+}
+
+hipError_t apply_operator(const SolveDev& d, const double* x, double* y, hipStream_t st) {
+  const long long nel = (long long)d.n * d.nrhs;
+  long long g = (nel + 256 * EPT - 1) / (256 * EPT);
+  if (g > 4096) g = 4096;
+  if (d.op == OP_CSR) hipLaunchKernelGGL(k_apply_op<OP_CSR>, dim3((unsigned)g), dim3(256), 0, st, d, x, y);
+  else hipLaunchKernelGGL(k_apply_op<OP_STENCIL>, dim3((unsigned)g), dim3(256), 0, st, d, x, y);
+  return hipGetLastError();
 }
 
 hipError_t bg_reduce(const SolveDev& d, int col, hipStream_t st) {

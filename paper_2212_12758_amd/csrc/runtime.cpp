@@ -61,6 +61,7 @@ hipError_t bg_reduce(const SolveDev& d, int col, hipStream_t st);
 hipError_t bg_gs(const SolveDev& d, double* cf, int i, int passes, hipStream_t st);
 hipError_t bg_update(const SolveDev& d, int esize, const double* cf, int i, hipStream_t st);
 hipError_t bg_set_attributes();
+hipError_t apply_operator(const SolveDev& d, const double* x, double* y, hipStream_t st);
 hipError_t wh_col(const SolveDev& d, const DenseDev& g, int a, int check, double thresh, int* flag,
                   hipStream_t st);
 hipError_t wh_whiten(const SolveDev& d, const DenseDev& g, int esize, int i, hipStream_t st);
@@ -158,6 +159,8 @@ struct fab_matrix_s {
   int* col = nullptr;
   float* val = nullptr;
   std::atomic<int> refs{0};
+  fab_matrix square = nullptr;   // A^2 as CSR, built at the first sign-function request
+  std::mutex sq_mu;
 };
 
 namespace {
@@ -179,6 +182,10 @@ struct Plan {
   int whitened_at = 0;         // step at which the last solve whitened (0: never)
   size_t oBgCf = 0;            // Algorithm 1 update weights [nrhs][m+2]
   size_t oFq = 0;              // quadrature partial sums of the square root (FAB_F_POW)
+  bool sign = false;           // FAB_F_SIGN: the solve runs on A^2 from A b
+  fab_matrix Aorig = nullptr;  // A itself (the operator of the start vector A b)
+  fab_func forig{};            // the caller's f (kind FAB_F_SIGN)
+  size_t oSignB = 0;           // A b, FP64 [n][nrhs]
   size_t oWflag = 0;           // whitening trigger flag
   int lnblk = 0;               // LSQR pass blocks
   size_t oLu = 0, oLpart = 0, oLst = 0, oLflag = 0;
@@ -201,8 +208,19 @@ int ilog2(long long v) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, int esize, Plan& P) {
+int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp, int esize, Plan& P) {
   if (!A || !pp) return FAB_EINVAL;
+  // sign(A) b = (A^2)^{-1/2} (A b): plan the inverse square root on A^2
+  fab_func f = fin;
+  const bool sign = fin.kind == FAB_F_SIGN;
+  if (sign) {
+    if (!A->square) return FAB_EINVAL;
+    P.Aorig = A;
+    P.forig = fin;
+    A = A->square;
+    f = fab_func{FAB_F_POW, 0.0, 0.0, -0.5, nullptr, 0};
+  }
+  P.sign = sign;
   const fab_params& p = *pp;
   const long long n = A->n;
   if (nrhs < 1 || nrhs > 32 || (nrhs & (nrhs - 1))) return FAB_EINVAL;
@@ -281,6 +299,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& f, const fab_params* pp, i
   if (bg || whiten) P.oBgCf = take((size_t)nrhs * (m + 2) * 8);
   if (whiten) P.oWflag = take(256);
   if (f.kind == FAB_F_POW) P.oFq = take(fsqrt_partials_doubles(m, nrhs) * 8);
+  if (sign) P.oSignB = take((size_t)n * nrhs * 8);
   // LSQR refinement (FAB_LS_AUTO when the gate fails, FAB_LS_LSQR always)
   if (p.ls_mode == FAB_LS_AUTO || p.ls_mode == FAB_LS_LSQR) {
     const bool fits = lsqr_pass_lds(m, nrhs) <= 120 * 1024;
@@ -417,6 +436,23 @@ size_t host_info_doubles(int nrhs) { return (size_t)nrhs * NINFO + 4 + 2 * nrhs 
 // Enqueue the whole solve on `st`.  Host-visible results land in `hinfo` (pinned).
 // `side` runs the incremental sketched QR; `ev` orders it against `st`;
 // `rows` holds the sampled SRHT rows (cached per context).
+// Operator fields of a descriptor (the start vector of a sign-function solve).
+SolveDev operator_desc(fab_matrix A, int nrhs) {
+  SolveDev d{};
+  d.n = A->n;
+  d.nrhs = nrhs;
+  d.lognrhs = ilog2(nrhs);
+  d.op = A->op;
+  d.nx = A->nx;
+  d.ny = A->ny;
+  d.nz = A->nz;
+  for (int i = 0; i < 7; ++i) d.c[i] = A->c[i];
+  d.rowptr = A->rowptr;
+  d.col = A->col;
+  d.val = A->val;
+  return d;
+}
+
 // Kernel descriptors of a planned request in its workspace.
 void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev& g) {
   const fab_params& p = P.p;
@@ -441,7 +477,7 @@ void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev
   d.V = ws + P.oV;
   d.ldv = P.ldv;
   d.wbuf = A->op == OP_CSR ? (double*)(ws + P.oW) : nullptr;
-  d.b = P.b;
+  d.b = P.sign ? (const double*)(ws + P.oSignB) : P.b;
   d.H = (double*)(ws + P.oH);
   d.eta = (double*)(ws + P.oEta);
   d.wnorm = (double*)(ws + P.oWn);
@@ -513,6 +549,14 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
   auto E = [&]() {
     if (open_cls >= 0) { prof->end(st); open_cls = -1; }
   };
+  if (P.sign) {
+    // start vector A b of the solve on A^2
+    SolveDev da = operator_desc(P.Aorig, P.nrhs);
+    B(FAB_K_OTHER);
+    e = apply_operator(da, P.b, (double*)(ws + P.oSignB), st);
+    E();
+    if (e != hipSuccess) return FAB_EDEVICE;
+  }
   B(FAB_K_OTHER);
   e = basis_start(d, P.esize, st, P.lds_update);
   E();
@@ -726,9 +770,9 @@ void retire_locked(fab_ctx ctx, Request& r) {
   if (!r.fell_back && needs_fp64_rerun(r.plan, r.status, r.info)) {
     // FAB_PREC_AUTO: queue the request again, first in line, with an FP64 basis
     Plan P2;
-    fab_func f2 = r.plan.f;
+    fab_func f2 = r.plan.sign ? r.plan.forig : r.plan.f;
     if (f2.kind == FAB_F_POLY) f2.coef = r.plan.coef.data();   // the caller's array may be gone
-    if (make_plan(r.plan.A, r.plan.nrhs, f2, &r.plan.p, 8, P2) == FAB_OK &&
+    if (make_plan(r.plan.sign ? r.plan.Aorig : r.plan.A, r.plan.nrhs, f2, &r.plan.p, 8, P2) == FAB_OK &&
         ctx->arena.could_ever_fit(P2.bytes)) {
       P2.b = r.plan.b;
       P2.out = r.plan.out;
@@ -989,13 +1033,82 @@ int fab_create_matrix_csr(fab_ctx ctx, int64_t n, int64_t nnz, const int32_t* ro
   return FAB_OK;
 }
 
-int fab_destroy_matrix(fab_matrix A) {
-  if (!A) return FAB_EINVAL;
-  fab_ctx ctx = A->ctx;
-  // lock order everywhere: solve_mu, then mu
-  std::lock_guard<std::mutex> slk(ctx->solve_mu);
-  std::lock_guard<std::mutex> lk(ctx->mu);
-  if (A->refs.load() > 0) return FAB_EBUSY;
+// ---------------------------------------------------------------- A^2 for the sign function
+namespace {
+
+// A in CSR on the host (FP64 values): generated from the stencil, or copied back.
+int host_csr(fab_matrix A, std::vector<int>& rp, std::vector<int>& ci, std::vector<double>& va) {
+  const int n = A->n;
+  rp.assign(n + 1, 0);
+  ci.clear();
+  va.clear();
+  if (A->op == OP_STENCIL) {
+    const int nx = A->nx, ny = A->ny, nz = A->nz;
+    for (int r = 0; r < n; ++r) {
+      const int x = r % nx, y = (r / nx) % ny, z = r / (nx * ny);
+      auto put = [&](int cc, double v) {
+        if (v != 0.0) { ci.push_back(cc); va.push_back(v); }
+      };
+      if (z > 0) put(r - nx * ny, A->c[5]);
+      if (y > 0) put(r - nx, A->c[3]);
+      if (x > 0) put(r - 1, A->c[1]);
+      put(r, A->c[0]);
+      if (x < nx - 1) put(r + 1, A->c[2]);
+      if (y < ny - 1) put(r + nx, A->c[4]);
+      if (z < nz - 1) put(r + nx * ny, A->c[6]);
+      rp[r + 1] = (int)ci.size();
+    }
+    return FAB_OK;
+  }
+  std::vector<float> vf((size_t)A->nnz);
+  ci.resize((size_t)A->nnz);
+  if (hipMemcpy(rp.data(), A->rowptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      (A->nnz > 0 && hipMemcpy(ci.data(), A->col, (size_t)A->nnz * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
+      (A->nnz > 0 && hipMemcpy(vf.data(), A->val, (size_t)A->nnz * 4, hipMemcpyDeviceToHost) != hipSuccess))
+    return FAB_EDEVICE;
+  va.assign(vf.begin(), vf.end());
+  return FAB_OK;
+}
+
+// Row-by-row sparse product (Gustavson): C = A A, FP64 accumulation, FP32
+// values, columns of each row in increasing order.
+int ensure_square(fab_ctx ctx, fab_matrix A) {
+  std::lock_guard<std::mutex> lk(A->sq_mu);
+  if (A->square) return FAB_OK;
+  std::vector<int> rp, ci;
+  std::vector<double> va;
+  int rc = host_csr(A, rp, ci, va);
+  if (rc != FAB_OK) return rc;
+  const int n = A->n;
+  std::vector<int> crp(n + 1, 0), ccol, mark(n, -1);
+  std::vector<float> cval;
+  std::vector<double> acc(n, 0.0);
+  std::vector<int> cols;
+  for (int r = 0; r < n; ++r) {
+    cols.clear();
+    for (int p = rp[r]; p < rp[r + 1]; ++p) {
+      const int k = ci[p];
+      const double a = va[p];
+      for (int q = rp[k]; q < rp[k + 1]; ++q) {
+        const int c = ci[q];
+        if (mark[c] != r) { mark[c] = r; acc[c] = 0.0; cols.push_back(c); }
+        acc[c] += a * va[q];
+      }
+    }
+    std::sort(cols.begin(), cols.end());
+    for (int c : cols) { ccol.push_back(c); cval.push_back((float)acc[c]); }
+    if (ccol.size() >= (size_t)INT32_MAX) return FAB_ENOMEM;
+    crp[r + 1] = (int)ccol.size();
+  }
+  fab_matrix S = nullptr;
+  rc = fab_create_matrix_csr(ctx, n, (int64_t)ccol.size(), crp.data(), ccol.data(), cval.data(), 0, &S);
+  if (rc != FAB_OK) return rc;
+  A->square = S;
+  return FAB_OK;
+}
+
+// Release a matrix's graphs, memory and registration (callers hold solve_mu and mu).
+void release_matrix_locked(fab_ctx ctx, fab_matrix A) {
   for (auto it = ctx->graphs.begin(); it != ctx->graphs.end();) {
     fab_matrix gA;
     std::memcpy(&gA, it->key.data(), sizeof(gA));
@@ -1010,6 +1123,19 @@ int fab_destroy_matrix(fab_matrix A) {
   if (A->op == OP_CSR) ctx->arena.release(A->rowptr);
   ctx->matrices.erase(A);
   delete A;
+}
+
+}  // namespace
+
+int fab_destroy_matrix(fab_matrix A) {
+  if (!A) return FAB_EINVAL;
+  fab_ctx ctx = A->ctx;
+  // lock order everywhere: solve_mu, then mu
+  std::lock_guard<std::mutex> slk(ctx->solve_mu);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (A->refs.load() > 0 || (A->square && A->square->refs.load() > 0)) return FAB_EBUSY;
+  if (A->square) release_matrix_locked(ctx, A->square);
+  release_matrix_locked(ctx, A);
   return FAB_OK;
 }
 
@@ -1107,6 +1233,10 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
   const double t0 = now_us();
   std::lock_guard<std::mutex> slk(ctx->solve_mu);
   hipSetDevice(ctx->device);
+  if (f.kind == FAB_F_SIGN) {
+    const int rs = ensure_square(ctx, A);
+    if (rs != FAB_OK) return rs;
+  }
   int esize = esize_for(p->prec == FAB_PREC_FP64 ? FAB_PREC_FP64 : FAB_PREC_FP32);
   Plan P;
   std::vector<fab_info> fi;
@@ -1232,6 +1362,11 @@ int fab_profile_read(fab_ctx ctx, int cls, long long* launches, double* total_ms
 int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, const fab_params* p, double* out,
                fab_request* req) {
   if (!ctx || !A || !b || !out || !p || !req || A->ctx != ctx) return FAB_EINVAL;
+  if (f.kind == FAB_F_SIGN) {
+    hipSetDevice(ctx->device);
+    const int rs = ensure_square(ctx, A);
+    if (rs != FAB_OK) return rs;
+  }
   auto r = std::make_shared<Request>();
   int first_prec = p->prec == FAB_PREC_FP64 ? FAB_PREC_FP64 : FAB_PREC_FP32;
   int rc = make_plan(A, nrhs, f, p, esize_for(first_prec), r->plan);
@@ -1253,7 +1388,7 @@ int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
     return FAB_ENOMEM;
   }
   r->id = ctx->next_id++;
-  A->refs.fetch_add(1);
+  r->plan.A->refs.fetch_add(1);   // the planned operator (A^2 for the sign function), released at retirement
   ctx->reqs[r->id] = r;
   ctx->queue.push_back(r->id);
   *req = r->id;

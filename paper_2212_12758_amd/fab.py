@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfab.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EBUSY, ENOTFOUND = range(7)
-F_EXP, F_POW, F_POLY = 1, 2, 3
+F_EXP, F_POW, F_POLY, F_SIGN = 1, 2, 3, 4
 SKETCH_SRHT, SKETCH_SPARSE_SIGN = 1, 2
 PREC_FP32, PREC_FP64, PREC_AUTO = 1, 2, 3
 LS_AUTO, LS_SKETCH, LS_NONE, LS_LSQR = 0, 1, 2, 3
@@ -94,8 +94,8 @@ def _check(code: int, what: str):
 
 
 def make_func(f) -> tuple:
-    """Duck-typed f (kind 'exp' | 'pow' | 'poly', alpha, sigma, p, coef) -> (fab_func, keepalive)."""
-    kind = {"exp": F_EXP, "pow": F_POW, "poly": F_POLY}[f.kind]
+    """Duck-typed f (kind 'exp' | 'pow' | 'poly' | 'sign', alpha, sigma, p, coef) -> (fab_func, keepalive)."""
+    kind = {"exp": F_EXP, "pow": F_POW, "poly": F_POLY, "sign": F_SIGN}[f.kind]
     coef = tuple(getattr(f, "coef", ()) or ())
     arr = (C.c_double * max(1, len(coef)))(*coef) if coef else None
     ff = fab_func(kind, float(getattr(f, "alpha", 0.0)), float(getattr(f, "sigma", 0.0)),

@@ -115,8 +115,8 @@ def rhs(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
 
 @dataclasses.dataclass(frozen=True)
 class FuncSpec:
-    """f(z) = exp(alpha z)  |  (z + sigma)^p with p = +-1/2  |  sum_j coef[j] z^j."""
-    kind: str                # "exp" | "pow" | "poly"
+    """f(z) = exp(alpha z)  |  (z + sigma)^p with p = +-1/2  |  sum_j coef[j] z^j  |  sign(z)."""
+    kind: str                # "exp" | "pow" | "poly" | "sign"
     alpha: float = 0.0
     sigma: float = 0.0
     p: float = 0.0
