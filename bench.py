@@ -58,18 +58,24 @@ def algorithmic_bytes_bg(n, nrhs, m, esize, lsqr_iters):
             "solve": apply_ + update + start + lsqr + combine}
 
 
-def algorithmic_bytes(n, nrhs, m, k, esize):
-    """Bytes the method must move per solve and per kernel class (stencil operator).
+def algorithmic_bytes(n, nrhs, m, k, esize, nnz=None):
+    """Bytes the method must move per solve and per kernel class.
 
     Step i (1..m): the dots pass reads the window of min(i, k) vectors (the
     matvec source is its newest member); the update pass reads the same window
     and writes the new vector.  Start: read b (FP64), write u_0.  Combine: read
-    m basis vectors, write the FP64 result.
+    m basis vectors, write the FP64 result.  A CSR operator (nnz given) adds,
+    per step, its arrays (8 B per nonzero + 4 B per row) to the dots pass and
+    the FP64 product w~ written there and read by the update pass.
     """
     vec = n * nrhs * esize
     win = sum(min(i, k) for i in range(1, m + 1))
     dots = win * vec
     update = (win + m) * vec
+    if nnz is not None:
+        wb = 8 * n * nrhs
+        dots += m * (8 * nnz + 4 * (n + 1) + wb)
+        update += m * wb
     start = n * nrhs * 8 + vec
     combine = m * vec + n * nrhs * 8
     return {"dots_per_launch": dots / m, "update_per_launch": update / m,
@@ -88,6 +94,14 @@ BENCH = {
         "traffic_file": os.path.join(ROOT, "profiles", "traffic_k_update_convdiff3d_128_exp.json"),
         "sources": [CSRC + "k_basis.h", CSRC + "k_basis_part.inc", CSRC + "fab_dev.h"],
         "operator": "3D upwind convection-diffusion 7-point 128^3, Pe=50", "f": "exp(-1e-3 A)",
+    },
+    "convdiff2d_352_exp": {
+        "basis": "truncated",
+        "kernel": "k_update (Gram-Schmidt update + norm + fused SRHT), CSR operator",
+        "pmc_kernel": "k_update<float, 1, 1, false, 9, 1, 2>",
+        "traffic_file": os.path.join(ROOT, "profiles", "traffic_k_update_convdiff2d_352_exp.json"),
+        "sources": [CSRC + "k_basis.h", CSRC + "k_basis_part.inc", CSRC + "fab_dev.h"],
+        "operator": "2D variable-coefficient convection-diffusion 352^2 (Section 5.1.1), CSR", "f": "exp(-t A)",
     },
     "lap3d_80_invsqrt": {
         "basis": "sketched_gs2",
@@ -208,7 +222,9 @@ def main():
     bg = basis != "truncated"
     w = W.config(args.workload)
     n = w.n
-    b = W.rhs(n, w.b_seed)
+    b = W.rhs(n, w.b_seed) if w.b_seed >= 0 else None
+    if b is None:   # the sin(pi x) sin(pi y) start vector of the 2D workload
+        b = W.sine_rhs(int(round(n ** 0.5)))
     ctx = Context(0, arena_bytes=6 << 30)
     A = ctx.matrix(w.op)
     bd = torch.from_numpy(b).cuda()
@@ -242,7 +258,7 @@ def main():
     if bg:
         ab32 = algorithmic_bytes_bg(n, 1, w.m, esize, info[0]["ls_iters"])
     else:
-        ab32 = algorithmic_bytes(n, 1, w.m, w.k, esize)
+        ab32 = algorithmic_bytes(n, 1, w.m, w.k, esize, None if hasattr(w.op, "coeff") else len(w.op[1]))
 
     # kernel timing region: the same K solves with direct launches and a HIP
     # event pair around every launch of the dominant kernel on its stream

@@ -19,6 +19,10 @@ Matrix Market matrices of Sections 5.1.3 and 5.2, which are not available):
                         ||A||_inf = ||A||_1 = 1e3 (hence ||A||_2 <= 1e3).
 * ``rgg_laplacian(n)``  graph Laplacian D - W of a random geometric graph in
                         the unit square with mean degree ~10, CSR int32/FP32.
+* ``convdiff2d_varcoef(N)`` the variable-coefficient convection-diffusion
+                        operator of Section 5.1.1 (D_1 = 1000 on [0.25, 0.75]^2,
+                        else 1; D_2 = D_1 / 2; v = (x + y, x - y); Pe = 200) on an
+                        N x N interior grid, CSR int32/FP32 (construction below).
 
 Grid ordering everywhere: row = x + nx*(y + ny*z), x fastest.
 Stencil coefficient order: (centre, x-1, x+1, y-1, y+1, z-1, z+1); a
@@ -33,7 +37,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "Stencil", "laplacian2d", "laplacian3d", "convdiff3d", "rgg_laplacian",
+    "Stencil", "laplacian2d", "laplacian3d", "convdiff3d", "rgg_laplacian", "convdiff2d_varcoef", "sine_rhs",
     "rhs", "FuncSpec", "Workload", "config", "CONFIG_NAMES",
 ]
 
@@ -105,6 +109,57 @@ def rgg_laplacian(n: int, seed: int, mean_degree: float = 10.0):
     return rowptr.astype(np.int32), cols.astype(np.int32), vals.astype(np.float32)
 
 
+def convdiff2d_varcoef(N: int, Pe: float = 200.0):
+    """CSR (int32 rowptr/col, FP32 val) of
+    L[u] = -(D_1 u_x)_x - (D_2 u_y)_y + Pe (1/2 (v . grad u) + 1/2 div(v u))
+    on (0, 1)^2, homogeneous Dirichlet, N x N interior points, h = 1/(N+1),
+    row = i + N j for the point (x_i, y_j) = ((i+1) h, (j+1) h).
+    Diffusion: conservative three-point differences with D at the half
+    points; convection: centred differences of the split (skew-symmetric)
+    form, so the u_{i+1} entry of row i is Pe (v_1(x_i) + v_1(x_{i+1})) / (4h)
+    and the u_{i-1} entry is -Pe (v_1(x_i) + v_1(x_{i-1})) / (4h) (same in y
+    with v_2).  The discretisation is not given in the paper (it cites
+    Botchev & Knizhnerman 2020); this is a standard choice for that form."""
+    h = 1.0 / (N + 1)
+
+    def D1(x, y):
+        return np.where((x >= 0.25) & (x <= 0.75) & (y >= 0.25) & (y <= 0.75), 1000.0, 1.0)
+
+    idx = np.arange(N)
+    I, J = np.meshgrid(idx, idx, indexing="xy")     # I: x index, J: y index, shape (N, N) with [j, i]
+    x, y = (I + 1) * h, (J + 1) * h
+    v1 = lambda xx, yy: xx + yy
+    v2 = lambda xx, yy: xx - yy
+    dxm, dxp = D1(x - h / 2, y), D1(x + h / 2, y)
+    dym, dyp = 0.5 * D1(x, y - h / 2), 0.5 * D1(x, y + h / 2)
+    centre = (dxm + dxp + dym + dyp) / h**2
+    east = -dxp / h**2 + Pe * (v1(x, y) + v1(x + h, y)) / (4 * h)
+    west = -dxm / h**2 - Pe * (v1(x, y) + v1(x - h, y)) / (4 * h)
+    north = -dyp / h**2 + Pe * (v2(x, y) + v2(x, y + h)) / (4 * h)
+    south = -dym / h**2 - Pe * (v2(x, y) + v2(x, y - h)) / (4 * h)
+    row = (I + N * J).ravel()
+    rows, cols, vals = [row], [row], [centre.ravel()]
+    for val, di, dj in ((east, 1, 0), (west, -1, 0), (north, 0, 1), (south, 0, -1)):
+        ok = ((I + di >= 0) & (I + di < N) & (J + dj >= 0) & (J + dj < N)).ravel()
+        rows.append(row[ok])
+        cols.append(((I + di) + N * (J + dj)).ravel()[ok])
+        vals.append(val.ravel()[ok])
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(N * N + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=N * N), out=rowptr[1:])
+    return rowptr.astype(np.int32), cols.astype(np.int32), vals.astype(np.float32)
+
+
+def sine_rhs(N: int) -> np.ndarray:
+    """sin(pi x) sin(pi y) on the N x N interior grid, normalised (Section 5.1.1)."""
+    h = 1.0 / (N + 1)
+    t = np.sin(np.pi * (np.arange(N) + 1) * h)
+    b = np.outer(t, t).ravel()
+    return b / np.linalg.norm(b)
+
+
 def rhs(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
     """b ~ N(0,1) from numpy's default_rng(seed); nrhs > 1 gives columns seed..seed+nrhs-1,
     returned interleaved as an (n, nrhs) C-ordered array (layout [n][nrhs])."""
@@ -145,7 +200,7 @@ class Workload:
 
 
 CONFIG_NAMES = ("lap2d_100_exp", "convdiff3d_128_exp", "rgg_2p20_invsqrt", "convdiff3d_256_exp_8rhs",
-                "lap3d_80_invsqrt")
+                "lap3d_80_invsqrt", "convdiff2d_352_exp")
 
 
 def config(name: str, scale: int | None = None) -> Workload:
@@ -176,4 +231,15 @@ def config(name: str, scale: int | None = None) -> Workload:
         m = 120
         return Workload(name, laplacian3d(N), 8, 1, FuncSpec("pow", sigma=0.0, p=-0.5),
                         m=m, k=2, s=int(math.floor(1.05 * m)), sketch="srht", sketch_seed=8)
+    if name == "convdiff2d_352_exp":
+        # Section 5.1.1: 352 x 352 mesh, Pe = 200, exp(-t A) with the time scale
+        # t = 100 / ||A||_inf (the paper does not state t); b = sin(pi x) sin(pi y)
+        # normalised (b_seed -1 marks it: not a random vector)
+        N = 352 if scale is None else scale
+        op = convdiff2d_varcoef(N)
+        rp, _, va = op
+        rowsum = np.add.reduceat(np.abs(va.astype(np.float64)), rp[:-1].astype(np.int64))
+        t = 100.0 / float(rowsum.max())
+        return Workload(name, op, -1, 1, FuncSpec("exp", alpha=-t), m=100, k=2, s=200, sketch="srht",
+                        sketch_seed=11)
     raise KeyError(name)
