@@ -240,7 +240,82 @@ __device__ void qr_global(const double* __restrict__ S, const double* __restrict
   __syncthreads();
 }
 
-// Dynamic LDS: vsh[448] + z[m+1] + (R[mu*mu] when mu <= 111).
+// ----------------------------------------------------------------- Gram matrix and Cholesky factor
+// G = W^T W of the normalised sketch W = [S_0 / eta_0, ..., S_m / eta_m]
+// (upper triangle, ld m+1, in the rhs's scratch region oM): a 16 x 16 tile per
+// workgroup, rows staged through LDS in chunks of 64, each thread one entry.
+constexpr int GT = 16, GCH = 64;
+__global__ void __launch_bounds__(256) k_gram(SolveDev d, DenseDev g) {
+  const int q = blockIdx.x, tx = blockIdx.y, ty = blockIdx.z;
+  if (ty > tx) return;   // upper tiles only
+  __shared__ double As[GCH][GT], Bs[GCH][GT];
+  const int tid = threadIdx.x, a = tid & (GT - 1), b = tid >> 4;
+  const int m1 = d.m + 1, s = d.s;
+  const double* S = d.S + (long long)q * s * m1;
+  const double* eta = d.eta + (long long)q * m1;
+  const int ca0 = ty * GT, cb0 = tx * GT;
+  double acc = 0.0;
+  for (int r0 = 0; r0 < s; r0 += GCH) {
+    for (int x = tid; x < GCH * GT; x += 256) {
+      const int rr = x / GT, cc = x % GT, r = r0 + rr;
+      const int ca = ca0 + cc, cb = cb0 + cc;
+      const double ea = ca < m1 ? eta[ca] : 0.0, eb = cb < m1 ? eta[cb] : 0.0;
+      As[rr][cc] = (r < s && ca < m1 && ea > 0.0) ? S[(long long)ca * s + r] / ea : 0.0;
+      Bs[rr][cc] = (r < s && cb < m1 && eb > 0.0) ? S[(long long)cb * s + r] / eb : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 16
+    for (int rr = 0; rr < GCH; ++rr) acc += As[rr][a] * Bs[rr][b];
+    __syncthreads();
+  }
+  const int ca = ca0 + a, cb = cb0 + b;
+  if (ca < m1 && cb < m1 && ca <= cb) g.base[(long long)q * g.stride + g.oM + ca + (long long)cb * m1] = acc;
+}
+
+// Cholesky G = R^T R of the leading n x n block of G (global, ld m1) in LDS
+// (R overwrites the upper triangle, ld n), two barriers per column.  Fails
+// (returns false, every thread) on a non-positive pivot or when the diagonal
+// of R spreads more than CHOL_MAXRATIO over its first n-1 entries: then the
+// squared condition number would cost accuracy and the Householder path runs.
+constexpr double CHOL_MAXRATIO = 1e3;
+__device__ bool cholesky_lds(const double* __restrict__ G, int m1, int n, double* R, double* rmm) {
+  const int tid = threadIdx.x;
+  for (long long x = tid; x < (long long)n * n; x += LBLOCK) {
+    const int i = (int)(x % n), j = (int)(x / n);
+    R[x] = i <= j ? G[i + (long long)j * m1] : 0.0;
+  }
+  __syncthreads();
+  double rmax = 0.0, rmin = 1e308;
+  for (int k = 0; k < n; ++k) {
+    const double dkk = R[k + (long long)k * n];
+    if (!(dkk > 0.0) || !isfinite(dkk)) return false;   // uniform: every thread read the same value
+    const double rkk = sqrt(dkk);
+    if (k < n - 1) {
+      rmax = fmax(rmax, rkk);
+      rmin = fmin(rmin, rkk);
+    }
+    for (int j = k + 1 + tid; j < n; j += LBLOCK) R[k + (long long)j * n] /= rkk;
+    __syncthreads();
+    if (tid == 0) R[k + (long long)k * n] = rkk;
+    const int w = n - k - 1;
+    for (int x = tid; x < w * w; x += LBLOCK) {
+      const int i = k + 1 + x % w, j = k + 1 + x / w;
+      if (i <= j) R[i + (long long)j * n] -= R[k + (long long)i * n] * R[k + (long long)j * n];
+    }
+    __syncthreads();
+  }
+  if (!(rmax <= CHOL_MAXRATIO * rmin)) return false;
+  if (tid == 0) {
+    rmm[0] = rmax;
+    rmm[1] = rmin;
+    for (int w = 1; w < 8; ++w) { rmm[2 * w] = 0.0; rmm[2 * w + 1] = 1e308; }
+  }
+  __syncthreads();
+  return true;
+}
+
+// Dynamic LDS: vsh[448] + z[m+1] + (R[(m+1)^2] when the matrix fits the
+// registers) + z2[m+1].
 __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
   const int q = blockIdx.x;
   const int tid = threadIdx.x;
@@ -265,8 +340,21 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
   const double* Rm = Rl;
   int ldr = mu;
   double rmax = 0.0, rmin = 1e308;
+  // Cholesky of the Gram matrix (k_gram) when the sketch is well conditioned:
+  // the last column of R is [z; rho], so R_m and z come out together
+  bool chol = false;
+  if (do_ls && in_regs) {
+    chol = cholesky_lds(ws + g.oM, m1, mu + 1, Rl, rmm);
+    if (chol) {
+      ldr = mu + 1;
+      for (int r = tid; r < mu; r += LBLOCK) z[r] = Rl[r + (long long)mu * ldr];
+      __syncthreads();
+    }
+  }
   if (do_ls) {
-    if (in_regs) {
+    if (chol) {
+      // R and z are in Rl already
+    } else if (in_regs) {
       qr_registers(S, eta, s, mu + 1, vsh, Rl, z, tau_sh, rmm);
     } else {
       double* W = ws + g.oW;
@@ -313,7 +401,7 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
     if (md < 1) md = 0;
     for (int c = wave_id(); c < mu; c += LBLOCK / 64)
       for (int r = tid & 63; r < mu; r += 64) H1[r + (long long)c * mu] = H[(long long)c * m1 + r];
-    double* z2 = z + m1 + (in_regs ? (long long)m * m : 0);
+    double* z2 = z + m1 + (in_regs ? (long long)m1 * m1 : 0);
     if (md >= 1) {
       if (do_ls) {
         if (tid < 64) {
@@ -350,7 +438,7 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
 
 size_t lsq_lds_bytes(int s, int m) {
   const bool in_regs = s <= 64 * LRS && m + 1 <= 8 * LCS;
-  return (size_t)(2 * 64 * LRS + 2 * (m + 1) + (in_regs ? (size_t)m * m : 0)) * 8;
+  return (size_t)(2 * 64 * LRS + 2 * (m + 1) + (in_regs ? (size_t)(m + 1) * (m + 1) : 0)) * 8;
 }
 
 // ----------------------------------------------------------------- polynomial
@@ -483,6 +571,10 @@ hipError_t dense_after_refine(const SolveDev& d, const DenseDev& g, double* cf, 
 }
 
 hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, double* fq, hipStream_t st) {
+  if (d.s <= 64 * LRS && d.m + 1 <= 8 * LCS && g.ls_mode != 2) {
+    const unsigned t = (unsigned)((d.m + 1 + GT - 1) / GT);
+    hipLaunchKernelGGL(k_gram, dim3(d.nrhs, t, t), dim3(256), 0, st, d, g);
+  }
   hipLaunchKernelGGL(k_lsq, dim3(d.nrhs), dim3(LBLOCK), lsq_lds_bytes(d.s, d.m), st, d, g);
   const dim3 gv(d.nrhs, g.nvar);
   if (g.fkind == 1)
