@@ -273,19 +273,22 @@ __global__ void __launch_bounds__(256) k_gram(SolveDev d, DenseDev g) {
 }
 
 // Cholesky G = R^T R of the leading n x n block of G (global, ld m1) in LDS
-// (R overwrites the upper triangle, ld n), two barriers per column.  Fails
+// (R overwrites the upper triangle, ld n), one barrier per column: step k
+// updates the trailing block with the unscaled row k (G_ij -= G_ki G_kj / G_kk)
+// and scales row k-1, which no step from k on reads or writes.  Fails
 // (returns false, every thread) on a non-positive pivot or when the diagonal
 // of R spreads more than CHOL_MAXRATIO over its first n-1 entries: then the
 // squared condition number would cost accuracy and the Householder path runs.
 constexpr double CHOL_MAXRATIO = 1e3;
 __device__ bool cholesky_lds(const double* __restrict__ G, int m1, int n, double* R, double* rmm) {
   const int tid = threadIdx.x;
-  for (long long x = tid; x < (long long)n * n; x += LBLOCK) {
-    const int i = (int)(x % n), j = (int)(x / n);
+#pragma unroll 4
+  for (int x = tid; x < n * n; x += LBLOCK) {
+    const int i = x % n, j = x / n;
     R[x] = i <= j ? G[i + (long long)j * m1] : 0.0;
   }
   __syncthreads();
-  double rmax = 0.0, rmin = 1e308;
+  double rmax = 0.0, rmin = 1e308, dprev = 1.0;
   for (int k = 0; k < n; ++k) {
     const double dkk = R[k + (long long)k * n];
     if (!(dkk > 0.0) || !isfinite(dkk)) return false;   // uniform: every thread read the same value
@@ -294,16 +297,20 @@ __device__ bool cholesky_lds(const double* __restrict__ G, int m1, int n, double
       rmax = fmax(rmax, rkk);
       rmin = fmin(rmin, rkk);
     }
-    for (int j = k + 1 + tid; j < n; j += LBLOCK) R[k + (long long)j * n] /= rkk;
-    __syncthreads();
-    if (tid == 0) R[k + (long long)k * n] = rkk;
-    const int w = n - k - 1;
-    for (int x = tid; x < w * w; x += LBLOCK) {
-      const int i = k + 1 + x % w, j = k + 1 + x / w;
-      if (i <= j) R[i + (long long)j * n] -= R[k + (long long)i * n] * R[k + (long long)j * n];
+    const double inv = 1.0 / dkk;
+    // trailing update: columns over waves, rows over lanes (no index division)
+    for (int j = k + 1 + wave_id(); j < n; j += LBLOCK / 64) {
+      const double f = R[k + j * n] * inv;
+      for (int i = k + 1 + (tid & 63); i <= j; i += 64) R[i + j * n] -= R[k + i * n] * f;
     }
+    if (k >= 1) {
+      const double rp = sqrt(dprev);
+      for (int j = k - 1 + tid; j < n; j += LBLOCK) R[k - 1 + (long long)j * n] /= rp;
+    }
+    dprev = dkk;
     __syncthreads();
   }
+  if (tid == 0) R[n - 1 + (long long)(n - 1) * n] = sqrt(dprev);
   if (!(rmax <= CHOL_MAXRATIO * rmin)) return false;
   if (tid == 0) {
     rmm[0] = rmax;
@@ -312,6 +319,12 @@ __device__ bool cholesky_lds(const double* __restrict__ G, int m1, int n, double
   }
   __syncthreads();
   return true;
+}
+
+__device__ inline void lsq_upper_solve(int n, const double* U, long long ldu, const double* z, double* x) {
+  if (n <= 128) wave_upper_solve<2>(n, U, ldu, z, x);
+  else if (n <= 256) wave_upper_solve<4>(n, U, ldu, z, x);
+  else wave_upper_solve<8>(n, U, ldu, z, x);
 }
 
 // Dynamic LDS: vsh[448] + z[m+1] + (R[(m+1)^2] when the matrix fits the
@@ -366,31 +379,47 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
       rmax = fmax(rmax, rmm[2 * w]);
       rmin = fmin(rmin, rmm[2 * w + 1]);
     }
-    // back substitution R y = z by one wave (no barriers)
+    // back substitution R y = z by one wave (no barriers); R in LDS and in
+    // global memory are separate call sites so that each compiles to its
+    // own kind of load
     __syncthreads();
     if (tid < 64) {
-      if (mu <= 128) wave_upper_solve<2>(mu, Rm, ldr, z, z);
-      else if (mu <= 256) wave_upper_solve<4>(mu, Rm, ldr, z, z);
-      else wave_upper_solve<8>(mu, Rm, ldr, z, z);
+      if (in_regs) lsq_upper_solve(mu, (const double*)Rl, ldr, z, z);
+      else lsq_upper_solve(mu, Rm, ldr, z, z);
     }
     __syncthreads();
   } else {
     for (int x = tid; x < mu; x += LBLOCK) z[x] = 0.0;
     __syncthreads();
   }
-  // H_hat = H_m + h_{m+1,m} y e_m^T (m_used x m_used, ld = mu)
+  // H_hat = H_m + h_{m+1,m} y e_m^T (m_used x m_used, ld = mu); flat loops,
+  // four loads in flight per thread
   const double hlast = (mu > 0 && !brk) ? H[(long long)(mu - 1) * m1 + mu] : 0.0;
-  for (int c = wave_id(); c < mu; c += LBLOCK / 64)
-    for (int r = tid & 63; r < mu; r += 64) {
-      double v = H[(long long)c * m1 + r];
-      if (c == mu - 1) v += hlast * z[r];
-      Hh[r + (long long)c * mu] = v;
-    }
+  const int mu2 = mu * mu;
+#pragma unroll 4
+  for (int x = tid; x < mu2; x += LBLOCK) {
+    const int r = x % mu, c = x / mu;
+    double v = H[(long long)c * m1 + r];
+    if (c == mu - 1) v += hlast * z[r];
+    Hh[x] = v;
+  }
   // R_m for the estimates (ld m_used)
   double* Rg = ws + g.oR;
-  if (do_ls)
-    for (int c = wave_id(); c < mu; c += LBLOCK / 64)
-      for (int r = tid & 63; r < mu; r += 64) Rg[r + (long long)c * mu] = r <= c ? Rm[r + (long long)c * ldr] : 0.0;
+  if (do_ls) {
+    if (in_regs) {
+#pragma unroll 4
+      for (int x = tid; x < mu2; x += LBLOCK) {
+        const int r = x % mu, c = x / mu;
+        Rg[x] = r <= c ? Rl[r + (long long)c * ldr] : 0.0;
+      }
+    } else {
+#pragma unroll 4
+      for (int x = tid; x < mu2; x += LBLOCK) {
+        const int r = x % mu, c = x / mu;
+        Rg[x] = r <= c ? Rm[r + (long long)c * ldr] : 0.0;
+      }
+    }
+  }
   if (g.nvar == 3) {
     // variant 1: H_m (no least-squares correction); variant 2: the
     // compression at order md = m_used - max(5, m_used/10)
@@ -399,28 +428,28 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
     double* H2 = Hh + 2 * mmf;
     int md = mu - (mu / 10 > 5 ? mu / 10 : 5);
     if (md < 1) md = 0;
-    for (int c = wave_id(); c < mu; c += LBLOCK / 64)
-      for (int r = tid & 63; r < mu; r += 64) H1[r + (long long)c * mu] = H[(long long)c * m1 + r];
+#pragma unroll 4
+    for (int x = tid; x < mu2; x += LBLOCK) H1[x] = H[(long long)(x / mu) * m1 + x % mu];
     double* z2 = z + m1 + (in_regs ? (long long)m1 * m1 : 0);
     if (md >= 1) {
       if (do_ls) {
         if (tid < 64) {
           // y' = R_md^{-1} R[0:md, md]: the sketched LS solution at order md
-          if (md <= 128) wave_upper_solve<2>(md, Rm, ldr, Rm + (long long)md * ldr, z2);
-          else if (md <= 256) wave_upper_solve<4>(md, Rm, ldr, Rm + (long long)md * ldr, z2);
-          else wave_upper_solve<8>(md, Rm, ldr, Rm + (long long)md * ldr, z2);
+          if (in_regs) lsq_upper_solve(md, (const double*)Rl, ldr, (const double*)Rl + (long long)md * ldr, z2);
+          else lsq_upper_solve(md, Rm, ldr, Rm + (long long)md * ldr, z2);
         }
       } else {
         for (int x = tid; x < md; x += LBLOCK) z2[x] = 0.0;
       }
       __syncthreads();
       const double hl2 = brk ? 0.0 : H[(long long)(md - 1) * m1 + md];
-      for (int c = wave_id(); c < md; c += LBLOCK / 64)
-        for (int r = tid & 63; r < md; r += 64) {
-          double v = H[(long long)c * m1 + r];
-          if (c == md - 1) v += hl2 * z2[r];
-          H2[r + (long long)c * md] = v;
-        }
+#pragma unroll 4
+      for (int x = tid; x < md * md; x += LBLOCK) {
+        const int r = x % md, c = x / md;
+        double v = H[(long long)c * m1 + r];
+        if (c == md - 1) v += hl2 * z2[r];
+        H2[x] = v;
+      }
     }
     if (tid == 0) info[INFO_MD] = md;
   }
