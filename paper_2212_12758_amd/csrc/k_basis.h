@@ -813,22 +813,40 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
 
 // ------------------------------------------------------------------ combine
 // out = sum_j cf_j u_j with cf_j = beta c_j / eta_j (FP64 accumulation).
-template <typename T>
+// Full chunks issue four basis-vector loads at a time; with one right-hand
+// side (NR1) the weights are uniform values.
+template <typename T, bool NR1>
 __global__ void __launch_bounds__(256) k_combine(SolveDev d, const double* __restrict__ cf, int mmax,
                                                  double* __restrict__ out) {
   const T* __restrict__ V = (const T*)d.V;
   const long long nel = (long long)d.n * d.nrhs;
   const int nr = d.nrhs;
+  const long long cld = d.m + 1;
   for (long long e = ((long long)blockIdx.x * 256 + threadIdx.x) * EPT; e < nel;
        e += (long long)gridDim.x * 256 * EPT) {
+    long long cb[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) cb[j] = NR1 ? 0 : (long long)((e + j) & (nr - 1)) * cld;
     double a[EPT];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) a[j] = 0.0;
-    for (int jv = 0; jv < mmax; ++jv) {
+    int jv = 0;
+    if (e + EPT <= nel) {
+      for (; jv + 4 <= mmax; jv += 4) {
+        double v[4][EPT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) load8(V + (long long)(jv + u) * d.ldv + e, v[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int j = 0; j < EPT; ++j) a[j] += cf[cb[j] + jv + u] * v[u][j];
+      }
+    }
+    for (; jv < mmax; ++jv) {
       double v[EPT];
       get8(V + (long long)jv * d.ldv, e, nel, v);
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) a[j] += cf[(long long)((e + j) & (nr - 1)) * (d.m + 1) + jv] * v[j];
+      for (int j = 0; j < EPT; ++j) a[j] += cf[cb[j] + jv] * v[j];
     }
     if (e + EPT <= nel) {
 #pragma unroll

@@ -54,8 +54,14 @@ hipError_t basis_combine(const SolveDev& d, int esize, const double* cf, int mma
   const long long nel = (long long)d.n * d.nrhs;
   long long g = (nel + 256 * EPT - 1) / (256 * EPT);
   if (g > 4096) g = 4096;
-  if (esize == 4) hipLaunchKernelGGL(k_combine<float>, dim3((unsigned)g), dim3(256), 0, st, d, cf, mmax, out);
-  else hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)g), dim3(256), 0, st, d, cf, mmax, out);
+  const bool nr1 = d.nrhs == 1;
+  if (esize == 4) {
+    if (nr1) hipLaunchKernelGGL((k_combine<float, true>), dim3((unsigned)g), dim3(256), 0, st, d, cf, mmax, out);
+    else hipLaunchKernelGGL((k_combine<float, false>), dim3((unsigned)g), dim3(256), 0, st, d, cf, mmax, out);
+  } else {
+    if (nr1) hipLaunchKernelGGL((k_combine<double, true>), dim3((unsigned)g), dim3(256), 0, st, d, cf, mmax, out);
+    else hipLaunchKernelGGL((k_combine<double, false>), dim3((unsigned)g), dim3(256), 0, st, d, cf, mmax, out);
+  }
   return hipGetLastError();
 }
 
