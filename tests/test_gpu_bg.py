@@ -227,3 +227,38 @@ def test_bg_invalid_basis(ctx):
         ctx.solve(A, b, f, make_params(20, 2, 60, "srht", 8, 1, "fp64", "lsqr", basis=4))
     assert e.value.code == EINVAL
     A.destroy()
+
+
+# ------------------------------------------------------------------ beyond the LDS / register sizes
+def test_bg2_large_m_global_paths(ctx):
+    """m = 150, s = 320: the sketch columns exceed the LDS of the Gram-Schmidt
+    step, R_m the LDS of the LSQR step (m > 140), H_hat the LDS of the
+    quadrature square root (m > 128, four rows per lane) and the registers of
+    the sketched QR (Householder in global memory): every global-memory
+    variant, against the oracle's Algorithm 3 and Arnoldi's f_m; also the
+    truncated basis with sketch-and-solve on the same problem."""
+    from paper_2212_12758_amd import make_params
+
+    st = W.laplacian3d(24)
+    b = W.rhs(st.n, 8)
+    f = W.FuncSpec("pow", sigma=0.0, p=-0.5)
+    m, s = 150, 320
+    w = W.Workload("lap3d24", st, 8, 1, f, m=m, k=2, s=s, sketch="srht", sketch_seed=8)
+    Aor = operators.as_matrix(st)
+    sk = _sk(w)
+    ref = krylov.sgs(Aor, b, f, m, sk, passes=2)
+    fm = krylov.fm(Aor, b, f, m)
+    A = ctx.matrix(st)
+    print("case bg2 lap3d24 m=150 fp64", flush=True)
+    out, info, dg = ctx.solve(A, _dev(b), f, _p(w, "fp64", basis="sketched_gs2"), diag=True)
+    out = out.cpu().numpy()
+    assert info[0]["m_used"] == m and info[0]["ls_iters"] >= 1
+    SV = dg["sv"]
+    assert np.abs(SV.T @ SV - np.eye(m + 1)).max() < 1e-12
+    assert krylov.relerr(out, ref["f"]) < 1e-8
+    assert krylov.relerr(out, fm) < 1e-8
+    print("case truncated lap3d24 m=150 fp64", flush=True)
+    out_t, _ = ctx.solve(A, _dev(b), f, make_params(m, 2, s, "srht", 8, 8, "fp64", "sketch"))
+    ref_t = krylov.nt(Aor, b, f, m, 2, sk, "sketch")["f"]
+    assert krylov.relerr(out_t.cpu().numpy(), ref_t) < 1e-8
+    A.destroy()
