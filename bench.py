@@ -208,7 +208,7 @@ def main():
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the solve is not sharded "
-                                   "across GPUs (see DESIGN.md for how it would shard)", "n_gpus": args.gpus}))
+                                   "across GPUs; N > 1 is not supported", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
