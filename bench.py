@@ -191,7 +191,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-basis comparison run")
     ap.add_argument("--prec", default="auto", choices=["auto", "fp32", "fp64"],
                     help="basis precision policy (auto: FP32 + estimates + FP64 fallback)")
-    ap.add_argument("--ls", default="auto", choices=["auto", "sketch", "none", "lsqr"],
+    ap.add_argument("--ls", default="auto", choices=["auto", "sketch", "none", "lsqr", "gram"],
                     help="least-squares policy (auto: sketch-and-solve + gate + LSQR refinement)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (counter calibration)")

@@ -92,8 +92,15 @@ enum fab_ls_mode {
   FAB_LS_AUTO = 0,            /* sketch-and-solve, then LSQR refinement if the gate fails  */
   FAB_LS_SKETCH = 1,          /* sketch-and-solve only (Remark 3; equivalent to sFOM)      */
   FAB_LS_NONE = 2,            /* y = 0: Algorithm 5                                        */
-  FAB_LS_LSQR = 3             /* always refine with sketch-preconditioned LSQR (Algorithm 4
+  FAB_LS_LSQR = 3,            /* always refine with sketch-preconditioned LSQR (Algorithm 4
                                  with Blendenpik, Section 3.1.1)                            */
+  FAB_LS_GRAM = 4             /* the exact least squares through the Gram matrix of
+                                 V_{m+1} (one pass over the basis, Cholesky of the normal
+                                 equations; error ~ kappa(V)^2 u, for the well-conditioned
+                                 sketched-GS and whitened bases).  Blocking calls with one
+                                 right-hand side and m <= 127; otherwise, or when R's
+                                 diagonal spreads by more than 1e4 or a pivot fails, LSQR
+                                 as FAB_LS_LSQR.  Not in the paper, which uses LSQR.        */
 };
 
 /* Construction of the basis. */

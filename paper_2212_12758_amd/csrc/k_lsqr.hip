@@ -363,6 +363,165 @@ __global__ void __launch_bounds__(256) k_lsqr_finish(SolveDev d, DenseDev g, Lsq
     }
 }
 
+// ------------------------------------------------------------------ exact least squares from the Gram matrix
+// For a well-conditioned basis (sketched Gram-Schmidt, whitened) the least
+// squares of eq. (7) are solved exactly through the normal equations: one
+// pass over the stored vectors forms G = U^T U (FP64 accumulation, one right-
+// hand side, m + 1 <= GR_MAXC), then with D = diag(eta), G~ = D^{-1} G D^{-1},
+// G~_m = R^T R (Cholesky) and R^T R y = G~[:m, m].  The error is about
+// kappa(V)^2 u; the factorisation reports failure (the caller then runs LSQR)
+// on a non-positive pivot or a diagonal spread of R above GR_MAXRATIO.
+constexpr int GR_TILE = 16, GR_T = 8, GR_MAXC = GR_T * GR_TILE;   // m + 1 <= 128
+constexpr int GR_NT = GR_T * (GR_T + 1) / 2;                      // upper 16 x 16 tiles
+constexpr int GR_RCH = 32;                                          // rows per staged chunk
+constexpr int GR_BLOCKS = 240;
+constexpr double GR_MAXRATIO = 1e4;
+
+// Per-block partial sums of the upper tiles of U^T U: part[blk][tile][entry].
+template <typename T>
+__global__ void __launch_bounds__(256) k_vgram(SolveDev d, double* __restrict__ part) {
+  __shared__ double ul[GR_RCH][GR_MAXC + 1];
+  const int tid = threadIdx.x, a0 = tid & (GR_TILE - 1), b0 = tid >> 4;
+  const int m1 = d.m + 1;
+  const long long n = d.n;
+  const T* __restrict__ V = (const T*)d.V;
+  double acc[GR_NT];
+#pragma unroll
+  for (int t = 0; t < GR_NT; ++t) acc[t] = 0.0;
+  for (long long r0 = (long long)blockIdx.x * GR_RCH; r0 < n; r0 += (long long)gridDim.x * GR_RCH) {
+    // stage rows r0 .. r0+31 of every column (column-contiguous loads), 16 in flight
+    double t16[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int x = tid + 256 * u, c = x >> 5, rr = x & 31;
+      const long long r = r0 + rr;
+      t16[u] = (c < m1 && r < n) ? (double)V[(long long)c * d.ldv + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int x = tid + 256 * u;
+      ul[x & 31][x >> 5] = t16[u];
+    }
+    __syncthreads();
+    for (int rr = 0; rr < GR_RCH; ++rr) {
+      double xa[GR_T], xb[GR_T];
+#pragma unroll
+      for (int t = 0; t < GR_T; ++t) {
+        xa[t] = ul[rr][GR_TILE * t + a0];
+        xb[t] = ul[rr][GR_TILE * t + b0];
+      }
+      int idx = 0;
+#pragma unroll
+      for (int ti = 0; ti < GR_T; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < GR_T; ++tj) acc[idx++] += xa[ti] * xb[tj];
+    }
+    __syncthreads();
+  }
+  double* out = part + (long long)blockIdx.x * GR_NT * 256;
+#pragma unroll
+  for (int t = 0; t < GR_NT; ++t) out[t * 256 + tid] = acc[t];
+}
+
+// Fixed-order sum over the blocks, scaled to G~ = D^{-1} G D^{-1}; G~ (ld m1,
+// upper triangle) goes to the rhs's scratch region.  One workgroup per tile.
+__global__ void __launch_bounds__(256) k_vgram_reduce(SolveDev d, DenseDev g, const double* __restrict__ part,
+                                                      int nb) {
+  const int t = blockIdx.x, tid = threadIdx.x, a0 = tid & (GR_TILE - 1), b0 = tid >> 4;
+  int ti = 0, tj = 0, idx = 0;
+  for (int i = 0; i < GR_T; ++i)
+    for (int j = i; j < GR_T; ++j) {
+      if (idx == t) { ti = i; tj = j; }
+      ++idx;
+    }
+  const int a = GR_TILE * ti + a0, b = GR_TILE * tj + b0;
+  const int m1 = d.m + 1;
+  double s = 0.0;
+  int blk = 0;
+  for (; blk + 8 <= nb; blk += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[((long long)(blk + u) * GR_NT + t) * 256 + tid];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; blk < nb; ++blk) s += part[((long long)blk * GR_NT + t) * 256 + tid];
+  if (a < m1 && b < m1 && a <= b) {
+    const double ea = d.eta[a], eb = d.eta[b];
+    g.base[g.oM + a + (long long)b * m1] = (ea > 0.0 && eb > 0.0) ? s / (ea * eb) : 0.0;
+  }
+}
+
+// Cholesky of G~_m, y from the normal equations, H_hat; *fail = 1 when the
+// factorisation is not usable (the caller then refines by LSQR instead).
+__global__ void __launch_bounds__(512) k_vgram_solve(SolveDev d, DenseDev g, int* fail) {
+  extern __shared__ double R[];   // mu x mu, ld mu
+  __shared__ double rhs[GR_MAXC], y[GR_MAXC];
+  const int tid = threadIdx.x;
+  const int m = d.m, m1 = m + 1;
+  double* ws = g.base;
+  const double* G = ws + g.oM;
+  const int mu = d.status[4];
+  const int brk = d.status[5];
+  double* info = ws + g.oInfo;
+  if (tid == 0) {
+    *fail = 0;
+    info[INFO_LSQR_IT] = 0.0;
+    info[INFO_LSQR_RATIO] = 0.0;
+  }
+  if (brk || mu == 0 || g.ls_mode == 2) return;
+  for (int x = tid; x < mu * mu; x += 512) {
+    const int i = x % mu, j = x / mu;
+    R[x] = i <= j ? G[i + (long long)j * m1] : 0.0;
+  }
+  for (int i = tid; i < mu; i += 512) rhs[i] = G[i + (long long)mu * m1];
+  __syncthreads();
+  double rmax = 0.0, rmin = 1e308, dprev = 1.0;
+  for (int k = 0; k < mu; ++k) {
+    const double dkk = R[k + k * mu];
+    if (!(dkk > 0.0) || !isfinite(dkk)) {
+      if (tid == 0) *fail = 1;
+      return;
+    }
+    const double rkk = sqrt(dkk);
+    rmax = fmax(rmax, rkk);
+    rmin = fmin(rmin, rkk);
+    const double inv = 1.0 / dkk;
+    for (int j = k + 1 + wave_id(); j < mu; j += 8) {
+      const double f = R[k + j * mu] * inv;
+      for (int i = k + 1 + (tid & 63); i <= j; i += 64) R[i + j * mu] -= R[k + i * mu] * f;
+    }
+    if (k >= 1) {
+      const double rp = sqrt(dprev);
+      for (int j = k - 1 + tid; j < mu; j += 512) R[k - 1 + j * mu] /= rp;
+    }
+    dprev = dkk;
+    __syncthreads();
+  }
+  if (tid == 0) R[mu - 1 + (mu - 1) * mu] = sqrt(dprev);
+  __syncthreads();
+  if (!(rmax <= GR_MAXRATIO * rmin)) {
+    if (tid == 0) *fail = 1;
+    return;
+  }
+  if (tid < 64) {
+    upper_t_solve_any(mu, (const double*)R, mu, rhs, y);   // R^T w = G~[:m, m]
+    upper_solve_any(mu, (const double*)R, mu, y, y);       // R y = w
+  }
+  __syncthreads();
+  double* yout = ws + g.oVec + 2 * (long long)m;
+  for (int j = tid; j < mu; j += 512) yout[j] = y[j];
+  const double* H = d.H;
+  const double hlast = H[(long long)(mu - 1) * m1 + mu];
+  double* Hh = ws + g.oH;
+  for (int x = tid; x < mu * mu; x += 512) {
+    const int r = x % mu, c = x / mu;
+    double val = H[(long long)c * m1 + r];
+    if (c == mu - 1) val += hlast * y[r];
+    Hh[x] = val;
+  }
+}
+
 namespace {
 template <typename T>
 void pass_launch_t(const SolveDev& d, const LsqrDev& L, hipStream_t st, int first, size_t lds) {
@@ -414,12 +573,28 @@ hipError_t lsqr_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, i
   return e;
 }
 
+bool gram_ls_supported(const SolveDev& d) { return d.nrhs == 1 && d.m + 1 <= GR_MAXC; }
+size_t gram_ls_partial_doubles() { return (size_t)GR_BLOCKS * GR_NT * 256; }
+
+// The exact least-squares solve from the Gram matrix (one right-hand side).
+hipError_t gram_ls_launch(const SolveDev& d, const DenseDev& g, double* part, int* fail, int esize,
+                          hipStream_t st) {
+  if (!gram_ls_supported(d)) return hipErrorInvalidValue;
+  if (esize == 4) hipLaunchKernelGGL(k_vgram<float>, dim3(GR_BLOCKS), dim3(256), 0, st, d, part);
+  else hipLaunchKernelGGL(k_vgram<double>, dim3(GR_BLOCKS), dim3(256), 0, st, d, part);
+  hipLaunchKernelGGL(k_vgram_reduce, dim3(GR_NT), dim3(256), 0, st, d, g, (const double*)part, GR_BLOCKS);
+  hipLaunchKernelGGL(k_vgram_solve, dim3(1), dim3(512), (size_t)d.m * d.m * 8, st, d, g, fail);
+  return hipGetLastError();
+}
+
 hipError_t lsqr_set_attributes() {
   hipError_t e = hipSuccess, r;
   const void* passes[4] = {(const void*)k_lsqr_pass<float, true>, (const void*)k_lsqr_pass<float, false>,
                            (const void*)k_lsqr_pass<double, true>, (const void*)k_lsqr_pass<double, false>};
   for (const void* k : passes)
     if ((r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024)) != hipSuccess) e = r;
+  if ((r = hipFuncSetAttribute((const void*)k_vgram_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               GR_MAXC * GR_MAXC * 8)) != hipSuccess) e = r;
   if ((r = hipFuncSetAttribute((const void*)k_lsqr_step<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lsqr_step_lds(STEP_LDS_M))) != hipSuccess) e = r;
   return e;

@@ -55,6 +55,9 @@ hipError_t lsqr_begin(const SolveDev& d, const DenseDev& g, const LsqrDev& L, in
 hipError_t lsqr_iterate(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st,
                         int count);
 hipError_t lsqr_end(const SolveDev& d, const DenseDev& g, const LsqrDev& L, hipStream_t st);
+bool gram_ls_supported(const SolveDev& d);
+size_t gram_ls_partial_doubles();
+hipError_t gram_ls_launch(const SolveDev& d, const DenseDev& g, double* part, int* fail, int esize, hipStream_t st);
 hipError_t lsqr_set_attributes();
 hipError_t bg_apply(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds);
 hipError_t bg_reduce(const SolveDev& d, int col, hipStream_t st);
@@ -186,6 +189,9 @@ struct Plan {
   fab_matrix Aorig = nullptr;  // A itself (the operator of the start vector A b)
   fab_func forig{};            // the caller's f (kind FAB_F_SIGN)
   size_t oSignB = 0;           // A b, FP64 [n][nrhs]
+  bool gram = false;           // FAB_LS_GRAM with one rhs and m + 1 <= 128: exact least squares
+  bool gram_used = false;      // the last refinement solved through the Gram matrix
+  size_t oGpart = 0, oGflag = 0;
   size_t oWflag = 0;           // whitening trigger flag
   int lnblk = 0;               // LSQR pass blocks
   size_t oLu = 0, oLpart = 0, oLst = 0, oLflag = 0;
@@ -236,7 +242,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
   const long long npad = 1LL << ilog2(n);
   if (p.s <= p.m || p.s > 8192 || p.s > npad) return FAB_EINVAL;
   if (p.sketch == FAB_SKETCH_SPARSE_SIGN && (p.zeta < 1 || p.zeta > ZMAX || p.zeta > p.s)) return FAB_EINVAL;
-  if (p.ls_mode < FAB_LS_AUTO || p.ls_mode > FAB_LS_LSQR) return FAB_EINVAL;
+  if (p.ls_mode < FAB_LS_AUTO || p.ls_mode > FAB_LS_GRAM) return FAB_EINVAL;
   if (f.kind == FAB_F_POW) {
     if (!(f.p == 0.5 || f.p == -0.5)) return FAB_EINVAL;
   } else if (f.kind == FAB_F_POLY) {
@@ -301,11 +307,11 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
   if (f.kind == FAB_F_POW) P.oFq = take(fsqrt_partials_doubles(m, nrhs) * 8);
   if (sign) P.oSignB = take((size_t)n * nrhs * 8);
   // LSQR refinement (FAB_LS_AUTO when the gate fails, FAB_LS_LSQR always)
-  if (p.ls_mode == FAB_LS_AUTO || p.ls_mode == FAB_LS_LSQR) {
+  if (p.ls_mode == FAB_LS_AUTO || p.ls_mode == FAB_LS_LSQR || p.ls_mode == FAB_LS_GRAM) {
     const bool fits = lsqr_pass_lds(m, nrhs) <= 120 * 1024;
     // Algorithm 3 needs the refinement: the sketched problem is trivial for
     // a sketch-orthonormal basis
-    if (!fits && (p.ls_mode == FAB_LS_LSQR || bg || whiten)) return FAB_EINVAL;
+    if (!fits && (p.ls_mode == FAB_LS_LSQR || p.ls_mode == FAB_LS_GRAM || bg || whiten)) return FAB_EINVAL;
     if (fits) {
       P.lsqr = true;
       P.lnblk = (int)std::min<long long>((nel + 2047) / 2048, 512);
@@ -314,6 +320,11 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
       P.oLst = take((size_t)nrhs * lsqr_state_stride(m) * 8);
       P.oLflag = take(256);
     }
+  }
+  P.gram = p.ls_mode == FAB_LS_GRAM && nrhs == 1 && m + 1 <= 128;
+  if (P.gram) {
+    P.oGpart = take(gram_ls_partial_doubles() * 8);
+    P.oGflag = take(256);
   }
   P.bytes = w;
   return FAB_OK;
@@ -682,7 +693,9 @@ int collect_info(const Plan& P, const double* hinfo, std::vector<fab_info>& out)
     }
     fi.ls_iters = (int)in[INFO_LSQR_IT];
     // refined: the least-squares part of the error is the last LSQR step
+    // (zero after the exact solve through the Gram matrix)
     if (fi.ls_iters > 0) fi.err_est = std::max(in[INFO_LSQR_RATIO], fi.round_est);
+    if (P.gram_used) fi.err_est = fi.round_est;
     fi.fell_back = 0;
     fi.whitened_at = P.whitened_at;
     if (in[3] != 0.0) rc = FAB_ENUMERIC;
@@ -715,7 +728,21 @@ int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* h
   L.maxit = P.p.ls_maxit > 0 ? P.p.ls_maxit : ((P.bg || P.whitened_at) ? 128 : 32);
   L.tol = P.p.tol / 10;
   if (zero_fill(ws + P.oLflag, 256, st) != hipSuccess) return FAB_EDEVICE;
-  if (!host_flag) {
+  // FAB_LS_GRAM (blocking calls): the exact solve through the Gram matrix;
+  // LSQR below when its factorisation is not usable
+  P.gram_used = false;
+  if (P.gram && host_flag) {
+    int* gflag = (int*)(ws + P.oGflag);
+    if (gram_ls_launch(d, g, (double*)(ws + P.oGpart), gflag, P.esize, st) != hipSuccess) return FAB_EDEVICE;
+    *host_flag = 1;
+    if (hipMemcpyAsync(host_flag, gflag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return FAB_EDEVICE;
+    P.gram_used = *host_flag == 0;
+  }
+  if (P.gram_used) {
+    // y and H_hat are in place; nothing to iterate
+  } else if (!host_flag) {
     if (lsqr_launch(d, g, L, P.esize, st) != hipSuccess) return FAB_EDEVICE;
   } else {
     constexpr int CHUNK = 16;
@@ -746,7 +773,7 @@ int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* h
 
 bool needs_refine(const Plan& P, int rc, const std::vector<fab_info>& fi) {
   if (rc != FAB_OK || !P.lsqr) return false;
-  if (P.p.ls_mode == FAB_LS_LSQR || P.bg || P.whitened_at) return true;
+  if (P.p.ls_mode == FAB_LS_LSQR || P.p.ls_mode == FAB_LS_GRAM || P.bg || P.whitened_at) return true;
   for (const auto& x : fi)
     if (!x.breakdown && !(x.ls_gate <= P.p.tol / 10)) return true;
   return false;

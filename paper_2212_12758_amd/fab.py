@@ -17,7 +17,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EBUSY, ENOTFOUND = range(7)
 F_EXP, F_POW, F_POLY, F_SIGN = 1, 2, 3, 4
 SKETCH_SRHT, SKETCH_SPARSE_SIGN = 1, 2
 PREC_FP32, PREC_FP64, PREC_AUTO = 1, 2, 3
-LS_AUTO, LS_SKETCH, LS_NONE, LS_LSQR = 0, 1, 2, 3
+LS_AUTO, LS_SKETCH, LS_NONE, LS_LSQR, LS_GRAM = 0, 1, 2, 3, 4
 BASIS_TRUNCATED, BASIS_SKETCHED_GS, BASIS_SKETCHED_GS2, BASIS_WHITENED = 0, 1, 2, 3
 
 
@@ -107,7 +107,7 @@ def make_params(m, k, s, sketch="srht", zeta=8, seed=0, prec="fp32", ls_mode="sk
                 basis="truncated", ls_maxit=0) -> fab_params:
     sk = {"srht": SKETCH_SRHT, "sparse_sign": SKETCH_SPARSE_SIGN}[sketch] if isinstance(sketch, str) else sketch
     pr = {"fp32": PREC_FP32, "fp64": PREC_FP64, "auto": PREC_AUTO}[prec] if isinstance(prec, str) else prec
-    ls = {"auto": LS_AUTO, "sketch": LS_SKETCH, "none": LS_NONE, "lsqr": LS_LSQR}[ls_mode] \
+    ls = {"auto": LS_AUTO, "sketch": LS_SKETCH, "none": LS_NONE, "lsqr": LS_LSQR, "gram": LS_GRAM}[ls_mode] \
         if isinstance(ls_mode, str) else ls_mode
     bs = {"truncated": BASIS_TRUNCATED, "sketched_gs": BASIS_SKETCHED_GS,
           "sketched_gs2": BASIS_SKETCHED_GS2, "whitened": BASIS_WHITENED}[basis] \

@@ -262,3 +262,41 @@ def test_bg2_large_m_global_paths(ctx):
     ref_t = krylov.nt(Aor, b, f, m, 2, sk, "sketch")["f"]
     assert krylov.relerr(out_t.cpu().numpy(), ref_t) < 1e-8
     A.destroy()
+
+
+# ------------------------------------------------------------------ exact least squares through the Gram matrix
+def test_gram_least_squares_exact_and_fallback(ctx):
+    """FAB_LS_GRAM: with the two-pass sketched basis the normal equations give
+    the exact least-squares solution of Algorithm 3 (oracle: dense lstsq) with
+    no LSQR iteration; on the truncated basis of a graph Laplacian, whose
+    conditioning is lost, the factorisation is refused and the result is the
+    LSQR one, bit for bit."""
+    from paper_2212_12758_amd import make_params
+
+    st = W.laplacian3d(16)
+    b = W.rhs(st.n, 4)
+    m, s = 60, 63
+    f = W.FuncSpec("pow", sigma=0.0, p=-0.5)
+    w = W.Workload("lap3d16", st, 4, 1, f, m=m, k=2, s=s, sketch="srht", sketch_seed=5)
+    Aor = operators.as_matrix(st)
+    ref = krylov.sgs(Aor, b, f, m, _sk(w), passes=2)
+    A = ctx.matrix(st)
+    print("case gram bg2 lap3d16", flush=True)
+    out, info = ctx.solve(A, _dev(b), f, _p(w, "fp64", ls="gram", basis="sketched_gs2"))
+    assert info[0]["ls_iters"] == 0
+    assert krylov.relerr(out.cpu().numpy(), ref["f"]) < 1e-11
+    assert krylov.relerr(out.cpu().numpy(), krylov.fm(Aor, b, f, m)) < 1e-11
+    A.destroy()
+    n, m = 4096, 120
+    op = W.rgg_laplacian(n, seed=3)
+    fr = W.FuncSpec("pow", sigma=1e-3, p=-0.5)
+    br = W.rhs(n, 3)
+    A = ctx.matrix(op)
+    print("case gram fallback rgg4096", flush=True)
+    pg = make_params(m, 2, 2 * m, "sparse_sign", 8, 3, "fp64", "gram", 1e-10)
+    pl = make_params(m, 2, 2 * m, "sparse_sign", 8, 3, "fp64", "lsqr", 1e-10)
+    og, ig = ctx.solve(A, _dev(br), fr, pg)
+    ol, il = ctx.solve(A, _dev(br), fr, pl)
+    assert ig[0]["ls_iters"] >= 1 and ig[0]["ls_iters"] == il[0]["ls_iters"]
+    assert np.array_equal(og.cpu().numpy(), ol.cpu().numpy())
+    A.destroy()
