@@ -27,6 +27,11 @@ Gram-Schmidt step on the sketch runs twice (--basis sketched_gs2): with so
 few sketch rows one pass leaves Theta V far from orthonormal.  Its dominant
 kernel is the update u_i = w - V_{i-1} r_i, its oracle Algorithm 3 with the
 exact least-squares solution; it also reports the error against Arnoldi's f_m.
+--workload rgg_2p20_invsqrt times the whitened basis (Section 2.1.2) on a
+random geometric graph Laplacian with 2^20 nodes, (A + 1e-3 I)^{-1/2}, m = 150,
+where the truncated basis alone loses its conditioning; --workload
+convdiff2d_352_exp the variable-coefficient convection-diffusion of
+Section 5.1.1 (CSR, exp).
 """
 import argparse
 import json
@@ -56,6 +61,29 @@ def algorithmic_bytes_bg(n, nrhs, m, esize, lsqr_iters):
     combine = m * vec + n * nrhs * 8
     return {"dots_per_launch": apply_ / m, "update_per_launch": update / m,
             "solve": apply_ + update + start + lsqr + combine}
+
+
+def algorithmic_bytes_whitened(n, m, k, esize, nnz, wat, lsqr_iters):
+    """Bytes per solve and per kernel class for the whitened basis on a CSR
+    operator (one rhs): truncated steps 1..wat (the last one is discarded by
+    the whitening), the in-place transform of wat vectors, Algorithm 1 steps
+    wat..m; CSR arrays (8 B per nonzero + 4 B per row) and the FP64 product
+    (written by the first pass of a step, read by the second) per step."""
+    vec = n * esize
+    csr = 8 * nnz + 4 * (n + 1)
+    wb = 8 * n
+    wat = wat if wat > 0 else m + 1
+    nt_steps = range(1, min(wat, m) + 1)
+    bg_steps = range(wat, m + 1) if wat <= m else range(0)
+    dots = sum(min(i, k) * vec + csr + wb for i in nt_steps) + sum(vec + csr + wb for i in bg_steps)
+    update = sum(min(i, k) * vec + wb + vec for i in nt_steps) + sum(i * vec + wb + vec for i in bg_steps)
+    nupd = len(nt_steps) + len(bg_steps)
+    whiten = 2 * wat * vec if wat <= m else 0
+    start = 8 * n + vec
+    lsqr = lsqr_iters * (2 * m * vec + 48 * n)
+    combine = m * vec + 8 * n
+    return {"dots_per_launch": dots / max(1, nupd), "update_per_launch": update / max(1, nupd),
+            "solve": dots + update + whiten + start + lsqr + combine}
 
 
 def algorithmic_bytes(n, nrhs, m, k, esize, nnz=None):
@@ -102,6 +130,14 @@ BENCH = {
         "traffic_file": os.path.join(ROOT, "profiles", "traffic_k_update_convdiff2d_352_exp.json"),
         "sources": [CSRC + "k_basis.h", CSRC + "k_basis_part.inc", CSRC + "fab_dev.h"],
         "operator": "2D variable-coefficient convection-diffusion 352^2 (Section 5.1.1), CSR", "f": "exp(-t A)",
+    },
+    "rgg_2p20_invsqrt": {
+        "basis": "whitened",
+        "kernel": "update passes (k_update of the truncated steps, then k_bg_update after whitening), CSR",
+        "pmc_kernel": "k_update<float, 1, 1, false, 11, 1, 2>",
+        "traffic_file": os.path.join(ROOT, "profiles", "traffic_k_update_rgg_2p20_invsqrt.json"),
+        "sources": [CSRC + "k_basis.h", CSRC + "k_basis_part.inc", CSRC + "fab_dev.h"],
+        "operator": "random geometric graph Laplacian, 2^20 nodes, mean degree ~10, CSR", "f": "(A + 1e-3 I)^{-1/2}",
     },
     "lap3d_80_invsqrt": {
         "basis": "sketched_gs2",
@@ -197,7 +233,7 @@ def main():
                     help="first run one 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no GPU: turn two rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE outputs into the traffic summary")
-    ap.add_argument("--basis", default=None, choices=["truncated", "sketched_gs", "sketched_gs2"],
+    ap.add_argument("--basis", default=None, choices=["truncated", "sketched_gs", "sketched_gs2", "whitened"],
                     help="basis construction (default: the workload's)")
     ap.add_argument("--workload", default="convdiff3d_128_exp", choices=sorted(BENCH),
                     help="convdiff3d_128_exp (headline, truncated basis) or lap3d_80_invsqrt (sketched "
@@ -219,7 +255,8 @@ def main():
 
     cfg = BENCH[args.workload]
     basis = args.basis or cfg["basis"]
-    bg = basis != "truncated"
+    bg = basis in ("sketched_gs", "sketched_gs2")
+    whitened = basis == "whitened"
     w = W.config(args.workload)
     n = w.n
     b = W.rhs(n, w.b_seed) if w.b_seed >= 0 else None
@@ -257,6 +294,9 @@ def main():
     esize = 8 if info[0]["prec_used"] == 2 else 4
     if bg:
         ab32 = algorithmic_bytes_bg(n, 1, w.m, esize, info[0]["ls_iters"])
+    elif whitened:
+        ab32 = algorithmic_bytes_whitened(n, w.m, w.k, esize, len(w.op[1]), info[0]["whitened_at"],
+                                          info[0]["ls_iters"])
     else:
         ab32 = algorithmic_bytes(n, 1, w.m, w.k, esize, None if hasattr(w.op, "coeff") else len(w.op[1]))
 
@@ -304,12 +344,16 @@ def main():
             ref = krylov.sgs(Aor, b, w.f, w.m, sk, passes=2 if basis == "sketched_gs2" else 1)["f"]
             what = (f"Algorithm 3 with the exact least squares (FP64, numpy/scipy, "
                     f"{'two' if basis == 'sketched_gs2' else 'one'} Gram-Schmidt pass(es) on the sketch)")
+        elif whitened:
+            sk = osk.Sketch(w.sketch, n, w.s, w.sketch_seed, w.zeta)
+            ref = krylov.whitened(Aor, b, w.f, w.m, w.k, sk)["f"]
+            what = "the truncated basis whitened and continued by Algorithm 1, exact least squares (FP64)"
         else:
             ref = krylov.fm(Aor, b, w.f, w.m)
             what = "f_m by full Arnoldi (FP64, numpy/scipy)"
         tcpu = time.perf_counter() - c0
         relerr = krylov.relerr(res32, ref)
-        if bg:
+        if bg or whitened:
             relerr_fm = krylov.relerr(res32, krylov.fm(Aor, b, w.f, w.m))
         cpu = {"value": 1.0 / tcpu, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
                "sample": f"one full solve of the same workload: {what} at n={n}, m={w.m}, {tcpu:.1f} s"}
@@ -345,8 +389,10 @@ def main():
                      "dots_kernel_GBps": ab32["dots_per_launch"] / (dots_us * 1e-6) / 1e9 if dots_us > 0 else None},
         "cpu_baseline": cpu,
     }
-    if bg:
+    if bg or whitened:
         line["config"]["relerr_vs_arnoldi_fm"] = relerr_fm
+    if whitened:
+        line["config"]["whitened_at"] = info[0]["whitened_at"]
     print(json.dumps(line), flush=True)
     ctx.close()
 
