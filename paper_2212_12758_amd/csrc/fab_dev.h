@@ -61,6 +61,7 @@ struct SolveDev {
   int* status;           // [0] m_used, [1] breakdown, [2] non-finite
   // sketch
   int sketch;            // SketchKind
+  int sk_slices;         // sparse sign: LDS accumulators per block (1, or one per wave)
   const int* srht_rows;  // [s] sampled rows of the padded Hadamard transform
   unsigned long long key_a, key_b;   // SRHT: signs key; sparse: rows key, signs key
   double sk_scale;       // 1/sqrt(s) (SRHT) or 1/sqrt(zeta) (sparse sign)

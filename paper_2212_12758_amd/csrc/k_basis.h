@@ -5,7 +5,8 @@
 // One step i (1 <= i <= m) builds column i-1 of the Hessenberg matrix and the
 // basis vector u_i with two passes over the rows:
 //
-//   k_dots   : w~ = A u_{i-1} (stencil or CSR), window dots d_j = u_j^T w~ for
+//   k_dots   : w~ = A u_{i-1} (stencil; a CSR operator's w~ comes from
+//              the product kernel launched just before), window dots d_j = u_j^T w~ for
 //              j in [max(0,i-k), i-1] and ||w~||^2, written as per-block
 //              partials (a pure streaming pass).
 //   k_update : every streaming block first reduces those partials, in a fixed
@@ -35,6 +36,9 @@
 namespace fab {
 
 constexpr int EPT = 8;   // elements per thread per tile
+
+// y = A x for the CSR operator (k_csr.hip); x is FP32 (esize 4) or FP64.
+hipError_t csr_spmv(const SolveDev& d, const void* x, int esize, double* y, hipStream_t st);
 
 // ------------------------------------------------------------------ 8-element memory helpers
 __device__ inline void load8(const float* __restrict__ p, double* v) {
@@ -247,26 +251,12 @@ __device__ inline long long stencil_reach(const SolveDev& d) {
   return r > d.nrhs ? r : d.nrhs;
 }
 
+// w~ = A u for 8 elements of the stencil operator (a CSR operator is applied
+// by csr_spmv as a pass of its own).
 template <typename T>
-__device__ inline double csr_apply(const SolveDev& d, const T* __restrict__ u, int r, int q) {
-  const int p0 = d.rowptr[r], p1 = d.rowptr[r + 1];
-  double w = 0.0;
-  for (int p = p0; p < p1; ++p) w += (double)d.val[p] * (double)u[(long long)d.col[p] * d.nrhs + q];
-  return w;
-}
-
-template <typename T, int OP>
 __device__ inline void apply8(const SolveDev& d, const T* __restrict__ src, long long e, long long nel,
                               const double* c, double* w) {
-  if (OP == OP_STENCIL) {
-    stencil8(d, src, e, nel, c, w);
-  } else {
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const long long x = e + j;
-      w[j] = x < nel ? csr_apply(d, src, (int)(x >> d.lognrhs), (int)(x & (d.nrhs - 1))) : 0.0;
-    }
-  }
+  stencil8(d, src, e, nel, c, w);
 }
 
 __device__ inline double wave_sum_all(double v) {
@@ -402,21 +392,8 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int n
       if (e >= nel) continue;
       double c[EPT], w[EPT];
       get8(src, e, nel, c);
-      apply8<T, OP>(d, src, e, nel, c, w);
-      if (OP == OP_CSR) {
-        if (e + EPT <= nel) {
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            double2 o;
-            o.x = w[2 * h];
-            o.y = w[2 * h + 1];
-            *reinterpret_cast<double2*>(d.wbuf + e + 2 * h) = o;
-          }
-        } else {
-          for (int j = 0; j < EPT; ++j)
-            if (e + j < nel) d.wbuf[e + j] = w[j];
-        }
-      }
+      if constexpr (OP == OP_CSR) get8(d.wbuf, e, nel, w);   // w~ from the CSR product pass
+      else apply8<T>(d, src, e, nel, c, w);
 #pragma unroll
       for (int jj = 0; jj < KT; ++jj) {
         if (jj < nw) {
@@ -684,8 +661,12 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   double* X = lds;                                                   // SRHT tile (padded)
   double* acc = lds + (SK == SK_SRHT ? padx(TILE) : 0);              // sketch accumulator [s][nr]
   const int snr = d.s * nr;
-  int* rows_l = (int*)(acc + snr);                                    // sampled SRHT rows
-  for (int x = tid; x < snr; x += BLOCK) acc[x] = 0.0;
+  // sparse sign: one accumulator per wave when the host sized LDS for it, so
+  // that the LDS atomics of different waves never meet (fixed order)
+  const int nsl = (SK == SK_SPARSE && NW > 1 && d.sk_slices == NW) ? NW : 1;
+  double* acc_w = acc + (nsl > 1 ? wv * snr : 0);
+  int* rows_l = (int*)(acc + snr * nsl);                              // sampled SRHT rows
+  for (int x = tid; x < snr * nsl; x += BLOCK) acc[x] = 0.0;
   if (SK == SK_SRHT)
     for (int x = tid; x < d.s; x += BLOCK) rows_l[x] = d.srht_rows[x];
   __syncthreads();
@@ -765,7 +746,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
             sparse_sign_column(d.key_a, d.key_b, r, d.s, d.zeta, rows, &sb);
 #pragma unroll
             for (int tt = 0; tt < ZMAX; ++tt)
-              if (tt < d.zeta) atomicAdd(&acc[rows[tt] * nr + q], ((sb >> tt) & 1ull) ? -uu[j] : uu[j]);
+              if (tt < d.zeta) atomicAdd(&acc_w[rows[tt] * nr + q], ((sb >> tt) & 1ull) ? -uu[j] : uu[j]);
           }
         }
       }
@@ -791,7 +772,11 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   }
   __syncthreads();
   double* skp = d.skpart + (long long)(i & 1) * d.skstride;
-  for (int pq = tid; pq < snr; pq += BLOCK) skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = acc[pq];
+  for (int pq = tid; pq < snr; pq += BLOCK) {
+    double a = acc[pq];
+    for (int sl = 1; sl < nsl; ++sl) a += acc[sl * snr + pq];
+    skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = a;
+  }
 
   // norm partials per rhs
   for (int q = 0; q < nr; ++q) {

@@ -41,17 +41,21 @@ bool gs_staged(int s, int m) { return gs_lds_staged(s, m) <= GS_LDS_MAX; }
 template <typename T, int OP, int SK, int LT>
 __global__ void __launch_bounds__(1 << (LT - 3)) k_bg_apply(SolveDev d, int i) {
   constexpr int BLOCK = 1 << (LT - 3);
+  constexpr int NW = BLOCK / 64;
   constexpr int TILE = 1 << LT;
   extern __shared__ double lds[];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wv = wave_id();
   const int nr = d.nrhs;
   const long long nel = (long long)d.n * nr;
   const T* __restrict__ src = (const T*)d.V + (long long)(i - 1) * d.ldv;
   double* X = lds;                                          // SRHT tile (padded)
   double* acc = lds + (SK == SK_SRHT ? padx(TILE) : 0);     // sketch accumulator [s][nr]
   const int snr = d.s * nr;
-  int* rows_l = (int*)(acc + snr);
-  for (int x = tid; x < snr; x += BLOCK) acc[x] = 0.0;
+  // sparse sign: one accumulator per wave when LDS was sized for it (fixed order)
+  const int nsl = (SK == SK_SPARSE && NW > 1 && d.sk_slices == NW) ? NW : 1;
+  double* acc_w = acc + (nsl > 1 ? wv * snr : 0);
+  int* rows_l = (int*)(acc + snr * nsl);
+  for (int x = tid; x < snr * nsl; x += BLOCK) acc[x] = 0.0;
   if (SK == SK_SRHT)
     for (int x = tid; x < d.s; x += BLOCK) rows_l[x] = d.srht_rows[x];
   __syncthreads();
@@ -61,26 +65,16 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_bg_apply(SolveDev d, int i) {
 #pragma unroll
     for (int j = 0; j < EPT; ++j) w[j] = 0.0;
     if (e < nel) {
-      double c[EPT];
-      if (OP == OP_STENCIL) get8(src, e, nel, c);
-      apply8<T, OP>(d, src, e, nel, c, w);
-      // the stencil also yields values for padding rows past n: not part of w~
+      if constexpr (OP == OP_STENCIL) {
+        double c[EPT];
+        get8(src, e, nel, c);
+        apply8<T>(d, src, e, nel, c, w);
+        // the stencil also yields values for padding rows past n: not part of w~
 #pragma unroll
-      for (int j = 0; j < EPT; ++j)
-        if (e + j >= nel) w[j] = 0.0;
-      if (OP == OP_CSR) {
-        if (e + EPT <= nel) {
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            double2 o;
-            o.x = w[2 * h];
-            o.y = w[2 * h + 1];
-            *reinterpret_cast<double2*>(d.wbuf + e + 2 * h) = o;
-          }
-        } else {
-          for (int j = 0; j < EPT; ++j)
-            if (e + j < nel) d.wbuf[e + j] = w[j];
-        }
+        for (int j = 0; j < EPT; ++j)
+          if (e + j >= nel) w[j] = 0.0;
+      } else {
+        get8(d.wbuf, e, nel, w);   // w~ from the CSR product pass (zero past n)
       }
       if (SK == SK_SPARSE) {
 #pragma unroll
@@ -93,7 +87,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_bg_apply(SolveDev d, int i) {
             sparse_sign_column(d.key_a, d.key_b, r, d.s, d.zeta, rows, &sb);
 #pragma unroll
             for (int tt = 0; tt < ZMAX; ++tt)
-              if (tt < d.zeta) atomicAdd(&acc[rows[tt] * nr + q], ((sb >> tt) & 1ull) ? -w[j] : w[j]);
+              if (tt < d.zeta) atomicAdd(&acc_w[rows[tt] * nr + q], ((sb >> tt) & 1ull) ? -w[j] : w[j]);
           }
         }
       }
@@ -117,8 +111,11 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_bg_apply(SolveDev d, int i) {
   }
   __syncthreads();
   double* skp = d.skpart + (long long)(i & 1) * d.skstride;
-  for (int pq = tid; pq < snr; pq += BLOCK)
-    skp[((long long)(pq >> 3) * d.nblk + blockIdx.x) * 8 + (pq & 7)] = acc[pq];
+  for (int pq = tid; pq < snr; pq += BLOCK) {
+    double a = acc[pq];
+    for (int sl = 1; sl < nsl; ++sl) a += acc[sl * snr + pq];
+    skp[((long long)(pq >> 3) * d.nblk + blockIdx.x) * 8 + (pq & 7)] = a;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_bg_reduce(SolveDev d, int col) {
@@ -314,15 +311,15 @@ __global__ void __launch_bounds__(256) k_bg_update(SolveDev d, const double* __r
   }
 }
 
-// y = A x for FP64 vectors [n][nrhs] (the start vector A b of the sign function).
-template <int OP>
+// y = A x for FP64 vectors [n][nrhs] and the stencil operator (the start
+// vector A b of the sign function; csr_spmv serves a CSR operator).
 __global__ void __launch_bounds__(256) k_apply_op(SolveDev d, const double* __restrict__ x, double* __restrict__ y) {
   const long long nel = (long long)d.n * d.nrhs;
   for (long long e = ((long long)blockIdx.x * 256 + threadIdx.x) * EPT; e < nel;
        e += (long long)gridDim.x * 256 * EPT) {
     double c[EPT], w[EPT];
     get8(x, e, nel, c);
-    apply8<double, OP>(d, x, e, nel, c, w);
+    apply8<double>(d, x, e, nel, c, w);
     for (int j = 0; j < EPT; ++j)
       if (e + j < nel) y[e + j] = w[j];
   }
@@ -331,6 +328,10 @@ __global__ void __launch_bounds__(256) k_apply_op(SolveDev d, const double* __re
 template <typename T, int OP>
 hipError_t apply_t(const SolveDev& d, int i, hipStream_t st, size_t lds) {
   const dim3 g(d.nblk);
+  if (OP == OP_CSR) {
+    const hipError_t r = csr_spmv(d, (const T*)d.V + (long long)(i - 1) * d.ldv, (int)sizeof(T), d.wbuf, st);
+    if (r != hipSuccess) return r;
+  }
   if (d.log_tile == 11) {
     if (d.sketch == SK_SRHT) hipLaunchKernelGGL((k_bg_apply<T, OP, SK_SRHT, 11>), g, dim3(256), lds, st, d, i);
     else hipLaunchKernelGGL((k_bg_apply<T, OP, SK_SPARSE, 11>), g, dim3(256), lds, st, d, i);
@@ -375,8 +376,8 @@ hipError_t apply_operator(const SolveDev& d, const double* x, double* y, hipStre
   const long long nel = (long long)d.n * d.nrhs;
   long long g = (nel + 256 * EPT - 1) / (256 * EPT);
   if (g > 4096) g = 4096;
-  if (d.op == OP_CSR) hipLaunchKernelGGL(k_apply_op<OP_CSR>, dim3((unsigned)g), dim3(256), 0, st, d, x, y);
-  else hipLaunchKernelGGL(k_apply_op<OP_STENCIL>, dim3((unsigned)g), dim3(256), 0, st, d, x, y);
+  if (d.op == OP_CSR) return csr_spmv(d, x, 8, y, st);
+  hipLaunchKernelGGL(k_apply_op, dim3((unsigned)g), dim3(256), 0, st, d, x, y);
   return hipGetLastError();
 }
 

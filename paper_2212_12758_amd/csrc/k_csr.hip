@@ -1,0 +1,99 @@
+// y = A x for the CSR operator (the operator application of every Krylov
+// step, Algorithm 2 and Algorithm 1, when A is given as a sparse matrix).
+//
+// x and y are [n][nrhs] (element (row r, rhs q) at r*nrhs + q); x is FP32 or
+// FP64 (a basis column or an FP64 vector), y is FP64 (the w~ buffer read by
+// the passes that follow).  The nonzeros of a block of rows are consecutive
+// in memory, so a workgroup reads them as one coalesced stream instead of one
+// row per thread:
+//
+//   * a workgroup owns 256 consecutive elements (256/nrhs rows);
+//   * its nonzeros are taken in chunks of 4096 products: every thread loads
+//     16 (col, val) pairs at stride 256 (all loads in flight), then the 16
+//     gathered x values, and writes the products val * x to LDS;
+//   * the thread of element (r, q) then adds the products of row r that fall
+//     in the chunk, in increasing nonzero order.
+//
+// Every y element is the sum of its row's products in nonzero order (chunks
+// are visited in order), so the result is independent of the launch and
+// bitwise reproducible.  A row of any length is handled: it simply spans
+// several chunks.
+//
+// Blocks are dispatched round-robin over the 8 XCDs; the logical row block of
+// physical block b is remapped so that each XCD walks one contiguous eighth
+// of the rows, keeping the x neighbourhoods of a locality-ordered matrix in
+// that XCD's L2.
+#include "k_basis.h"
+
+namespace fab {
+
+namespace {
+
+constexpr int SPMV_BLOCK = 256;
+constexpr int SPMV_PER_THREAD = 16;
+constexpr int SPMV_CHUNK = SPMV_BLOCK * SPMV_PER_THREAD;   // products per chunk
+constexpr int NXCD = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(SPMV_BLOCK)
+k_csr_spmv(const int* __restrict__ rowptr, const int* __restrict__ col, const float* __restrict__ val,
+           const T* __restrict__ x, double* __restrict__ y, int n, int lognr) {
+  __shared__ double prod[SPMV_CHUNK];
+  const int nr = 1 << lognr;
+  const int tid = threadIdx.x;
+  const int G = gridDim.x, b = blockIdx.x;
+  const int lb = (G % NXCD == 0) ? (b % NXCD) * (G / NXCD) + b / NXCD : b;
+  const int rpb = SPMV_BLOCK >> lognr;                     // rows per block
+  const int r0 = lb * rpb;
+  const int r1 = r0 + rpb < n ? r0 + rpb : n;
+  const int r = r0 + (tid >> lognr), q = tid & (nr - 1);
+  const bool own = r < r1;
+  const int pb = rowptr[r0], pe = rowptr[r1];
+  const int a0 = own ? rowptr[r] : 0, a1 = own ? rowptr[r + 1] : 0;
+  const int cpe = SPMV_CHUNK >> lognr;                     // nonzeros per chunk
+  double acc = 0.0;
+  for (int c0 = pb; c0 < pe; c0 += cpe) {
+    const int ce = pe - c0 < cpe ? pe - c0 : cpe;          // nonzeros in this chunk
+    const int cn = ce << lognr;                            // products in this chunk
+    int cl[SPMV_PER_THREAD];
+    float vl[SPMV_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < SPMV_PER_THREAD; ++k) {
+      const int g = tid + k * SPMV_BLOCK;
+      const int p = c0 + (g >> lognr);
+      cl[k] = g < cn ? col[p] : 0;
+      vl[k] = g < cn ? val[p] : 0.0f;
+    }
+    // g & (nr - 1) == q for every k: the block stride is a multiple of nrhs
+#pragma unroll
+    for (int k = 0; k < SPMV_PER_THREAD; ++k) {
+      const int g = tid + k * SPMV_BLOCK;
+      const double xv = g < cn ? (double)x[((long long)cl[k] << lognr) + q] : 0.0;
+      prod[g] = (double)vl[k] * xv;
+    }
+    __syncthreads();
+    const int lo = a0 > c0 ? a0 : c0;
+    const int hi = a1 < c0 + ce ? a1 : c0 + ce;
+    for (int p = lo; p < hi; ++p) acc += prod[((p - c0) << lognr) + q];
+    __syncthreads();
+  }
+  if (own) y[((long long)r << lognr) + q] = acc;
+}
+
+}  // namespace
+
+hipError_t csr_spmv(const SolveDev& d, const void* x, int esize, double* y, hipStream_t st) {
+  const int rpb = SPMV_BLOCK >> d.lognrhs;
+  const long long g = ((long long)d.n + rpb - 1) / rpb;
+  if (g > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (g == 0) return hipSuccess;
+  if (esize == 4)
+    hipLaunchKernelGGL(k_csr_spmv<float>, dim3((unsigned)g), dim3(SPMV_BLOCK), 0, st, d.rowptr, d.col, d.val,
+                       (const float*)x, y, d.n, d.lognrhs);
+  else
+    hipLaunchKernelGGL(k_csr_spmv<double>, dim3((unsigned)g), dim3(SPMV_BLOCK), 0, st, d.rowptr, d.col, d.val,
+                       (const double*)x, y, d.n, d.lognrhs);
+  return hipGetLastError();
+}
+
+}  // namespace fab

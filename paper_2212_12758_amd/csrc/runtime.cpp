@@ -199,6 +199,7 @@ struct Plan {
   int LT = 12, R = 0, logR = 0, ntiles = 0, nblk = 0, nred = 0;
   long long ldv = 0;
   size_t lds_update = 0;
+  int sk_slices = 1;
   size_t bytes = 0;
   // offsets in the workspace
   size_t oV, oW, oH, oEta, oWn, oCoef, oS, oPart, oNpart, oSk, oCnt, oStatus, oRows, oDense, oCf, oInfoHost;
@@ -273,6 +274,13 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
   P.nred = (int)std::max<long long>(1, std::min<long long>((snr + 7) / 8, 128));   // one per 8 sketch rows
   P.lds_update = (size_t)(snr + (p.sketch == FAB_SKETCH_SRHT ? tile + tile / 32 : 0)) * 8 + (size_t)p.s * 4;
   if (P.lds_update > 160 * 1024) return FAB_EINVAL;
+  // sparse sign with 4-wave blocks: one LDS accumulator per wave when the four
+  // fit in 96 KB, which makes the sketch sums independent of wave timing
+  P.sk_slices = 1;
+  if (p.sketch == FAB_SKETCH_SPARSE_SIGN && P.LT == 11 && (size_t)snr * 4 * 8 <= 96 * 1024) {
+    P.sk_slices = 4;
+    P.lds_update = (size_t)snr * 4 * 8 + (size_t)p.s * 4;
+  }
   P.ldv = (nel + 63) & ~63LL;
   const int m = p.m, s = p.s;
   // dense workspace per rhs
@@ -507,6 +515,7 @@ void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev
   d.counter = (unsigned*)(ws + P.oCnt);
   d.status = (int*)(ws + P.oStatus);
   d.sketch = p.sketch == FAB_SKETCH_SRHT ? SK_SRHT : SK_SPARSE;
+  d.sk_slices = P.sk_slices;
   d.srht_rows = rows;
   if (d.sketch == SK_SRHT) {
     d.key_a = sm64_out(p.seed, 1);
