@@ -9,8 +9,10 @@
 //
 //   * a workgroup owns 256 consecutive elements (256/nrhs rows);
 //   * its nonzeros are taken in chunks of 4096 products: every thread loads
-//     16 (col, val) pairs at stride 256 (all loads in flight), then the 16
-//     gathered x values, and writes the products val * x to LDS;
+//     16 (col, val) pairs (with one rhs as 4 groups of 4 consecutive pairs in
+//     16-byte loads, else one pair at a time at stride 256; all loads in
+//     flight), then the 16 gathered x values, and writes the products val * x
+//     to LDS;
 //   * the thread of element (r, q) then adds the products of row r that fall
 //     in the chunk, in increasing nonzero order.
 //
@@ -80,6 +82,66 @@ k_csr_spmv(const int* __restrict__ rowptr, const int* __restrict__ col, const fl
   if (own) y[((long long)r << lognr) + q] = acc;
 }
 
+// One right-hand side: the same scheme with 16-byte loads.  Chunks start on
+// a multiple of 4 nonzeros (the index and value arrays start on 256-byte
+// boundaries), each thread loads 4 groups of 4 consecutive (col, val) pairs,
+// and the up to 3 nonzeros of the previous row block that precede the first
+// row are loaded but never summed.
+template <typename T>
+__global__ void __launch_bounds__(SPMV_BLOCK)
+k_csr_spmv1(const int* __restrict__ rowptr, const int* __restrict__ col, const float* __restrict__ val,
+            const T* __restrict__ x, double* __restrict__ y, int n) {
+  constexpr int NV = SPMV_PER_THREAD / 4;
+  __shared__ double prod[SPMV_CHUNK];
+  const int tid = threadIdx.x;
+  const int G = gridDim.x, b = blockIdx.x;
+  const int lb = (G % NXCD == 0) ? (b % NXCD) * (G / NXCD) + b / NXCD : b;
+  const int r0 = lb * SPMV_BLOCK;
+  const int r1 = r0 + SPMV_BLOCK < n ? r0 + SPMV_BLOCK : n;
+  const int r = r0 + tid;
+  const bool own = r < r1;
+  const int pb = rowptr[r0], pe = rowptr[r1];
+  const int a0 = own ? rowptr[r] : 0, a1 = own ? rowptr[r + 1] : 0;
+  double acc = 0.0;
+  for (int c0 = pb & ~3; c0 < pe; c0 += SPMV_CHUNK) {
+    int cl[SPMV_PER_THREAD];
+    float vl[SPMV_PER_THREAD];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int q = c0 + 4 * (tid + v * SPMV_BLOCK);
+      if (q + 4 <= pe) {
+        const int4 c4 = *reinterpret_cast<const int4*>(col + q);
+        const float4 v4 = *reinterpret_cast<const float4*>(val + q);
+        cl[4 * v] = c4.x;
+        cl[4 * v + 1] = c4.y;
+        cl[4 * v + 2] = c4.z;
+        cl[4 * v + 3] = c4.w;
+        vl[4 * v] = v4.x;
+        vl[4 * v + 1] = v4.y;
+        vl[4 * v + 2] = v4.z;
+        vl[4 * v + 3] = v4.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cl[4 * v + j] = q + j < pe ? col[q + j] : 0;
+          vl[4 * v + j] = q + j < pe ? val[q + j] : 0.0f;
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        prod[4 * (tid + v * SPMV_BLOCK) + j] = (double)vl[4 * v + j] * (double)x[cl[4 * v + j]];
+    __syncthreads();
+    const int lo = a0 > c0 ? a0 : c0;
+    const int hi = a1 < c0 + SPMV_CHUNK ? a1 : c0 + SPMV_CHUNK;
+    for (int p = lo; p < hi; ++p) acc += prod[p - c0];
+    __syncthreads();
+  }
+  if (own) y[r] = acc;
+}
+
 }  // namespace
 
 hipError_t csr_spmv(const SolveDev& d, const void* x, int esize, double* y, hipStream_t st) {
@@ -87,6 +149,15 @@ hipError_t csr_spmv(const SolveDev& d, const void* x, int esize, double* y, hipS
   const long long g = ((long long)d.n + rpb - 1) / rpb;
   if (g > 0x7fffffffLL) return hipErrorInvalidValue;
   if (g == 0) return hipSuccess;
+  if (d.nrhs == 1) {
+    if (esize == 4)
+      hipLaunchKernelGGL(k_csr_spmv1<float>, dim3((unsigned)g), dim3(SPMV_BLOCK), 0, st, d.rowptr, d.col, d.val,
+                         (const float*)x, y, d.n);
+    else
+      hipLaunchKernelGGL(k_csr_spmv1<double>, dim3((unsigned)g), dim3(SPMV_BLOCK), 0, st, d.rowptr, d.col, d.val,
+                         (const double*)x, y, d.n);
+    return hipGetLastError();
+  }
   if (esize == 4)
     hipLaunchKernelGGL(k_csr_spmv<float>, dim3((unsigned)g), dim3(SPMV_BLOCK), 0, st, d.rowptr, d.col, d.val,
                        (const float*)x, y, d.n, d.lognrhs);

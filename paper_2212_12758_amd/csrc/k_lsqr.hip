@@ -370,12 +370,72 @@ __global__ void __launch_bounds__(256) k_lsqr_finish(SolveDev d, DenseDev g, Lsq
 // hand side, m + 1 <= GR_MAXC), then with D = diag(eta), G~ = D^{-1} G D^{-1},
 // G~_m = R^T R (Cholesky) and R^T R y = G~[:m, m].  The error is about
 // kappa(V)^2 u; the factorisation reports failure (the caller then runs LSQR)
-// on a non-positive pivot or a diagonal spread of R above GR_MAXRATIO.
+// on a non-positive pivot, a diagonal spread of R above GR_MAXRATIO or an
+// estimated kappa_1(R) above GR_MAXCOND.
 constexpr int GR_TILE = 16, GR_T = 8, GR_MAXC = GR_T * GR_TILE;   // m + 1 <= 128
 constexpr int GR_NT = GR_T * (GR_T + 1) / 2;                      // upper 16 x 16 tiles
 constexpr int GR_RCH = 32;                                          // rows per staged chunk
 constexpr int GR_BLOCKS = 240;
 constexpr double GR_MAXRATIO = 1e4;
+constexpr double GR_MAXCOND = 1e4;   // largest accepted kappa_1(R) estimate
+
+// kappa_1(R) = ||R||_1 ||R^{-1}||_1 of an upper triangular R (n <= 128) by
+// one wave: ||R||_1 exactly, ||R^{-1}||_1 by Hager's 1-norm estimator (Hager
+// 1984, in Higham's formulation): x = ones/n; y = R^{-1} x, z = R^{-T} sign(y);
+// stop when ||z||_inf <= z^T x or ||y||_1 stops growing, else x = e_j at the
+// largest |z_j|; at most 5 rounds.  The estimate is a lower bound, in practice
+// within a small factor.  xv, zv: LDS vectors of n doubles.  A small diagonal
+// spread does not imply a small condition number (the columns of a truncated
+// Krylov basis can be nearly dependent while every pivot stays O(1)), hence
+// this check beside the spread test.
+__device__ double wave_kappa1_upper(int n, const double* R, long long ld, double* xv, double* zv) {
+  const int lane = threadIdx.x & 63;
+  double rn = 0.0;
+  for (int j = lane; j < n; j += 64) {
+    double c = 0.0;
+    for (int i = 0; i <= j; ++i) c += fabs(R[i + (long long)j * ld]);
+    rn = fmax(rn, c);
+  }
+  for (int off = 32; off >= 1; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, 64));
+  for (int i = lane; i < n; i += 64) xv[i] = 1.0 / n;
+  double est = 0.0;
+  int jprev = -1;
+  for (int it = 0; it < 5; ++it) {
+    upper_solve_any(n, R, ld, xv, xv);   // y = R^{-1} x
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      s += fabs(xv[i]);
+      zv[i] = xv[i] >= 0.0 ? 1.0 : -1.0;
+    }
+    const double e = wave_sum_all(s);
+    if (it > 0 && !(e > est)) break;
+    est = e;
+    upper_t_solve_any(n, R, ld, zv, zv);   // z = R^{-T} sign(y)
+    double bv = -1.0, zs = 0.0;
+    int bi = 0;
+    for (int i = lane; i < n; i += 64) {
+      const double a = fabs(zv[i]);
+      zs += zv[i];
+      if (a > bv) {
+        bv = a;
+        bi = i;
+      }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    const double zx = jprev < 0 ? wave_sum_all(zs) / n : zv[jprev];
+    if (!(bv > zx)) break;
+    jprev = bi;
+    for (int i = lane; i < n; i += 64) xv[i] = i == bi ? 1.0 : 0.0;
+  }
+  return rn * est;
+}
 
 // Per-block partial sums of the upper tiles of U^T U: part[blk][tile][entry].
 template <typename T>
@@ -501,6 +561,17 @@ __global__ void __launch_bounds__(512) k_vgram_solve(SolveDev d, DenseDev g, int
   if (tid == 0) R[mu - 1 + (mu - 1) * mu] = sqrt(dprev);
   __syncthreads();
   if (!(rmax <= GR_MAXRATIO * rmin)) {
+    if (tid == 0) *fail = 1;
+    return;
+  }
+  __shared__ double ez[GR_MAXC];
+  __shared__ double kap;
+  if (tid < 64) {
+    const double k1 = wave_kappa1_upper(mu, (const double*)R, mu, y, ez);
+    if (tid == 0) kap = k1;
+  }
+  __syncthreads();
+  if (!(kap <= GR_MAXCOND)) {
     if (tid == 0) *fail = 1;
     return;
   }
