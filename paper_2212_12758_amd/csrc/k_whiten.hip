@@ -23,7 +23,8 @@
 //   k_wh_basis  u_j <- sum_{l <= j} C[l, j] u_l for 1 <= j < i, in place
 //               (each thread owns one element of every vector; output
 //               columns are produced in descending blocks so that no input is
-//               overwritten before it is read).
+//               overwritten before it is read); k_wh_basis1, for one rhs,
+//               stages the coefficients in LDS.
 //
 // Per-rhs scratch in the dense workspace (region oM, ld m): R at 0, X at m^2,
 // products at 2m^2 and 3m^2, C at 4m^2, scalars at 5m^2; the rescaled sketch
@@ -209,6 +210,73 @@ __global__ void __launch_bounds__(256) k_wh_basis(SolveDev d, DenseDev g, int i)
   }
 }
 
+// One right-hand side: the same transform with the coefficients of each
+// group of WJB output columns staged in LDS (Cs[l][u] = C[l, j0+u], zero
+// where l > j), two consecutive elements per thread (one 8- or 16-byte load
+// per input column) and WJB outputs accumulated per element, so the basis is
+// read ceil((i-1)/WJB) times in total per group instead of once per group of
+// a single element's registers, and every coefficient read is an LDS
+// broadcast.  Groups go from the last columns down, so a group only reads
+// columns that no earlier group has overwritten.
+constexpr int WJB = 32;
+template <typename T>
+__global__ void __launch_bounds__(256) k_wh_basis1(SolveDev d, DenseDev g, int i) {
+  extern __shared__ double Cs[];   // [i][WJB]
+  if (d.status[5]) return;         // the rhs broke down
+  const int m = d.m;
+  const long long n = d.n;
+  T* __restrict__ V = (T*)d.V;
+  const double* C = g.base + g.oM + 4 * (long long)m * m;
+  const long long e = ((long long)blockIdx.x * 256 + threadIdx.x) * 2;
+  const bool pair = e + 1 < n;
+  const int nb = (i - 1 + WJB - 1) / WJB;
+  for (int bj = nb - 1; bj >= 0; --bj) {
+    const int j0 = 1 + bj * WJB, j1 = j0 + WJB < i ? j0 + WJB : i;   // outputs [j0, j1)
+    __syncthreads();
+    for (int x = threadIdx.x; x < j1 * WJB; x += 256) {
+      const int l = x / WJB, j = j0 + x % WJB;
+      Cs[x] = (j < j1 && l <= j) ? C[l + (long long)j * m] : 0.0;
+    }
+    __syncthreads();
+    if (e >= n) continue;
+    double a0[WJB], a1[WJB];
+#pragma unroll
+    for (int u = 0; u < WJB; ++u) a0[u] = a1[u] = 0.0;
+#pragma unroll 2
+    for (int l = 0; l < j1; ++l) {
+      const T* src = V + (long long)l * d.ldv + e;
+      double x0, x1 = 0.0;
+      if (pair) {
+        if constexpr (sizeof(T) == 4) {
+          const float2 v = *reinterpret_cast<const float2*>(src);
+          x0 = v.x;
+          x1 = v.y;
+        } else {
+          const double2 v = *reinterpret_cast<const double2*>(src);
+          x0 = v.x;
+          x1 = v.y;
+        }
+      } else {
+        x0 = (double)src[0];
+      }
+      const double* cl = Cs + l * WJB;
+#pragma unroll
+      for (int u = 0; u < WJB; ++u) {
+        a0[u] += cl[u] * x0;
+        a1[u] += cl[u] * x1;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < WJB; ++u) {
+      if (j0 + u < j1) {
+        T* dst = V + (long long)(j0 + u) * d.ldv + e;
+        dst[0] = (T)a0[u];
+        if (pair) dst[1] = (T)a1[u];
+      }
+    }
+  }
+}
+
 }  // namespace
 
 // Column a = i-1 of the incremental factor; check != 0 tests the threshold.
@@ -221,6 +289,14 @@ hipError_t wh_col(const SolveDev& d, const DenseDev& g, int a, int check, double
 
 hipError_t wh_whiten(const SolveDev& d, const DenseDev& g, int esize, int i, hipStream_t st) {
   hipLaunchKernelGGL(k_wh_apply, dim3(d.nrhs), dim3(WB), 0, st, d, g, i);
+  if (d.nrhs == 1) {
+    const long long gr = ((long long)d.n + 511) / 512;
+    const size_t lds = (size_t)i * WJB * 8;
+    if (gr > 0x7fffffffLL || lds > 160 * 1024) return hipErrorInvalidValue;
+    if (esize == 4) hipLaunchKernelGGL(k_wh_basis1<float>, dim3((unsigned)gr), dim3(256), lds, st, d, g, i);
+    else hipLaunchKernelGGL(k_wh_basis1<double>, dim3((unsigned)gr), dim3(256), lds, st, d, g, i);
+    return hipGetLastError();
+  }
   const long long nel = (long long)d.n * d.nrhs;
   long long gr = (nel + 255) / 256;
   if (gr > 8192) gr = 8192;
@@ -230,7 +306,15 @@ hipError_t wh_whiten(const SolveDev& d, const DenseDev& g, int esize, int i, hip
 }
 
 hipError_t wh_set_attributes() {
-  return hipFuncSetAttribute((const void*)k_wh_col, hipFuncAttributeMaxDynamicSharedMemorySize, WH_MAXS * 8);
+  hipError_t e = hipFuncSetAttribute((const void*)k_wh_col, hipFuncAttributeMaxDynamicSharedMemorySize, WH_MAXS * 8);
+  hipError_t r;
+  if ((r = hipFuncSetAttribute((const void*)k_wh_basis1<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               160 * 1024)) != hipSuccess)
+    e = r;
+  if ((r = hipFuncSetAttribute((const void*)k_wh_basis1<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               160 * 1024)) != hipSuccess)
+    e = r;
+  return e;
 }
 
 }  // namespace fab
