@@ -140,8 +140,11 @@ __device__ inline double gs_block_sum(double v, double* red) {
 // (r = r' + r''), which keeps S orthonormal to rounding when one classical
 // pass does not; the long vectors still see one update with the total r.
 template <bool STAGED>
-__global__ void __launch_bounds__(GS_BLOCK) k_bg_gs(SolveDev d, double* __restrict__ cfall, int i, int passes) {
-  extern __shared__ double psh[];      // p, then the residual (s values); staged: S[:, 0..i-1] behind it
+__global__ void __launch_bounds__(GS_BLOCK) k_bg_gs(SolveDev d, double* __restrict__ cfall, int i, int passes,
+                                                    int cj) {
+  // p, then the residual (s values); staged: S[:, 0..i-1] behind it;
+  // chunked (!STAGED, cj > 0): the residual, then cj columns of S
+  extern __shared__ double psh[];
   __shared__ double csh[512];          // r_j / eta_j
   __shared__ double cnew[512];         // this pass's coefficients
   __shared__ double red[GS_BLOCK / 64];
@@ -200,36 +203,96 @@ __global__ void __launch_bounds__(GS_BLOCK) k_bg_gs(SolveDev d, double* __restri
   const double pn = sqrt(gs_block_sum(a, red));   // includes the barrier after psh (and Sl) is written
   for (int j = tid; j < i; j += GS_BLOCK) csh[j] = 0.0;
   double rii = 0.0;
-  for (int pass = 0; pass < passes; ++pass) {
-    // coefficients s_j^T x of the current vector x (p, then the residual),
-    // s_j = S[:, j] / eta_j: one wave per column, stored as r_j / eta_j
-    // (four columns per wave at a time, so that their loads overlap)
-    for (int j0 = 4 * wv; j0 < i; j0 += 4 * (GS_BLOCK / 64)) {
-      double t[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int r = lane; r < s; r += 64) {
-        const double x = psh[r];
+  if (!STAGED && cj > 0) {
+    // S too large for LDS: columns visited in chunks of cj staged in LDS.
+    // The dots of a chunk use the pass's vector x (psh, unchanged during the
+    // pass) and its terms are subtracted from the residual res at once, so
+    // one sweep over S serves both halves of the classical Gram-Schmidt
+    // step, in the same order of operations as the unchunked loops.
+    double* res = psh + s;
+    double* ch = psh + 2 * s;
+    for (int pass = 0; pass < passes; ++pass) {
+      for (int r = tid; r < s; r += GS_BLOCK) res[r] = psh[r];
+      for (int jc = 0; jc < i; jc += cj) {
+        const int cn = i - jc < cj ? i - jc : cj;
+        __syncthreads();   // the previous chunk's residual is done with ch
+        const double* src = S + (long long)jc * s;
+        const long long n2 = (long long)cn * s;
+        long long x = tid;
+        for (; x + 7 * GS_BLOCK < n2; x += 8 * GS_BLOCK) {
+          double t[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (j0 + u < i) t[u] += Sc[(long long)(j0 + u) * s + r] * x;
-      }
+          for (int u = 0; u < 8; ++u) t[u] = src[x + u * GS_BLOCK];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double tu = wave_sum_all(t[u]);
-        if (lane == 0 && j0 + u < i) cnew[j0 + u] = tu / (eta[j0 + u] * eta[j0 + u]);
-      }
-    }
-    __syncthreads();
-    // residual x - sum_j r_j s_j (each thread its own rows)
-    double b2 = 0.0;
-    for (int r = tid; r < s; r += GS_BLOCK) {
-      double v = psh[r];
+          for (int u = 0; u < 8; ++u) ch[x + u * GS_BLOCK] = t[u];
+        }
+        for (; x < n2; x += GS_BLOCK) ch[x] = src[x];
+        __syncthreads();
+        for (int j0 = 4 * wv; j0 < cn; j0 += 4 * (GS_BLOCK / 64)) {
+          double t[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int r = lane; r < s; r += 64) {
+            const double xv = psh[r];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (j0 + u < cn) t[u] += ch[(long long)(j0 + u) * s + r] * xv;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double tu = wave_sum_all(t[u]);
+            const int j = jc + j0 + u;
+            if (lane == 0 && j0 + u < cn) cnew[j] = tu / (eta[j] * eta[j]);
+          }
+        }
+        __syncthreads();
+        for (int r = tid; r < s; r += GS_BLOCK) {
+          double v = res[r];
 #pragma unroll 8
-      for (int j = 0; j < i; ++j) v -= cnew[j] * Sc[(long long)j * s + r];
-      psh[r] = v;
-      b2 += v * v;
+          for (int j = 0; j < cn; ++j) v -= cnew[jc + j] * ch[(long long)j * s + r];
+          res[r] = v;
+        }
+      }
+      __syncthreads();
+      double b2 = 0.0;
+      for (int r = tid; r < s; r += GS_BLOCK) {
+        const double v = res[r];
+        psh[r] = v;
+        b2 += v * v;
+      }
+      for (int j = tid; j < i; j += GS_BLOCK) csh[j] += cnew[j];
+      rii = sqrt(gs_block_sum(b2, red));   // barriers: psh, csh complete before the next pass
     }
-    for (int j = tid; j < i; j += GS_BLOCK) csh[j] += cnew[j];
-    rii = sqrt(gs_block_sum(b2, red));   // barriers: psh, csh complete before the next pass
+  } else {
+    for (int pass = 0; pass < passes; ++pass) {
+      // coefficients s_j^T x of the current vector x (p, then the residual),
+      // s_j = S[:, j] / eta_j: one wave per column, stored as r_j / eta_j
+      // (four columns per wave at a time, so that their loads overlap)
+      for (int j0 = 4 * wv; j0 < i; j0 += 4 * (GS_BLOCK / 64)) {
+        double t[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int r = lane; r < s; r += 64) {
+          const double x = psh[r];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (j0 + u < i) t[u] += Sc[(long long)(j0 + u) * s + r] * x;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double tu = wave_sum_all(t[u]);
+          if (lane == 0 && j0 + u < i) cnew[j0 + u] = tu / (eta[j0 + u] * eta[j0 + u]);
+        }
+      }
+      __syncthreads();
+      // residual x - sum_j r_j s_j (each thread its own rows)
+      double b2 = 0.0;
+      for (int r = tid; r < s; r += GS_BLOCK) {
+        double v = psh[r];
+#pragma unroll 8
+        for (int j = 0; j < i; ++j) v -= cnew[j] * Sc[(long long)j * s + r];
+        psh[r] = v;
+        b2 += v * v;
+      }
+      for (int j = tid; j < i; j += GS_BLOCK) csh[j] += cnew[j];
+      rii = sqrt(gs_block_sum(b2, red));   // barriers: psh, csh complete before the next pass
+    }
   }
   for (int r = tid; r < s; r += GS_BLOCK) Si[r] = psh[r];   // Theta u_i
   const bool nonfinite = !isfinite(pn) || !isfinite(rii);
@@ -390,10 +453,17 @@ hipError_t bg_reduce(const SolveDev& d, int col, hipStream_t st) {
 // (passes = 1 as in Algorithm 1, 2 with the step repeated).
 hipError_t bg_gs(const SolveDev& d, double* cf, int i, int passes, hipStream_t st) {
   if (d.s > GS_MAXS || d.m + 1 > 512 || passes < 1 || passes > 2) return hipErrorInvalidValue;
-  if (gs_staged(d.s, d.m))
-    hipLaunchKernelGGL(k_bg_gs<true>, dim3(d.nrhs), dim3(GS_BLOCK), gs_lds_staged(d.s, d.m), st, d, cf, i, passes);
-  else
-    hipLaunchKernelGGL(k_bg_gs<false>, dim3(d.nrhs), dim3(GS_BLOCK), (size_t)d.s * 8, st, d, cf, i, passes);
+  if (gs_staged(d.s, d.m)) {
+    hipLaunchKernelGGL(k_bg_gs<true>, dim3(d.nrhs), dim3(GS_BLOCK), gs_lds_staged(d.s, d.m), st, d, cf, i, passes, 0);
+  } else {
+    // columns in LDS chunks when at least 4 fit beside p and the residual
+    const long long cj = ((long long)(GS_LDS_MAX / 8) - 2LL * d.s) / d.s;
+    if (cj >= 4)
+      hipLaunchKernelGGL(k_bg_gs<false>, dim3(d.nrhs), dim3(GS_BLOCK), (size_t)(2 + cj) * d.s * 8, st, d, cf, i,
+                         passes, (int)cj);
+    else
+      hipLaunchKernelGGL(k_bg_gs<false>, dim3(d.nrhs), dim3(GS_BLOCK), (size_t)d.s * 8, st, d, cf, i, passes, 0);
+  }
   return hipGetLastError();
 }
 
@@ -412,7 +482,8 @@ hipError_t bg_set_attributes() {
   hipError_t r = hipFuncSetAttribute((const void*)k_bg_gs<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)GS_LDS_MAX);
   if (r != hipSuccess) e = r;
-  r = hipFuncSetAttribute((const void*)k_bg_gs<false>, hipFuncAttributeMaxDynamicSharedMemorySize, GS_MAXS * 8);
+  r = hipFuncSetAttribute((const void*)k_bg_gs<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(GS_MAXS * 8 > (int)GS_LDS_MAX ? GS_MAXS * 8 : (int)GS_LDS_MAX));
   if (r != hipSuccess) e = r;
   return e;
 }
