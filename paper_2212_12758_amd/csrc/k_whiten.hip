@@ -14,12 +14,14 @@
 //               product is kappa_1(R) = ||R||_1 ||R^{-1}||_1.  On a check step
 //               it raises the flag when kappa_1(R) exceeds the threshold (or
 //               the factorisation broke down).
-//   k_wh_apply  one workgroup per rhs: Hbar_{i-1} <- R_i Hbar_{i-1} X_{i-1}
-//               (column i-1 of H, left by the discarded step i, is cleared),
-//               the sketch S[:, j] <- (Theta V_i X)[:, j] (j >= 1), the scales
-//               eta_0 <- eta_0 R_00 (the stored u_0 = b is kept) and eta_j <- 1,
-//               and the coefficients C[l, j] = X[l, j] / eta_l of the basis
-//               transform.
+//   k_wh_prod,  many workgroups (one output per thread): Hbar_{i-1} <-
+//   k_wh_fin    R_i Hbar_{i-1} X_{i-1} (column i-1 of H, left by the
+//               discarded step i, is cleared), the sketch S[:, j] <-
+//               (Theta V_i X)[:, j] (j >= 1), the scales eta_0 <- eta_0 R_00
+//               (the stored u_0 = b is kept) and eta_j <- 1, and the
+//               coefficients C[l, j] = X[l, j] / eta_l of the basis
+//               transform; k_wh_prod forms T = Hbar X, the rescaled sketch
+//               and C, k_wh_fin the products with R and the copies.
 //   k_wh_basis  u_j <- sum_{l <= j} C[l, j] u_l for 1 <= j < i, in place
 //               (each thread owns one element of every vector; output
 //               columns are produced in descending blocks so that no input is
@@ -123,58 +125,80 @@ __global__ void __launch_bounds__(WB) k_wh_col(SolveDev d, DenseDev g, int a, in
   }
 }
 
-// Whitening of the small quantities at step i (columns 0..i-1).
-__global__ void __launch_bounds__(WB) k_wh_apply(SolveDev d, DenseDev g, int i) {
-  const int q = blockIdx.x, tid = threadIdx.x;
+// The products of the whitening transform, spread over many workgroups (one
+// output per thread, each summed in the same order as a single workgroup
+// would): T = Hbar_{i-1} X_{i-1} (i x (i-1), ld m), the rescaled sketch
+// Sw[:, j] = sum_{l <= j} (S[:, l] / eta_l) X[l, j] (s x i) and the basis
+// coefficients C[l, j] = X[l, j] / eta_l (1 <= j < i).  blockIdx.y = rhs.
+__global__ void __launch_bounds__(WB) k_wh_prod(SolveDev d, DenseDev g, int i) {
+  const int q = blockIdx.y;
+  if (d.status[5 + 2 * q]) return;
+  const int m = d.m, m1 = m + 1, s = d.s;
+  const long long mm = (long long)m * m;
+  double* base = g.base + (long long)q * g.stride;
+  double* ws = base + g.oM;
+  const double* X = ws + mm;
+  double* T = ws + 2 * mm;
+  double* C = ws + 4 * mm;
+  double* Sw = base + g.oW;
+  const double* H = d.H + (long long)q * m1 * m;
+  const double* S = d.S + (long long)q * s * m1;
+  const double* eta = d.eta + (long long)q * m1;
+  const long long nT = (long long)i * (i - 1), nS = (long long)s * i, nC = (long long)i * i;
+  for (long long x = (long long)blockIdx.x * WB + threadIdx.x; x < nT + nS + nC; x += (long long)gridDim.x * WB) {
+    if (x < nT) {
+      const int r = (int)(x % i), c = (int)(x / i);
+      double t = 0.0;
+      for (int l = 0; l <= c; ++l) t += H[r + (long long)l * m1] * X[l + (long long)c * m];
+      T[r + (long long)c * m] = t;
+    } else if (x < nT + nS) {
+      const long long y = x - nT;
+      const int r = (int)(y % s), j = (int)(y / s);
+      double t = 0.0;
+      for (int l = 0; l <= j; ++l) t += S[(long long)l * s + r] / eta[l] * X[l + (long long)j * m];
+      Sw[r + (long long)j * s] = t;
+    } else {
+      const long long y = x - nT - nS;
+      const int l = (int)(y % i), j = (int)(y / i);
+      C[l + (long long)j * m] = (j >= 1 && l <= j) ? X[l + (long long)j * m] / eta[l] : 0.0;
+    }
+  }
+}
+
+// Hbar_{i-1} <- R_i T (rows 0..i-1, columns 0..i-2; column i-1 cleared), the
+// sketch S[:, j] <- Sw[:, j] for 1 <= j < i (column 0 keeps Theta u_0 =
+// eta'_0 q_0) and the scales eta_0 <- eta_0 R_00, eta_j <- 1.  blockIdx.y = rhs.
+__global__ void __launch_bounds__(WB) k_wh_fin(SolveDev d, DenseDev g, int i) {
+  const int q = blockIdx.y;
   if (d.status[5 + 2 * q]) return;
   const int m = d.m, m1 = m + 1, s = d.s;
   const long long mm = (long long)m * m;
   double* base = g.base + (long long)q * g.stride;
   double* ws = base + g.oM;
   const double* R = ws;
-  const double* X = ws + mm;
-  double* T = ws + 2 * mm;    // Hbar X, i x (i-1), ld m
-  double* C = ws + 4 * mm;
-  double* Sw = base + g.oW;   // rescaled sketch, s x i
+  const double* T = ws + 2 * mm;
+  const double* Sw = base + g.oW;
   double* H = d.H + (long long)q * m1 * m;
   double* S = d.S + (long long)q * s * m1;
   double* eta = d.eta + (long long)q * m1;
-  // T = Hbar_{i-1} X_{i-1}: T[r, c] = sum_{l <= c} H[r, l] X[l, c]
-  for (long long x = tid; x < (long long)i * (i - 1); x += WB) {
-    const int r = (int)(x % i), c = (int)(x / i);
-    double t = 0.0;
-    for (int l = 0; l <= c; ++l) t += H[r + (long long)l * m1] * X[l + (long long)c * m];
-    T[r + (long long)c * m] = t;
+  const long long nH = (long long)i * (i - 1), nS = (long long)s * i;
+  for (long long x = (long long)blockIdx.x * WB + threadIdx.x; x < nH + nS + m1; x += (long long)gridDim.x * WB) {
+    if (x < nH) {
+      const int r = (int)(x % i), c = (int)(x / i);
+      double t = 0.0;
+      for (int l = r; l < i; ++l) t += R[r + (long long)l * m] * T[l + (long long)c * m];
+      H[r + (long long)c * m1] = t;
+    } else if (x < nH + nS) {
+      const long long y = x - nH;
+      if (y >= s) S[y] = Sw[y];
+    } else {
+      H[(x - nH - nS) + (long long)(i - 1) * m1] = 0.0;
+    }
   }
-  // rescaled sketch: Sw[:, j] = sum_{l <= j} (S[:, l] / eta_l) X[l, j]
-  for (long long x = tid; x < (long long)s * i; x += WB) {
-    const int r = (int)(x % s), j = (int)(x / s);
-    double t = 0.0;
-    for (int l = 0; l <= j; ++l) t += S[(long long)l * s + r] / eta[l] * X[l + (long long)j * m];
-    Sw[r + (long long)j * s] = t;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) eta[0] = eta[0] * R[0];
+    for (int j = 1 + threadIdx.x; j < i; j += WB) eta[j] = 1.0;
   }
-  // basis coefficients C[l, j] = X[l, j] / eta_l (1 <= j < i)
-  for (long long x = tid; x < (long long)i * i; x += WB) {
-    const int l = (int)(x % i), j = (int)(x / i);
-    C[l + (long long)j * m] = (j >= 1 && l <= j) ? X[l + (long long)j * m] / eta[l] : 0.0;
-  }
-  __syncthreads();
-  // H <- R T (rows 0..i-1, columns 0..i-2); column i-1 cleared
-  for (long long x = tid; x < (long long)i * (i - 1); x += WB) {
-    const int r = (int)(x % i), c = (int)(x / i);
-    double t = 0.0;
-    for (int l = r; l < i; ++l) t += R[r + (long long)l * m] * T[l + (long long)c * m];
-    H[r + (long long)c * m1] = t;
-  }
-  for (int r = tid; r <= m; r += WB) H[r + (long long)(i - 1) * m1] = 0.0;
-  // S[:, j] <- Q[:, j] for 1 <= j < i; column 0 keeps Theta u_0 = eta'_0 q_0
-  for (long long x = tid; x < (long long)s * i; x += WB) {
-    const int j = (int)(x / s);
-    if (j >= 1) S[x] = Sw[x];
-  }
-  __syncthreads();
-  if (tid == 0) eta[0] = eta[0] * R[0];
-  for (int j = 1 + tid; j < i; j += WB) eta[j] = 1.0;
 }
 
 // In-place u_j <- sum_{l <= j} C[l, j] u_l, 1 <= j < i.
@@ -288,7 +312,13 @@ hipError_t wh_col(const SolveDev& d, const DenseDev& g, int a, int check, double
 }
 
 hipError_t wh_whiten(const SolveDev& d, const DenseDev& g, int esize, int i, hipStream_t st) {
-  hipLaunchKernelGGL(k_wh_apply, dim3(d.nrhs), dim3(WB), 0, st, d, g, i);
+  {
+    const long long work = (long long)d.s * i + 2LL * i * i;
+    long long gb = (work + WB - 1) / WB;
+    if (gb > 1024) gb = 1024;
+    hipLaunchKernelGGL(k_wh_prod, dim3((unsigned)gb, d.nrhs), dim3(WB), 0, st, d, g, i);
+    hipLaunchKernelGGL(k_wh_fin, dim3((unsigned)gb, d.nrhs), dim3(WB), 0, st, d, g, i);
+  }
   if (d.nrhs == 1) {
     const long long gr = ((long long)d.n + 511) / 512;
     const size_t lds = (size_t)i * WJB * 8;
