@@ -53,8 +53,8 @@ __device__ inline double wh_sum(double v, double* red) {
 }
 
 __global__ void __launch_bounds__(WB) k_wh_col(SolveDev d, DenseDev g, int a, int check, double thresh,
-                                               int* flag) {
-  extern __shared__ double sa[];     // Theta v_a (s values)
+                                               int* flag, int cj) {
+  extern __shared__ double sa[];     // Theta v_a (s values), then cj staged columns of S
   __shared__ double gsh[512], rsh[512];
   __shared__ double red[WB / 64];
   const int q = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = wave_id();
@@ -70,19 +70,38 @@ __global__ void __launch_bounds__(WB) k_wh_col(SolveDev d, DenseDev g, int a, in
   const double ea = eta[a];
   for (int r = tid; r < s; r += WB) sa[r] = S[(long long)a * s + r] / ea;
   __syncthreads();
-  // g_l = (Theta v_l)^T Theta v_a, l <= a: four columns per wave at a time
-  for (int l0 = 4 * wv; l0 <= a; l0 += 4 * (WB / 64)) {
-    double t[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r = lane; r < s; r += 64) {
-      const double x = sa[r];
+  // g_l = (Theta v_l)^T Theta v_a, l <= a: four columns per wave at a time,
+  // the columns staged in LDS in chunks of cj (eight loads in flight)
+  double* ch = sa + s;
+  for (int lc = 0; lc <= a; lc += cj) {
+    const int cn = a + 1 - lc < cj ? a + 1 - lc : cj;
+    __syncthreads();   // sa written / the previous chunk's dots are done
+    const double* src = S + (long long)lc * s;
+    const long long n2 = (long long)cn * s;
+    long long x = tid;
+    for (; x + 7 * WB < n2; x += 8 * WB) {
+      double t[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (l0 + u <= a) t[u] += S[(long long)(l0 + u) * s + r] * x;
+      for (int u = 0; u < 8; ++u) t[u] = src[x + u * WB];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ch[x + u * WB] = t[u];
     }
+    for (; x < n2; x += WB) ch[x] = src[x];
+    __syncthreads();
+    for (int l0 = 4 * wv; l0 < cn; l0 += 4 * (WB / 64)) {
+      double t[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int r = lane; r < s; r += 64) {
+        const double xv = sa[r];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double tu = wave_sum_all(t[u]);
-      if (lane == 0 && l0 + u <= a) gsh[l0 + u] = tu / eta[l0 + u];
+        for (int u = 0; u < 4; ++u)
+          if (l0 + u < cn) t[u] += ch[(long long)(l0 + u) * s + r] * xv;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double tu = wave_sum_all(t[u]);
+        const int l = lc + l0 + u;
+        if (lane == 0 && l0 + u < cn) gsh[l] = tu / eta[l];
+      }
     }
   }
   __syncthreads();
@@ -90,6 +109,7 @@ __global__ void __launch_bounds__(WB) k_wh_col(SolveDev d, DenseDev g, int a, in
   double p2 = 0.0;
   for (int l = tid; l < a; l += WB) {
     double t = 0.0;
+#pragma unroll 8
     for (int u = 0; u <= l; ++u) t += X[u + (long long)l * m] * gsh[u];
     rsh[l] = t;
     R[l + (long long)a * m] = t;
@@ -102,6 +122,7 @@ __global__ void __launch_bounds__(WB) k_wh_col(SolveDev d, DenseDev g, int a, in
   double cx = 0.0, cr = 0.0;
   for (int t0 = tid; t0 < a; t0 += WB) {
     double v = 0.0;
+#pragma unroll 8
     for (int l = t0; l < a; ++l) v += X[t0 + (long long)l * m] * rsh[l];
     const double xv = sing ? 0.0 : -v / raa;
     X[t0 + (long long)a * m] = xv;
@@ -307,7 +328,12 @@ __global__ void __launch_bounds__(256) k_wh_basis1(SolveDev d, DenseDev g, int i
 hipError_t wh_col(const SolveDev& d, const DenseDev& g, int a, int check, double thresh, int* flag,
                   hipStream_t st) {
   if (d.s > WH_MAXS || d.m + 1 > 512) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_wh_col, dim3(d.nrhs), dim3(WB), (size_t)d.s * 8, st, d, g, a, check, thresh, flag);
+  // columns of S staged in LDS beside Theta v_a: as many as fit in 150 KB
+  long long cj = ((long long)(150 * 1024 / 8) - d.s) / d.s;
+  if (cj < 1) return hipErrorInvalidValue;
+  if (cj > a + 1) cj = a + 1;
+  hipLaunchKernelGGL(k_wh_col, dim3(d.nrhs), dim3(WB), (size_t)(1 + cj) * d.s * 8, st, d, g, a, check, thresh, flag,
+                     (int)cj);
   return hipGetLastError();
 }
 
@@ -336,7 +362,7 @@ hipError_t wh_whiten(const SolveDev& d, const DenseDev& g, int esize, int i, hip
 }
 
 hipError_t wh_set_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_wh_col, hipFuncAttributeMaxDynamicSharedMemorySize, WH_MAXS * 8);
+  hipError_t e = hipFuncSetAttribute((const void*)k_wh_col, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
   hipError_t r;
   if ((r = hipFuncSetAttribute((const void*)k_wh_basis1<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                160 * 1024)) != hipSuccess)
