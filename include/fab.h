@@ -59,7 +59,8 @@ enum fab_status {
 
 /* The function f (Section 1: analytic on a domain containing the spectrum). */
 enum fab_func_kind {
-  FAB_F_EXP = 1,      /* f(z) = exp(alpha z)                                      */
+  FAB_F_EXP = 1,      /* f(z) = exp(alpha z); the solve returns FAB_ENUMERIC when
+                         ||alpha H_hat||_1 > 16384 (work bound of the Taylor action) */
   FAB_F_POW = 2,      /* f(z) = (z + sigma)^p, p = +1/2 or -1/2 (principal branch) */
   FAB_F_POLY = 3,     /* f(z) = sum_j coef[j] z^j (test hook: exact for deg <= m-1) */
   FAB_F_SIGN = 4      /* f(z) = sign(Re z), computed as (A^2)^{-1/2} (A b) (Section 5.1.3):

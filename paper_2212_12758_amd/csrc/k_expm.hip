@@ -24,6 +24,12 @@ constexpr int EMAXM = 512;
 constexpr double RHO_MAX = 4.0;    // scaled norm per step
 constexpr double TAYLOR_TOL = 1e-18;
 constexpr int KMAX_TAYLOR = 64;
+// Work bound: at most EXP_MAX_STEPS scaling steps (||alpha H_hat||_1 <=
+// RHO_MAX * EXP_MAX_STEPS = 16384); beyond it the kernel stores NaN and
+// reports INFO_FAIL = 3 (the solve then returns FAB_ENUMERIC) instead of
+// running for a time proportional to the norm (a least-squares correction
+// of an ill-conditioned basis can make ||H_hat|| arbitrarily large).
+constexpr double EXP_MAX_STEPS = 4096.0;
 
 // S, K and ||B||_1 for B = alpha H_hat (H_hat m x m, column-major); every
 // thread of the 256-thread workgroup gets the same values.
@@ -41,7 +47,14 @@ __device__ __forceinline__ void taylor_plan(int m, const double* H, double alpha
   if ((tid & 63) == 0) red[tid >> 6] = cmax;
   __syncthreads();
   const double nrm = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * fabs(alpha);
-  int S = (int)ceil(nrm / RHO_MAX);
+  *nrm_out = nrm;
+  const double Sd = ceil(nrm / RHO_MAX);
+  if (!(Sd <= EXP_MAX_STEPS)) {   // also NaN
+    *Sout = 0;
+    *Kout = 0;
+    return;
+  }
+  int S = (int)Sd;
   if (S < 1) S = 1;
   const double rho = nrm / S;
   // degree: first omitted term rho^(K+1)/(K+1)! below the tolerance
@@ -57,7 +70,17 @@ __device__ __forceinline__ void taylor_plan(int m, const double* H, double alpha
   }
   *Sout = S;
   *Kout = K;
-  *nrm_out = nrm;
+}
+
+// The result when the norm is beyond the work bound: NaN, INFO_FAIL = 3.
+__device__ void taylor_refuse(int m, double nrm, double* out, double* info) {
+  for (int r = threadIdx.x; r < m; r += 256) out[r] = __builtin_nan("");
+  if (threadIdx.x == 0) {
+    info[INFO_FAIL] = 3.0;
+    info[INFO_NSQ] = 0.0;
+    info[INFO_SCHUR_IT] = 0.0;
+    info[INFO_NRM] = nrm;
+  }
 }
 
 // m <= 128: H_hat in registers.  Wave w owns columns [w cw, (w+1) cw) with
@@ -74,6 +97,10 @@ __device__ void taylor_action_regs(int m, const double* __restrict__ H, double a
   int S, K;
   double nrm;
   taylor_plan(m, H, alpha, red, &S, &K, &nrm);
+  if (S == 0) {
+    taylor_refuse(m, nrm, out, info);
+    return;
+  }
   const double bscale = alpha / S;
   const int cw = (m + 3) / 4, cb = w * cw;
   double h0[32], h1[32];
@@ -128,6 +155,10 @@ __device__ __forceinline__ void taylor_action(int m, Ptr H, double alpha, double
   int S, K;
   double nrm;
   taylor_plan(m, H, alpha, red, &S, &K, &nrm);
+  if (S == 0) {
+    taylor_refuse(m, nrm, out, info);
+    return;
+  }
   const double bscale = alpha / S;
   // thread (r, h): rows r = (tid & 127) + 128 j, column half h = tid >> 7
   const int h = tid >> 7, r0 = tid & 127;

@@ -68,6 +68,71 @@ __device__ void upper_t_solve_any(int n, const double* U, long long ldu, const d
   else wave_upper_t_solve<8>(n, U, ldu, z, x);
 }
 
+// The same substitutions on a packed upper triangle (column c at c(c+1)/2,
+// rows 0..c), for factors too large to keep whole in LDS; the order of
+// operations is that of the full-storage versions.
+template <int R>
+__device__ void wave_upper_solve_packed(int n, const double* Up, const double* z, double* x) {
+  const int lane = threadIdx.x & 63;
+  double y[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    y[u] = r < n ? z[r] : 0.0;
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    const int uj = j >> 6;
+    double src = y[0];
+#pragma unroll
+    for (int u = 1; u < R; ++u)
+      if (uj == u) src = y[u];
+    const int cb = j * (j + 1) / 2;
+    const double ujj = Up[cb + j];
+    const double xj = ujj != 0.0 ? readlane_d(src, j & 63) / ujj : 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int r = lane + 64 * u;
+      if (r == j) y[u] = xj;
+      else if (r < j) y[u] -= Up[cb + r] * xj;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    if (r < n) x[r] = y[u];
+  }
+}
+template <int R>
+__device__ void wave_upper_t_solve_packed(int n, const double* Up, const double* z, double* x) {
+  const int lane = threadIdx.x & 63;
+  double y[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    y[u] = r < n ? z[r] : 0.0;
+  }
+  for (int j = 0; j < n; ++j) {
+    const int uj = j >> 6;
+    double src = y[0];
+#pragma unroll
+    for (int u = 1; u < R; ++u)
+      if (uj == u) src = y[u];
+    const double ujj = Up[j * (j + 1) / 2 + j];
+    const double xj = ujj != 0.0 ? readlane_d(src, j & 63) / ujj : 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int r = lane + 64 * u;
+      if (r == j) y[u] = xj;
+      else if (r > j && r < n) y[u] -= Up[r * (r + 1) / 2 + j] * xj;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    if (r < n) x[r] = y[u];
+  }
+}
+
 __device__ inline double bsum256(double v, double* sh) {
   v = wave_sum_all(v);
   __syncthreads();
@@ -85,6 +150,9 @@ size_t lsqr_state_stride(int m) { return (size_t)5 * (m + 1) + LS_NSCAL; }
 // solves are sequential in the column index, so each access is latency-bound)
 constexpr int STEP_LDS_M = 140;
 size_t lsqr_step_lds(int m) { return m <= STEP_LDS_M ? (size_t)m * m * 8 : 0; }
+// R_m packed (upper triangle only) in LDS above STEP_LDS_M, while it fits
+size_t lsqr_step_lds_packed(int m) { return (size_t)m * (m + 1) / 2 * 8; }
+bool lsqr_step_packed(int m) { return m > STEP_LDS_M && m <= 199 && lsqr_step_lds_packed(m) <= 160 * 1024; }
 size_t lsqr_pass_lds(int m, int nrhs) { return (size_t)4 * nrhs * (m + 1) * 8; }
 
 // Stream the basis once.  first: u~ = u_m / eta_m (the right-hand side
@@ -191,7 +259,9 @@ __global__ void __launch_bounds__(256) k_lsqr_pass(SolveDev d, LsqrDev L, int fi
 
 // One LSQR step per rhs (first: the initialisation).  RL: R_m is copied to
 // LDS (a compile-time choice, so that its accesses compile to LDS loads).
-template <bool RL>
+// RL: 0 R_m read from global memory, 1 R_m staged in LDS, 2 its upper
+// triangle staged packed in LDS.
+template <int RL>
 __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrDev L, int first) {
   if (*L.alldone) return;
   const int q = blockIdx.x, tid = threadIdx.x;
@@ -220,7 +290,7 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
     __syncthreads();
   }
   if (sc[LS_DONE] != 0.0) return;
-  if (RL) {
+  if (RL == 1) {
     // eight loads in flight per thread (visible after the barrier below)
     const int n2 = mu * mu;
     int x = tid;
@@ -232,8 +302,26 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
       for (int u = 0; u < 8; ++u) rlds[x + u * 256] = t[u];
     }
     for (; x < n2; x += 256) rlds[x] = Rg[x];
+  } else if (RL == 2) {
+    // the upper triangle, column c at c(c+1)/2 (eight loads in flight)
+    const int n2 = mu * mu;
+    int x = tid;
+    for (; x + 7 * 256 < n2; x += 8 * 256) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = Rg[x + u * 256];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = (x + u * 256) % mu, c = (x + u * 256) / mu;
+        if (r <= c) rlds[c * (c + 1) / 2 + r] = t[u];
+      }
+    }
+    for (; x < n2; x += 256) {
+      const int r = x % mu, c = x / mu;
+      if (r <= c) rlds[c * (c + 1) / 2 + r] = Rg[x];
+    }
   }
-  const double* R = RL ? (const double*)rlds : Rg;
+  const double* R = RL == 1 ? (const double*)rlds : Rg;
   // reduce the pass partials in a fixed order: thread (group g, slot j)
   // sums blocks [g nb / G, (g+1) nb / G) in order, eight loads in flight,
   // then the G group sums are added in order
@@ -271,7 +359,14 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
   // s = R^{-T} (d / eta) / beta  ->  cf (scratch)
   for (int j = tid; j < mu; j += 256) cf[j] = beta > 0.0 ? tmp[j] / (eta[j] * beta) : 0.0;
   __syncthreads();
-  if (tid < 64) upper_t_solve_any(mu, R, mu, cf, tmp);
+  if (tid < 64) {
+    if constexpr (RL == 2) {
+      if (mu <= 128) wave_upper_t_solve_packed<2>(mu, rlds, cf, tmp);
+      else wave_upper_t_solve_packed<4>(mu, rlds, cf, tmp);
+    } else {
+      upper_t_solve_any(mu, R, mu, cf, tmp);
+    }
+  }
   __syncthreads();
   // alpha v = s - beta v_old
   double p2 = 0.0;
@@ -317,7 +412,14 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
   }
   __syncthreads();
   // coefficients of the next pass: cf = R^{-1} v / eta, a = alpha / beta
-  if (tid < 64) upper_solve_any(mu, R, mu, v, tmp);
+  if (tid < 64) {
+    if constexpr (RL == 2) {
+      if (mu <= 128) wave_upper_solve_packed<2>(mu, rlds, v, tmp);
+      else wave_upper_solve_packed<4>(mu, rlds, v, tmp);
+    } else {
+      upper_solve_any(mu, R, mu, v, tmp);
+    }
+  }
   __syncthreads();
   for (int j = tid; j < m; j += 256) cf[j] = j < mu ? tmp[j] / eta[j] : 0.0;
   if (tid == 0) sc[LS_A] = beta > 0.0 ? alpha / beta : 0.0;
@@ -601,9 +703,11 @@ void pass_launch_t(const SolveDev& d, const LsqrDev& L, hipStream_t st, int firs
 }
 void step_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, hipStream_t st, int first) {
   if (d.m <= STEP_LDS_M)
-    hipLaunchKernelGGL(k_lsqr_step<true>, dim3(d.nrhs), dim3(256), lsqr_step_lds(d.m), st, d, g, L, first);
+    hipLaunchKernelGGL(k_lsqr_step<1>, dim3(d.nrhs), dim3(256), lsqr_step_lds(d.m), st, d, g, L, first);
+  else if (lsqr_step_packed(d.m))
+    hipLaunchKernelGGL(k_lsqr_step<2>, dim3(d.nrhs), dim3(256), lsqr_step_lds_packed(d.m), st, d, g, L, first);
   else
-    hipLaunchKernelGGL(k_lsqr_step<false>, dim3(d.nrhs), dim3(256), 0, st, d, g, L, first);
+    hipLaunchKernelGGL(k_lsqr_step<0>, dim3(d.nrhs), dim3(256), 0, st, d, g, L, first);
 }
 void lsqr_pass_launch(const SolveDev& d, const LsqrDev& L, int esize, hipStream_t st, int first) {
   const size_t lds = lsqr_pass_lds(d.m, d.nrhs);
@@ -666,8 +770,10 @@ hipError_t lsqr_set_attributes() {
     if ((r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024)) != hipSuccess) e = r;
   if ((r = hipFuncSetAttribute((const void*)k_vgram_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
                                GR_MAXC * GR_MAXC * 8)) != hipSuccess) e = r;
-  if ((r = hipFuncSetAttribute((const void*)k_lsqr_step<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  if ((r = hipFuncSetAttribute((const void*)k_lsqr_step<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lsqr_step_lds(STEP_LDS_M))) != hipSuccess) e = r;
+  if ((r = hipFuncSetAttribute((const void*)k_lsqr_step<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               160 * 1024)) != hipSuccess) e = r;
   return e;
 }
 

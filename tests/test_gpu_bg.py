@@ -232,11 +232,13 @@ def test_bg_invalid_basis(ctx):
 # ------------------------------------------------------------------ beyond the LDS / register sizes
 def test_bg2_large_m_global_paths(ctx):
     """m = 150, s = 320: the sketch columns exceed the LDS of the Gram-Schmidt
-    step, R_m the LDS of the LSQR step (m > 140), H_hat the LDS of the
-    quadrature square root (m > 128, four rows per lane) and the registers of
-    the sketched QR (Householder in global memory): every global-memory
-    variant, against the oracle's Algorithm 3 and Arnoldi's f_m; also the
-    truncated basis with sketch-and-solve on the same problem."""
+    step (chunked staging), R_m the full-storage LDS of the LSQR step (m > 140:
+    packed triangle in LDS), H_hat the LDS of the quadrature square root
+    (m > 128, four rows per lane) and the registers of the sketched QR
+    (Householder in global memory), against the oracle's Algorithm 3 and
+    Arnoldi's f_m; also the truncated basis with sketch-and-solve on the same
+    problem.  m = 210, s = 440: R_m beyond the packed LDS size (global memory
+    in the LSQR step)."""
     from paper_2212_12758_amd import make_params
 
     st = W.laplacian3d(24)
@@ -261,6 +263,39 @@ def test_bg2_large_m_global_paths(ctx):
     out_t, _ = ctx.solve(A, _dev(b), f, make_params(m, 2, s, "srht", 8, 8, "fp64", "sketch"))
     ref_t = krylov.nt(Aor, b, f, m, 2, sk, "sketch")["f"]
     assert krylov.relerr(out_t.cpu().numpy(), ref_t) < 1e-8
+    A.destroy()
+    # m = 210 needs a larger grid: on 24^3 the Krylov space of that size is
+    # numerically degenerate (kappa(V) ~ 1e10 in the oracle, ||H_hat|| ~ 1e11)
+    st2 = W.laplacian3d(40)
+    b2 = W.rhs(st2.n, 8)
+    m2, s2 = 210, 440
+    f2 = W.FuncSpec("exp", alpha=-0.05)
+    w2 = W.Workload("lap3d40", st2, 8, 1, f2, m=m2, k=2, s=s2, sketch="srht", sketch_seed=8)
+    ref2 = krylov.sgs(operators.as_matrix(st2), b2, f2, m2, _sk(w2), passes=2)
+    A2 = ctx.matrix(st2)
+    print("case bg2 lap3d40 m=210 fp64", flush=True)
+    out2, info2 = ctx.solve(A2, _dev(b2), f2, _p(w2, "fp64", basis="sketched_gs2"))
+    assert info2[0]["m_used"] == m2 and info2[0]["ls_iters"] >= 1
+    assert krylov.relerr(out2.cpu().numpy(), ref2["f"]) < 1e-8
+    A2.destroy()
+
+
+def test_exp_norm_beyond_work_bound_is_refused(ctx):
+    """The Taylor action needs ceil(||alpha H_hat||_1 / 4) steps; beyond 4096
+    of them the solve returns FAB_ENUMERIC at once instead of running for a
+    time proportional to the norm."""
+    from paper_2212_12758_amd import ENUMERIC, FabError, make_params
+
+    st = W.laplacian2d(30)
+    b = W.rhs(st.n, 3)
+    A = ctx.matrix(st)
+    print("case exp refused", flush=True)
+    with pytest.raises(FabError) as e:
+        ctx.solve(A, _dev(b), W.FuncSpec("exp", alpha=-1e4), make_params(20, 2, 60, "srht", 8, 1, "fp64", "sketch"))
+    assert e.value.code == ENUMERIC
+    # just inside the bound: a result (||H_hat||_1 <= 16 for this Laplacian)
+    out, _ = ctx.solve(A, _dev(b), W.FuncSpec("exp", alpha=-1.0), make_params(20, 2, 60, "srht", 8, 1, "fp64", "sketch"))
+    assert np.isfinite(out.cpu().numpy()).all()
     A.destroy()
 
 
