@@ -291,15 +291,15 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
   }
   if (sc[LS_DONE] != 0.0) return;
   if (RL == 1) {
-    // eight loads in flight per thread (visible after the barrier below)
+    // sixteen loads in flight per thread (visible after the barrier below)
     const int n2 = mu * mu;
     int x = tid;
-    for (; x + 7 * 256 < n2; x += 8 * 256) {
-      double t[8];
+    for (; x + 15 * 256 < n2; x += 16 * 256) {
+      double t[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] = Rg[x + u * 256];
+      for (int u = 0; u < 16; ++u) t[u] = Rg[x + u * 256];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) rlds[x + u * 256] = t[u];
+      for (int u = 0; u < 16; ++u) rlds[x + u * 256] = t[u];
     }
     for (; x < n2; x += 256) rlds[x] = Rg[x];
   } else if (RL == 2) {
@@ -335,7 +335,15 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
       if (j < ns && grp < G) {
         const int slot = j < mu ? j : m;
         const int b0 = (int)((long long)grp * L.nblk / G), b1 = (int)((long long)(grp + 1) * L.nblk / G);
+        // 32 loads in flight (the sum itself stays in block order)
         int b = b0;
+        for (; b + 32 <= b1; b += 32) {
+          double t[32];
+#pragma unroll
+          for (int u = 0; u < 32; ++u) t[u] = L.part[((long long)(b + u) * nr + q) * m1 + slot];
+#pragma unroll
+          for (int u = 0; u < 32; ++u) a += t[u];
+        }
         for (; b + 8 <= b1; b += 8) {
           double t[8];
 #pragma unroll
