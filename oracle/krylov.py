@@ -354,20 +354,18 @@ def sfom(A, b: np.ndarray, f, m: int, k: int, sketch) -> np.ndarray:
 
 
 def square_operator(A):
-    """A^2 as a sparse matrix whose values are rounded to FP32: the operator
-    the sign function is evaluated with (CSR values are FP32 in the library;
-    A^2 of an integer stencil is exact)."""
+    """A^2 as an exact FP64 sparse product (the operator whose inverse square
+    root gives the sign function, Section 5.1.3).  Only FP64 rounding of the
+    product itself: no value is rounded to a lower precision."""
     import scipy.sparse as sps
 
-    A2 = sps.csr_matrix(A @ A)
-    A2.data = A2.data.astype(np.float32).astype(np.float64)
-    return A2
+    return sps.csr_matrix(A @ A)
 
 
 def sign_fAb(A, b: np.ndarray, m: int, k: int, sketch=None, ls: str = "sketch") -> dict:
     """sign(A) b = (A^2)^{-1/2} (A b) (Section 5.1.3, after Higham's
-    Chapter 5): the method of ``nt`` applied to the operator A^2 (FP32
-    values, ``square_operator``), the start vector A b and f(z) = z^{-1/2}."""
+    Chapter 5): the method of ``nt`` applied to the operator A^2
+    (``square_operator``), the start vector A b and f(z) = z^{-1/2}."""
     from types import SimpleNamespace
 
     f = SimpleNamespace(kind="pow", sigma=0.0, p=-0.5, alpha=0.0, coef=())

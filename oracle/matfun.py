@@ -8,6 +8,7 @@ Supported f (the function classes of the workloads):
   exp   f(z) = exp(alpha z)
   pow   f(z) = (z + sigma)^p, p in {+1/2, -1/2}  (principal branch)
   poly  f(z) = sum_j coef[j] z^j
+  sign  f(z) = sign(Re z)  (scalars only: the closed forms of sign(A) b)
 """
 from __future__ import annotations
 
@@ -77,4 +78,8 @@ def fscalar(f, z: np.ndarray) -> np.ndarray:
         for c in reversed(f.coef):
             y = y * z + c
         return y
+    if f.kind == "sign":
+        # the matrix sign function maps each eigenvalue to the sign of its
+        # real part (Section 5.1.3; undefined on the imaginary axis)
+        return np.sign(np.real(z))
     raise ValueError(f.kind)

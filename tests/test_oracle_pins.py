@@ -371,6 +371,81 @@ def test_estimates_definitions_pinned():
     assert krylov.estimates(none, f, 2.0**-24)["ls_gate"] == 0.0
 
 
+def _fp32_storage_basis(A, b, m, k):
+    """Algorithm 2 with every basis vector rounded to FP32 as it is stored
+    (the arithmetic stays FP64): the basis the FP32 path builds."""
+    n = b.size
+    V = np.zeros((m + 1, n))
+    H = np.zeros((m + 1, m))
+    beta = float(np.linalg.norm(b))
+    V[0] = (b / beta).astype(np.float32)
+    for i in range(1, m + 1):
+        w = A @ V[i - 1]
+        for j in range(max(0, i - k), i):
+            H[j, i - 1] = V[j] @ w
+            w = w - H[j, i - 1] * V[j]
+        H[i, i - 1] = np.linalg.norm(w)
+        V[i] = (w / H[i, i - 1]).astype(np.float32)
+    return V, H, beta
+
+
+@pytest.mark.parametrize("case", ["convdiff3d_exp", "lap2d_invsqrt", "rgg_invsqrt"])
+def test_round_est_pinned_against_fp32_rounding(case):
+    """The rounding estimate round_est = u sum_j |c_j| ||R e_j|| / ||R c||
+    (the FAB_PREC_AUTO fallback rule rests on it) against what rounding the
+    basis to FP32 actually does, on three operator families:
+
+    * storage rounding: rounding each v_j of the FP64 basis to FP32 moves
+      V_m c by `actual`; |fl(x) - x| <= u |x| gives the exact first-order
+      bound actual <= u sum_j |c_j| ||v_j|| / ||V_m c||;
+    * round_est is that bound with norms taken through the sketch (within
+      the embedding distortion, here 25%), and it overestimates `actual` by
+      at most C = 20 (rounding errors of different vectors add like random
+      vectors, not linearly);
+    * on the converged workloads (least-squares gate far below u) the whole
+      FP32-storage method, run step by step with rounded vectors, lands
+      within round_est of the FP64 result.
+    A unit roundoff of 2^-53 or a dropped |c_j| weight fails these bounds."""
+    u32 = 2.0 ** -24
+    if case == "convdiff3d_exp":
+        st = W.convdiff3d(16, 50.0)
+        A, b, f = operators.as_matrix(st), W.rhs(st.n, 2), W.FuncSpec("exp", alpha=-1e-3)
+        m, k, s, kind = 60, 4, 240, "srht"
+    elif case == "lap2d_invsqrt":
+        st = W.laplacian2d(64)
+        A, b, f = operators.as_matrix(st), W.rhs(st.n, 3), W.FuncSpec("pow", sigma=1e-3, p=-0.5)
+        m, k, s, kind = 80, 2, 200, "sparse_sign"
+    else:
+        A = operators.as_matrix(W.rgg_laplacian(4096, seed=3))
+        b, f = W.rhs(4096, 3), W.FuncSpec("pow", sigma=1e-3, p=-0.5)
+        m, k, s, kind = 60, 2, 120, "sparse_sign"
+    sk = sketch.Sketch(kind, b.size, s, 5, 8)
+    res = krylov.nt(A, b, f, m, k, sk, "sketch")
+    est = krylov.estimates(res, f, u32)["round_est"]
+    mu = res["m_used"]
+    V, c = res["V"][:mu].T, res["c"]
+    nvc = np.linalg.norm(V @ c)
+    actual = np.linalg.norm((V.astype(np.float32).astype(np.float64) - V) @ c) / nvc
+    bound = u32 * float(np.abs(c) @ np.linalg.norm(V, axis=0)) / nvc
+    assert actual <= bound
+    assert 0.8 * bound <= est <= 1.25 * bound
+    assert actual <= est <= 20.0 * actual
+    # planted slips: FP64's unit roundoff, or the weights |c_j| dropped
+    assert krylov.estimates(res, f, 2.0 ** -53)["round_est"] < actual
+    R = res["R"][:mu, :mu]
+    assert u32 * float(np.linalg.norm(R, axis=0).sum()) / np.linalg.norm(R @ c) > 20.0 * actual
+    if case in ("convdiff3d_exp",):
+        # end to end: the FP32-storage method (sketch-and-solve, as the FP32 path)
+        Vs, H, beta = _fp32_storage_basis(A, b, m, k)
+        SV = sk.apply(Vs.T)
+        Q, Rs = np.linalg.qr(SV[:, :m])
+        y = sl.solve_triangular(Rs, Q.T @ SV[:, m])
+        Hh = H[:m, :m].copy()
+        Hh[:, m - 1] += H[m, m - 1] * y
+        e2e = krylov.relerr(beta * (Vs[:m].T @ matfun.fmat_e1(f, Hh)), res["f"])
+        assert est / 20.0 <= e2e <= est
+
+
 def test_sketched_gs_basis_algorithm1_pinned():
     """Algorithm 1: the sketch of the basis is orthonormal, the Arnoldi-like
     relation (eq. (3)) holds, r_11 = ||Theta b||, and with the exact
@@ -480,37 +555,55 @@ def test_whitening_pinned():
 
 
 def test_sign_function_pinned():
-    """sign(A) b = (A^2)^{-1/2} (A b).  On a diagonal operator with entries
-    k/4 of both signs (squares exact in FP32 and distinct) the Krylov space of
-    A^2 is invariant after 8 steps, so the method at m = 8 returns
-    sign(d) * b; applying it twice returns b.  On a shifted (indefinite) 2D
-    Laplacian the full-Arnoldi form of the same formula approaches the DST
-    closed form S sign(lambda) S b as m grows."""
+    """sign(A) b = (A^2)^{-1/2} (A b) (Section 5.1.3).
+
+    * A non-normal, non-integer operator A = X diag(d) X^{-1} with six
+      distinct eigenvalues whose squares are distinct and not representable
+      in FP32: the Krylov space of A^2 for A b is invariant after 6 steps, so
+      the method at m = 8 with a window k = 8 (full orthogonalisation)
+      finds h_{7,6} at rounding level and returns sign(A) b exactly; the
+      reference is the dense eigendecomposition X sign(Lambda) X^{-1} b.
+      Rounding A^2 to FP32 (a planted slip) moves the result by ~1e-8 and
+      fails the 1e-12 bound.
+    * Applying the computed sign function twice returns b (sign^2 = I).
+    * On a shifted (indefinite) 2D Laplacian with a non-integer centre, A^2
+      is the exact FP64 product, and the full-Arnoldi form of the formula
+      approaches the DST closed form S sign(lambda) S b as m grows."""
     import scipy.fft as sfft
 
-    d = np.repeat([-3.0, -2.0, -1.5, -0.75, 0.5, 1.25, 2.5, 3.25], 100)
-    A = sp.diags(d).tocsr()
-    b = W.rhs(d.size, 4)
-    # m = 8: the degree of the minimal polynomial of A^2 for A b, so the
-    # compression is exact (Section 3's exactness at that degree)
-    res = krylov.sign_fAb(A, b, 8, 2, ls="none")
-    assert krylov.relerr(res["f"], np.sign(d) * b) < 1e-13
-    twice = krylov.sign_fAb(A, res["f"], 8, 2, ls="none")["f"]
-    assert krylov.relerr(twice, b) < 1e-13
-    # a planted slip (z^{-1/2} applied to A instead of A^2 through a shift) fails
+    SIGN = W.FuncSpec("sign")
+    n = 60
+    r = np.random.default_rng(41)
+    X = np.eye(n) + 0.3 * r.standard_normal((n, n)) / math.sqrt(n)
+    d = np.repeat([-2.3, -1.7, -0.45, 0.6, 1.35, 2.85], n // 6)
+    Ad = X @ np.diag(d) @ np.linalg.inv(X)
+    A = sp.csr_matrix(Ad)
+    b = r.standard_normal(n)
+    ref = closed_form.dense_fAb(Ad, SIGN, b)
+    res = krylov.sign_fAb(A, b, 8, 8, ls="none")   # window k = m: full orthogonalisation
+    H = res["Hbar"]
+    assert abs(H[6, 5]) < 1e-10 * np.abs(H).max()   # invariant after 6 steps (to rounding)
+    assert krylov.relerr(res["f"], ref) < 1e-12
+    twice = krylov.sign_fAb(A, res["f"], 8, 8, ls="none")["f"]
+    assert krylov.relerr(twice, b) < 1e-11
+    # planted slip: A^2 with FP32-rounded values
+    A2r = sp.csr_matrix(A @ A)
+    A2r.data = A2r.data.astype(np.float32).astype(np.float64)
     f = W.FuncSpec("pow", sigma=0.0, p=-0.5)
-    wrong = krylov.nt(A @ A + 0.5 * sp.identity(d.size), A @ b, f, 8, 2, None, "none")["f"]
-    assert krylov.relerr(wrong, np.sign(d) * b) > 1e-3
-    # shifted Laplacian: A^2 of the integer stencil is exact in FP32
+    wrong = krylov.nt(A2r, A @ b, f, 8, 8, None, "none")["f"]
+    assert krylov.relerr(wrong, ref) > 1e-9
+    # planted slip: z^{-1/2} applied to a shifted A^2
+    wrong = krylov.nt(A @ A + 0.5 * sp.identity(n), A @ b, f, 8, 8, None, "none")["f"]
+    assert krylov.relerr(wrong, ref) > 1e-3
+    # shifted Laplacian, non-integer centre 2.7: the exact FP64 square
     N, shift = 8, 1.3
     st = W.Stencil(2, N, N, 1, (4.0 - shift, -1.0, -1.0, -1.0, -1.0, 0.0, 0.0))
     L = operators.as_matrix(st)
-    st0 = W.Stencil(2, N, N, 1, (4.0, -1.0, -1.0, -1.0, -1.0, 0.0, 0.0))
-    L0 = operators.as_matrix(st0)
-    assert np.abs(krylov.square_operator(L0) - L0 @ L0).max() == 0.0
+    assert np.abs((krylov.square_operator(L) - L @ L).toarray()).max() == 0.0
     bl = W.rhs(st.n, 4)
     lam = closed_form.laplacian_eigs(W.laplacian2d(N)) - shift
     ref = sfft.dstn(sfft.dstn(bl.reshape(N, N), type=1, norm="ortho") * np.sign(lam), type=1, norm="ortho").ravel()
+    np.testing.assert_allclose(closed_form.dense_fAb(L.toarray(), SIGN, bl, symmetric=True), ref, atol=1e-12)
     e30 = krylov.relerr(krylov.fm(krylov.square_operator(L), L @ bl, f, 30), ref)
     e45 = krylov.relerr(krylov.fm(krylov.square_operator(L), L @ bl, f, 45), ref)
     assert e45 < 1e-5 and e45 < 1e-2 * e30
