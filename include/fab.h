@@ -64,11 +64,11 @@ enum fab_func_kind {
   FAB_F_POW = 2,      /* f(z) = (z + sigma)^p, p = +1/2 or -1/2 (principal branch) */
   FAB_F_POLY = 3,     /* f(z) = sum_j coef[j] z^j (test hook: exact for deg <= m-1) */
   FAB_F_SIGN = 4      /* f(z) = sign(Re z), computed as (A^2)^{-1/2} (A b) (Section 5.1.3):
-                         the method runs on the operator A^2 (formed once per matrix as
-                         CSR with FP32 values, exact for integer stencils, and kept until
-                         the matrix is destroyed) from the start vector A b, with
-                         f(z) = z^{-1/2}; m, k, s, ... apply to that solve; info.beta
-                         is ||A b||.  alpha, sigma, p are ignored.                   */
+                         the basis is built for the operator A^2, applied in every step
+                         as two products with A (FP64 arithmetic, the intermediate A u
+                         kept in FP64; A^2 is never formed), from the start vector A b,
+                         with f(z) = z^{-1/2}; m, k, s, ... apply to that solve;
+                         info.beta is ||A b||.  alpha, sigma, p are ignored.          */
 };
 typedef struct {
   int kind;
@@ -94,14 +94,18 @@ enum fab_ls_mode {
   FAB_LS_SKETCH = 1,          /* sketch-and-solve only (Remark 3; equivalent to sFOM)      */
   FAB_LS_NONE = 2,            /* y = 0: Algorithm 5                                        */
   FAB_LS_LSQR = 3,            /* always refine with sketch-preconditioned LSQR (Algorithm 4
-                                 with Blendenpik, Section 3.1.1)                            */
+                                 with Blendenpik, Section 3.1.1); LSQR stops when
+                                 ||M^T r|| <= (tol/10) ||M||_F ||r|| (Paige & Saunders'
+                                 test, M = V_m R^{-1}) or at ls_maxit (info.ls_limit = 1) */
   FAB_LS_GRAM = 4             /* the exact least squares through the Gram matrix of
                                  V_{m+1} (one pass over the basis, Cholesky of the normal
                                  equations; error ~ kappa(V)^2 u, for the well-conditioned
                                  sketched-GS and whitened bases).  Blocking calls with one
                                  right-hand side and m <= 127; otherwise, or when R's
-                                 diagonal spreads by more than 1e4 or a pivot fails, LSQR
-                                 as FAB_LS_LSQR.  Not in the paper, which uses LSQR.        */
+                                 diagonal spreads by more than 1e4, a pivot fails or the
+                                 estimated kappa_1(R) exceeds min(1e4, sqrt(tol/(10 u)))
+                                 (u = 2^-53, so that kappa^2 u <= tol/10), LSQR as
+                                 FAB_LS_LSQR.  Not in the paper, which uses LSQR.           */
 };
 
 /* Construction of the basis. */
@@ -144,7 +148,8 @@ typedef struct {
 
 /* Per right-hand side diagnostics. */
 typedef struct {
-  double err_est;     /* max(ls_gate, round_est): a-posteriori error estimate      */
+  double err_est;     /* max(ls_gate, round_est): a-posteriori error estimate; after an
+                         LSQR refinement max(Paige-Saunders measure, round_est)    */
   double ls_gate;     /* ||R (c_y - c_0)|| / ||R c_y||: sensitivity to the last column */
   double round_est;   /* basis-rounding amplification estimate                      */
   double conv_est;    /* ||R (c_m - [c_{m-d}; 0])|| / ||R c_m||, d = max(5, m/10)     */
@@ -158,6 +163,8 @@ typedef struct {
   int prec_used;      /* FAB_PREC_FP32 or FAB_PREC_FP64                              */
   int whitened_at;    /* FAB_BASIS_WHITENED: step at which the basis was whitened
                          (0: never)                                                  */
+  int ls_limit;       /* 1: the LSQR refinement stopped at its iteration limit before
+                         meeting its stopping test (err_est then exceeds tol/10)     */
   double latency_us;  /* submit-to-completion wall time                              */
 } fab_info;
 

@@ -21,7 +21,12 @@ constexpr int NSLOT = KMAX + 1;  // dot slots per rhs: k window dots + ||w||^2
 constexpr int BLOCK = 256;       // threads per streaming block
 constexpr int TILE_ELEMS = 4096; // max elements (rows * nrhs) per tile
 
+// Operator path of the streaming kernels: OP_STENCIL recomputes A u inside
+// the passes; OP_CSR reads w~ = A u from wbuf, written by a product launch
+// before the passes (a CSR matrix, or A applied twice for the sign function).
 enum OpKind { OP_STENCIL = 0, OP_CSR = 1 };
+// How that product launch forms w~ (operator_product, k_csr.hip).
+enum ProdKind { PROD_FUSED = 0, PROD_CSR = 1, PROD_SQ_STENCIL = 2, PROD_SQ_CSR = 3 };
 enum SketchKind { SK_SRHT = 1, SK_SPARSE = 2 };
 
 struct SolveDev {
@@ -30,7 +35,8 @@ struct SolveDev {
   int nrhs, lognrhs;     // rhs count (power of two <= 32)
   int m, k, s, zeta;
   // operator
-  int op;                // OpKind
+  int op;                // OpKind of the streaming kernels
+  int prod;              // ProdKind: how w~ is formed for op == OP_CSR
   int nx, ny, nz;
   double c[7];           // stencil coefficients (centre, x-, x+, y-, y+, z-, z+)
   const int* rowptr;
@@ -39,7 +45,8 @@ struct SolveDev {
   // basis
   void* V;
   long long ldv;         // n * nrhs
-  double* wbuf;          // CSR: w~ [n][nrhs]
+  double* wbuf;          // OP_CSR: w~ [n][nrhs]
+  double* wtmp;          // PROD_SQ_*: A u, the intermediate of A (A u) [n][nrhs]
   const double* b;       // right-hand sides [n][nrhs]
   // small state, per rhs
   double* H;             // [nrhs][(m+1)*m]
@@ -70,7 +77,7 @@ struct SolveDev {
 
 // Per-rhs workspace of the small dense stages (FP64, column-major).
 constexpr int MAXCOEF = 64;
-constexpr int NINFO = 16;
+constexpr int NINFO = 20;
 struct DenseDev {
   int m, s, nrhs;
   long long stride;      // doubles per rhs
@@ -102,7 +109,8 @@ enum {
   INFO_ROUND = 10,   // u sum_j |c_j| ||R e_j|| / ||R c||
   INFO_CONV = 11,    // ||R (c - [c_{m-d}; 0])|| / ||R c||
   INFO_VFAIL = 12,   // [12 + v]: failure of variant v's f evaluation
-  INFO_LSQR_RATIO = 15   // last LSQR step relative to the solution (z-norm)
+  INFO_LSQR_RATIO = 15,  // Paige-Saunders measure ||M^T r|| / (||M||_F ||r||) of the last LSQR iteration
+  INFO_LSQR_LIMIT = 16   // 1: LSQR stopped at its iteration limit before meeting its test
 };
 
 // LSQR refinement state (see k_lsqr.hip)
@@ -113,7 +121,7 @@ struct LsqrDev {
   long long stride;
   int* alldone;          // every rhs stopped: remaining launches return
   int nblk, maxit;
-  double tol;            // stop when the step is below tol relative to z
+  double tol;            // stop when ||M^T r|| <= tol ||M||_F ||r|| (Paige-Saunders)
 };
 
 // The f evaluations of the dense tail.  Variant 0 is the result (H_hat of

@@ -39,6 +39,8 @@ constexpr int EPT = 8;   // elements per thread per tile
 
 // y = A x for the CSR operator (k_csr.hip); x is FP32 (esize 4) or FP64.
 hipError_t csr_spmv(const SolveDev& d, const void* x, int esize, double* y, hipStream_t st);
+// w~ = A x (d.prod == PROD_CSR) or A (A x) (PROD_SQ_*) into y (k_csr.hip).
+hipError_t operator_product(const SolveDev& d, const void* x, int esize, double* y, hipStream_t st);
 
 // ------------------------------------------------------------------ 8-element memory helpers
 __device__ inline void load8(const float* __restrict__ p, double* v) {

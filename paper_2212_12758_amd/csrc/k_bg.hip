@@ -374,25 +374,11 @@ __global__ void __launch_bounds__(256) k_bg_update(SolveDev d, const double* __r
   }
 }
 
-// y = A x for FP64 vectors [n][nrhs] and the stencil operator (the start
-// vector A b of the sign function; csr_spmv serves a CSR operator).
-__global__ void __launch_bounds__(256) k_apply_op(SolveDev d, const double* __restrict__ x, double* __restrict__ y) {
-  const long long nel = (long long)d.n * d.nrhs;
-  for (long long e = ((long long)blockIdx.x * 256 + threadIdx.x) * EPT; e < nel;
-       e += (long long)gridDim.x * 256 * EPT) {
-    double c[EPT], w[EPT];
-    get8(x, e, nel, c);
-    apply8<double>(d, x, e, nel, c, w);
-    for (int j = 0; j < EPT; ++j)
-      if (e + j < nel) y[e + j] = w[j];
-  }
-}
-
 template <typename T, int OP>
 hipError_t apply_t(const SolveDev& d, int i, hipStream_t st, size_t lds) {
   const dim3 g(d.nblk);
   if (OP == OP_CSR) {
-    const hipError_t r = csr_spmv(d, (const T*)d.V + (long long)(i - 1) * d.ldv, (int)sizeof(T), d.wbuf, st);
+    const hipError_t r = operator_product(d, (const T*)d.V + (long long)(i - 1) * d.ldv, (int)sizeof(T), d.wbuf, st);
     if (r != hipSuccess) return r;
   }
   if (d.log_tile == 11) {
@@ -433,15 +419,6 @@ hipError_t bg_apply(const SolveDev& d, int esize, int i, hipStream_t st, size_t 
   const bool csr = d.op == OP_CSR;
   if (esize == 4) return csr ? apply_t<float, OP_CSR>(d, i, st, lds) : apply_t<float, OP_STENCIL>(d, i, st, lds);
   return csr ? apply_t<double, OP_CSR>(d, i, st, lds) : apply_t<double, OP_STENCIL>(d, i, st, lds);
-}
-
-hipError_t apply_operator(const SolveDev& d, const double* x, double* y, hipStream_t st) {
-  const long long nel = (long long)d.n * d.nrhs;
-  long long g = (nel + 256 * EPT - 1) / (256 * EPT);
-  if (g > 4096) g = 4096;
-  if (d.op == OP_CSR) return csr_spmv(d, x, 8, y, st);
-  hipLaunchKernelGGL(k_apply_op, dim3((unsigned)g), dim3(256), 0, st, d, x, y);
-  return hipGetLastError();
 }
 
 hipError_t bg_reduce(const SolveDev& d, int col, hipStream_t st) {

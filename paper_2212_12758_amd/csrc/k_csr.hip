@@ -1,5 +1,14 @@
-// y = A x for the CSR operator (the operator application of every Krylov
-// step, Algorithm 2 and Algorithm 1, when A is given as a sparse matrix).
+// Operator products that run as launches of their own:
+//
+//  * y = A x for the CSR operator (the operator application of every Krylov
+//    step, Algorithm 2 and Algorithm 1, when A is given as a sparse matrix);
+//  * y = A (A x) for the sign function, sign(A) b = (A^2)^{-1/2} (A b)
+//    (Section 5.1.3): the basis is built for A^2, which is applied as two
+//    products with A (stencil or CSR), the intermediate A x kept in FP64, so
+//    A^2 is never formed;
+//  * y = A x of FP64 vectors (the start vector A b of the sign function).
+//
+// CSR scheme:
 //
 // x and y are [n][nrhs] (element (row r, rhs q) at r*nrhs + q); x is FP32 or
 // FP64 (a basis column or an FP64 vector), y is FP64 (the w~ buffer read by
@@ -142,6 +151,42 @@ k_csr_spmv1(const int* __restrict__ rowptr, const int* __restrict__ col, const f
   if (own) y[r] = acc;
 }
 
+// y = A x for the stencil operator, x FP32 or FP64 [n][nrhs], y FP64.
+template <typename T>
+__global__ void __launch_bounds__(256) k_stencil_apply(SolveDev d, const T* __restrict__ x, double* __restrict__ y) {
+  const long long nel = (long long)d.n * d.nrhs;
+  for (long long e = ((long long)blockIdx.x * 256 + threadIdx.x) * EPT; e < nel;
+       e += (long long)gridDim.x * 256 * EPT) {
+    double c[EPT], w[EPT];
+    get8(x, e, nel, c);
+    stencil8(d, x, e, nel, c, w);
+    if (e + EPT <= nel) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        double2 o;
+        o.x = w[2 * h];
+        o.y = w[2 * h + 1];
+        *reinterpret_cast<double2*>(y + e + 2 * h) = o;
+      }
+    } else {
+      for (int j = 0; j < EPT; ++j)
+        if (e + j < nel) y[e + j] = w[j];
+    }
+  }
+}
+
+hipError_t stencil_apply(const SolveDev& d, const void* x, int esize, double* y, hipStream_t st) {
+  const long long nel = (long long)d.n * d.nrhs;
+  long long g = (nel + 256 * EPT - 1) / (256 * EPT);
+  if (g > 4096) g = 4096;
+  if (g == 0) return hipSuccess;
+  if (esize == 4)
+    hipLaunchKernelGGL(k_stencil_apply<float>, dim3((unsigned)g), dim3(256), 0, st, d, (const float*)x, y);
+  else
+    hipLaunchKernelGGL(k_stencil_apply<double>, dim3((unsigned)g), dim3(256), 0, st, d, (const double*)x, y);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t csr_spmv(const SolveDev& d, const void* x, int esize, double* y, hipStream_t st) {
@@ -165,6 +210,30 @@ hipError_t csr_spmv(const SolveDev& d, const void* x, int esize, double* y, hipS
     hipLaunchKernelGGL(k_csr_spmv<double>, dim3((unsigned)g), dim3(SPMV_BLOCK), 0, st, d.rowptr, d.col, d.val,
                        (const double*)x, y, d.n, d.lognrhs);
   return hipGetLastError();
+}
+
+hipError_t operator_product(const SolveDev& d, const void* x, int esize, double* y, hipStream_t st) {
+  switch (d.prod) {
+    case PROD_CSR:
+      return csr_spmv(d, x, esize, y, st);
+    case PROD_SQ_STENCIL: {
+      const hipError_t r = stencil_apply(d, x, esize, d.wtmp, st);
+      return r != hipSuccess ? r : stencil_apply(d, d.wtmp, 8, y, st);
+    }
+    case PROD_SQ_CSR: {
+      const hipError_t r = csr_spmv(d, x, esize, d.wtmp, st);
+      return r != hipSuccess ? r : csr_spmv(d, d.wtmp, 8, y, st);
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// y = A x for FP64 x with the operator A itself (stencil or CSR), whatever
+// the basis is built for: the start vector A b of the sign function.
+hipError_t apply_operator(const SolveDev& d, const double* x, double* y, hipStream_t st) {
+  if (d.prod == PROD_CSR || d.prod == PROD_SQ_CSR) return csr_spmv(d, x, 8, y, st);
+  return stencil_apply(d, x, 8, y, st);
 }
 
 }  // namespace fab

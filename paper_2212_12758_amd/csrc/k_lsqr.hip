@@ -13,6 +13,14 @@
 // solves with R and R^T, the LSQR recurrences, the stopping test and the
 // coefficients of the next pass).  The launch sequence has a fixed length;
 // once every rhs has stopped the remaining launches return immediately.
+//
+// Stopping test: Paige & Saunders' second criterion, ||M^T r|| <= atol
+// ||M|| ||r|| (the iterate then solves a least-squares problem whose matrix
+// is within a relative atol of M), with ||r_k|| = phibar_{k+1},
+// ||M^T r_k|| = phibar_{k+1} alpha_{k+1} |c_k| and their Frobenius-norm
+// estimate ||M||_F^2 ~ sum (alpha_k^2 + beta_{k+1}^2), so the test reads
+// alpha_{k+1} |c_k| / ||M||_F <= atol.  An iteration limit reached before
+// that is recorded (INFO_LSQR_LIMIT).
 #include "k_basis.h"
 
 namespace fab {
@@ -22,7 +30,11 @@ namespace {
 // per-rhs state, stride lsqr_state_stride(m) doubles:
 //   [0, m1) v   [m1, 2m1) w   [2m1, 3m1) x   [3m1, 4m1) pass coefficients
 //   [4m1, 5m1) scratch   then scalars at 5m1 + k
-enum { LS_A = 0, LS_ALPHA, LS_BETA, LS_RHOBAR, LS_PHIBAR, LS_DONE, LS_ITERS, LS_RATIO, LS_NSCAL = 16 };
+// LS_RATIO: the Paige-Saunders measure alpha |c| / ||M||_F of the last
+// iteration; LS_ANORM2: the running ||M||_F^2 estimate; LS_LIMIT: 1 when the
+// iteration limit stopped the refinement before the test was met.
+enum { LS_A = 0, LS_ALPHA, LS_BETA, LS_RHOBAR, LS_PHIBAR, LS_DONE, LS_ITERS, LS_RATIO, LS_ANORM2, LS_LIMIT,
+       LS_NSCAL = 16 };
 
 // Solve U^T x = z (U upper triangular, column-major, leading dimension ldu)
 // by one wave: forward substitution with rows in registers.
@@ -285,6 +297,8 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
       sc[LS_DONE] = (brk || mu == 0 || g.ls_mode == 2) ? 1.0 : 0.0;
       sc[LS_ITERS] = 0.0;
       sc[LS_RATIO] = 0.0;
+      sc[LS_ANORM2] = 0.0;
+      sc[LS_LIMIT] = 0.0;
     }
     for (int j = tid; j < m1; j += 256) x[j] = 0.0;
     __syncthreads();
@@ -391,6 +405,7 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
     if (tid == 0) {
       sc[LS_PHIBAR] = beta;
       sc[LS_RHOBAR] = alpha;
+      sc[LS_ALPHA] = alpha;
       if (!(beta > 0.0) || !(alpha > 0.0)) sc[LS_DONE] = 1.0;   // y = 0 solves it
     }
   } else {
@@ -399,23 +414,29 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
     const double c = rho > 0.0 ? rhobar / rho : 1.0, s = rho > 0.0 ? beta / rho : 0.0;
     const double theta = s * alpha, phi = c * phibar;
     const double step = rho > 0.0 ? phi / rho : 0.0;
-    double dx2 = 0.0, x2 = 0.0;
     for (int j = tid; j < mu; j += 256) {
-      const double dx = step * w[j];
-      x[j] += dx;
-      dx2 += dx * dx;
-      x2 += x[j] * x[j];
+      x[j] += step * w[j];
       w[j] = v[j] - (rho > 0.0 ? theta / rho : 0.0) * w[j];
     }
-    dx2 = bsum256(dx2, sh);
-    x2 = bsum256(x2, sh);
+    __syncthreads();
     if (tid == 0) {
+      const double alpha_old = sc[LS_ALPHA];
+      const double anorm2 = sc[LS_ANORM2] + alpha_old * alpha_old + beta * beta;
+      sc[LS_ANORM2] = anorm2;
+      sc[LS_ALPHA] = alpha;
       sc[LS_RHOBAR] = -c * alpha;
       sc[LS_PHIBAR] = s * phibar;
       sc[LS_ITERS] += 1.0;
-      const double ratio = x2 > 0.0 ? sqrt(dx2 / x2) : 0.0;
-      sc[LS_RATIO] = ratio;
-      if (ratio <= L.tol || sc[LS_ITERS] >= L.maxit || !(alpha > 0.0) || !(beta > 0.0)) sc[LS_DONE] = 1.0;
+      // ||M^T r|| / (||M||_F ||r||)
+      const double ps = anorm2 > 0.0 ? alpha * fabs(c) / sqrt(anorm2) : 0.0;
+      sc[LS_RATIO] = ps;
+      const bool met = ps <= L.tol || !(alpha > 0.0) || !(beta > 0.0);
+      if (met) {
+        sc[LS_DONE] = 1.0;
+      } else if (sc[LS_ITERS] >= L.maxit) {
+        sc[LS_DONE] = 1.0;
+        sc[LS_LIMIT] = 1.0;
+      }
     }
   }
   __syncthreads();
@@ -455,6 +476,7 @@ __global__ void __launch_bounds__(256) k_lsqr_finish(SolveDev d, DenseDev g, Lsq
   if (tid == 0) {
     info[INFO_LSQR_IT] = sc[LS_ITERS];
     info[INFO_LSQR_RATIO] = sc[LS_RATIO];
+    info[INFO_LSQR_LIMIT] = sc[LS_LIMIT];
   }
   if (brk || mu == 0 || g.ls_mode == 2) return;
   __shared__ double y[512];
@@ -479,9 +501,10 @@ __global__ void __launch_bounds__(256) k_lsqr_finish(SolveDev d, DenseDev g, Lsq
 // pass over the stored vectors forms G = U^T U (FP64 accumulation, one right-
 // hand side, m + 1 <= GR_MAXC), then with D = diag(eta), G~ = D^{-1} G D^{-1},
 // G~_m = R^T R (Cholesky) and R^T R y = G~[:m, m].  The error is about
-// kappa(V)^2 u; the factorisation reports failure (the caller then runs LSQR)
-// on a non-positive pivot, a diagonal spread of R above GR_MAXRATIO or an
-// estimated kappa_1(R) above GR_MAXCOND.
+// kappa(V)^2 u (u the FP64 unit roundoff); the factorisation reports failure
+// (the caller then runs LSQR) on a non-positive pivot, a diagonal spread of R
+// above GR_MAXRATIO, or an estimated kappa_1(R) above `maxcond` =
+// min(GR_MAXCOND, sqrt(tol / (10 u))), so that kappa^2 u <= tol / 10.
 constexpr int GR_TILE = 16, GR_T = 8, GR_MAXC = GR_T * GR_TILE;   // m + 1 <= 128
 constexpr int GR_NT = GR_T * (GR_T + 1) / 2;                      // upper 16 x 16 tiles
 constexpr int GR_RCH = 32;                                          // rows per staged chunk
@@ -624,7 +647,7 @@ __global__ void __launch_bounds__(256) k_vgram_reduce(SolveDev d, DenseDev g, co
 
 // Cholesky of G~_m, y from the normal equations, H_hat; *fail = 1 when the
 // factorisation is not usable (the caller then refines by LSQR instead).
-__global__ void __launch_bounds__(512) k_vgram_solve(SolveDev d, DenseDev g, int* fail) {
+__global__ void __launch_bounds__(512) k_vgram_solve(SolveDev d, DenseDev g, int* fail, double maxcond) {
   extern __shared__ double R[];   // mu x mu, ld mu
   __shared__ double rhs[GR_MAXC], y[GR_MAXC];
   const int tid = threadIdx.x;
@@ -638,6 +661,7 @@ __global__ void __launch_bounds__(512) k_vgram_solve(SolveDev d, DenseDev g, int
     *fail = 0;
     info[INFO_LSQR_IT] = 0.0;
     info[INFO_LSQR_RATIO] = 0.0;
+    info[INFO_LSQR_LIMIT] = 0.0;
   }
   if (brk || mu == 0 || g.ls_mode == 2) return;
   for (int x = tid; x < mu * mu; x += 512) {
@@ -681,7 +705,7 @@ __global__ void __launch_bounds__(512) k_vgram_solve(SolveDev d, DenseDev g, int
     if (tid == 0) kap = k1;
   }
   __syncthreads();
-  if (!(kap <= GR_MAXCOND)) {
+  if (!(kap <= maxcond)) {
     if (tid == 0) *fail = 1;
     return;
   }
@@ -760,13 +784,14 @@ bool gram_ls_supported(const SolveDev& d) { return d.nrhs == 1 && d.m + 1 <= GR_
 size_t gram_ls_partial_doubles() { return (size_t)GR_BLOCKS * GR_NT * 256; }
 
 // The exact least-squares solve from the Gram matrix (one right-hand side).
-hipError_t gram_ls_launch(const SolveDev& d, const DenseDev& g, double* part, int* fail, int esize,
+hipError_t gram_ls_launch(const SolveDev& d, const DenseDev& g, double* part, int* fail, int esize, double tol,
                           hipStream_t st) {
   if (!gram_ls_supported(d)) return hipErrorInvalidValue;
+  const double maxcond = fmin(GR_MAXCOND, sqrt(fmax(tol, 0.0) / (10.0 * ldexp(1.0, -53))));
   if (esize == 4) hipLaunchKernelGGL(k_vgram<float>, dim3(GR_BLOCKS), dim3(256), 0, st, d, part);
   else hipLaunchKernelGGL(k_vgram<double>, dim3(GR_BLOCKS), dim3(256), 0, st, d, part);
   hipLaunchKernelGGL(k_vgram_reduce, dim3(GR_NT), dim3(256), 0, st, d, g, (const double*)part, GR_BLOCKS);
-  hipLaunchKernelGGL(k_vgram_solve, dim3(1), dim3(512), (size_t)d.m * d.m * 8, st, d, g, fail);
+  hipLaunchKernelGGL(k_vgram_solve, dim3(1), dim3(512), (size_t)d.m * d.m * 8, st, d, g, fail, maxcond);
   return hipGetLastError();
 }
 

@@ -57,7 +57,8 @@ hipError_t lsqr_iterate(const SolveDev& d, const DenseDev& g, const LsqrDev& L, 
 hipError_t lsqr_end(const SolveDev& d, const DenseDev& g, const LsqrDev& L, hipStream_t st);
 bool gram_ls_supported(const SolveDev& d);
 size_t gram_ls_partial_doubles();
-hipError_t gram_ls_launch(const SolveDev& d, const DenseDev& g, double* part, int* fail, int esize, hipStream_t st);
+hipError_t gram_ls_launch(const SolveDev& d, const DenseDev& g, double* part, int* fail, int esize, double tol,
+                          hipStream_t st);
 hipError_t lsqr_set_attributes();
 hipError_t bg_apply(const SolveDev& d, int esize, int i, hipStream_t st, size_t lds);
 hipError_t bg_reduce(const SolveDev& d, int col, hipStream_t st);
@@ -162,8 +163,6 @@ struct fab_matrix_s {
   int* col = nullptr;
   float* val = nullptr;
   std::atomic<int> refs{0};
-  fab_matrix square = nullptr;   // A^2 as CSR, built at the first sign-function request
-  std::mutex sq_mu;
 };
 
 namespace {
@@ -185,10 +184,10 @@ struct Plan {
   int whitened_at = 0;         // step at which the last solve whitened (0: never)
   size_t oBgCf = 0;            // Algorithm 1 update weights [nrhs][m+2]
   size_t oFq = 0;              // quadrature partial sums of the square root (FAB_F_POW)
-  bool sign = false;           // FAB_F_SIGN: the solve runs on A^2 from A b
-  fab_matrix Aorig = nullptr;  // A itself (the operator of the start vector A b)
+  bool sign = false;           // FAB_F_SIGN: the basis is built for A^2 (A applied twice) from A b
   fab_func forig{};            // the caller's f (kind FAB_F_SIGN)
   size_t oSignB = 0;           // A b, FP64 [n][nrhs]
+  size_t oWtmp = 0;            // A u, the intermediate of A (A u), FP64 [n][nrhs]
   bool gram = false;           // FAB_LS_GRAM with one rhs and m + 1 <= 128: exact least squares
   bool gram_used = false;      // the last refinement solved through the Gram matrix
   size_t oGpart = 0, oGflag = 0;
@@ -217,14 +216,12 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp, int esize, Plan& P) {
   if (!A || !pp) return FAB_EINVAL;
-  // sign(A) b = (A^2)^{-1/2} (A b): plan the inverse square root on A^2
+  // sign(A) b = (A^2)^{-1/2} (A b): plan the inverse square root with the
+  // operator A^2, applied as two products with A in every step
   fab_func f = fin;
   const bool sign = fin.kind == FAB_F_SIGN;
   if (sign) {
-    if (!A->square) return FAB_EINVAL;
-    P.Aorig = A;
     P.forig = fin;
-    A = A->square;
     f = fab_func{FAB_F_POW, 0.0, 0.0, -0.5, nullptr, 0};
   }
   P.sign = sign;
@@ -296,7 +293,8 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
   size_t w = 0;
   auto take = [&](size_t bytes) { size_t at = w; w = align256(w + bytes); return at; };
   P.oV = take((size_t)(m + 1) * P.ldv * esize);
-  P.oW = A->op == OP_CSR ? take((size_t)n * nrhs * 8) : 0;
+  P.oW = (A->op == OP_CSR || sign) ? take((size_t)n * nrhs * 8) : 0;
+  P.oWtmp = sign ? take((size_t)n * nrhs * 8) : 0;
   P.oH = take((size_t)nrhs * (m + 1) * m * 8);
   P.oEta = take((size_t)nrhs * (m + 1) * 8);
   P.oWn = take((size_t)nrhs * (m + 1) * 8);
@@ -462,6 +460,7 @@ SolveDev operator_desc(fab_matrix A, int nrhs) {
   d.nrhs = nrhs;
   d.lognrhs = ilog2(nrhs);
   d.op = A->op;
+  d.prod = A->op == OP_CSR ? PROD_CSR : PROD_FUSED;
   d.nx = A->nx;
   d.ny = A->ny;
   d.nz = A->nz;
@@ -485,7 +484,10 @@ void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev
   d.k = p.k;
   d.s = s;
   d.zeta = p.zeta;
-  d.op = A->op;
+  // a CSR matrix and the sign function's A^2 reach the streaming passes as
+  // a product written to wbuf before them; a stencil alone is fused
+  d.op = (A->op == OP_CSR || P.sign) ? OP_CSR : OP_STENCIL;
+  d.prod = P.sign ? (A->op == OP_CSR ? PROD_SQ_CSR : PROD_SQ_STENCIL) : (A->op == OP_CSR ? PROD_CSR : PROD_FUSED);
   d.nx = A->nx;
   d.ny = A->ny;
   d.nz = A->nz;
@@ -495,7 +497,8 @@ void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev
   d.val = A->val;
   d.V = ws + P.oV;
   d.ldv = P.ldv;
-  d.wbuf = A->op == OP_CSR ? (double*)(ws + P.oW) : nullptr;
+  d.wbuf = d.op == OP_CSR ? (double*)(ws + P.oW) : nullptr;
+  d.wtmp = P.sign ? (double*)(ws + P.oWtmp) : nullptr;
   d.b = P.sign ? (const double*)(ws + P.oSignB) : P.b;
   d.H = (double*)(ws + P.oH);
   d.eta = (double*)(ws + P.oEta);
@@ -571,7 +574,7 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
   };
   if (P.sign) {
     // start vector A b of the solve on A^2
-    SolveDev da = operator_desc(P.Aorig, P.nrhs);
+    SolveDev da = operator_desc(P.A, P.nrhs);
     B(FAB_K_OTHER);
     e = apply_operator(da, P.b, (double*)(ws + P.oSignB), st);
     E();
@@ -701,8 +704,11 @@ int collect_info(const Plan& P, const double* hinfo, std::vector<fab_info>& out)
       fi.err_est = fi.ls_gate = fi.round_est = fi.conv_est = 0.0;
     }
     fi.ls_iters = (int)in[INFO_LSQR_IT];
-    // refined: the least-squares part of the error is the last LSQR step
-    // (zero after the exact solve through the Gram matrix)
+    fi.ls_limit = in[INFO_LSQR_LIMIT] != 0.0 ? 1 : 0;
+    // refined: the least-squares part of the error is the Paige-Saunders
+    // measure of the last LSQR iteration (a backward error of the least
+    // squares; zero after the exact solve through the Gram matrix, which is
+    // only accepted when kappa(R)^2 u <= tol / 10)
     if (fi.ls_iters > 0) fi.err_est = std::max(in[INFO_LSQR_RATIO], fi.round_est);
     if (P.gram_used) fi.err_est = fi.round_est;
     fi.fell_back = 0;
@@ -742,7 +748,8 @@ int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* h
   P.gram_used = false;
   if (P.gram && host_flag) {
     int* gflag = (int*)(ws + P.oGflag);
-    if (gram_ls_launch(d, g, (double*)(ws + P.oGpart), gflag, P.esize, st) != hipSuccess) return FAB_EDEVICE;
+    if (gram_ls_launch(d, g, (double*)(ws + P.oGpart), gflag, P.esize, P.p.tol, st) != hipSuccess)
+      return FAB_EDEVICE;
     *host_flag = 1;
     if (hipMemcpyAsync(host_flag, gflag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
@@ -808,7 +815,7 @@ void retire_locked(fab_ctx ctx, Request& r) {
     Plan P2;
     fab_func f2 = r.plan.sign ? r.plan.forig : r.plan.f;
     if (f2.kind == FAB_F_POLY) f2.coef = r.plan.coef.data();   // the caller's array may be gone
-    if (make_plan(r.plan.sign ? r.plan.Aorig : r.plan.A, r.plan.nrhs, f2, &r.plan.p, 8, P2) == FAB_OK &&
+    if (make_plan(r.plan.A, r.plan.nrhs, f2, &r.plan.p, 8, P2) == FAB_OK &&
         ctx->arena.could_ever_fit(P2.bytes)) {
       P2.b = r.plan.b;
       P2.out = r.plan.out;
@@ -1069,79 +1076,7 @@ int fab_create_matrix_csr(fab_ctx ctx, int64_t n, int64_t nnz, const int32_t* ro
   return FAB_OK;
 }
 
-// ---------------------------------------------------------------- A^2 for the sign function
 namespace {
-
-// A in CSR on the host (FP64 values): generated from the stencil, or copied back.
-int host_csr(fab_matrix A, std::vector<int>& rp, std::vector<int>& ci, std::vector<double>& va) {
-  const int n = A->n;
-  rp.assign(n + 1, 0);
-  ci.clear();
-  va.clear();
-  if (A->op == OP_STENCIL) {
-    const int nx = A->nx, ny = A->ny, nz = A->nz;
-    for (int r = 0; r < n; ++r) {
-      const int x = r % nx, y = (r / nx) % ny, z = r / (nx * ny);
-      auto put = [&](int cc, double v) {
-        if (v != 0.0) { ci.push_back(cc); va.push_back(v); }
-      };
-      if (z > 0) put(r - nx * ny, A->c[5]);
-      if (y > 0) put(r - nx, A->c[3]);
-      if (x > 0) put(r - 1, A->c[1]);
-      put(r, A->c[0]);
-      if (x < nx - 1) put(r + 1, A->c[2]);
-      if (y < ny - 1) put(r + nx, A->c[4]);
-      if (z < nz - 1) put(r + nx * ny, A->c[6]);
-      rp[r + 1] = (int)ci.size();
-    }
-    return FAB_OK;
-  }
-  std::vector<float> vf((size_t)A->nnz);
-  ci.resize((size_t)A->nnz);
-  if (hipMemcpy(rp.data(), A->rowptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-      (A->nnz > 0 && hipMemcpy(ci.data(), A->col, (size_t)A->nnz * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
-      (A->nnz > 0 && hipMemcpy(vf.data(), A->val, (size_t)A->nnz * 4, hipMemcpyDeviceToHost) != hipSuccess))
-    return FAB_EDEVICE;
-  va.assign(vf.begin(), vf.end());
-  return FAB_OK;
-}
-
-// Row-by-row sparse product (Gustavson): C = A A, FP64 accumulation, FP32
-// values, columns of each row in increasing order.
-int ensure_square(fab_ctx ctx, fab_matrix A) {
-  std::lock_guard<std::mutex> lk(A->sq_mu);
-  if (A->square) return FAB_OK;
-  std::vector<int> rp, ci;
-  std::vector<double> va;
-  int rc = host_csr(A, rp, ci, va);
-  if (rc != FAB_OK) return rc;
-  const int n = A->n;
-  std::vector<int> crp(n + 1, 0), ccol, mark(n, -1);
-  std::vector<float> cval;
-  std::vector<double> acc(n, 0.0);
-  std::vector<int> cols;
-  for (int r = 0; r < n; ++r) {
-    cols.clear();
-    for (int p = rp[r]; p < rp[r + 1]; ++p) {
-      const int k = ci[p];
-      const double a = va[p];
-      for (int q = rp[k]; q < rp[k + 1]; ++q) {
-        const int c = ci[q];
-        if (mark[c] != r) { mark[c] = r; acc[c] = 0.0; cols.push_back(c); }
-        acc[c] += a * va[q];
-      }
-    }
-    std::sort(cols.begin(), cols.end());
-    for (int c : cols) { ccol.push_back(c); cval.push_back((float)acc[c]); }
-    if (ccol.size() >= (size_t)INT32_MAX) return FAB_ENOMEM;
-    crp[r + 1] = (int)ccol.size();
-  }
-  fab_matrix S = nullptr;
-  rc = fab_create_matrix_csr(ctx, n, (int64_t)ccol.size(), crp.data(), ccol.data(), cval.data(), 0, &S);
-  if (rc != FAB_OK) return rc;
-  A->square = S;
-  return FAB_OK;
-}
 
 // Release a matrix's graphs, memory and registration (callers hold solve_mu and mu).
 void release_matrix_locked(fab_ctx ctx, fab_matrix A) {
@@ -1169,8 +1104,7 @@ int fab_destroy_matrix(fab_matrix A) {
   // lock order everywhere: solve_mu, then mu
   std::lock_guard<std::mutex> slk(ctx->solve_mu);
   std::lock_guard<std::mutex> lk(ctx->mu);
-  if (A->refs.load() > 0 || (A->square && A->square->refs.load() > 0)) return FAB_EBUSY;
-  if (A->square) release_matrix_locked(ctx, A->square);
+  if (A->refs.load() > 0) return FAB_EBUSY;
   release_matrix_locked(ctx, A);
   return FAB_OK;
 }
@@ -1269,10 +1203,6 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
   const double t0 = now_us();
   std::lock_guard<std::mutex> slk(ctx->solve_mu);
   hipSetDevice(ctx->device);
-  if (f.kind == FAB_F_SIGN) {
-    const int rs = ensure_square(ctx, A);
-    if (rs != FAB_OK) return rs;
-  }
   int esize = esize_for(p->prec == FAB_PREC_FP64 ? FAB_PREC_FP64 : FAB_PREC_FP32);
   Plan P;
   std::vector<fab_info> fi;
@@ -1398,11 +1328,6 @@ int fab_profile_read(fab_ctx ctx, int cls, long long* launches, double* total_ms
 int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, const fab_params* p, double* out,
                fab_request* req) {
   if (!ctx || !A || !b || !out || !p || !req || A->ctx != ctx) return FAB_EINVAL;
-  if (f.kind == FAB_F_SIGN) {
-    hipSetDevice(ctx->device);
-    const int rs = ensure_square(ctx, A);
-    if (rs != FAB_OK) return rs;
-  }
   auto r = std::make_shared<Request>();
   int first_prec = p->prec == FAB_PREC_FP64 ? FAB_PREC_FP64 : FAB_PREC_FP32;
   int rc = make_plan(A, nrhs, f, p, esize_for(first_prec), r->plan);
@@ -1424,7 +1349,7 @@ int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
     return FAB_ENOMEM;
   }
   r->id = ctx->next_id++;
-  r->plan.A->refs.fetch_add(1);   // the planned operator (A^2 for the sign function), released at retirement
+  r->plan.A->refs.fetch_add(1);   // released at retirement
   ctx->reqs[r->id] = r;
   ctx->queue.push_back(r->id);
   *req = r->id;
@@ -1459,7 +1384,12 @@ int fab_wait(fab_ctx ctx, fab_request req, fab_info* info) {
   std::unique_lock<std::mutex> lk(ctx->mu);
   auto it = ctx->reqs.find(req);
   if (it == ctx->reqs.end()) return FAB_ENOTFOUND;
-  ctx->cv.wait(lk, [&] { return it->second->state == 2; });
+  // hold the request itself across the wait: a submit from another thread
+  // may rehash the table (invalidating iterators) while mu is released
+  const std::shared_ptr<Request> r = it->second;
+  ctx->cv.wait(lk, [&] { return r->state == 2; });
+  it = ctx->reqs.find(req);
+  if (it == ctx->reqs.end()) return FAB_ENOTFOUND;   // released by a concurrent fab_poll/fab_wait
   return finish_request(ctx, it, info);
 }
 

@@ -37,7 +37,7 @@ class fab_info(C.Structure):
                 ("conv_est", C.c_double), ("kappa_R", C.c_double), ("h_last", C.c_double),
                 ("beta", C.c_double), ("m_used", C.c_int), ("breakdown", C.c_int), ("fell_back", C.c_int),
                 ("ls_iters", C.c_int), ("prec_used", C.c_int), ("whitened_at", C.c_int),
-                ("latency_us", C.c_double)]
+                ("ls_limit", C.c_int), ("latency_us", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -5,8 +5,9 @@ Tolerances: the Hessenberg matrix and the sketched basis agree with the
 oracle's FP64 construction to 1e-9 relative (both run one classical
 Gram-Schmidt step per column, so rounding differences stay at the level of
 the sketch's conditioning); the result agrees with the oracle's exact
-least-squares Algorithm 3 to 1e-8 (FP64 basis; LSQR stops at a relative step
-of tol/10) and to 1e-5 with an FP32 basis.
+least-squares Algorithm 3 to 1e-10 (FP64 basis, tol = 1e-11: LSQR stops at
+the Paige-Saunders test ||M^T r|| <= (tol/10) ||M||_F ||r||) and to 1e-6 with
+an FP32 basis.
 """
 import numpy as np
 import pytest
@@ -36,7 +37,7 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
 
 
-def _p(w, prec, ls="lsqr", tol=1e-12, m=None, basis="sketched_gs"):
+def _p(w, prec, ls="lsqr", tol=1e-11, m=None, basis="sketched_gs"):
     from paper_2212_12758_amd import make_params
 
     return make_params(m or w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, prec, ls, tol, basis=basis)
@@ -46,7 +47,7 @@ def _sk(w):
     return osk.Sketch(w.sketch, w.n, w.s, w.sketch_seed, w.zeta)
 
 
-def _stagewise(ctx, w, b, ncols=None, tol_f=1e-8):
+def _stagewise(ctx, w, b, ncols=None, tol_f=1e-10):
     """ncols: leading Hessenberg / sketch columns compared elementwise.  Like any
     Krylov recurrence, the construction amplifies rounding differences step by
     step (in the oracle alone, a relative perturbation of b by 1e-16 moves
@@ -73,6 +74,7 @@ def _stagewise(ctx, w, b, ncols=None, tol_f=1e-8):
     orth_ref = np.abs(ref["S"].T @ ref["S"] - np.eye(mu + 1)).max()
     assert np.abs(SV.T @ SV - np.eye(mu + 1)).max() <= max(10 * orth_ref, 1e-12)
     print("ls_iters", info[0]["ls_iters"], "relerr", krylov.relerr(out, ref["f"]), flush=True)
+    assert info[0]["ls_limit"] == 0
     assert krylov.relerr(out, ref["f"]) < tol_f
     return A, Aor, ref, out, info
 
@@ -86,9 +88,9 @@ def test_bg_convdiff_srht_stagewise(ctx, N):
     b = W.rhs(w.n, w.b_seed)
     A, Aor, ref, out64, info = _stagewise(ctx, w, b)
     fm = krylov.fm(Aor, b, w.f, w.m)
-    assert krylov.relerr(out64, fm) < 1e-8
-    out32, info32 = ctx.solve(A, _dev(b), w.f, _p(w, "fp32"))
-    assert krylov.relerr(out32.cpu().numpy(), ref["f"]) < 1e-5
+    assert krylov.relerr(out64, fm) < 1e-10
+    out32, info32 = ctx.solve(A, _dev(b), w.f, _p(w, "fp32", tol=1e-6))
+    assert krylov.relerr(out32.cpu().numpy(), ref["f"]) < 1e-6
     A.destroy()
 
 
@@ -112,10 +114,11 @@ def test_bg_lap3d_invsqrt_small_sketch(ctx):
     w = W.Workload(base.name, base.op, base.b_seed, 1, base.f, m=m, k=2, s=int(1.05 * m), sketch="srht",
                    sketch_seed=base.sketch_seed)
     b = W.rhs(w.n, w.b_seed)
-    # with s = 1.05 m the sketch is a weak preconditioner and LSQR stops at its
-    # iteration limit short of the exact least-squares solution
-    A, Aor, ref, out, info = _stagewise(ctx, w, b, ncols=20, tol_f=1e-7)
-    assert krylov.relerr(out, krylov.fm(Aor, b, w.f, m)) < 1e-7
+    # with s = 1.05 m one Gram-Schmidt pass leaves Theta V far from
+    # orthonormal; preconditioned by the factor R of Theta V_m, LSQR still
+    # meets its test within the iteration limit (about 95 iterations)
+    A, Aor, ref, out, info = _stagewise(ctx, w, b, ncols=20)
+    assert krylov.relerr(out, krylov.fm(Aor, b, w.f, m)) < 1e-10
     A.destroy()
 
 
@@ -143,11 +146,11 @@ def test_bg2_keeps_sketch_orthonormal_with_small_sketch(ctx):
     assert np.abs(SV.T @ SV - np.eye(m + 1)).max() < 1e-12
     H = ref["Hbar"]
     assert np.abs(dg["hbar"][:21, :20] - H[:21, :20]).max() <= 1e-9 * np.abs(H).max()
-    assert krylov.relerr(out, ref["f"]) < 1e-8
-    assert krylov.relerr(out, fm) < 1e-8
+    assert krylov.relerr(out, ref["f"]) < 1e-10
+    assert krylov.relerr(out, fm) < 1e-10
     print("case bg2 lap3d16 fp32", flush=True)
-    out32, info32 = ctx.solve(A, _dev(b), f, _p(w, "fp32", tol=1e-8, basis="sketched_gs2"))
-    assert krylov.relerr(out32.cpu().numpy(), fm) < 1e-5
+    out32, info32 = ctx.solve(A, _dev(b), f, _p(w, "fp32", tol=1e-6, basis="sketched_gs2"))
+    assert krylov.relerr(out32.cpu().numpy(), fm) < 1e-6
     A.destroy()
 
 
@@ -183,7 +186,7 @@ def test_bg_multi_rhs_and_serving(ctx):
     sk = _sk(w)
     for r in range(nrhs):
         ref = krylov.sgs(Aor, np.ascontiguousarray(B[:, r]), w.f, w.m, sk)
-        assert krylov.relerr(outB[:, r], ref["f"]) < 1e-8, r
+        assert krylov.relerr(outB[:, r], ref["f"]) < 1e-10, r
     print("case bg serving", flush=True)
     outs = _dev(np.zeros_like(B))
     info_s = ctx.submit(A, _dev(B), w.f, _p(w, "fp64"), outs).wait()
@@ -209,7 +212,7 @@ def test_bg_auto_policies_refine(ctx):
     p = make_params(m, 2, 2 * (m + 1), "sparse_sign", 8, 9, "auto", "auto", 1e-6, basis="sketched_gs")
     out, info = ctx.solve(A, _dev(b), f, p)
     assert info[0]["ls_iters"] >= 1
-    assert krylov.relerr(out.cpu().numpy(), fm) < 1e-5
+    assert krylov.relerr(out.cpu().numpy(), fm) < 1e-6
     ps = make_params(m, 2, 2 * (m + 1), "sparse_sign", 8, 9, "fp64", "sketch", 1e-6, basis="sketched_gs")
     out_s, info_s = ctx.solve(A, _dev(b), f, ps)
     assert info_s[0]["ls_iters"] == 0
@@ -257,12 +260,12 @@ def test_bg2_large_m_global_paths(ctx):
     assert info[0]["m_used"] == m and info[0]["ls_iters"] >= 1
     SV = dg["sv"]
     assert np.abs(SV.T @ SV - np.eye(m + 1)).max() < 1e-12
-    assert krylov.relerr(out, ref["f"]) < 1e-8
-    assert krylov.relerr(out, fm) < 1e-8
+    assert krylov.relerr(out, ref["f"]) < 1e-10
+    assert krylov.relerr(out, fm) < 1e-10
     print("case truncated lap3d24 m=150 fp64", flush=True)
     out_t, _ = ctx.solve(A, _dev(b), f, make_params(m, 2, s, "srht", 8, 8, "fp64", "sketch"))
     ref_t = krylov.nt(Aor, b, f, m, 2, sk, "sketch")["f"]
-    assert krylov.relerr(out_t.cpu().numpy(), ref_t) < 1e-8
+    assert krylov.relerr(out_t.cpu().numpy(), ref_t) < 1e-10
     A.destroy()
     # m = 210 needs a larger grid: on 24^3 the Krylov space of that size is
     # numerically degenerate (kappa(V) ~ 1e10 in the oracle, ||H_hat|| ~ 1e11)
@@ -276,7 +279,7 @@ def test_bg2_large_m_global_paths(ctx):
     print("case bg2 lap3d40 m=210 fp64", flush=True)
     out2, info2 = ctx.solve(A2, _dev(b2), f2, _p(w2, "fp64", basis="sketched_gs2"))
     assert info2[0]["m_used"] == m2 and info2[0]["ls_iters"] >= 1
-    assert krylov.relerr(out2.cpu().numpy(), ref2["f"]) < 1e-8
+    assert krylov.relerr(out2.cpu().numpy(), ref2["f"]) < 1e-10
     A2.destroy()
 
 
@@ -317,10 +320,16 @@ def test_gram_least_squares_exact_and_fallback(ctx):
     ref = krylov.sgs(Aor, b, f, m, _sk(w), passes=2)
     A = ctx.matrix(st)
     print("case gram bg2 lap3d16", flush=True)
-    out, info = ctx.solve(A, _dev(b), f, _p(w, "fp64", ls="gram", basis="sketched_gs2"))
+    # kappa_1 of the Gram factor is 145 here: accepted while kappa^2 u <= tol/10
+    # (tol = 1e-10: bound 300), refused for tol = 1e-11 (bound 95), where LSQR
+    # runs instead
+    out, info = ctx.solve(A, _dev(b), f, _p(w, "fp64", ls="gram", tol=1e-10, basis="sketched_gs2"))
     assert info[0]["ls_iters"] == 0
     assert krylov.relerr(out.cpu().numpy(), ref["f"]) < 1e-11
     assert krylov.relerr(out.cpu().numpy(), krylov.fm(Aor, b, f, m)) < 1e-11
+    out, info = ctx.solve(A, _dev(b), f, _p(w, "fp64", ls="gram", tol=1e-11, basis="sketched_gs2"))
+    assert info[0]["ls_iters"] >= 1 and info[0]["ls_limit"] == 0
+    assert krylov.relerr(out.cpu().numpy(), ref["f"]) < 1e-10
     A.destroy()
     n, m = 4096, 120
     op = W.rgg_laplacian(n, seed=3)

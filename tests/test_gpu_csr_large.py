@@ -92,7 +92,7 @@ def test_csr_ragged_large_truncated_sparse_sign(ctx, big):
         assert np.array_equal(dg2["sv"], dg["sv"]), rep
     print("case csr ragged n=2^20+37 truncated fp32", flush=True)
     o32, _ = ctx.solve(A, _dev(b), f, make_params(m, k, s, "sparse_sign", 8, 5, "fp32", "sketch"))
-    assert krylov.relerr(o32.cpu().numpy(), ref["f"]) < 1e-5
+    assert krylov.relerr(o32.cpu().numpy(), ref["f"]) < 1e-6
     A.destroy()
 
 
@@ -107,7 +107,7 @@ def test_csr_ragged_large_sketched_gs(ctx, big):
     sk = osk.Sketch("sparse_sign", N_LARGE, s, 6, 8)
     ref = krylov.sgs(Aor, b, f, m, sk)
     A = ctx.matrix(op)
-    p = make_params(m, 2, s, "sparse_sign", 8, 6, "fp64", "lsqr", 1e-12, basis="sketched_gs")
+    p = make_params(m, 2, s, "sparse_sign", 8, 6, "fp64", "lsqr", 1e-11, basis="sketched_gs")
     print("case csr ragged n=2^20+37 sketched GS fp64", flush=True)
     out, info, dg = ctx.solve(A, _dev(b), f, p, diag=True)
     out = out.cpu().numpy()
@@ -115,7 +115,7 @@ def test_csr_ragged_large_sketched_gs(ctx, big):
     assert info[0]["m_used"] == m
     assert np.abs(dg["hbar"] - H).max() <= 1e-10 * np.abs(H).max()
     assert np.abs(dg["sv"][:, : m + 1] - ref["S"]).max() < 1e-10
-    assert krylov.relerr(out, ref["f"]) < 1e-9
+    assert krylov.relerr(out, ref["f"]) < 1e-10
     o2, _ = ctx.solve(A, _dev(b), f, p)
     assert np.array_equal(o2.cpu().numpy(), out)
     A.destroy()

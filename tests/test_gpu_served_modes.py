@@ -63,3 +63,50 @@ def test_served_algorithm5_and_sfom(ctx):
         r.wait()
         assert np.array_equal(o.cpu().numpy(), outs[ls]), ls
     A.destroy()
+
+
+def test_wait_while_another_thread_submits(ctx):
+    """fab_wait blocks with the context lock released while another thread
+    keeps submitting (the request table grows and rehashes meanwhile): every
+    request completes with the blocking call's result, bit for bit."""
+    import queue
+    import threading
+
+    import torch
+
+    from paper_2212_12758_amd import make_params
+
+    st = W.laplacian2d(32)
+    A = ctx.matrix(st)
+    f = W.FuncSpec("exp", alpha=-0.5)
+    p = make_params(20, 2, 50, "srht", 8, 3, "fp32", "sketch")
+    b = _dev(W.rhs(st.n, 9))
+    ref, _ = ctx.solve(A, b, f, p)
+    ref = ref.cpu().numpy()
+    print("case wait while submitting", flush=True)
+    q, outs, errs = queue.Queue(), [], []
+
+    def submitter():
+        try:
+            for _ in range(200):
+                o = torch.empty_like(b)
+                outs.append(o)
+                q.put(ctx.submit(A, b, f, p, o))
+        except Exception as e:   # reported by the main thread
+            errs.append(e)
+        q.put(None)
+
+    t = threading.Thread(target=submitter)
+    t.start()
+    done = 0
+    while True:
+        r = q.get()
+        if r is None:
+            break
+        r.wait()
+        done += 1
+    t.join()
+    assert not errs and done == 200
+    for o in outs:
+        assert np.array_equal(o.cpu().numpy(), ref)
+    A.destroy()

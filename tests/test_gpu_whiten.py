@@ -3,8 +3,9 @@ the CPU oracle ``krylov.whitened`` (trigger kappa_1(R) > 1000 of the sketched
 basis every 5 steps, then Algorithm 1 and the exact least squares).
 
 Parity: the trigger step equals the oracle's (FP64 basis), the result agrees
-with the oracle and with Arnoldi's f_m to 1e-8 (LSQR to a relative step of
-1e-13), and the whitened sketch is orthonormal.  Without a trigger the mode
+with the oracle and with Arnoldi's f_m to 1e-10 (FP64 basis, LSQR to the
+Paige-Saunders test at tol/10 = 1e-12) and f_m to 1e-6 with an FP32 basis,
+and the whitened sketch is orthonormal.  Without a trigger the mode
 is the truncated basis, bit for bit.
 """
 import numpy as np
@@ -41,7 +42,7 @@ def _rgg_case():
     return W.Workload("rgg4096", op, 3, 1, f, m=m, k=2, s=2 * m, sketch="sparse_sign", zeta=8, sketch_seed=3)
 
 
-def _params(w, prec, ls="lsqr", tol=1e-12, basis="whitened"):
+def _params(w, prec, ls="lsqr", tol=1e-11, basis="whitened"):
     from paper_2212_12758_amd import make_params
 
     return make_params(w.m, w.k, w.s, w.sketch, w.zeta, w.sketch_seed, prec, ls, tol, basis=basis)
@@ -63,18 +64,20 @@ def test_whitening_restores_the_basis(ctx):
     assert abs(info[0]["beta"] - ref["scale"]) <= 1e-10 * ref["scale"]
     SV = dg["sv"]
     assert np.abs(SV.T @ SV - np.eye(w.m + 1)).max() < 1e-6
-    assert krylov.relerr(out, ref["f"]) < 1e-8
-    assert krylov.relerr(out, fm) < 1e-8
+    assert info[0]["ls_limit"] == 0
+    assert krylov.relerr(out, ref["f"]) < 1e-10
+    assert krylov.relerr(out, fm) < 1e-10
     # the truncated basis alone with sketch-and-solve is 10% off here (the
     # oracle's Algorithm 4 with sketch-and-solve: 0.10)
     out_t, info_t = ctx.solve(A, _dev(b), w.f, _params(w, "fp64", ls="sketch", basis="truncated"))
     assert info_t[0]["whitened_at"] == 0
     assert krylov.relerr(out_t.cpu().numpy(), fm) > 1e-2
     print("case whiten rgg4096 fp32", flush=True)
-    out32, info32 = ctx.solve(A, _dev(b), w.f, _params(w, "fp32", tol=1e-8))
+    out32, info32 = ctx.solve(A, _dev(b), w.f, _params(w, "fp32", tol=1e-6))
     # rounding in the FP32 vectors spoils the truncated basis sooner (step 60 here)
     assert 0 < info32[0]["whitened_at"] <= 90
-    assert krylov.relerr(out32.cpu().numpy(), fm) < 1e-5
+    print("fp32 whitened", info32[0], krylov.relerr(out32.cpu().numpy(), fm), flush=True)
+    assert krylov.relerr(out32.cpu().numpy(), fm) < 1e-6
     A.destroy()
 
 
@@ -104,7 +107,7 @@ def test_whitening_two_rhs_and_serving_refused(ctx):
     out = out.cpu().numpy()
     assert info[0]["whitened_at"] == info[1]["whitened_at"] > 0
     for r in range(2):
-        assert krylov.relerr(out[:, r], krylov.fm(Aor, np.ascontiguousarray(B[:, r]), w.f, w.m)) < 1e-8, r
+        assert krylov.relerr(out[:, r], krylov.fm(Aor, np.ascontiguousarray(B[:, r]), w.f, w.m)) < 1e-10, r
     with pytest.raises(FabError) as e:
         ctx.submit(A, _dev(B), w.f, _params(w, "fp64"), _dev(np.zeros_like(B)))
     assert e.value.code == EINVAL
