@@ -240,6 +240,40 @@ def test_fm_at_config1_matches_dst_closed_form():
     assert krylov.relerr(krylov.fm(A, b, w.f, w.m), closed_form.laplacian_fAb(w.op, w.f, b)) < 1e-13
 
 
+def test_kronecker_exp_closed_form_matches_dense_expm():
+    # nonsymmetric (upwind) operator with distinct grid sides, so a transposed
+    # factor or a swapped axis changes the result
+    cd = W.convdiff3d(5, 100.0).coeff
+    for st in (W.Stencil(3, 6, 5, 4, cd), W.laplacian2d(7, 5), W.Stencil(2, 7, 5, 1, cd[:5] + (0.0, 0.0))):
+        A = operators.stencil_matrix(st).toarray()
+        b = np.random.default_rng(st.n).standard_normal((st.n, 3))
+        alpha = -0.7 / np.abs(A).sum(axis=1).max() * 1e3 if st.dim == 3 else -0.3
+        ref = sl.expm(alpha * A) @ b
+        got = closed_form.kronecker_exp_fAb(st, alpha, b)
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+        # one column at a time gives the same
+        np.testing.assert_allclose(closed_form.kronecker_exp_fAb(st, alpha, b[:, 1]), got[:, 1], rtol=0, atol=0)
+    # a transposed x factor is a plausible slip; it is visible on the upwind operator
+    st = W.Stencil(3, 6, 5, 4, cd)
+    A = operators.stencil_matrix(st).toarray()
+    At = operators.stencil_matrix(W.Stencil(3, 6, 5, 4, (cd[0], cd[2], cd[1]) + cd[3:])).toarray()
+    b = np.random.default_rng(1).standard_normal(st.n)
+    assert krylov.relerr(sl.expm(-0.7 * At) @ b, sl.expm(-0.7 * A) @ b) > 1e-3
+
+
+def test_kronecker_exp_matches_dst_and_converged_fm():
+    st = W.laplacian3d(9)
+    b = np.random.default_rng(2).standard_normal(st.n)
+    np.testing.assert_allclose(closed_form.kronecker_exp_fAb(st, -1.0, b),
+                               closed_form.laplacian_fAb(st, EXP1, b), rtol=1e-12, atol=1e-13)
+    # the scaled 3D convection-diffusion exponential with ||tA||_inf = 1: full
+    # Arnoldi has converged long before m = 200, so f_m equals exp(tA) b
+    w = W.config("convdiff3d_256_exp_8rhs", scale=14)
+    b = W.rhs(w.n, w.b_seed)
+    ref = closed_form.kronecker_exp_fAb(w.op, w.f.alpha, b)
+    assert krylov.relerr(krylov.fm(operators.as_matrix(w.op), b, w.f, 40), ref) < 1e-13
+
+
 # --------------------------------------------------------------------------- Algorithm 2 and the compression
 def test_truncated_basis_relation_window_orthogonality():
     n, m, k = 500, 30, 3
