@@ -7,7 +7,8 @@
 //           H_hat = H_m + h_{m+1,m} y e_m^T (eq. (6)).  The matrix is held in
 //           registers across the workgroup when s <= 448 and m + 1 <= 104,
 //           else it is factorised in global memory.
-//  (exp(alpha H_hat) e_1 lives in k_expm.hip: multi-workgroup Pade products.)
+//  (exp(alpha H_hat) e_1 lives in k_expm.hip: the action of the exponential on
+//   e_1 by a scaled truncated Taylor series.)
 //  ((H_hat + sigma I)^{+-1/2} e_1 lives in k_fsqrt.hip: resolvent quadrature.)
 //  k_fpoly  sum_j coef_j H_hat^j e_1 (polynomial test functions).
 //  k_coef   combination weights beta c_j / eta_j for the final V c.

@@ -114,6 +114,24 @@ struct Arena {
     }
     return nullptr;
   }
+  // Long-lived regions (resident matrices, cached sketch rows) are carved from
+  // the top of the highest free block that fits, so that they never split the
+  // space left for the large per-request workspaces, which come from the bottom.
+  void* alloc_high(size_t n) {
+    n = (n + 255) & ~size_t(255);
+    if (n == 0) n = 256;
+    for (auto it = free_.rbegin(); it != free_.rend(); ++it) {
+      if (it->second >= n) {
+        const size_t off = it->first + it->second - n;
+        if (it->second == n) free_.erase(std::next(it).base());
+        else it->second -= n;
+        in_use += n;
+        sizes_[off] = n;
+        return base + off;
+      }
+    }
+    return nullptr;
+  }
   void release(void* p) {
     if (!p) return;
     const size_t off = (char*)p - base;
@@ -437,7 +455,7 @@ const int* srht_rows_cached(fab_ctx ctx, long long npad, int s, uint64_t seed, h
   const auto key = std::make_tuple(npad, s, seed);
   auto it = ctx->srht_cache.find(key);
   if (it != ctx->srht_cache.end()) return it->second;
-  int* rows = (int*)ctx->arena.alloc((size_t)s * 4);
+  int* rows = (int*)ctx->arena.alloc_high((size_t)s * 4);
   if (!rows) { *rc = FAB_ENOMEM; return nullptr; }
   if (srht_sample_rows(rows, npad, s, sm64_out(seed, 2), st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
     ctx->arena.release(rows);
@@ -1049,7 +1067,7 @@ int fab_create_matrix_csr(fab_ctx ctx, int64_t n, int64_t nnz, const int32_t* ro
   char* mem;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    mem = (char*)ctx->arena.alloc(brp + bcol + bval);
+    mem = (char*)ctx->arena.alloc_high(brp + bcol + bval);
   }
   if (!mem) return FAB_ENOMEM;
   const hipMemcpyKind kind = ptr_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
