@@ -54,7 +54,9 @@ enum fab_status {
   FAB_EDEVICE = 3,    /* a HIP runtime call failed                                */
   FAB_ENUMERIC = 4,   /* NaN/Inf in b, in the basis or in f(H_hat)                */
   FAB_EBUSY = 5,      /* matrix still referenced by in-flight requests            */
-  FAB_ENOTFOUND = 6   /* unknown request handle                                   */
+  FAB_ENOTFOUND = 6,  /* unknown request handle                                   */
+  FAB_ESCRATCH = 7    /* fab_solve_noalloc: the request's workspace exceeds
+                         FAB_NOALLOC_SCRATCH_BYTES                               */
 };
 
 /* The function f (Section 1: analytic on a domain containing the spectrum). */
@@ -225,6 +227,29 @@ typedef struct {
  * stage-by-stage verification).  Same arguments, errors and semantics.       */
 int fab_solve_diag(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
                    const fab_params* p, double* out, fab_info* info, const fab_diag* diag);
+
+/* Size of the static device scratch that fab_solve_noalloc works in (per GPU). */
+#define FAB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* Allocation-free fab_solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, semantics and results as fab_solve (the same
+ * kernels, launched directly), but the per-request workspace and the sampled
+ * SRHT rows live in a static device array of FAB_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends, instead
+ * of the context's arena; the call allocates nothing (no hipMalloc, no graph).
+ * The caller still passes b and out (FP64 device arrays [n][nrhs]).
+ * The array is shared by every call on that GPU and keeps the last call's
+ * contents (every region the solve reads first is cleared by the solve
+ * itself).  Calls on one GPU are serialised by the library (blocking, one at
+ * a time per device); work of other kinds that a caller enqueues on the same
+ * memory by other means would race with them.
+ * Errors: as fab_solve; FAB_ESCRATCH when the workspace of the request (the
+ * basis, (m+1) n nrhs elements of 4 or 8 bytes, plus small per-request
+ * regions) exceeds FAB_NOALLOC_SCRATCH_BYTES, checked before any launch; with
+ * FAB_PREC_AUTO an FP64 rerun that does not fit also returns FAB_ESCRATCH.  */
+int fab_solve_noalloc(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
+                      const fab_params* p, double* out, fab_info* info);
 
 /* Non-blocking submit to the context's serving loop.  The request is admitted
  * when its workspace fits the arena next to the requests already running

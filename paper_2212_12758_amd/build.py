@@ -22,7 +22,7 @@ OUT = os.path.join(HERE, "libfab.so")
 ARCH = os.environ.get("FAB_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["k_basis_f32_stencil.hip", "k_basis_f32_csr.hip", "k_basis_f64_stencil.hip", "k_basis_f64_csr.hip",
-           "k_basis.hip", "k_csr.hip", "k_bg.hip", "k_whiten.hip", "k_fsqrt.hip", "k_dense.hip", "k_expm.hip", "k_lsqr.hip", "runtime.cpp"]
+           "k_basis.hip", "k_csr.hip", "k_bg.hip", "k_whiten.hip", "k_fsqrt.hip", "k_dense.hip", "k_expm.hip", "k_lsqr.hip", "noalloc.hip", "runtime.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

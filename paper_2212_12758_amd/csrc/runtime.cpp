@@ -77,6 +77,8 @@ constexpr int WH_EVERY = 5;
 constexpr double WH_THRESH = 1000.0;
 size_t lsqr_state_stride(int m);
 size_t lsqr_pass_lds(int m, int nrhs);
+// Per-device address of the static scratch of fab_solve_noalloc (noalloc.hip).
+int noalloc_setup(int device);
 }  // namespace fab
 
 using namespace fab;
@@ -949,6 +951,7 @@ const char* fab_strerror(int code) {
     case FAB_ENUMERIC: return "non-finite input or result";
     case FAB_EBUSY: return "matrix in use by in-flight requests";
     case FAB_ENOTFOUND: return "unknown request";
+    case FAB_ESCRATCH: return "request exceeds the static scratch of fab_solve_noalloc";
     default: return "unknown status";
   }
 }
@@ -983,6 +986,10 @@ int fab_init(fab_ctx* out, int device, void* arena_dev_ptr, size_t arena_bytes, 
   (void)wh_set_attributes();
   (void)fsqrt_set_attributes();
   (void)hipGetLastError();
+  if (noalloc_setup(device) != FAB_OK) {
+    delete ctx;
+    return FAB_EDEVICE;
+  }
   if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev, hipEventDisableTiming) != hipSuccess) {
     delete ctx;
@@ -1215,8 +1222,12 @@ static int launch_solve(fab_ctx ctx, Plan& P, char* ws, const int* rows, const f
   return hipGraphLaunch(exec, ctx->stream) == hipSuccess ? FAB_OK : FAB_EDEVICE;
 }
 
+// ws_fixed != nullptr: the workspace (and the sampled SRHT rows behind it) is
+// the caller-supplied region of fixed_bytes instead of a block of the arena,
+// launched directly (no graph), nothing allocated.
 static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, const fab_params* p,
-                      double* out, fab_info* info, const fab_diag* diag) {
+                      double* out, fab_info* info, const fab_diag* diag, char* ws_fixed = nullptr,
+                      size_t fixed_bytes = 0) {
   if (!ctx || !A || !b || !out || !p || A->ctx != ctx) return FAB_EINVAL;
   const double t0 = now_us();
   std::lock_guard<std::mutex> slk(ctx->solve_mu);
@@ -1232,7 +1243,10 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
     if (rc != FAB_OK) return rc;
     P.b = b;
     P.out = out;
-    {
+    if (ws_fixed) {
+      if (align256(P.bytes) + align256((size_t)P.p.s * 4) > fixed_bytes) return FAB_ESCRATCH;
+      ws = ws_fixed;
+    } else {
       std::unique_lock<std::mutex> lk(ctx->mu);
       if (!ctx->arena.could_ever_fit(P.bytes)) return FAB_ENOMEM;
       while (!(ws = (char*)ctx->arena.alloc(P.bytes))) {
@@ -1245,10 +1259,20 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
     }
     const int* rows = nullptr;
     if (P.p.sketch == FAB_SKETCH_SRHT) {
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      rows = srht_rows_cached(ctx, 1LL << ilog2(A->n), P.p.s, P.p.seed, ctx->stream, &rc);
+      if (ws_fixed) {
+        int* r = (int*)(ws_fixed + align256(P.bytes));
+        if (srht_sample_rows(r, 1LL << ilog2(A->n), P.p.s, sm64_out(P.p.seed, 2), ctx->stream) != hipSuccess)
+          rc = FAB_EDEVICE;
+        rows = r;
+      } else {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        rows = srht_rows_cached(ctx, 1LL << ilog2(A->n), P.p.s, P.p.seed, ctx->stream, &rc);
+      }
     }
-    if (rc == FAB_OK) rc = launch_solve(ctx, P, ws, rows, f);
+    if (rc == FAB_OK)
+      rc = ws_fixed ? enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, nullptr,
+                                    ctx->host_flag)
+                    : launch_solve(ctx, P, ws, rows, f);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == FAB_OK) rc = FAB_EDEVICE;
     if (ctx->prof.mask) ctx->prof.harvest();
     fi.clear();
@@ -1258,8 +1282,10 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
     }
     if (attempt == 0 && needs_fp64_rerun(P, rc, fi)) {
       // FAB_PREC_AUTO: recompute the whole request with an FP64 basis
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      ctx->arena.release(ws);
+      if (!ws_fixed) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->arena.release(ws);
+      }
       ws = nullptr;
       esize = 8;
       fell_back = true;
@@ -1301,7 +1327,7 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
       if (e != hipSuccess) rc = FAB_EDEVICE;
     }
   }
-  {
+  if (!ws_fixed) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->arena.release(ws);
   }
@@ -1457,3 +1483,14 @@ int fab_finalize(fab_ctx ctx) {
 }
 
 }  // extern "C"
+
+namespace fab {
+// The blocking solve on a caller-supplied device workspace (the static
+// scratch of fab_solve_noalloc, noalloc.hip).
+int solve_fixed_workspace(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f, const fab_params* p,
+                          double* out, fab_info* info, char* ws, size_t bytes) {
+  if (!ws) return FAB_EINVAL;
+  return solve_impl(ctx, A, b, nrhs, f, p, out, info, nullptr, ws, bytes);
+}
+int ctx_device(fab_ctx ctx) { return ctx ? ctx->device : -1; }
+}  // namespace fab

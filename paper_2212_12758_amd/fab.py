@@ -13,7 +13,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfab.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EBUSY, ENOTFOUND = range(7)
+OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EBUSY, ENOTFOUND, ESCRATCH = range(8)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 F_EXP, F_POW, F_POLY, F_SIGN = 1, 2, 3, 4
 SKETCH_SRHT, SKETCH_SPARSE_SIGN = 1, 2
 PREC_FP32, PREC_FP64, PREC_AUTO = 1, 2, 3
@@ -68,6 +69,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fab_solve.argtypes = [vp, vp, vp, i, fab_func, C.POINTER(fab_params), vp, C.POINTER(fab_info)]
     lib.fab_solve_diag.argtypes = [vp, vp, vp, i, fab_func, C.POINTER(fab_params), vp, C.POINTER(fab_info),
                                    C.POINTER(fab_diag)]
+    lib.fab_solve_noalloc.argtypes = [vp, vp, vp, i, fab_func, C.POINTER(fab_params), vp, C.POINTER(fab_info)]
     lib.fab_submit.argtypes = [vp, vp, vp, i, fab_func, C.POINTER(fab_params), vp, C.POINTER(u64)]
     lib.fab_poll.argtypes = [vp, u64, C.POINTER(i), C.POINTER(fab_info)]
     lib.fab_wait.argtypes = [vp, u64, C.POINTER(fab_info)]
@@ -202,6 +204,21 @@ class Context:
         if nrhs == 1:
             d = {k: v[0] for k, v in d.items()}
         return out, [i.as_dict() for i in infos], d
+
+    def solve_noalloc(self, A: Matrix, b, f, params: fab_params, out):
+        """fab_solve_noalloc: the blocking solve in the library's static device
+        scratch (no allocation).  out must be given.  Returns [info dict per rhs]."""
+        import torch
+
+        assert b.dtype == torch.float64 and b.is_cuda and b.is_contiguous()
+        assert out.dtype == torch.float64 and out.is_cuda and out.shape == b.shape
+        nrhs = self._shape(b)
+        ff, keep = make_func(f)
+        infos = (fab_info * nrhs)()
+        rc = self.lib.fab_solve_noalloc(self.handle, A.handle, C.c_void_p(b.data_ptr()), nrhs, ff, C.byref(params),
+                                        C.c_void_p(out.data_ptr()), infos)
+        _check(rc, "fab_solve_noalloc")
+        return [i.as_dict() for i in infos]
 
     def submit(self, A: Matrix, b, f, params: fab_params, out):
         """Non-blocking; the request runs on a library stream, so pending torch
