@@ -69,6 +69,9 @@ struct SolveDev {
   // sketch
   int sketch;            // SketchKind
   int sk_slices;         // sparse sign: LDS accumulators per block (1, or one per wave)
+  int sk_reg;            // SRHT: 1 = each thread holds its sketch accumulators in registers
+  int tgroups;           // streaming blocks form tgroups groups (blk mod tgroups), 8 or 1
+  long long tchunk;      // tiles per group: group g walks tiles [g*tchunk, (g+1)*tchunk)
   const int* srht_rows;  // [s] sampled rows of the padded Hadamard transform
   unsigned long long key_a, key_b;   // SRHT: signs key; sparse: rows key, signs key
   double sk_scale;       // 1/sqrt(s) (SRHT) or 1/sqrt(zeta) (sparse sign)
@@ -241,6 +244,22 @@ __device__ inline void sparse_sign_column(unsigned long long key_rows, unsigned 
 __device__ inline double wave_sum_rhs(double v, int nrhs) {
   for (int off = 32; off >= nrhs; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// Tiles of streaming block blk: blocks blk = g + tgroups * c form group g.
+// Consecutive workgroups of a launch are dispatched round-robin over the 8
+// XCDs, so with tgroups = 8 one group runs on one XCD; group g walks the
+// contiguous tile range [g tchunk, (g+1) tchunk) with its members
+// interleaved, so that neighbouring tiles (the stencil's y and z neighbours,
+// the tiles the previous pass wrote) are read through that XCD's L2.
+__device__ inline void tile_walk(const SolveDev& d, int blk, int& t0, int& hi, int& step) {
+  const int G = d.tgroups;
+  const int g = blk % G, c = blk / G;
+  const long long lo = (long long)g * d.tchunk;
+  const long long h = lo + d.tchunk < (long long)d.ntiles ? lo + d.tchunk : (long long)d.ntiles;
+  t0 = (int)(lo + c);
+  hi = (int)h;
+  step = d.nblk / G;
 }
 
 }  // namespace fab

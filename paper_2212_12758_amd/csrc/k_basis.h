@@ -77,6 +77,15 @@ __device__ inline void store8(double* __restrict__ p, const double* v, double* r
 #pragma unroll
   for (int j = 0; j < 8; ++j) rounded[j] = v[j];
 }
+// 8 consecutive elements kept in the storage type until they are used (FP32
+// values take one register each instead of two).
+__device__ inline void load8r(const float* __restrict__ p, float* v) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  const float4 b = *reinterpret_cast<const float4*>(p + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+__device__ inline void load8r(const double* __restrict__ p, double* v) { load8(p, v); }
 template <typename T>
 __device__ inline double ldg1(const T* __restrict__ u, long long x, long long nel) {
   return (x >= 0 && x < nel) ? (double)u[x] : 0.0;
@@ -237,6 +246,45 @@ __device__ inline void stencil8_fast(const SolveDev& d, const T* __restrict__ u,
   }
 }
 
+// As stencil8_fast, with the loaded values kept in the storage type T until
+// each is multiplied (same operations in the same order, FP64 arithmetic).
+template <typename T>
+__device__ inline void stencil8_fast_raw(const SolveDev& d, const T* __restrict__ u, long long e, const T* c,
+                                         double* w) {
+  const Masks8 mk = masks8(d, e);
+  const int nr = d.nrhs;
+  const long long sy = (long long)d.nx * nr, sz = d.nz > 1 ? sy * d.ny : 0;
+  T xm[EPT], xp[EPT], ym[EPT], yp[EPT], zm[EPT], zp[EPT];
+  const long long nel = (long long)d.n * nr;
+  load8r(u + (e >= sy ? e - sy : e), ym);
+  load8r(u + (e + sy + EPT <= nel ? e + sy : e), yp);
+  load8r(u + (e >= sz ? e - sz : e), zm);
+  load8r(u + (e + sz + EPT <= nel ? e + sz : e), zp);
+  if (nr == 1) {
+    const T l = u[e >= 1 ? e - 1 : e];
+    const T r = u[e + EPT < nel ? e + EPT : e];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      xm[j] = j == 0 ? l : c[j > 0 ? j - 1 : 0];
+      xp[j] = j == EPT - 1 ? r : c[j < EPT - 1 ? j + 1 : 0];
+    }
+  } else {
+    load8r(u + (e >= nr ? e - nr : e), xm);
+    load8r(u + (e + nr + EPT <= nel ? e + nr : e), xp);
+  }
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    double a = d.c[0] * (double)c[j];
+    a += d.c[1] * (((mk.mx0 >> j) & 1u) ? (double)xm[j] : 0.0);
+    a += d.c[2] * (((mk.mx1 >> j) & 1u) ? (double)xp[j] : 0.0);
+    a += d.c[3] * (((mk.my0 >> j) & 1u) ? (double)ym[j] : 0.0);
+    a += d.c[4] * (((mk.my1 >> j) & 1u) ? (double)yp[j] : 0.0);
+    a += d.c[5] * (((mk.mz0 >> j) & 1u) ? (double)zm[j] : 0.0);
+    a += d.c[6] * (((mk.mz1 >> j) & 1u) ? (double)zp[j] : 0.0);
+    w[j] = a;
+  }
+}
+
 template <typename T>
 __device__ inline bool stencil_fast_ok(const SolveDev& d) {
   return d.op == OP_STENCIL && (d.nrhs == 1 || d.nrhs >= 8) && ((long long)d.nx * d.nrhs) % vec_align<T>() == 0;
@@ -371,22 +419,26 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int n
     const long long nel = (long long)d.n * nr;
     const bool fast_ok = OP == OP_STENCIL && nw == KT && stencil_fast_ok<T>(d);
     const long long reach = stencil_reach(d);
-    for (int t = blockIdx.x; t < d.ntiles; t += d.nblk) {
+    int t0, thi, tstep;
+    tile_walk(d, blockIdx.x, t0, thi, tstep);
+    for (int t = t0; t < thi; t += tstep) {
       const long long e = ((long long)t << LT) + (long long)tid * EPT;
       if (fast_ok && ((long long)t << LT) >= reach && (((long long)t + 1) << LT) + reach <= nel) {
-        // interior tile, full window: all loads first, no branches
-        double c[EPT], w[EPT], win[KT > 1 ? KT - 1 : 1][EPT];
-        load8(src + e, c);
+        // interior tile, full window: all loads first, no branches; loaded
+        // values stay in the storage type until used
+        T c[EPT], win[KT > 1 ? KT - 1 : 1][EPT];
+        double w[EPT];
+        load8r(src + e, c);
 #pragma unroll
-        for (int jj = 0; jj < KT - 1; ++jj) load8(V + (long long)(j0 + jj) * d.ldv + e, win[jj]);
-        stencil8_fast(d, src, e, c, w);
+        for (int jj = 0; jj < KT - 1; ++jj) load8r(V + (long long)(j0 + jj) * d.ldv + e, win[jj]);
+        stencil8_fast_raw(d, src, e, c, w);
 #pragma unroll
         for (int jj = 0; jj < KT - 1; ++jj)
 #pragma unroll
-          for (int j = 0; j < EPT; ++j) acc[jj][slot_of<QC>(j)] += win[jj][j] * w[j];
+          for (int j = 0; j < EPT; ++j) acc[jj][slot_of<QC>(j)] += (double)win[jj][j] * w[j];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-          acc[KT - 1][slot_of<QC>(j)] += c[j] * w[j];
+          acc[KT - 1][slot_of<QC>(j)] += (double)c[j] * w[j];
           acc[KMAX][slot_of<QC>(j)] += w[j] * w[j];
         }
         continue;
@@ -617,12 +669,37 @@ __device__ inline void fwht_tile(double* v, double* X, int lnr) {
 }
 
 // ------------------------------------------------------------------ pass 2
+// Slot pq of the s x nrhs SRHT accumulators belongs to thread pq mod BLOCK
+// for the whole launch.  With one rhs (at most srht_reg_slots * BLOCK slots)
+// a thread keeps its slots in registers, so the per-tile sums need no LDS
+// read-modify-write; otherwise the slots live in LDS and each thread updates
+// its own in batches of SK_BATCH (all loads of a batch before its stores).
+// The host sets d.sk_reg when the register variant applies.
+template <int QC>
+constexpr int srht_reg_slots() { return QC == 1 ? 4 : 0; }
+constexpr int SK_BATCH = 8;
+
+// Update coefficient `slot` (0: of w~, 1 + j: of window vector j) of the rhs
+// of element j of this thread.  One rhs: uniform registers; several: read
+// from the block's coefficient table in LDS at the point of use, which keeps
+// 8 x NSLOT values per thread out of the registers.
+template <int QC>
+struct UpdCoef {
+  double c1[NSLOT];   // QC == 1
+  const double* tab;  // QC == 8: cfl
+  __device__ inline double get(int tid, int j, int nr, int slot) const {
+    if constexpr (QC == 1) return c1[slot];
+    else return tab[rhs_of<QC>(tid, j, nr) * NSLOT + slot];
+  }
+};
+
 // START: u_0 = fl(b).  Otherwise u_i = cf0 * w~ - sum_j cf_{1+j} u_{j0+j}.
 template <typename T, int OP, int SK, bool START, int LT, int QC, int KT>
 __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   constexpr int BLOCK = 1 << (LT - 3);
   constexpr int TILE = 1 << LT;
   constexpr int NW = BLOCK / 64;
+  constexpr int RA = (SK == SK_SRHT && srht_reg_slots<QC>() > 0) ? srht_reg_slots<QC>() : 1;
   if (d.status[0]) return;
   extern __shared__ double lds[];
   __shared__ double nred[NW][32];
@@ -649,28 +726,35 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   const T* __restrict__ src = START ? nullptr : V + (long long)(i - 1) * d.ldv;
   T* __restrict__ dst = V + (long long)i * d.ldv;
 
-  double cw[QC];
-  double cj[KT][QC];
+  UpdCoef<QC> cf;
+  if constexpr (QC == 1) {
 #pragma unroll
-  for (int c = 0; c < QC; ++c) {
-    const int q = rhs_of<QC>(tid, c, nr);
-    const double* cf = cfl + q * NSLOT;
-    cw[c] = START ? 1.0 : cf[0];
-#pragma unroll
-    for (int jj = 0; jj < KT; ++jj) cj[jj][c] = (START || jj >= nw) ? 0.0 : cf[1 + jj];
+    for (int sl = 0; sl < NSLOT; ++sl)
+      cf.c1[sl] = START ? (sl == 0 ? 1.0 : 0.0) : (sl == 0 || sl <= nw ? cfl[sl] : 0.0);
+  } else {
+    // (step_scalars has set every slot, zeros beyond the window; the start
+    // pass stores b itself)
+    if (START)
+      for (int x = tid; x < nr * NSLOT; x += BLOCK) cfl[x] = (x % NSLOT) == 0 ? 1.0 : 0.0;
+    cf.tab = cfl;
   }
 
   double* X = lds;                                                   // SRHT tile (padded)
-  double* acc = lds + (SK == SK_SRHT ? padx(TILE) : 0);              // sketch accumulator [s][nr]
+  double* acc = lds + (SK == SK_SRHT ? padx(TILE) : 0);              // sketch accumulator [s][nr] (LDS path)
   const int snr = d.s * nr;
+  const bool reg_acc = SK == SK_SRHT && srht_reg_slots<QC>() > 0 && d.sk_reg;
   // sparse sign: one accumulator per wave when the host sized LDS for it, so
   // that the LDS atomics of different waves never meet (fixed order)
   const int nsl = (SK == SK_SPARSE && NW > 1 && d.sk_slices == NW) ? NW : 1;
   double* acc_w = acc + (nsl > 1 ? wv * snr : 0);
-  int* rows_l = (int*)(acc + snr * nsl);                              // sampled SRHT rows
-  for (int x = tid; x < snr * nsl; x += BLOCK) acc[x] = 0.0;
+  int* rows_l = (int*)(acc + (reg_acc ? 0 : snr * nsl));             // sampled SRHT rows
+  if (!reg_acc)
+    for (int x = tid; x < snr * nsl; x += BLOCK) acc[x] = 0.0;
   if (SK == SK_SRHT)
     for (int x = tid; x < d.s; x += BLOCK) rows_l[x] = d.srht_rows[x];
+  double racc[RA];
+#pragma unroll
+  for (int a = 0; a < RA; ++a) racc[a] = 0.0;
   __syncthreads();
 
   double nrm[QC];
@@ -678,7 +762,9 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   for (int c = 0; c < QC; ++c) nrm[c] = 0.0;
   const bool fast_ok = !START && OP == OP_STENCIL && nw == KT && stencil_fast_ok<T>(d);
   const long long reach = stencil_reach(d);
-  for (int t = blk; t < d.ntiles; t += d.nblk) {
+  int t0, thi, tstep;
+  tile_walk(d, blk, t0, thi, tstep);
+  for (int t = t0; t < thi; t += tstep) {
     const long long e = ((long long)t << LT) + (long long)tid * EPT;
     double uu[EPT];
 #pragma unroll
@@ -688,21 +774,23 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
       if (START) {
         get8(d.b, e, nel, u);
       } else if (fast_ok && ((long long)t << LT) >= reach && (((long long)t + 1) << LT) + reach <= nel) {
-        // interior tile, full window: all loads first, no branches
-        double c[EPT], w[EPT], win[KT > 1 ? KT - 1 : 1][EPT];
-        load8(src + e, c);
+        // interior tile, full window: all loads first, no branches; loaded
+        // values stay in the storage type until used
+        T c[EPT], win[KT > 1 ? KT - 1 : 1][EPT];
+        double w[EPT];
+        load8r(src + e, c);
 #pragma unroll
-        for (int jj = 0; jj < KT - 1; ++jj) load8(V + (long long)(j0 + jj) * d.ldv + e, win[jj]);
-        stencil8_fast(d, src, e, c, w);
+        for (int jj = 0; jj < KT - 1; ++jj) load8r(V + (long long)(j0 + jj) * d.ldv + e, win[jj]);
+        stencil8_fast_raw(d, src, e, c, w);
         // same order of operations as the general path below
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) u[j] = cw[slot_of<QC>(j)] * w[j];
+        for (int j = 0; j < EPT; ++j) u[j] = cf.get(tid, j, nr, 0) * w[j];
 #pragma unroll
         for (int jj = 0; jj < KT - 1; ++jj)
 #pragma unroll
-          for (int j = 0; j < EPT; ++j) u[j] -= cj[jj][slot_of<QC>(j)] * win[jj][j];
+          for (int j = 0; j < EPT; ++j) u[j] -= cf.get(tid, j, nr, 1 + jj) * (double)win[jj][j];
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) u[j] -= cj[KT - 1][slot_of<QC>(j)] * c[j];
+        for (int j = 0; j < EPT; ++j) u[j] -= cf.get(tid, j, nr, KT) * (double)c[j];
       } else {
         double w[EPT];
         if (OP == OP_STENCIL) {
@@ -713,14 +801,14 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
           get8(d.wbuf, e, nel, w);
         }
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) u[j] = cw[slot_of<QC>(j)] * w[j];
+        for (int j = 0; j < EPT; ++j) u[j] = cf.get(tid, j, nr, 0) * w[j];
 #pragma unroll
         for (int jj = 0; jj < KT; ++jj) {
           if (jj < nw) {
             double vj[EPT];
             get8(V + (long long)(j0 + jj) * d.ldv, e, nel, vj);
 #pragma unroll
-            for (int j = 0; j < EPT; ++j) u[j] -= cj[jj][slot_of<QC>(j)] * vj[j];
+            for (int j = 0; j < EPT; ++j) u[j] -= cf.get(tid, j, nr, 1 + jj) * vj[j];
           }
         }
       }
@@ -762,22 +850,59 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
       }
       fwht_tile<LT>(uu, X, d.lognrhs);
       // sampled rows r = (r_hi, r_lo): contribution (-1)^popcount(r_hi & t) * X[r_lo]
-      for (int pq = tid; pq < snr; pq += BLOCK) {
-        const int p = pq >> d.lognrhs, qq = pq & (nr - 1);
-        const int rr = rows_l[p];
-        const int par = __popc((unsigned)(rr >> d.log_rows) & (unsigned)t) & 1;
-        const double v = X[padx(((rr & (d.rows_per_tile - 1)) << d.lognrhs) + qq)];
-        acc[pq] += par ? -v : v;
+      if (reg_acc) {
+        const int lomask = d.rows_per_tile - 1;
+#pragma unroll
+        for (int a = 0; a < RA; ++a) {
+          const int pq = tid + a * BLOCK;
+          if (pq < snr) {
+            const int rr = rows_l[pq >> d.lognrhs];
+            const int par = __popc((unsigned)(rr >> d.log_rows) & (unsigned)t) & 1;
+            const double v = X[padx(((rr & lomask) << d.lognrhs) + (pq & (nr - 1)))];
+            racc[a] += par ? -v : v;
+          }
+        }
+      } else {
+        const int lomask = d.rows_per_tile - 1;
+        for (int pq0 = tid; pq0 < snr; pq0 += SK_BATCH * BLOCK) {
+          double v[SK_BATCH], o[SK_BATCH];
+#pragma unroll
+          for (int u = 0; u < SK_BATCH; ++u) {
+            const int pq = pq0 + u * BLOCK;
+            v[u] = 0.0;
+            o[u] = 0.0;
+            if (pq < snr) {
+              const int rr = rows_l[pq >> d.lognrhs];
+              const int par = __popc((unsigned)(rr >> d.log_rows) & (unsigned)t) & 1;
+              const double x = X[padx(((rr & lomask) << d.lognrhs) + (pq & (nr - 1)))];
+              v[u] = par ? -x : x;
+              o[u] = acc[pq];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < SK_BATCH; ++u) {
+            const int pq = pq0 + u * BLOCK;
+            if (pq < snr) acc[pq] = o[u] + v[u];
+          }
+        }
       }
       __syncthreads();
     }
   }
   __syncthreads();
   double* skp = d.skpart + (long long)(i & 1) * d.skstride;
-  for (int pq = tid; pq < snr; pq += BLOCK) {
-    double a = acc[pq];
-    for (int sl = 1; sl < nsl; ++sl) a += acc[sl * snr + pq];
-    skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = a;
+  if (reg_acc) {
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      const int pq = tid + a * BLOCK;
+      if (pq < snr) skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = racc[a];
+    }
+  } else {
+    for (int pq = tid; pq < snr; pq += BLOCK) {
+      double a = acc[pq];
+      for (int sl = 1; sl < nsl; ++sl) a += acc[sl * snr + pq];
+      skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = a;
+    }
   }
 
   // norm partials per rhs

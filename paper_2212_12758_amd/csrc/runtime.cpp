@@ -218,7 +218,10 @@ struct Plan {
   int LT = 12, R = 0, logR = 0, ntiles = 0, nblk = 0, nred = 0;
   long long ldv = 0;
   size_t lds_update = 0;
+  size_t lds_kupdate = 0;      // dynamic LDS of k_update (smaller with register SRHT accumulators)
   int sk_slices = 1;
+  int sk_reg = 0;              // SRHT accumulators in registers (k_update)
+  int tgroups = 1;             // XCD groups of the streaming blocks
   size_t bytes = 0;
   // offsets in the workspace
   size_t oV, oW, oH, oEta, oWn, oCoef, oS, oPart, oNpart, oSk, oCnt, oStatus, oRows, oDense, oCf, oInfoHost;
@@ -289,6 +292,11 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
   P.nblk = std::min(P.ntiles, P.LT == 11 ? 512 : 2048);
   const long long snr = (long long)p.s * nrhs;
   P.nred = (int)std::max<long long>(1, std::min<long long>((snr + 7) / 8, 128));   // one per 8 sketch rows
+  // streaming blocks in 8 XCD groups when the grid divides; the leading
+  // sketch-reduction blocks of the update pass are a multiple of 8 then, so a
+  // block index means the same XCD in both passes of a step
+  P.tgroups = (P.nblk >= 8 && P.nblk % 8 == 0) ? 8 : 1;
+  if (P.tgroups == 8) P.nred = (P.nred + 7) & ~7;
   P.lds_update = (size_t)(snr + (p.sketch == FAB_SKETCH_SRHT ? tile + tile / 32 : 0)) * 8 + (size_t)p.s * 4;
   if (P.lds_update > 160 * 1024) return FAB_EINVAL;
   // sparse sign with 4-wave blocks: one LDS accumulator per wave when the four
@@ -297,6 +305,14 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
   if (p.sketch == FAB_SKETCH_SPARSE_SIGN && P.LT == 11 && (size_t)snr * 4 * 8 <= 96 * 1024) {
     P.sk_slices = 4;
     P.lds_update = (size_t)snr * 4 * 8 + (size_t)p.s * 4;
+  }
+  // SRHT with one rhs: each thread of k_update holds its s/BLOCK sketch
+  // accumulators in registers when there are at most 4
+  P.lds_kupdate = P.lds_update;
+  P.sk_reg = 0;
+  if (p.sketch == FAB_SKETCH_SRHT && nrhs == 1 && snr <= 4LL * (tile / 8)) {
+    P.sk_reg = 1;
+    P.lds_kupdate = (size_t)(tile + tile / 32) * 8 + (size_t)p.s * 4;
   }
   P.ldv = (nel + 63) & ~63LL;
   const int m = p.m, s = p.s;
@@ -539,6 +555,9 @@ void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev
   d.status = (int*)(ws + P.oStatus);
   d.sketch = p.sketch == FAB_SKETCH_SRHT ? SK_SRHT : SK_SPARSE;
   d.sk_slices = P.sk_slices;
+  d.sk_reg = P.sk_reg;
+  d.tgroups = P.tgroups;
+  d.tchunk = ((long long)P.ntiles + P.tgroups - 1) / P.tgroups;
   d.srht_rows = rows;
   if (d.sketch == SK_SRHT) {
     d.key_a = sm64_out(p.seed, 1);
@@ -601,7 +620,7 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
     if (e != hipSuccess) return FAB_EDEVICE;
   }
   B(FAB_K_OTHER);
-  e = basis_start(d, P.esize, st, P.lds_update);
+  e = basis_start(d, P.esize, st, P.lds_kupdate);
   E();
   if (e != hipSuccess) return FAB_EDEVICE;
   if (P.bg) {
@@ -637,7 +656,7 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_
     E();
     if (e != hipSuccess) return FAB_EDEVICE;
     B(FAB_K_UPDATE);
-    e = basis_update(d, P.esize, i, st, P.lds_update);
+    e = basis_update(d, P.esize, i, st, P.lds_kupdate);
     E();
     if (e != hipSuccess) return FAB_EDEVICE;
     if (!P.whiten) continue;
