@@ -274,6 +274,168 @@ def oracle_sample_fm(Aor, b, f, m, m_sample=20):
                         f"by {m}/{ms} (a lower bound on the full solve's time: later steps cost more)")
 
 
+def serving_main(args):
+    """The serving mix: Poisson arrivals of single-rhs requests of mixed n, m
+    and f (workloads.serving_mix), served by the context's request loop
+    (continuous batching; queued requests on a shared resident matrix with
+    the same parameters merged into block solves), FP32 basis with the
+    automatic precision and least-squares policies at tol = 1e-6, SRHT
+    sketch (as in the paper's experiments; --sketch sparse_sign).
+
+    1. closed loop: every request queued at once; the makespan gives the
+       saturated throughput;
+    2. open loop: the trace replayed at 0.8 x that rate (exponential gaps
+       from the workload's seed): value = requests / (last completion - first
+       arrival), p50/p99 of submit-to-completion latency;
+    3. the plain FP64 path: the same requests, FP64 basis, one blocking solve
+       at a time (its throughput is 1 / mean service time; its latencies are
+       those of a single server fed the same trace);
+    4. accuracy: the oracle's f_m for a sample of requests (both paths).
+
+    The context's 8 serving streams (and their side streams) run concurrently
+    only on as many hardware queues: HIP's default of 4 per process would
+    serialise them, so this mode asks for 16 (GPU_MAX_HW_QUEUES, read when HIP
+    starts; --hw-queues, at most 32)."""
+    os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2212_12758_amd import Context, make_params
+
+    nreq = args.requests
+    reqs, gaps = W.serving_mix(nreq=nreq)
+    nev = len(gaps)
+    print(f"serving mix: {nreq} requests, {nev} arrival events", file=sys.stderr, flush=True)
+    ctx = Context(0, arena_bytes=args.arena_gb << 30)
+    pool = {}
+    mats = []
+    for r in reqs:
+        if r.pool >= 0:
+            if r.pool not in pool:
+                pool[r.pool] = ctx.matrix(r.op)
+            mats.append(pool[r.pool])
+        else:
+            mats.append(ctx.matrix(r.op))
+    # right-hand sides: N(0,1) from a per-request seeded device generator
+    bs, outs = [], []
+    for r in reqs:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1_000_000 + r.rid)
+        bs.append(torch.randn(r.op.n, generator=g, dtype=torch.float64, device="cuda"))
+        outs.append(torch.empty_like(bs[-1]))
+    torch.cuda.synchronize()
+
+    def params(r, prec, tol):
+        return make_params(r.m, r.k, r.s, args.sketch, 8, r.sketch_seed, prec, "auto", tol)
+
+    p32 = [params(r, "auto", 1e-6) for r in reqs]
+
+    def run(arrivals):
+        """Submit request i at arrivals[event of i] (seconds from start);
+        returns (makespan from first arrival, latencies in ms, infos)."""
+        handles = [None] * nreq
+        t0 = time.perf_counter()
+        i = 0
+        while i < nreq:
+            due = arrivals[reqs[i].event]
+            now = time.perf_counter() - t0
+            if due > now:
+                time.sleep(min(due - now, 0.002))
+                continue
+            handles[i] = ctx.submit(mats[i], bs[i], reqs[i].f, p32[i], outs[i])
+            i += 1
+        infos = [h.wait()[0] for h in handles]
+        t_end = time.perf_counter() - t0
+        lat = np.array([inf["latency_us"] for inf in infos]) / 1e3
+        return t_end, lat, infos
+
+    # warm-up: a few requests of each kind (graph-free served path; builds caches)
+    for i in range(min(16, nreq)):
+        ctx.submit(mats[i], bs[i], reqs[i].f, p32[i], outs[i]).wait()
+    torch.cuda.synchronize()
+    # 1. closed loop
+    t_sat, lat_sat, _ = run(np.zeros(nev))
+    rate_sat = nreq / t_sat
+    print(f"closed loop: {t_sat:.2f} s, {rate_sat:.1f} solves/s", file=sys.stderr, flush=True)
+    # 2. open loop at 0.8 x the saturated rate
+    lam = 0.8 * rate_sat * nev / nreq           # arrival events per second
+    arrivals = np.concatenate([[0.0], np.cumsum(gaps[:-1])]) / lam
+    t_open, lat, infos = run(arrivals)
+    value = nreq / t_open
+    res32 = [o.clone() for o in outs]
+    blocks = np.array([inf["block_rhs"] for inf in infos])
+    print(f"open loop: {t_open:.2f} s, {value:.1f} solves/s, p50 {np.percentile(lat, 50):.2f} ms "
+          f"p99 {np.percentile(lat, 99):.2f} ms", file=sys.stderr, flush=True)
+    # 3. plain FP64 path, one request at a time
+    p64 = [params(r, "fp64", 1e-6) for r in reqs]
+    serv = np.zeros(nreq)
+    for i in range(nreq):
+        ts = time.perf_counter()
+        ctx.solve(mats[i], bs[i], reqs[i].f, p64[i], outs[i])
+        torch.cuda.synchronize()
+        serv[i] = time.perf_counter() - ts
+    rate64 = nreq / serv.sum()
+    done, lat64 = 0.0, np.zeros(nreq)
+    for i in range(nreq):
+        a = arrivals[reqs[i].event]
+        done = max(done, a) + serv[i]
+        lat64[i] = (done - a) * 1e3
+    print(f"plain fp64: {rate64:.1f} solves/s", file=sys.stderr, flush=True)
+    res64 = [o.clone() for o in outs]
+    # 4. accuracy on a sample (the smallest requests, every f kind and both
+    # kinds of matrix), oracle timed as the CPU baseline
+    from oracle import krylov, operators
+
+    order = sorted(range(nreq), key=lambda i: reqs[i].op.n)
+    sample = order[:args.oracle_sample]
+    c0 = time.perf_counter()
+    errs32, errs64 = [], []
+    for i in sample:
+        r = reqs[i]
+        b = bs[i].cpu().numpy()
+        ref = krylov.fm(operators.as_matrix(r.op), b, r.f, r.m)
+        errs32.append(krylov.relerr(res32[i].cpu().numpy(), ref))
+        errs64.append(krylov.relerr(res64[i].cpu().numpy(), ref))
+    tcpu = time.perf_counter() - c0
+    for A in set(mats):
+        A.destroy()
+    ctx.close()
+    errs32, errs64 = np.array(errs32), np.array(errs64)
+    basis_bytes = sum(r.op.n * (r.m + 1) * 4 for r in reqs)
+    line = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": nreq, "warmup": 16,
+        "ms_per_step": 1e3 * t_open / nreq, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": "serving_mix", "requests": nreq, "arrival_events": nev,
+            "operators": "2D 5-point / 3D 7-point Dirichlet Laplacians, n log-uniform in [2^14, 2^21]",
+            "f": "exp(-tA) (||tA|| log-uniform [1, 50]), A^{1/2}, (A + 1e-3 I)^{-1/2}",
+            "m": "U[30, 200]", "k": "U{2, 3, 4}", "s": "2m", "sketch": args.sketch,
+            "shared_matrix_fraction": float(np.mean([r.pool >= 0 for r in reqs])),
+            "arena_GB": args.arena_gb, "basis_GB_total": basis_bytes / 1e9,
+            "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
+            "saturated_solves_per_s": rate_sat, "arrival_rate_solves_per_s": 0.8 * rate_sat,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "closed_loop_p50_ms": float(np.percentile(lat_sat, 50)),
+            "block_rhs_histogram": {str(int(g)): int((blocks == g).sum()) for g in np.unique(blocks)},
+            "fell_back": int(sum(inf["fell_back"] for inf in infos)),
+            "refined": int(sum(inf["ls_iters"] > 0 for inf in infos)),
+            "plain_fp64_solves_per_s": rate64, "fp32_over_plain_fp64": value / rate64,
+            "plain_fp64_p50_ms": float(np.percentile(lat64, 50)), "plain_fp64_p99_ms": float(np.percentile(lat64, 99)),
+            "oracle_sample": len(sample), "relerr_vs_oracle_max": float(errs32.max()),
+            "relerr_vs_oracle_median": float(np.median(errs32)),
+            "meets_tol_fraction": float(np.mean(errs32 <= 1e-6)),
+            "plain_fp64_relerr_vs_oracle_max": float(errs64.max()),
+        },
+        "roofline": None,
+        "cpu_baseline": {"value": len(sample) / tcpu, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+                         "sample": f"f_m by full Arnoldi (FP64, numpy/scipy) for the {len(sample)} smallest requests "
+                                   f"of the mix (n <= {reqs[sample[-1]].op.n}), {tcpu:.1f} s"},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,7 +454,12 @@ def main():
                     help="no GPU: turn two rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE outputs into the traffic summary")
     ap.add_argument("--basis", default=None, choices=["truncated", "sketched_gs", "sketched_gs2", "whitened"],
                     help="basis construction (default: the workload's)")
-    ap.add_argument("--workload", default="convdiff3d_256_exp_8rhs", choices=sorted(BENCH),
+    ap.add_argument("--requests", type=int, default=4096, help="serving_mix: number of requests")
+    ap.add_argument("--arena-gb", type=int, default=16, help="serving_mix: arena budget (admission binds)")
+    ap.add_argument("--oracle-sample", type=int, default=24, help="serving_mix: requests checked by the oracle")
+    ap.add_argument("--hw-queues", type=int, default=16, help="serving_mix: GPU_MAX_HW_QUEUES for this process")
+    ap.add_argument("--sketch", default="srht", choices=["srht", "sparse_sign"], help="serving_mix: sketch")
+    ap.add_argument("--workload", default="convdiff3d_256_exp_8rhs", choices=sorted(BENCH) + ["serving_mix"],
                     help="convdiff3d_256_exp_8rhs (default: 256^3, 8 rhs), convdiff3d_128_exp, "
                          "lap3d_80_invsqrt (Algorithm 3), rgg_2p20_invsqrt (whitened), convdiff2d_352_exp")
     args = ap.parse_args()
@@ -303,6 +470,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the solve is not sharded "
                                    "across GPUs; N > 1 is not supported", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "serving_mix":
+        serving_main(args)
+        return
 
     import numpy as np
     import torch

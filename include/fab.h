@@ -167,6 +167,8 @@ typedef struct {
                          (0: never)                                                  */
   int ls_limit;       /* 1: the LSQR refinement stopped at its iteration limit before
                          meeting its stopping test (err_est then exceeds tol/10)     */
+  int block_rhs;      /* served requests: right-hand sides of the block solve this
+                         request ran in (1: on its own; see fab_set_block_limit)     */
   double latency_us;  /* submit-to-completion wall time                              */
 } fab_info;
 
@@ -254,9 +256,16 @@ int fab_solve_noalloc(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
 /* Non-blocking submit to the context's serving loop.  The request is admitted
  * when its workspace fits the arena next to the requests already running
  * (continuous batching: admitted requests run concurrently on separate
- * streams); until then it waits in FIFO order.  b and out must stay valid
- * until completion is reported.  Errors as fab_solve, reported at submit for
- * argument checks and at fab_poll/fab_wait for execution.                    */
+ * streams); until then it waits in FIFO order.  Single-rhs requests queued
+ * together on the same matrix with the same function and fab_params (the
+ * sketch seed included) are merged into one block solve of up to
+ * fab_set_block_limit right-hand sides (a power of two): the operator is
+ * applied to the whole block in each step (Algorithm 2 on a block of vectors;
+ * Table 1 "matrix access" once per step for all of them).  Each column's
+ * result equals the request's result alone to the basis precision (the
+ * reductions group differently).  b and out must stay valid until completion
+ * is reported.  Errors as fab_solve, reported at submit for argument checks
+ * and at fab_poll/fab_wait for execution.                                    */
 int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
                const fab_params* p, double* out, fab_request* req);
 
@@ -268,6 +277,16 @@ int fab_poll(fab_ctx ctx, fab_request req, int* done, fab_info* info);
 
 /* Blocks until the request finishes; then as fab_poll with done = 1.          */
 int fab_wait(fab_ctx ctx, fab_request req, fab_info* info);
+
+/* Largest number of single-rhs served requests merged into one block solve
+ * (1..32; 1 disables merging; default 32).  Errors: FAB_EINVAL.               */
+int fab_set_block_limit(fab_ctx ctx, int max_rhs);
+
+/* hold != 0: the serving loop admits no queued request until fab_hold(ctx, 0),
+ * so that a burst submitted meanwhile is admitted (and merged) together;
+ * running requests continue.  Blocking calls are not affected.
+ * Errors: FAB_EINVAL (null ctx).                                              */
+int fab_hold(fab_ctx ctx, int hold);
 
 /* Kernel timing for measurement.  For the classes selected by a bit mask,
  * blocking solves on this context record a HIP event pair on the context's

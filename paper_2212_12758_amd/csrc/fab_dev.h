@@ -21,6 +21,10 @@ constexpr int NSLOT = KMAX + 1;  // dot slots per rhs: k window dots + ||w||^2
 constexpr int BLOCK = 256;       // threads per streaming block
 constexpr int TILE_ELEMS = 4096; // max elements (rows * nrhs) per tile
 
+// Column pointers of a block of single-rhs requests (at most 32).
+struct ColPtrs { const double* p[32]; };
+struct OutPtrs { double* p[32]; };
+
 // Operator path of the streaming kernels: OP_STENCIL recomputes A u inside
 // the passes; OP_CSR reads w~ = A u from wbuf, written by a product launch
 // before the passes (a CSR matrix, or A applied twice for the sign function).
@@ -72,6 +76,8 @@ struct SolveDev {
   int sk_reg;            // SRHT: 1 = each thread holds its sketch accumulators in registers
   int tgroups;           // streaming blocks form tgroups groups (blk mod tgroups), 8 or 1
   long long tchunk;      // tiles per group: group g walks tiles [g*tchunk, (g+1)*tchunk)
+  int wtp, wc, wpen;     // pencil walk (wtp > 0): tiles per z-plane, tiles per pencil row,
+                         // pencils per group (3D stencils with large planes)
   const int* srht_rows;  // [s] sampled rows of the padded Hadamard transform
   unsigned long long key_a, key_b;   // SRHT: signs key; sparse: rows key, signs key
   double sk_scale;       // 1/sqrt(s) (SRHT) or 1/sqrt(zeta) (sparse sign)
@@ -248,18 +254,41 @@ __device__ inline double wave_sum_rhs(double v, int nrhs) {
 
 // Tiles of streaming block blk: blocks blk = g + tgroups * c form group g.
 // Consecutive workgroups of a launch are dispatched round-robin over the 8
-// XCDs, so with tgroups = 8 one group runs on one XCD; group g walks the
-// contiguous tile range [g tchunk, (g+1) tchunk) with its members
-// interleaved, so that neighbouring tiles (the stencil's y and z neighbours,
-// the tiles the previous pass wrote) are read through that XCD's L2.
-__device__ inline void tile_walk(const SolveDev& d, int blk, int& t0, int& hi, int& step) {
+// XCDs, so with tgroups = 8 one group runs on one XCD.  The block visits
+// tiles walk_tile(w, u) for u = u0, u0 + step, ... < uhi (the members of a
+// group interleaved), so that neighbouring tiles -- the stencil's y and z
+// neighbours -- are read through that XCD's L2 while still resident:
+//  * linear walk: group g takes the contiguous tiles [g tchunk, (g+1) tchunk);
+//  * pencil walk (3D stencil whose z-plane is large): a z-plane of wtp tiles
+//    is cut into pencils of wc consecutive tiles; group g takes pencils
+//    g, g + 8, ... (wpen of them) and walks each through all z-planes, so
+//    the planes z - 1, z, z + 1 of a pencil are touched close together.
+struct TileWalk {
+  int u0, uhi, step, g;
+  long long lo;
+};
+__device__ inline TileWalk tile_walk(const SolveDev& d, int blk) {
   const int G = d.tgroups;
-  const int g = blk % G, c = blk / G;
-  const long long lo = (long long)g * d.tchunk;
-  const long long h = lo + d.tchunk < (long long)d.ntiles ? lo + d.tchunk : (long long)d.ntiles;
-  t0 = (int)(lo + c);
-  hi = (int)h;
-  step = d.nblk / G;
+  TileWalk w;
+  w.g = blk % G;
+  w.u0 = blk / G;
+  w.step = d.nblk / G;
+  if (d.wtp > 0) {
+    w.lo = 0;
+    w.uhi = d.wpen * d.nz * d.wc;
+  } else {
+    w.lo = (long long)w.g * d.tchunk;
+    const long long h = w.lo + d.tchunk < (long long)d.ntiles ? w.lo + d.tchunk : (long long)d.ntiles;
+    w.uhi = (int)(h - w.lo);
+  }
+  return w;
+}
+__device__ inline int walk_tile(const SolveDev& d, const TileWalk& w, int u) {
+  if (d.wtp <= 0) return (int)(w.lo + u);
+  const int zc = d.nz * d.wc;
+  const int j = u / zc, rem = u - j * zc;
+  const int z = rem / d.wc, cc = rem - z * d.wc;
+  return z * d.wtp + (w.g + 8 * j) * d.wc + cc;
 }
 
 }  // namespace fab

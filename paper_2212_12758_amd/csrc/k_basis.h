@@ -246,13 +246,59 @@ __device__ inline void stencil8_fast(const SolveDev& d, const T* __restrict__ u,
   }
 }
 
+// Grid coordinates of row r by floating-point division with an integer
+// correction (exact for r < 2^31): cheaper than two integer divisions.
+__device__ inline void row_xyz(const SolveDev& d, int r, int& x, int& y, int& z) {
+  int q = (int)((double)r / (double)d.nx);
+  if (q * d.nx > r) --q;
+  else if ((q + 1) * d.nx <= r) ++q;
+  x = r - q * d.nx;
+  int zz = (int)((double)q / (double)d.ny);
+  if (zz * d.ny > q) --zz;
+  else if ((zz + 1) * d.ny <= q) ++zz;
+  y = q - zz * d.ny;
+  z = zz;
+}
+
 // As stencil8_fast, with the loaded values kept in the storage type T until
 // each is multiplied (same operations in the same order, FP64 arithmetic).
+// With nrhs >= 8 the 8 elements are the right-hand sides of one grid row:
+// the boundary conditions are applied once per thread to the coefficients
+// (a neighbour outside the grid gets coefficient 0) instead of per element
+// to the values.
 template <typename T>
 __device__ inline void stencil8_fast_raw(const SolveDev& d, const T* __restrict__ u, long long e, const T* c,
                                          double* w) {
-  const Masks8 mk = masks8(d, e);
   const int nr = d.nrhs;
+  if (nr >= EPT) {
+    int x, y, z;
+    row_xyz(d, (int)(e >> d.lognrhs), x, y, z);
+    const long long sy = (long long)d.nx * nr, sz = d.nz > 1 ? sy * d.ny : 0;
+    const long long nel = (long long)d.n * nr;
+    T xm[EPT], xp[EPT], ym[EPT], yp[EPT], zm[EPT], zp[EPT];
+    load8r(u + (e >= sy ? e - sy : e), ym);
+    load8r(u + (e + sy + EPT <= nel ? e + sy : e), yp);
+    load8r(u + (e >= sz ? e - sz : e), zm);
+    load8r(u + (e + sz + EPT <= nel ? e + sz : e), zp);
+    load8r(u + (e >= nr ? e - nr : e), xm);
+    load8r(u + (e + nr + EPT <= nel ? e + nr : e), xp);
+    const double c1 = x > 0 ? d.c[1] : 0.0, c2 = x < d.nx - 1 ? d.c[2] : 0.0;
+    const double c3 = y > 0 ? d.c[3] : 0.0, c4 = y < d.ny - 1 ? d.c[4] : 0.0;
+    const double c5 = z > 0 ? d.c[5] : 0.0, c6 = z < d.nz - 1 ? d.c[6] : 0.0;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      double a = d.c[0] * (double)c[j];
+      a += c1 * (double)xm[j];
+      a += c2 * (double)xp[j];
+      a += c3 * (double)ym[j];
+      a += c4 * (double)yp[j];
+      a += c5 * (double)zm[j];
+      a += c6 * (double)zp[j];
+      w[j] = a;
+    }
+    return;
+  }
+  const Masks8 mk = masks8(d, e);
   const long long sy = (long long)d.nx * nr, sz = d.nz > 1 ? sy * d.ny : 0;
   T xm[EPT], xp[EPT], ym[EPT], yp[EPT], zm[EPT], zp[EPT];
   const long long nel = (long long)d.n * nr;
@@ -419,9 +465,9 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int n
     const long long nel = (long long)d.n * nr;
     const bool fast_ok = OP == OP_STENCIL && nw == KT && stencil_fast_ok<T>(d);
     const long long reach = stencil_reach(d);
-    int t0, thi, tstep;
-    tile_walk(d, blockIdx.x, t0, thi, tstep);
-    for (int t = t0; t < thi; t += tstep) {
+    const TileWalk tw = tile_walk(d, blockIdx.x);
+    for (int iw = tw.u0; iw < tw.uhi; iw += tw.step) {
+      const int t = walk_tile(d, tw, iw);
       const long long e = ((long long)t << LT) + (long long)tid * EPT;
       if (fast_ok && ((long long)t << LT) >= reach && (((long long)t + 1) << LT) + reach <= nel) {
         // interior tile, full window: all loads first, no branches; loaded
@@ -481,7 +527,8 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_dots(SolveDev d, int i, int n
       if (tid < NSLOT) pblk[tid * nr + q] = o[tid];
     }
     __syncthreads();
-    for (int x = tid; x < RS; x += BLOCK) d.part[(long long)blockIdx.x * RS + x] = pblk[x];
+    // column-major: the partials of one quantity are contiguous over the blocks
+    for (int x = tid; x < RS; x += BLOCK) d.part[(long long)x * d.nblk + blockIdx.x] = pblk[x];
   }
 }
 
@@ -514,25 +561,41 @@ __device__ void step_scalars(const SolveDev& d, int i, bool have_dots, const dou
     for (int jj = 0; jj < KMAX; ++jj)
       if (jj < nw - 1) ej_pre[jj] = d.eta[(long long)tid * (m + 1) + j0 + jj];
   }
+  // Quantity rr (dot slot sl = rr / nr of rhs rr % nr, or the norm of rhs
+  // rr - RS) is summed over the blocks by one wave: lane l adds blocks
+  // l, l + 64, ... in order, then a fixed butterfly over the lanes.  The
+  // partials are column-major (contiguous over the blocks), so each wave has
+  // all loads of four quantities in flight at once.
   const int RT = RS + nr;
-  for (int r0 = 0; r0 < RT; r0 += RC) {
-    double a[RC];
+  {
+    constexpr int NWV = BLOCK / 64;
+    constexpr int CPW = 4;
+    const int lane = tid & 63, wv = wave_id();
+    const int nb = d.nblk;
+    for (int r0 = wv * CPW; r0 < RT; r0 += NWV * CPW) {
+      double a[CPW];
 #pragma unroll
-    for (int c = 0; c < RC; ++c) a[c] = 0.0;
-    for (int b = tid; b < d.nblk; b += BLOCK) {
-#pragma unroll
-      for (int c = 0; c < RC; ++c) {
+      for (int c = 0; c < CPW; ++c) {
+        a[c] = 0.0;
         const int rr = r0 + c;
+        const double* col = nullptr;
         if (rr < RS) {
-          if (have_dots) a[c] += d.part[(long long)b * RS + rr];
+          const int sl = rr / nr;
+          if (have_dots && (sl < nw || sl == KMAX)) col = d.part + (long long)rr * nb;
         } else if (rr < RT) {
-          a[c] += npb[(long long)b * nr + (rr - RS)];
+          col = npb + (long long)(rr - RS) * nb;
+        }
+        if (col) {
+#pragma unroll 8
+          for (int b = lane; b < nb; b += 64) a[c] += col[b];
         }
       }
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const double v = wave_sum_all(a[c]);
+        if (lane == 0 && r0 + c < RT) sums[r0 + c] = v;
+      }
     }
-    double o[RC];
-    block_sums<BLOCK, RC>(a, red, o);
-    if (tid < RC && r0 + tid < RT) sums[r0 + tid] = o[tid];
   }
   __syncthreads();
 
@@ -743,6 +806,8 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   double* acc = lds + (SK == SK_SRHT ? padx(TILE) : 0);              // sketch accumulator [s][nr] (LDS path)
   const int snr = d.s * nr;
   const bool reg_acc = SK == SK_SRHT && srht_reg_slots<QC>() > 0 && d.sk_reg;
+  // SRHT sums kept rhs-major (several rhs per row, LDS path)
+  const bool qmajor = SK == SK_SRHT && QC > 1 && !reg_acc && nr >= EPT;
   // sparse sign: one accumulator per wave when the host sized LDS for it, so
   // that the LDS atomics of different waves never meet (fixed order)
   const int nsl = (SK == SK_SPARSE && NW > 1 && d.sk_slices == NW) ? NW : 1;
@@ -762,9 +827,28 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   for (int c = 0; c < QC; ++c) nrm[c] = 0.0;
   const bool fast_ok = !START && OP == OP_STENCIL && nw == KT && stencil_fast_ok<T>(d);
   const long long reach = stencil_reach(d);
-  int t0, thi, tstep;
-  tile_walk(d, blk, t0, thi, tstep);
-  for (int t = t0; t < thi; t += tstep) {
+  const TileWalk tw = tile_walk(d, blk);
+  auto interior = [&](int tt) {
+    return fast_ok && ((long long)tt << LT) >= reach && (((long long)tt + 1) << LT) + reach <= nel;
+  };
+  // FP32 storage, one rhs: the source and window values of the block's next
+  // interior tile are loaded before this tile's store and sketch (LDS) phase,
+  // so that they are in flight meanwhile (the barriers of that phase wait for
+  // LDS operations only).  With several rhs the extra registers would cost a
+  // wave per SIMD (measured: slower).
+  constexpr bool PF = sizeof(T) == 4 && QC == 1;
+  T pc[EPT], pwin[KT > 1 ? KT - 1 : 1][EPT];
+  int pf_t = -1;   // the tile whose values pc / pwin hold
+  auto prefetch = [&](int tt) {
+    const long long ee = ((long long)tt << LT) + (long long)tid * EPT;
+    load8r(src + ee, pc);
+#pragma unroll
+    for (int jj = 0; jj < KT - 1; ++jj) load8r(V + (long long)(j0 + jj) * d.ldv + ee, pwin[jj]);
+    pf_t = tt;
+  };
+  if (PF && tw.u0 < tw.uhi && interior(walk_tile(d, tw, tw.u0))) prefetch(walk_tile(d, tw, tw.u0));
+  for (int iw = tw.u0; iw < tw.uhi; iw += tw.step) {
+    const int t = walk_tile(d, tw, iw);
     const long long e = ((long long)t << LT) + (long long)tid * EPT;
     double uu[EPT];
 #pragma unroll
@@ -773,14 +857,23 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
       double u[EPT];
       if (START) {
         get8(d.b, e, nel, u);
-      } else if (fast_ok && ((long long)t << LT) >= reach && (((long long)t + 1) << LT) + reach <= nel) {
+      } else if (interior(t)) {
         // interior tile, full window: all loads first, no branches; loaded
         // values stay in the storage type until used
         T c[EPT], win[KT > 1 ? KT - 1 : 1][EPT];
         double w[EPT];
-        load8r(src + e, c);
+        if (PF && pf_t == t) {
 #pragma unroll
-        for (int jj = 0; jj < KT - 1; ++jj) load8r(V + (long long)(j0 + jj) * d.ldv + e, win[jj]);
+          for (int j = 0; j < EPT; ++j) c[j] = pc[j];
+#pragma unroll
+          for (int jj = 0; jj < KT - 1; ++jj)
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) win[jj][j] = pwin[jj][j];
+        } else {
+          load8r(src + e, c);
+#pragma unroll
+          for (int jj = 0; jj < KT - 1; ++jj) load8r(V + (long long)(j0 + jj) * d.ldv + e, win[jj]);
+        }
         stencil8_fast_raw(d, src, e, c, w);
         // same order of operations as the general path below
 #pragma unroll
@@ -791,6 +884,14 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
           for (int j = 0; j < EPT; ++j) u[j] -= cf.get(tid, j, nr, 1 + jj) * (double)win[jj][j];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) u[j] -= cf.get(tid, j, nr, KT) * (double)c[j];
+        if (PF) {
+          pf_t = -1;
+          const int iwn = iw + tw.step;
+          if (iwn < tw.uhi) {
+            const int tn = walk_tile(d, tw, iwn);
+            if (interior(tn)) prefetch(tn);
+          }
+        }
       } else {
         double w[EPT];
         if (OP == OP_STENCIL) {
@@ -826,14 +927,16 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
 #pragma unroll
       for (int j = 0; j < EPT; ++j) nrm[slot_of<QC>(j)] += uu[j] * uu[j];
       if (SK == SK_SPARSE) {
+        // the column of Theta is a function of the row: hashed once per row
+        // (the rhs of a row are consecutive elements)
+        int rows[ZMAX];
+        unsigned long long sb = 0;
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
           if (e + j < nel) {
             const int r = (int)((e + j) >> d.lognrhs);
             const int q = (int)((e + j) & (nr - 1));
-            int rows[ZMAX];
-            unsigned long long sb;
-            sparse_sign_column(d.key_a, d.key_b, r, d.s, d.zeta, rows, &sb);
+            if (j == 0 || q == 0) sparse_sign_column(d.key_a, d.key_b, r, d.s, d.zeta, rows, &sb);
 #pragma unroll
             for (int tt = 0; tt < ZMAX; ++tt)
               if (tt < d.zeta) atomicAdd(&acc_w[rows[tt] * nr + q], ((sb >> tt) & 1ull) ? -uu[j] : uu[j]);
@@ -842,11 +945,14 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
       }
     }
     if (SK == SK_SRHT) {
-      // D signs, then the transform of the tile along rows
+      // D signs (hashed once per row: the rhs of a row are consecutive
+      // elements), then the transform of the tile along rows
+      bool neg = false;
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
-        const unsigned long long r = (unsigned long long)((e + j) >> d.lognrhs);
-        if (sm64_out(d.key_a, r) >> 63) uu[j] = -uu[j];
+        const long long ej = e + j;
+        if (j == 0 || (ej & (nr - 1)) == 0) neg = (sm64_out(d.key_a, (unsigned long long)(ej >> d.lognrhs)) >> 63) != 0;
+        if (neg) uu[j] = -uu[j];
       }
       fwht_tile<LT>(uu, X, d.lognrhs);
       // sampled rows r = (r_hi, r_lo): contribution (-1)^popcount(r_hi & t) * X[r_lo]
@@ -864,6 +970,32 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
         }
       } else {
         const int lomask = d.rows_per_tile - 1;
+        if (qmajor) {
+          // several rhs: thread tid owns the sampled rows p = tid + a BLOCK
+          // with all their rhs; the rhs of a row are consecutive in the tile,
+          // so one row index, one sign and one address serve nr sums.  The
+          // accumulators are rhs-major here (sum (p, q) at q s + p), so the
+          // lanes of a wave touch consecutive LDS words.
+          for (int p = tid; p < d.s; p += BLOCK) {
+            const int rr = rows_l[p];
+            const double sg = (__popc((unsigned)(rr >> d.log_rows) & (unsigned)t) & 1) ? -1.0 : 1.0;
+            const int b = (rr & lomask) << d.lognrhs;
+            for (int q0 = 0; q0 < nr; q0 += EPT) {
+              // 8 consecutive elements from a multiple of 8 share one
+              // padding group of the tile
+              const double* xp = X + padx(b + q0);
+              double* ap = acc + q0 * d.s + p;
+              double xv[EPT], av[EPT];
+#pragma unroll
+              for (int q = 0; q < EPT; ++q) {
+                xv[q] = xp[q];
+                av[q] = ap[q * d.s];
+              }
+#pragma unroll
+              for (int q = 0; q < EPT; ++q) ap[q * d.s] = av[q] + sg * xv[q];
+            }
+          }
+        } else
         for (int pq0 = tid; pq0 < snr; pq0 += SK_BATCH * BLOCK) {
           double v[SK_BATCH], o[SK_BATCH];
 #pragma unroll
@@ -899,7 +1031,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
     }
   } else {
     for (int pq = tid; pq < snr; pq += BLOCK) {
-      double a = acc[pq];
+      double a = acc[qmajor ? (pq & (nr - 1)) * d.s + (pq >> d.lognrhs) : pq];
       for (int sl = 1; sl < nsl; ++sl) a += acc[sl * snr + pq];
       skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = a;
     }
@@ -919,7 +1051,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   for (int q = tid; q < nr; q += BLOCK) {
     double t = 0.0;
     for (int w = 0; w < NW; ++w) t += nred[w][q];
-    npw[(long long)blk * nr + q] = t;
+    npw[(long long)q * d.nblk + blk] = t;   // column-major, as the dot partials
   }
 }
 

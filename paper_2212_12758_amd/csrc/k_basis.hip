@@ -81,6 +81,34 @@ hipError_t zero_fill(void* p, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Blocked requests: the b vectors of g single-rhs requests into one
+// interleaved [n][g] block (element (r, q) at r g + q), and the block's result
+// back into each request's out.  g is a power of two <= 32.
+__global__ void k_gather_cols(ColPtrs src, int logg, long long n, double* __restrict__ dst) {
+  const long long tot = n << logg;
+  const int gm = (1 << logg) - 1;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long long)gridDim.x * 256)
+    dst[e] = src.p[(int)(e & gm)][e >> logg];
+}
+__global__ void k_scatter_cols(const double* __restrict__ src, int logg, long long n, OutPtrs dst) {
+  const long long tot = n << logg;
+  const int gm = (1 << logg) - 1;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long long)gridDim.x * 256)
+    dst.p[(int)(e & gm)][e >> logg] = src[e];
+}
+static unsigned col_grid(long long tot) {
+  long long g = (tot + 255) / 256;
+  return (unsigned)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+}
+hipError_t gather_cols(const ColPtrs& src, int logg, long long n, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_cols, dim3(col_grid(n << logg)), dim3(256), 0, st, src, logg, n, dst);
+  return hipGetLastError();
+}
+hipError_t scatter_cols(const double* src, int logg, long long n, const OutPtrs& dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_cols, dim3(col_grid(n << logg)), dim3(256), 0, st, src, logg, n, dst);
+  return hipGetLastError();
+}
+
 // SRHT row sampling, one wave: Floyd's algorithm draws s distinct rows of
 // [0, npad): for t = 0..s-1 with j = npad - s + t, q = floor(u_t (j+1) / 2^64)
 // (u_t the t-th output of the row stream); q is taken unless already

@@ -59,9 +59,9 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_bg_apply(SolveDev d, int i) {
   if (SK == SK_SRHT)
     for (int x = tid; x < d.s; x += BLOCK) rows_l[x] = d.srht_rows[x];
   __syncthreads();
-  int t0, thi, tstep;
-  tile_walk(d, blockIdx.x, t0, thi, tstep);
-  for (int t = t0; t < thi; t += tstep) {
+  const TileWalk tw = tile_walk(d, blockIdx.x);
+  for (int u = tw.u0; u < tw.uhi; u += tw.step) {
+    const int t = walk_tile(d, tw, u);
     const long long e = ((long long)t << LT) + (long long)tid * EPT;
     double w[EPT];
 #pragma unroll

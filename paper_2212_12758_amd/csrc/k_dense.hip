@@ -1,12 +1,15 @@
 // Small dense FP64 stages of the method, one workgroup per right-hand side:
 //
-//  k_lsq    Householder QR of the sketched basis Theta V_{m+1} (its last
-//           column carried along gives Q^T Theta v_{m+1}); y = R_m^{-1} Q^T
-//           Theta v_{m+1} (sketch-and-solve of the least-squares problem
-//           eq. (7), Remark 3) by back substitution; the compression
-//           H_hat = H_m + h_{m+1,m} y e_m^T (eq. (6)).  The matrix is held in
-//           registers across the workgroup when s <= 448 and m + 1 <= 104,
-//           else it is factorised in global memory.
+//  k_gram   G = W^T W of the normalised sketch W = Theta V_{m+1} (many
+//           workgroups).
+//  k_lsq    the triangular factor R of W: Cholesky of G (whose last column
+//           of R is [z; rho] with z = Q^T Theta v_{m+1}), in LDS when
+//           s <= 448 and m + 1 <= 104, else in global memory; when a pivot
+//           fails or R's diagonal spreads by more than 1e3, Householder QR of
+//           W (in registers, or in global memory); y = R_m^{-1} z
+//           (sketch-and-solve of the least-squares problem eq. (7), Remark 3)
+//           by back substitution; the compression H_hat = H_m + h_{m+1,m} y
+//           e_m^T (eq. (6)).
 //  (exp(alpha H_hat) e_1 lives in k_expm.hip: the action of the exponential on
 //   e_1 by a scaled truncated Taylor series.)
 //  ((H_hat + sigma I)^{+-1/2} e_1 lives in k_fsqrt.hip: resolvent quadrature.)
@@ -243,34 +246,47 @@ __device__ void qr_global(const double* __restrict__ S, const double* __restrict
 
 // ----------------------------------------------------------------- Gram matrix and Cholesky factor
 // G = W^T W of the normalised sketch W = [S_0 / eta_0, ..., S_m / eta_m]
-// (upper triangle, ld m+1, in the rhs's scratch region oM): a 16 x 16 tile per
-// workgroup, rows staged through LDS in chunks of 64, each thread one entry.
-constexpr int GT = 16, GCH = 64;
-__global__ void __launch_bounds__(256) k_gram(SolveDev d, DenseDev g) {
+// (upper triangle, ld m+1, in the rhs's scratch region oM) on the FP64
+// matrix cores: one wave per 16 x 16 tile of G, every rhs and tile in its own
+// workgroup (a batch of small GEMMs).  v_mfma_f64_16x16x4f64 accumulates
+// D += A B with A = W[r0 .. r0+3, ca0 .. ca0+15]^T and B = W[r0 .. r0+3,
+// cb0 .. cb0+15] for r0 = 0, 4, ..., s-4: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] and receives D[4 r + l / 16][l % 16] in its register
+// r (the layout measured on gfx950).  Rows beyond s and columns beyond m are
+// zero.
+constexpr int GT = 16;
+typedef double gram_d4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(64) k_gram(SolveDev d, DenseDev g) {
   const int q = blockIdx.x, tx = blockIdx.y, ty = blockIdx.z;
   if (ty > tx) return;   // upper tiles only
-  __shared__ double As[GCH][GT], Bs[GCH][GT];
-  const int tid = threadIdx.x, a = tid & (GT - 1), b = tid >> 4;
+  const int lane = threadIdx.x;
   const int m1 = d.m + 1, s = d.s;
   const double* S = d.S + (long long)q * s * m1;
   const double* eta = d.eta + (long long)q * m1;
-  const int ca0 = ty * GT, cb0 = tx * GT;
-  double acc = 0.0;
-  for (int r0 = 0; r0 < s; r0 += GCH) {
-    for (int x = tid; x < GCH * GT; x += 256) {
-      const int rr = x / GT, cc = x % GT, r = r0 + rr;
-      const int ca = ca0 + cc, cb = cb0 + cc;
-      const double ea = ca < m1 ? eta[ca] : 0.0, eb = cb < m1 ? eta[cb] : 0.0;
-      As[rr][cc] = (r < s && ca < m1 && ea > 0.0) ? S[(long long)ca * s + r] / ea : 0.0;
-      Bs[rr][cc] = (r < s && cb < m1 && eb > 0.0) ? S[(long long)cb * s + r] / eb : 0.0;
+  const int ca = ty * GT + (lane & 15), cb = tx * GT + (lane & 15), kr = lane >> 4;
+  const double ea = ca < m1 ? eta[ca] : 0.0, eb = cb < m1 ? eta[cb] : 0.0;
+  const double ia = (ca < m1 && ea > 0.0) ? 1.0 / ea : 0.0, ib = (cb < m1 && eb > 0.0) ? 1.0 / eb : 0.0;
+  const double* pa = S + (long long)(ca < m1 ? ca : 0) * s;
+  const double* pb = S + (long long)(cb < m1 ? cb : 0) * s;
+  gram_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  constexpr int U = 8;   // MFMA steps per batch of loads (32 rows)
+  for (int r0 = 0; r0 < s; r0 += 4 * U) {
+    double xa[U], xb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + 4 * u + kr;
+      xa[u] = r < s ? pa[r] * ia : 0.0;
+      xb[u] = r < s ? pb[r] * ib : 0.0;
     }
-    __syncthreads();
-#pragma unroll 16
-    for (int rr = 0; rr < GCH; ++rr) acc += As[rr][a] * Bs[rr][b];
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], acc, 0, 0, 0);
   }
-  const int ca = ca0 + a, cb = cb0 + b;
-  if (ca < m1 && cb < m1 && ca <= cb) g.base[(long long)q * g.stride + g.oM + ca + (long long)cb * m1] = acc;
+  double* G = g.base + (long long)q * g.stride + g.oM;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = ty * GT + 4 * r + (lane >> 4), j = tx * GT + (lane & 15);
+    if (i < m1 && j < m1 && i <= j) G[i + (long long)j * m1] = acc[r];
+  }
 }
 
 // Cholesky G = R^T R of the leading n x n block of G (global, ld m1) in LDS
@@ -303,6 +319,50 @@ __device__ bool cholesky_lds(const double* __restrict__ G, int m1, int n, double
     for (int j = k + 1 + wave_id(); j < n; j += LBLOCK / 64) {
       const double f = R[k + j * n] * inv;
       for (int i = k + 1 + (tid & 63); i <= j; i += 64) R[i + j * n] -= R[k + i * n] * f;
+    }
+    if (k >= 1) {
+      const double rp = sqrt(dprev);
+      for (int j = k - 1 + tid; j < n; j += LBLOCK) R[k - 1 + (long long)j * n] /= rp;
+    }
+    dprev = dkk;
+    __syncthreads();
+  }
+  if (tid == 0) R[n - 1 + (long long)(n - 1) * n] = sqrt(dprev);
+  if (!(rmax <= CHOL_MAXRATIO * rmin)) return false;
+  if (tid == 0) {
+    rmm[0] = rmax;
+    rmm[1] = rmin;
+    for (int w = 1; w < 8; ++w) { rmm[2 * w] = 0.0; rmm[2 * w + 1] = 1e308; }
+  }
+  __syncthreads();
+  return true;
+}
+
+// The same factorisation with G and R in global memory (R, ld n, may be any
+// region of n*n doubles; G is read only), for factors too large for LDS.
+// The workgroup's waves share one CU and its write-through L1, so the
+// barrier per column orders the updates as in the LDS version.
+__device__ bool cholesky_global(const double* __restrict__ G, int m1, int n, double* R, double* rmm) {
+  const int tid = threadIdx.x;
+#pragma unroll 4
+  for (int x = tid; x < n * n; x += LBLOCK) {
+    const int i = x % n, j = x / n;
+    R[x] = i <= j ? G[i + (long long)j * m1] : 0.0;
+  }
+  __syncthreads();
+  double rmax = 0.0, rmin = 1e308, dprev = 1.0;
+  for (int k = 0; k < n; ++k) {
+    const double dkk = R[k + (long long)k * n];
+    if (!(dkk > 0.0) || !isfinite(dkk)) return false;   // uniform: every thread read the same value
+    const double rkk = sqrt(dkk);
+    if (k < n - 1) {
+      rmax = fmax(rmax, rkk);
+      rmin = fmin(rmin, rkk);
+    }
+    const double inv = 1.0 / dkk;
+    for (int j = k + 1 + wave_id(); j < n; j += LBLOCK / 64) {
+      const double f = R[k + (long long)j * n] * inv;
+      for (int i = k + 1 + (tid & 63); i <= j; i += 64) R[i + (long long)j * n] -= R[k + (long long)i * n] * f;
     }
     if (k >= 1) {
       const double rp = sqrt(dprev);
@@ -372,9 +432,17 @@ __global__ void __launch_bounds__(LBLOCK) k_lsq(SolveDev d, DenseDev g) {
       qr_registers(S, eta, s, mu + 1, vsh, Rl, z, tau_sh, rmm);
     } else {
       double* W = ws + g.oW;
-      qr_global(S, eta, s, mu + 1, W, z, sh, rmm);
-      Rm = W;
-      ldr = s;
+      if (cholesky_global(ws + g.oM, m1, mu + 1, W, rmm)) {
+        // the last column of R is [z; rho]
+        Rm = W;
+        ldr = mu + 1;
+        for (int r = tid; r < mu; r += LBLOCK) z[r] = W[r + (long long)mu * ldr];
+        __syncthreads();
+      } else {
+        qr_global(S, eta, s, mu + 1, W, z, sh, rmm);
+        Rm = W;
+        ldr = s;
+      }
     }
     for (int w = 0; w < 8; ++w) {
       rmax = fmax(rmax, rmm[2 * w]);
@@ -601,9 +669,10 @@ hipError_t dense_after_refine(const SolveDev& d, const DenseDev& g, double* cf, 
 }
 
 hipError_t dense_tail(const SolveDev& d, const DenseDev& g, double* cf, double* fq, hipStream_t st) {
-  if (d.s <= 64 * LRS && d.m + 1 <= 8 * LCS && g.ls_mode != 2) {
+  if (g.ls_mode != 2) {
+    // G = W^T W for the Cholesky factorisation (LDS or global memory)
     const unsigned t = (unsigned)((d.m + 1 + GT - 1) / GT);
-    hipLaunchKernelGGL(k_gram, dim3(d.nrhs, t, t), dim3(256), 0, st, d, g);
+    hipLaunchKernelGGL(k_gram, dim3(d.nrhs, t, t), dim3(64), 0, st, d, g);
   }
   hipLaunchKernelGGL(k_lsq, dim3(d.nrhs), dim3(LBLOCK), lsq_lds_bytes(d.s, d.m), st, d, g);
   const dim3 gv(d.nrhs, g.nvar);

@@ -77,6 +77,8 @@ constexpr int WH_EVERY = 5;
 constexpr double WH_THRESH = 1000.0;
 size_t lsqr_state_stride(int m);
 size_t lsqr_pass_lds(int m, int nrhs);
+hipError_t gather_cols(const ColPtrs& src, int logg, long long n, double* dst, hipStream_t st);
+hipError_t scatter_cols(const double* src, int logg, long long n, const OutPtrs& dst, hipStream_t st);
 // Per-device address of the static scratch of fab_solve_noalloc (noalloc.hip).
 int noalloc_setup(int device);
 }  // namespace fab
@@ -222,6 +224,7 @@ struct Plan {
   int sk_slices = 1;
   int sk_reg = 0;              // SRHT accumulators in registers (k_update)
   int tgroups = 1;             // XCD groups of the streaming blocks
+  int wtp = 0, wc = 0, wpen = 0;   // pencil walk of the streaming blocks (wtp = 0: linear)
   size_t bytes = 0;
   // offsets in the workspace
   size_t oV, oW, oH, oEta, oWn, oCoef, oS, oPart, oNpart, oSk, oCnt, oStatus, oRows, oDense, oCf, oInfoHost;
@@ -297,6 +300,28 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
   // block index means the same XCD in both passes of a step
   P.tgroups = (P.nblk >= 8 && P.nblk % 8 == 0) ? 8 : 1;
   if (P.tgroups == 8) P.nred = (P.nred + 7) & ~7;
+  // 3D stencil whose z-plane of one vector exceeds 256 KB: pencils of at most
+  // 256 KB per plane walked through z, narrow enough that the members of a
+  // group work on at least 4 consecutive planes of their pencil at a time, so
+  // a tile's z-neighbours are being read by sibling blocks of the same XCD
+  // (a whole plane per vector no longer fits its L2)
+  P.wtp = P.wc = P.wpen = 0;
+  {
+    const long long plane = (long long)A->nx * A->ny;   // rows per z-plane
+    const long long rows_tile = tile / nrhs;
+    const long long tile_bytes = tile * esize;
+    if (A->op == OP_STENCIL && !sign && A->nz > 1 && P.tgroups == 8 && plane % rows_tile == 0 &&
+        plane * nrhs * esize > (256LL << 10)) {
+      const long long tp = plane / rows_tile;
+      long long c = tp / 8;
+      while (c > 1 && (c * tile_bytes > (256LL << 10) || 4 * c > P.nblk / 8)) c /= 2;
+      if (c >= 1 && tp % (8 * c) == 0) {
+        P.wtp = (int)tp;
+        P.wc = (int)c;
+        P.wpen = (int)(tp / (8 * c));
+      }
+    }
+  }
   P.lds_update = (size_t)(snr + (p.sketch == FAB_SKETCH_SRHT ? tile + tile / 32 : 0)) * 8 + (size_t)p.s * 4;
   if (P.lds_update > 160 * 1024) return FAB_EINVAL;
   // sparse sign with 4-wave blocks: one LDS accumulator per wave when the four
@@ -421,6 +446,8 @@ struct fab_ctx_s {
   std::vector<hipStream_t> pool_side;   // paired side streams (incremental QR)
   std::vector<hipEvent_t> pool_ev;
   std::vector<int> pool_busy;
+  int block_max = 32;            // largest block of merged single-rhs requests (1: no merging)
+  bool hold = false;             // fab_hold: admit nothing while set
   hipStream_t side = nullptr;    // side stream of the blocking path
   hipEvent_t ev = nullptr;
   // sampled SRHT rows per (padded length, s, seed), device arrays in the arena
@@ -465,6 +492,22 @@ struct Request {
   std::vector<fab_info> info;
   int fell_back = 0;             // recomputed with an FP64 basis (FAB_PREC_AUTO)
   int refined = 0;               // least-squares refinement enqueued
+  // Blocked requests: single-rhs requests on the same resident matrix with
+  // the same function and parameters run as the columns of one block solve
+  // (nrhs = members.size()), a request of the library's own that gathers
+  // their b into its workspace and scatters the columns of its result.
+  std::vector<uint64_t> members;        // block: the user requests, column q = members[q]
+  std::vector<const double*> mb;        // block: their b
+  std::vector<double*> mout;            // block: their out
+  uint64_t block = 0;                   // user request: the block that runs it (0: runs on its own)
+  size_t oBlkB = 0, oBlkO = 0;          // block: interleaved b and result in the workspace
+  // Whitened basis: its trigger is read on the host every few steps, so the
+  // launch sequence is issued by a worker thread of its own (the scheduler
+  // keeps serving the other requests meanwhile).
+  std::thread worker;
+  std::atomic<bool> worker_done{false};
+  int worker_rc = FAB_OK;
+  int* wflag_host = nullptr;            // pinned: the trigger flag read by the worker
 };
 
 // Sampled SRHT rows for (npad, s, seed): computed once on `st` (which the
@@ -558,6 +601,9 @@ void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev
   d.sk_reg = P.sk_reg;
   d.tgroups = P.tgroups;
   d.tchunk = ((long long)P.ntiles + P.tgroups - 1) / P.tgroups;
+  d.wtp = P.wtp;
+  d.wc = P.wc;
+  d.wpen = P.wpen;
   d.srht_rows = rows;
   if (d.sketch == SK_SRHT) {
     d.key_a = sm64_out(p.seed, 1);
@@ -752,6 +798,7 @@ int collect_info(const Plan& P, const double* hinfo, std::vector<fab_info>& out)
     if (P.gram_used) fi.err_est = fi.round_est;
     fi.fell_back = 0;
     fi.whitened_at = P.whitened_at;
+    fi.block_rhs = 1;
     if (in[3] != 0.0) rc = FAB_ENUMERIC;
     if (!std::isfinite(fi.beta)) rc = FAB_ENUMERIC;
   }
@@ -847,21 +894,58 @@ bool needs_fp64_rerun(const Plan& P, int rc, const std::vector<fab_info>& fi) {
 }
 
 // ---------------------------------------------------------------- scheduler
+// The caller's function of a plan (the sign function plans the inverse
+// square root; a polynomial's coefficients are the plan's own copy).
+fab_func plan_func(const Plan& P) {
+  fab_func f = P.sign ? P.forig : P.f;
+  if (f.kind == FAB_F_POLY) f.coef = P.coef.data();
+  return f;
+}
+
+// Workspace of a block: the plan's, then the interleaved b and result.
+void add_block_buffers(Request& r) {
+  const size_t nb = align256((size_t)r.plan.A->n * r.plan.nrhs * 8);
+  r.oBlkB = align256(r.plan.bytes);
+  r.oBlkO = r.oBlkB + nb;
+  r.plan.bytes = r.oBlkO + nb;
+}
+
+// Copy the block's result columns to the member requests' out.
+hipError_t scatter_block(const Request& r, hipStream_t st) {
+  OutPtrs o{};
+  for (size_t q = 0; q < r.mout.size(); ++q) o.p[q] = r.mout[q];
+  return scatter_cols((const double*)(r.ws + r.oBlkO), ilog2(r.plan.nrhs), r.plan.A->n, o, st);
+}
+
 void retire_locked(fab_ctx ctx, Request& r) {
+  if (r.worker.joinable()) r.worker.join();
+  if (r.worker_rc != FAB_OK) {
+    // the worker could not issue the solve
+    hipStreamSynchronize(ctx->pool[r.stream_idx]);
+    ctx->arena.release(r.ws);
+    r.ws = nullptr;
+    ctx->pool_busy[r.stream_idx] = 0;
+    r.status = r.worker_rc;
+    r.t_done = now_us();
+    r.plan.A->refs.fetch_sub(1);
+    r.state = 2;
+    return;
+  }
   r.status = collect_info(r.plan, r.host_info, r.info);
+  const bool blk = !r.members.empty();
   if (!r.fell_back && needs_fp64_rerun(r.plan, r.status, r.info)) {
     // FAB_PREC_AUTO: queue the request again, first in line, with an FP64 basis
     Plan P2;
-    fab_func f2 = r.plan.sign ? r.plan.forig : r.plan.f;
-    if (f2.kind == FAB_F_POLY) f2.coef = r.plan.coef.data();   // the caller's array may be gone
+    const fab_func f2 = plan_func(r.plan);
     if (make_plan(r.plan.A, r.plan.nrhs, f2, &r.plan.p, 8, P2) == FAB_OK &&
-        ctx->arena.could_ever_fit(P2.bytes)) {
+        ctx->arena.could_ever_fit(P2.bytes + (blk ? 2 * align256((size_t)r.plan.A->n * r.plan.nrhs * 8) + 256 : 0))) {
       P2.b = r.plan.b;
       P2.out = r.plan.out;
       ctx->arena.release(r.ws);
       r.ws = nullptr;
       ctx->pool_busy[r.stream_idx] = 0;
       r.plan = P2;
+      if (blk) add_block_buffers(r);
       r.fell_back = 1;
       r.state = 0;
       ctx->queue.push_front(r.id);
@@ -872,7 +956,8 @@ void retire_locked(fab_ctx ctx, Request& r) {
     // least-squares refinement on the request's stream; retired when it ends
     r.refined = 1;
     const hipStream_t st = ctx->pool[r.stream_idx];
-    if (enqueue_refine(r.plan, r.ws, st, nullptr, r.host_info) == FAB_OK && hipEventRecord(r.done_ev, st) == hipSuccess)
+    if (enqueue_refine(r.plan, r.ws, st, nullptr, r.host_info) == FAB_OK &&
+        (!blk || scatter_block(r, st) == hipSuccess) && hipEventRecord(r.done_ev, st) == hipSuccess)
       return;
     hipStreamSynchronize(st);
     r.status = FAB_EDEVICE;
@@ -880,23 +965,113 @@ void retire_locked(fab_ctx ctx, Request& r) {
   if (r.fell_back)
     for (auto& fi : r.info) fi.fell_back = 1;
   r.t_done = now_us();
-  for (auto& fi : r.info) fi.latency_us = r.t_done - r.t_submit;
   ctx->arena.release(r.ws);
   r.ws = nullptr;
   ctx->pool_busy[r.stream_idx] = 0;
-  r.plan.A->refs.fetch_sub(1);
-  r.state = 2;
+  if (!blk) {
+    for (auto& fi : r.info) fi.latency_us = r.t_done - r.t_submit;
+    r.plan.A->refs.fetch_sub(1);
+    r.state = 2;
+    return;
+  }
+  // a block: each member request gets its column's record and completes
+  for (size_t q = 0; q < r.members.size(); ++q) {
+    auto it = ctx->reqs.find(r.members[q]);
+    if (it == ctx->reqs.end()) continue;
+    Request& u = *it->second;
+    u.info.assign(1, q < r.info.size() ? r.info[q] : fab_info{});
+    u.info[0].block_rhs = (int)r.members.size();
+    u.status = r.status;
+    u.t_done = r.t_done;
+    u.info[0].latency_us = u.t_done - u.t_submit;
+    u.fell_back = r.fell_back;
+    u.block = 0;
+    u.plan.A->refs.fetch_sub(1);
+    u.state = 2;
+  }
+  r.state = 3;   // the block itself is dropped by the scheduler
+}
+
+// Single-rhs requests that can run as columns of one block solve: the same
+// resident matrix, function and parameters, the sketch seed included, so that
+// every column uses the sketch it would use alone.
+bool blockable(const Request& r) {
+  return r.members.empty() && r.block == 0 && r.plan.nrhs == 1 && !r.fell_back && !r.plan.whiten;
+}
+bool same_solve(const Plan& a, const Plan& b) {
+  const fab_func fa = plan_func(a), fb = plan_func(b);
+  if (a.A != b.A || a.esize != b.esize || a.sign != b.sign) return false;
+  if (fa.kind != fb.kind || fa.alpha != fb.alpha || fa.sigma != fb.sigma || fa.p != fb.p || a.coef != b.coef)
+    return false;
+  const fab_params &p = a.p, &q = b.p;
+  return p.m == q.m && p.k == q.k && p.s == q.s && p.sketch == q.sketch && p.zeta == q.zeta && p.seed == q.seed &&
+         p.prec == q.prec && p.ls_mode == q.ls_mode && p.tol == q.tol && p.basis == q.basis &&
+         p.ls_maxit == q.ls_maxit;
+}
+
+// Merge the queued single-rhs requests compatible with `head` (in queue
+// order, at most block_max, a power of two >= 2 of them) into a block placed
+// at the front of the queue.  Returns false when there is nothing to merge.
+bool form_block_locked(fab_ctx ctx, const Request& head) {
+  std::vector<uint64_t> ids;
+  for (uint64_t id : ctx->queue) {
+    auto jt = ctx->reqs.find(id);
+    if (jt == ctx->reqs.end()) continue;
+    if (blockable(*jt->second) && same_solve(jt->second->plan, head.plan)) {
+      ids.push_back(id);
+      if ((int)ids.size() >= ctx->block_max) break;
+    }
+  }
+  int g = 1;
+  while (2 * g <= (int)ids.size() && 2 * g <= 32) g *= 2;
+  // the largest such block that can fit the arena at all
+  auto b = std::make_shared<Request>();
+  for (; g >= 2; g /= 2) {
+    if (make_plan(head.plan.A, g, plan_func(head.plan), &head.plan.p, head.plan.esize, b->plan) != FAB_OK) return false;
+    add_block_buffers(*b);
+    if (ctx->arena.could_ever_fit(b->plan.bytes)) break;
+  }
+  if (g < 2) return false;
+  ids.resize(g);
+  if (hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming) != hipSuccess) return false;
+  if (hipHostMalloc((void**)&b->host_info, host_info_doubles(g) * 8, hipHostMallocDefault) != hipSuccess) {
+    hipEventDestroy(b->done_ev);
+    b->done_ev = nullptr;
+    return false;
+  }
+  b->id = ctx->next_id++;
+  b->t_submit = now_us();
+  for (uint64_t id : ids) {
+    Request& u = *ctx->reqs[id];
+    b->members.push_back(id);
+    b->mb.push_back(u.plan.b);
+    b->mout.push_back(u.plan.out);
+    u.block = b->id;
+    u.state = 1;
+    b->t_submit = std::min(b->t_submit, u.t_submit);
+  }
+  std::deque<uint64_t> rest;
+  for (uint64_t id : ctx->queue)
+    if (std::find(ids.begin(), ids.end(), id) == ids.end()) rest.push_back(id);
+  rest.push_front(b->id);
+  ctx->queue.swap(rest);
+  ctx->reqs[b->id] = b;
+  return true;
 }
 
 void admit_locked(fab_ctx ctx) {
-  while (!ctx->queue.empty()) {
+  while (!ctx->hold && !ctx->queue.empty()) {
     auto it = ctx->reqs.find(ctx->queue.front());
     if (it == ctx->reqs.end()) { ctx->queue.pop_front(); continue; }
-    Request& r = *it->second;
     int si = -1;
     for (size_t i = 0; i < ctx->pool.size(); ++i)
       if (!ctx->pool_busy[i]) { si = (int)i; break; }
     if (si < 0) return;
+    // continuous batching: queued single-rhs requests on the same matrix
+    // with the same function and parameters become one block solve
+    if (ctx->block_max >= 2 && blockable(*it->second) && form_block_locked(ctx, *it->second)) continue;
+    Request& r = *it->second;
+    const bool blk = !r.members.empty();
     char* ws = (char*)ctx->arena.alloc(r.plan.bytes);
     if (!ws) return;   // FIFO: wait until running requests free memory
     ctx->queue.pop_front();
@@ -904,25 +1079,79 @@ void admit_locked(fab_ctx ctx) {
     r.stream_idx = si;
     ctx->pool_busy[si] = 1;
     hipSetDevice(ctx->device);
+    const hipStream_t st = ctx->pool[si];
     int rc = FAB_OK;
+    if (blk) {
+      r.plan.b = (const double*)(ws + r.oBlkB);
+      r.plan.out = (double*)(ws + r.oBlkO);
+      ColPtrs c{};
+      for (size_t q = 0; q < r.mb.size(); ++q) c.p[q] = r.mb[q];
+      if (gather_cols(c, ilog2(r.plan.nrhs), r.plan.A->n, (double*)(ws + r.oBlkB), st) != hipSuccess) rc = FAB_EDEVICE;
+    }
     const int* rows = nullptr;
-    if (r.plan.p.sketch == FAB_SKETCH_SRHT)
-      rows = srht_rows_cached(ctx, 1LL << ilog2(r.plan.A->n), r.plan.p.s, r.plan.p.seed, ctx->pool[si], &rc);
-    if (rc == FAB_OK)
-      rc = enqueue_solve(r.plan, ws, ctx->pool[si], ctx->pool_side[si], ctx->pool_ev[si], rows, r.host_info);
-    if (rc == FAB_OK && hipEventRecord(r.done_ev, ctx->pool[si]) != hipSuccess) rc = FAB_EDEVICE;
+    if (rc == FAB_OK && r.plan.p.sketch == FAB_SKETCH_SRHT)
+      rows = srht_rows_cached(ctx, 1LL << ilog2(r.plan.A->n), r.plan.p.s, r.plan.p.seed, st, &rc);
+    if (rc == FAB_OK && r.plan.whiten) {
+      // the worker issues the sequence (reading the trigger on the host) and
+      // records done_ev; the scheduler retires the request after both
+      Request* rp = &r;
+      const int dev = ctx->device;
+      const hipStream_t side = ctx->pool_side[si];
+      const hipEvent_t pev = ctx->pool_ev[si];
+      r.worker_done.store(false);
+      r.worker_rc = FAB_OK;
+      r.worker = std::thread([rp, dev, st, side, pev, rows, ws]() {
+        hipSetDevice(dev);
+        int wrc = enqueue_solve(rp->plan, ws, st, side, pev, rows, rp->host_info, nullptr, rp->wflag_host);
+        if (wrc == FAB_OK && hipEventRecord(rp->done_ev, st) != hipSuccess) wrc = FAB_EDEVICE;
+        rp->worker_rc = wrc;
+        rp->worker_done.store(true);
+      });
+      r.state = 1;
+      continue;
+    }
+    if (rc == FAB_OK) rc = enqueue_solve(r.plan, ws, st, ctx->pool_side[si], ctx->pool_ev[si], rows, r.host_info);
+    if (rc == FAB_OK && blk && scatter_block(r, st) != hipSuccess) rc = FAB_EDEVICE;
+    if (rc == FAB_OK && hipEventRecord(r.done_ev, st) != hipSuccess) rc = FAB_EDEVICE;
     if (rc != FAB_OK) {
-      hipStreamSynchronize(ctx->pool[si]);
+      hipStreamSynchronize(st);
       ctx->arena.release(ws);
       r.ws = nullptr;
       ctx->pool_busy[si] = 0;
-      r.plan.A->refs.fetch_sub(1);
       r.status = rc;
-      r.state = 2;
       r.t_done = now_us();
+      if (!blk) {
+        r.plan.A->refs.fetch_sub(1);
+        r.state = 2;
+        continue;
+      }
+      for (uint64_t id : r.members) {
+        auto jt = ctx->reqs.find(id);
+        if (jt == ctx->reqs.end()) continue;
+        Request& u = *jt->second;
+        u.status = rc;
+        u.t_done = r.t_done;
+        u.block = 0;
+        u.plan.A->refs.fetch_sub(1);
+        u.state = 2;
+      }
+      r.state = 3;
       continue;
     }
     r.state = 1;
+  }
+}
+
+// Drop finished blocks (their members carry the results).
+void drop_blocks_locked(fab_ctx ctx) {
+  for (auto it = ctx->reqs.begin(); it != ctx->reqs.end();) {
+    if (it->second->state == 3) {
+      if (it->second->done_ev) hipEventDestroy(it->second->done_ev);
+      if (it->second->host_info) hipHostFree(it->second->host_info);
+      it = ctx->reqs.erase(it);
+    } else {
+      ++it;
+    }
   }
 }
 
@@ -933,12 +1162,15 @@ void scheduler_main(fab_ctx ctx) {
     bool progressed = false;
     for (auto& kv : ctx->reqs) {
       Request& r = *kv.second;
-      if (r.state == 1 && hipEventQuery(r.done_ev) == hipSuccess) {
+      // members of a block complete with their block
+      if (r.state == 1 && r.block == 0 && (!r.worker.joinable() || r.worker_done.load()) &&
+          hipEventQuery(r.done_ev) == hipSuccess) {
         retire_locked(ctx, r);
         progressed = true;
       }
     }
     admit_locked(ctx);
+    drop_blocks_locked(ctx);
     if (progressed) ctx->cv.notify_all();
     bool running = false;
     for (auto& kv : ctx->reqs)
@@ -1369,6 +1601,7 @@ int fab_solve_diag(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_fun
   return solve_impl(ctx, A, b, nrhs, f, p, out, info, diag);
 }
 
+
 int fab_profile_enable(fab_ctx ctx, int class_mask) {
   if (!ctx || class_mask < 0 || class_mask >= (1 << FAB_K_NCLASS)) return FAB_EINVAL;
   std::lock_guard<std::mutex> slk(ctx->solve_mu);
@@ -1395,7 +1628,6 @@ int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
   int first_prec = p->prec == FAB_PREC_FP64 ? FAB_PREC_FP64 : FAB_PREC_FP32;
   int rc = make_plan(A, nrhs, f, p, esize_for(first_prec), r->plan);
   if (rc != FAB_OK) return rc;
-  if (r->plan.whiten) return FAB_EINVAL;   // its trigger is read on the host mid-solve: blocking calls only
   r->plan.b = b;
   r->plan.out = out;
   hipSetDevice(ctx->device);
@@ -1404,11 +1636,17 @@ int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
     hipEventDestroy(r->done_ev);
     return FAB_EDEVICE;
   }
+  if (r->plan.whiten && hipHostMalloc((void**)&r->wflag_host, 256, hipHostMallocDefault) != hipSuccess) {
+    hipEventDestroy(r->done_ev);
+    hipHostFree(r->host_info);
+    return FAB_EDEVICE;
+  }
   r->t_submit = now_us();
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (!ctx->arena.could_ever_fit(r->plan.bytes)) {
     hipEventDestroy(r->done_ev);
     hipHostFree(r->host_info);
+    if (r->wflag_host) hipHostFree(r->wflag_host);
     return FAB_ENOMEM;
   }
   r->id = ctx->next_id++;
@@ -1420,6 +1658,21 @@ int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
   return FAB_OK;
 }
 
+int fab_hold(fab_ctx ctx, int hold) {
+  if (!ctx) return FAB_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->hold = hold != 0;
+  ctx->cv.notify_all();
+  return FAB_OK;
+}
+
+int fab_set_block_limit(fab_ctx ctx, int max_rhs) {
+  if (!ctx || max_rhs < 1 || max_rhs > 32) return FAB_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->block_max = max_rhs;
+  return FAB_OK;
+}
+
 static int finish_request(fab_ctx ctx, std::unordered_map<uint64_t, std::shared_ptr<Request>>::iterator it,
                           fab_info* info) {
   Request& r = *it->second;
@@ -1428,6 +1681,7 @@ static int finish_request(fab_ctx ctx, std::unordered_map<uint64_t, std::shared_
     for (size_t q = 0; q < r.info.size(); ++q) info[q] = r.info[q];
   hipEventDestroy(r.done_ev);
   hipHostFree(r.host_info);
+  if (r.wflag_host) hipHostFree(r.wflag_host);
   ctx->reqs.erase(it);
   return rc;
 }
@@ -1461,13 +1715,16 @@ int fab_finalize(fab_ctx ctx) {
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->stop = true;
+    ctx->hold = false;
     ctx->cv.notify_all();
   }
   if (ctx->sched.joinable()) ctx->sched.join();
   hipSetDevice(ctx->device);
   for (auto& kv : ctx->reqs) {
+    if (kv.second->worker.joinable()) kv.second->worker.join();
     if (kv.second->done_ev) hipEventDestroy(kv.second->done_ev);
     if (kv.second->host_info) hipHostFree(kv.second->host_info);
+    if (kv.second->wflag_host) hipHostFree(kv.second->wflag_host);
   }
   ctx->reqs.clear();
   for (auto* M : ctx->matrices) delete M;

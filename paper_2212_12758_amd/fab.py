@@ -38,7 +38,7 @@ class fab_info(C.Structure):
                 ("conv_est", C.c_double), ("kappa_R", C.c_double), ("h_last", C.c_double),
                 ("beta", C.c_double), ("m_used", C.c_int), ("breakdown", C.c_int), ("fell_back", C.c_int),
                 ("ls_iters", C.c_int), ("prec_used", C.c_int), ("whitened_at", C.c_int),
-                ("ls_limit", C.c_int), ("latency_us", C.c_double)]
+                ("ls_limit", C.c_int), ("block_rhs", C.c_int), ("latency_us", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -74,6 +74,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fab_poll.argtypes = [vp, u64, C.POINTER(i), C.POINTER(fab_info)]
     lib.fab_wait.argtypes = [vp, u64, C.POINTER(fab_info)]
     lib.fab_finalize.argtypes = [vp]
+    lib.fab_set_block_limit.argtypes = [vp, i]
+    lib.fab_hold.argtypes = [vp, i]
     lib.fab_profile_enable.argtypes = [vp, i]
     lib.fab_profile_read.argtypes = [vp, i, C.POINTER(C.c_longlong), C.POINTER(C.c_double), i]
     lib.fab_strerror.argtypes = [i]
@@ -229,6 +231,14 @@ class Context:
         _check(self.lib.fab_submit(self.handle, A.handle, C.c_void_p(b.data_ptr()), self._shape(b), ff,
                                    C.byref(params), C.c_void_p(out.data_ptr()), C.byref(req)), "fab_submit")
         return Request(self, req.value, self._shape(b), (b, out, keep))
+
+    def set_block_limit(self, max_rhs: int):
+        """Largest block of merged single-rhs served requests (1 disables merging)."""
+        _check(self.lib.fab_set_block_limit(self.handle, int(max_rhs)), "fab_set_block_limit")
+
+    def hold(self, on: bool = True):
+        """Hold (or release) admission of queued served requests."""
+        _check(self.lib.fab_hold(self.handle, 1 if on else 0), "fab_hold")
 
     # ---------------------------------------------------------------- measurement
     K_DOTS, K_UPDATE, K_COMBINE, K_DENSE, K_OTHER = range(5)

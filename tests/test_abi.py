@@ -41,7 +41,7 @@ def test_binding_marshalling_matches_header_struct_sizes():
     # fab_params: 5 ints, u64 seed, 2 ints, double tol, 2 ints -> 56 bytes with natural alignment
     assert ctypes.sizeof(fab.fab_params) == 56
     assert fab.fab_params.basis.offset == 48 and fab.fab_params.ls_maxit.offset == 52
-    # fab_info: 7 doubles, 7 ints (+4 bytes padding), 1 double -> 96 bytes
+    # fab_info: 7 doubles, 8 ints, 1 double -> 96 bytes
     assert ctypes.sizeof(fab.fab_info) == 96
     assert ctypes.sizeof(fab.fab_func) == 48
 

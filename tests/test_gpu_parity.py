@@ -214,6 +214,10 @@ def test_serving_mix_equals_alone(ctx):
     from paper_2212_12758_amd import make_params
 
     params = [make_params(40, 3, 90, "srht", 8, 1000 + i, "fp32", "sketch") for i in range(len(cases))]
+    # repeats of one case would be merged into block solves (equal to the
+    # result alone within the tolerance, tests/test_gpu_serving_blocks.py);
+    # without merging the served results are the blocking ones bit for bit
+    ctx.set_block_limit(1)
     alone = []
     for (st, f, b), A, p in zip(cases, mats, params):
         o, _ = ctx.solve(A, _dev(b), f, p)
@@ -230,6 +234,7 @@ def test_serving_mix_equals_alone(ctx):
     for j, o in enumerate(outs):
         ref = alone[j % len(cases)]
         assert np.array_equal(o.cpu().numpy(), ref), j        # fixed-order reductions: bitwise
+    ctx.set_block_limit(32)
     for A in mats:
         A.destroy()
 

@@ -54,7 +54,9 @@ def test_served_algorithm5_and_sfom(ctx):
         out = out.cpu().numpy()
         assert krylov.relerr(out, ref) < 1e-10, ls
         outs[ls] = out
-    # served, both modes in flight at once
+    # served, both modes in flight at once (merging off: two requests of one
+    # mode would otherwise run as one block solve)
+    ctx.set_block_limit(1)
     reqs = []
     for ls in ("none", "sketch", "none", "sketch"):
         o = _dev(np.zeros(st.n))
@@ -62,13 +64,16 @@ def test_served_algorithm5_and_sfom(ctx):
     for ls, o, r in reqs:
         r.wait()
         assert np.array_equal(o.cpu().numpy(), outs[ls]), ls
+    ctx.set_block_limit(32)
     A.destroy()
 
 
 def test_wait_while_another_thread_submits(ctx):
     """fab_wait blocks with the context lock released while another thread
     keeps submitting (the request table grows and rehashes meanwhile): every
-    request completes with the blocking call's result, bit for bit."""
+    request completes with the blocking call's result, bit for bit when it ran
+    on its own, within the FP32-basis tolerance when the scheduler merged it
+    with other queued copies into a block solve."""
     import queue
     import threading
 
@@ -90,8 +95,9 @@ def test_wait_while_another_thread_submits(ctx):
         try:
             for _ in range(200):
                 o = torch.empty_like(b)
-                outs.append(o)
-                q.put(ctx.submit(A, b, f, p, o))
+                r = ctx.submit(A, b, f, p, o)
+                outs.append((o, r))
+                q.put(r)
         except Exception as e:   # reported by the main thread
             errs.append(e)
         q.put(None)
@@ -107,6 +113,10 @@ def test_wait_while_another_thread_submits(ctx):
         done += 1
     t.join()
     assert not errs and done == 200
-    for o in outs:
-        assert np.array_equal(o.cpu().numpy(), ref)
+    for o, r in outs:
+        got = o.cpu().numpy()
+        if r.info[0]["block_rhs"] == 1:
+            assert np.array_equal(got, ref)
+        else:
+            assert krylov.relerr(got, ref) < 1e-6
     A.destroy()

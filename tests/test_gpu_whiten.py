@@ -95,8 +95,14 @@ def test_whitening_without_trigger_is_the_truncated_basis(ctx):
     A.destroy()
 
 
-def test_whitening_two_rhs_and_serving_refused(ctx):
-    from paper_2212_12758_amd import EINVAL, FabError
+def test_whitening_two_rhs_and_served(ctx):
+    """Two rhs whiten together; a served whitened request (its trigger read by
+    a worker thread of the serving loop) returns the blocking result bit for
+    bit (the same kernels in the same order), next to a served request of
+    another kind."""
+    import torch
+
+    from paper_2212_12758_amd import make_params
 
     w = _rgg_case()
     Aor = operators.as_matrix(w.op)
@@ -108,7 +114,17 @@ def test_whitening_two_rhs_and_serving_refused(ctx):
     assert info[0]["whitened_at"] == info[1]["whitened_at"] > 0
     for r in range(2):
         assert krylov.relerr(out[:, r], krylov.fm(Aor, np.ascontiguousarray(B[:, r]), w.f, w.m)) < 1e-10, r
-    with pytest.raises(FabError) as e:
-        ctx.submit(A, _dev(B), w.f, _params(w, "fp64"), _dev(np.zeros_like(B)))
-    assert e.value.code == EINVAL
+    print("case whiten served", flush=True)
+    outs = _dev(np.zeros_like(B))
+    other_b = _dev(W.rhs(w.n, 9))
+    other_out = torch.empty_like(other_b)
+    p_other = make_params(40, 2, 80, "sparse_sign", 8, 5, "fp64", "sketch")
+    r1 = ctx.submit(A, _dev(B), w.f, _params(w, "fp64"), outs)
+    r2 = ctx.submit(A, other_b, w.f, p_other, other_out)
+    info_s = r1.wait()
+    r2.wait()
+    assert np.array_equal(outs.cpu().numpy(), out)
+    assert [i["whitened_at"] for i in info_s] == [i["whitened_at"] for i in info]
+    alone, _ = ctx.solve(A, other_b, w.f, p_other)
+    assert np.array_equal(other_out.cpu().numpy(), alone.cpu().numpy())
     A.destroy()

@@ -243,3 +243,91 @@ def config(name: str, scale: int | None = None) -> Workload:
         return Workload(name, op, -1, 1, FuncSpec("exp", alpha=-t), m=100, k=2, s=200, sketch="srht",
                         sketch_seed=11)
     raise KeyError(name)
+
+
+def laplacian_norm2(st: Stencil) -> float:
+    """||A||_2 of a Dirichlet Laplacian stencil: the largest eigenvalue,
+    sum over the grid directions of 2 + 2 cos(pi / (N + 1))."""
+    sides = (st.nx, st.ny) if st.dim == 2 else (st.nx, st.ny, st.nz)
+    return float(sum(2.0 + 2.0 * math.cos(math.pi / (N + 1)) for N in sides))
+
+
+@dataclasses.dataclass(frozen=True)
+class ServedRequest:
+    rid: int                 # request id (b seed 10^6 + rid)
+    event: int               # arrival event (a burst of shared-matrix requests shares one)
+    op: Stencil
+    pool: int                # index of the shared resident matrix, -1 for a fresh matrix
+    f: FuncSpec
+    m: int
+    k: int
+    s: int
+    sketch_seed: int
+
+
+def serving_mix(nreq: int = 4096, seed: int = 4, shared_frac: float = 0.3, pool_size: int = 4):
+    """The serving mix: nreq single-rhs requests on 2D 5-point / 3D 7-point
+    Dirichlet Laplacians with n log-uniform in [2^14, 2^21] (rounded to a
+    square or cube grid), f uniform over {exp(-tA) with ||tA||_2 log-uniform
+    in [1, 50], A^{1/2}, (A + 1e-3 I)^{-1/2}}, m uniform in [30, 200], k
+    uniform in {2, 3, 4}, a sketch of s = 2m rows (its kind is the server's
+    choice).
+
+    A fraction shared_frac of the requests use one of pool_size resident
+    matrices, each with its own fixed f, m, k, s and sketch seed, and arrive
+    in bursts of 8..32 requests (one arrival event per burst) that a server
+    can run as one block solve; every other request has a fresh matrix and
+    its own sketch seed and arrives alone.  Returns (requests in arrival
+    order, unit-rate exponential gaps between the arrival events)."""
+    rng = np.random.default_rng(seed)
+
+    def draw_op():
+        dim = int(rng.integers(2, 4))
+        n = math.exp(rng.uniform(math.log(2 ** 14), math.log(2 ** 21)))
+        side = max(4, int(round(n ** (1.0 / dim))))
+        return laplacian2d(side) if dim == 2 else laplacian3d(side)
+
+    def draw_f(op):
+        kind = int(rng.integers(0, 3))
+        if kind == 0:
+            tnorm = math.exp(rng.uniform(0.0, math.log(50.0)))
+            return FuncSpec("exp", alpha=-tnorm / laplacian_norm2(op))
+        if kind == 1:
+            return FuncSpec("pow", sigma=0.0, p=0.5)
+        return FuncSpec("pow", sigma=1e-3, p=-0.5)
+
+    def draw_mk():
+        m = int(rng.integers(30, 201))
+        return m, int(rng.integers(2, 5)), 2 * m
+
+    pool = []
+    for j in range(pool_size):
+        op = draw_op()
+        m, k, s = draw_mk()
+        pool.append((op, draw_f(op), m, k, s, 7_000_000 + j))
+    n_shared = int(round(shared_frac * nreq))
+    events = []   # list of ('fresh', None) or ('burst', (pool index, count))
+    left = n_shared
+    while left > 0:
+        c = min(left, int(rng.integers(8, 33)))
+        events.append(("burst", (int(rng.integers(0, pool_size)), c)))
+        left -= c
+    events += [("fresh", None)] * (nreq - n_shared)
+    order = rng.permutation(len(events))
+    gaps = rng.exponential(1.0, size=len(events))
+    reqs = []
+    rid = 0
+    for e, idx in enumerate(order):
+        kind, val = events[idx]
+        if kind == "fresh":
+            op = draw_op()
+            m, k, s = draw_mk()
+            reqs.append(ServedRequest(rid, e, op, -1, draw_f(op), m, k, s, 5_000_000 + rid))
+            rid += 1
+        else:
+            pj, c = val
+            op, f, m, k, s, sseed = pool[pj]
+            for _ in range(c):
+                reqs.append(ServedRequest(rid, e, op, pj, f, m, k, s, sseed))
+                rid += 1
+    return reqs, gaps
