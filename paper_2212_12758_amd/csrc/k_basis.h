@@ -806,7 +806,7 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
   double* acc = lds + (SK == SK_SRHT ? padx(TILE) : 0);              // sketch accumulator [s][nr] (LDS path)
   const int snr = d.s * nr;
   const bool reg_acc = SK == SK_SRHT && srht_reg_slots<QC>() > 0 && d.sk_reg;
-  // SRHT sums kept rhs-major (several rhs per row, LDS path)
+  // SRHT sums kept by rhs pairs (several rhs per row, LDS path)
   const bool qmajor = SK == SK_SRHT && QC > 1 && !reg_acc && nr >= EPT;
   // sparse sign: one accumulator per wave when the host sized LDS for it, so
   // that the LDS atomics of different waves never meet (fixed order)
@@ -974,25 +974,32 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
           // several rhs: thread tid owns the sampled rows p = tid + a BLOCK
           // with all their rhs; the rhs of a row are consecutive in the tile,
           // so one row index, one sign and one address serve nr sums.  The
-          // accumulators are rhs-major here (sum (p, q) at q s + p), so the
-          // lanes of a wave touch consecutive LDS words.
+          // accumulators are kept by rhs pairs (sum (p, q) at
+          // ((q/2) s + p) 2 + q mod 2), so each access moves two sums and the
+          // lanes of a wave touch consecutive 16-byte words.
           for (int p = tid; p < d.s; p += BLOCK) {
             const int rr = rows_l[p];
-            const double sg = (__popc((unsigned)(rr >> d.log_rows) & (unsigned)t) & 1) ? -1.0 : 1.0;
+            // the sign as a mask on the sign bit of the transformed values
+            const int smask = (int)((unsigned)__popc((unsigned)(rr >> d.log_rows) & (unsigned)t) << 31);
             const int b = (rr & lomask) << d.lognrhs;
             for (int q0 = 0; q0 < nr; q0 += EPT) {
               // 8 consecutive elements from a multiple of 8 share one
               // padding group of the tile
               const double* xp = X + padx(b + q0);
-              double* ap = acc + q0 * d.s + p;
-              double xv[EPT], av[EPT];
+              double2* ap = reinterpret_cast<double2*>(acc) + (q0 / 2) * d.s + p;
+              double xv[EPT];
+              double2 av[EPT / 2];
 #pragma unroll
-              for (int q = 0; q < EPT; ++q) {
-                xv[q] = xp[q];
-                av[q] = ap[q * d.s];
+              for (int q = 0; q < EPT; ++q) xv[q] = xp[q];
+#pragma unroll
+              for (int h = 0; h < EPT / 2; ++h) av[h] = ap[h * d.s];
+#pragma unroll
+              for (int h = 0; h < EPT / 2; ++h) {
+                double2 o;
+                o.x = av[h].x + __hiloint2double(__double2hiint(xv[2 * h]) ^ smask, __double2loint(xv[2 * h]));
+                o.y = av[h].y + __hiloint2double(__double2hiint(xv[2 * h + 1]) ^ smask, __double2loint(xv[2 * h + 1]));
+                ap[h * d.s] = o;
               }
-#pragma unroll
-              for (int q = 0; q < EPT; ++q) ap[q * d.s] = av[q] + sg * xv[q];
             }
           }
         } else
@@ -1031,7 +1038,8 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
     }
   } else {
     for (int pq = tid; pq < snr; pq += BLOCK) {
-      double a = acc[qmajor ? (pq & (nr - 1)) * d.s + (pq >> d.lognrhs) : pq];
+      const int q = pq & (nr - 1);
+      double a = acc[qmajor ? (((q >> 1) * d.s + (pq >> d.lognrhs)) << 1) + (q & 1) : pq];
       for (int sl = 1; sl < nsl; ++sl) a += acc[sl * snr + pq];
       skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = a;
     }
