@@ -370,11 +370,13 @@ def serving_main(args):
     # 3. plain FP64 path, one request at a time
     p64 = [params(r, "fp64", 1e-6) for r in reqs]
     serv = np.zeros(nreq)
+    infos64 = []
     for i in range(nreq):
         ts = time.perf_counter()
-        ctx.solve(mats[i], bs[i], reqs[i].f, p64[i], outs[i])
+        _, inf64 = ctx.solve(mats[i], bs[i], reqs[i].f, p64[i], outs[i])
         torch.cuda.synchronize()
         serv[i] = time.perf_counter() - ts
+        infos64.append(inf64[0])
     rate64 = nreq / serv.sum()
     done, lat64 = 0.0, np.zeros(nreq)
     for i in range(nreq):
@@ -433,6 +435,16 @@ def serving_main(args):
                          "sample": f"f_m by full Arnoldi (FP64, numpy/scipy) for the {len(sample)} smallest requests "
                                    f"of the mix (n <= {reqs[sample[-1]].op.n}), {tcpu:.1f} s"},
     }
+    if args.dump_requests:
+        # per-request record of both paths (for studying where the time goes)
+        recs = [{"n": r.op.n, "m": r.m, "k": r.k, "f": r.f.kind + (f" {r.f.p}" if r.f.kind == "pow" else ""),
+                 "pool": r.pool,
+                 "block_rhs": int(infos[i]["block_rhs"]), "latency_ms": float(lat[i]),
+                 "fell_back": int(infos[i]["fell_back"]), "ls_iters": int(infos[i]["ls_iters"]),
+                 "err_est": float(infos[i]["err_est"]), "fp64_service_ms": 1e3 * float(serv[i]),
+                 "fp64_ls_iters": int(infos64[i]["ls_iters"])} for i, r in enumerate(reqs)]
+        with open(args.dump_requests, "w") as fh:
+            json.dump(recs, fh)
     print(json.dumps(line), flush=True)
 
 
@@ -458,6 +470,8 @@ def main():
     ap.add_argument("--arena-gb", type=int, default=16, help="serving_mix: arena budget (admission binds)")
     ap.add_argument("--oracle-sample", type=int, default=24, help="serving_mix: requests checked by the oracle")
     ap.add_argument("--hw-queues", type=int, default=16, help="serving_mix: GPU_MAX_HW_QUEUES for this process")
+    ap.add_argument("--dump-requests", default=None,
+                    help="serving_mix: write a JSON list of per-request records (both paths) to this file")
     ap.add_argument("--sketch", default="srht", choices=["srht", "sparse_sign"], help="serving_mix: sketch")
     ap.add_argument("--workload", default="convdiff3d_256_exp_8rhs", choices=sorted(BENCH) + ["serving_mix"],
                     help="convdiff3d_256_exp_8rhs (default: 256^3, 8 rhs), convdiff3d_128_exp, "

@@ -435,6 +435,36 @@ struct Prof {
 
 }  // namespace
 
+// Fixed-size pinned host slots (a request's info block, a whitening flag),
+// allocated in chunks and reused: freeing pinned memory synchronises the
+// whole device, which would drain every serving stream each time a request
+// completes.  Chunks are freed at fab_finalize only.  Caller holds the
+// context's mutex.
+struct PinnedSlots {
+  static constexpr size_t SLOT = 6144;   // >= host_info_doubles(32) * 8
+  static constexpr int PER_CHUNK = 64;
+  std::vector<void*> chunks, free_;
+  void* get() {
+    if (free_.empty()) {
+      void* c = nullptr;
+      if (hipHostMalloc(&c, SLOT * PER_CHUNK, hipHostMallocDefault) != hipSuccess) return nullptr;
+      chunks.push_back(c);
+      for (int i = PER_CHUNK - 1; i >= 0; --i) free_.push_back((char*)c + (size_t)i * SLOT);
+    }
+    void* p = free_.back();
+    free_.pop_back();
+    return p;
+  }
+  void put(void* p) {
+    if (p) free_.push_back(p);
+  }
+  void release_all() {
+    for (void* c : chunks) hipHostFree(c);
+    chunks.clear();
+    free_.clear();
+  }
+};
+
 struct fab_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -458,6 +488,7 @@ struct fab_ctx_s {
   std::thread sched;
   bool stop = false;
   std::set<fab_matrix> matrices;
+  PinnedSlots pinned;            // requests' pinned info blocks and flags
   double* host_info = nullptr;   // pinned staging for blocking solves
   int* host_flag = nullptr;      // pinned: LSQR stop flag of blocking solves
   std::mutex solve_mu;
@@ -501,9 +532,11 @@ struct Request {
   std::vector<double*> mout;            // block: their out
   uint64_t block = 0;                   // user request: the block that runs it (0: runs on its own)
   size_t oBlkB = 0, oBlkO = 0;          // block: interleaved b and result in the workspace
-  // Whitened basis: its trigger is read on the host every few steps, so the
-  // launch sequence is issued by a worker thread of its own (the scheduler
-  // keeps serving the other requests meanwhile).
+  // The launch sequence of each phase (the solve, then a refinement) is
+  // issued by a worker thread of the request's own, so that the launches of
+  // the requests on the pool streams are issued in parallel while the
+  // scheduler keeps admitting and retiring; the whitened basis also reads
+  // its trigger on the host every few steps in that thread.
   std::thread worker;
   std::atomic<bool> worker_done{false};
   int worker_rc = FAB_OK;
@@ -527,7 +560,8 @@ const int* srht_rows_cached(fab_ctx ctx, long long npad, int s, uint64_t seed, h
   return rows;
 }
 
-size_t host_info_doubles(int nrhs) { return (size_t)nrhs * NINFO + 4 + 2 * nrhs + 8; }
+constexpr size_t host_info_doubles(int nrhs) { return (size_t)nrhs * NINFO + 4 + 2 * nrhs + 8; }
+static_assert(host_info_doubles(32) * 8 <= PinnedSlots::SLOT, "a pinned slot holds the info block of 32 rhs");
 
 // Enqueue the whole solve on `st`.  Host-visible results land in `hinfo` (pinned).
 // `side` runs the incremental sketched QR; `ev` orders it against `st`;
@@ -919,21 +953,16 @@ hipError_t scatter_block(const Request& r, hipStream_t st) {
 
 void retire_locked(fab_ctx ctx, Request& r) {
   if (r.worker.joinable()) r.worker.join();
-  if (r.worker_rc != FAB_OK) {
-    // the worker could not issue the solve
-    hipStreamSynchronize(ctx->pool[r.stream_idx]);
-    ctx->arena.release(r.ws);
-    r.ws = nullptr;
-    ctx->pool_busy[r.stream_idx] = 0;
-    r.status = r.worker_rc;
-    r.t_done = now_us();
-    r.plan.A->refs.fetch_sub(1);
-    r.state = 2;
-    return;
-  }
-  r.status = collect_info(r.plan, r.host_info, r.info);
   const bool blk = !r.members.empty();
-  if (!r.fell_back && needs_fp64_rerun(r.plan, r.status, r.info)) {
+  if (r.worker_rc != FAB_OK) {
+    // the worker could not issue the phase: wait for what it did issue, then
+    // complete the request (or the block's members) with its error
+    hipStreamSynchronize(ctx->pool[r.stream_idx]);
+    r.status = r.worker_rc;
+  } else {
+    r.status = collect_info(r.plan, r.host_info, r.info);
+  }
+  if (r.worker_rc == FAB_OK && !r.fell_back && needs_fp64_rerun(r.plan, r.status, r.info)) {
     // FAB_PREC_AUTO: queue the request again, first in line, with an FP64 basis
     Plan P2;
     const fab_func f2 = plan_func(r.plan);
@@ -952,15 +981,24 @@ void retire_locked(fab_ctx ctx, Request& r) {
       return;
     }
   }
-  if (!r.refined && needs_refine(r.plan, r.status, r.info)) {
-    // least-squares refinement on the request's stream; retired when it ends
+  if (r.worker_rc == FAB_OK && !r.refined && needs_refine(r.plan, r.status, r.info)) {
+    // least-squares refinement on the request's stream, issued by a worker
+    // as the solve was; retired when it ends
     r.refined = 1;
+    Request* rp = &r;
+    const int dev = ctx->device;
     const hipStream_t st = ctx->pool[r.stream_idx];
-    if (enqueue_refine(r.plan, r.ws, st, nullptr, r.host_info) == FAB_OK &&
-        (!blk || scatter_block(r, st) == hipSuccess) && hipEventRecord(r.done_ev, st) == hipSuccess)
-      return;
-    hipStreamSynchronize(st);
-    r.status = FAB_EDEVICE;
+    r.worker_done.store(false);
+    r.worker_rc = FAB_OK;
+    r.worker = std::thread([rp, dev, st, blk]() {
+      hipSetDevice(dev);
+      int wrc = enqueue_refine(rp->plan, rp->ws, st, nullptr, rp->host_info);
+      if (wrc == FAB_OK && blk && scatter_block(*rp, st) != hipSuccess) wrc = FAB_EDEVICE;
+      if (wrc == FAB_OK && hipEventRecord(rp->done_ev, st) != hipSuccess) wrc = FAB_EDEVICE;
+      rp->worker_rc = wrc;
+      rp->worker_done.store(true);
+    });
+    return;
   }
   if (r.fell_back)
     for (auto& fi : r.info) fi.fell_back = 1;
@@ -1034,7 +1072,7 @@ bool form_block_locked(fab_ctx ctx, const Request& head) {
   if (g < 2) return false;
   ids.resize(g);
   if (hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming) != hipSuccess) return false;
-  if (hipHostMalloc((void**)&b->host_info, host_info_doubles(g) * 8, hipHostMallocDefault) != hipSuccess) {
+  if (!(b->host_info = (double*)ctx->pinned.get())) {
     hipEventDestroy(b->done_ev);
     b->done_ev = nullptr;
     return false;
@@ -1091,18 +1129,21 @@ void admit_locked(fab_ctx ctx) {
     const int* rows = nullptr;
     if (rc == FAB_OK && r.plan.p.sketch == FAB_SKETCH_SRHT)
       rows = srht_rows_cached(ctx, 1LL << ilog2(r.plan.A->n), r.plan.p.s, r.plan.p.seed, st, &rc);
-    if (rc == FAB_OK && r.plan.whiten) {
-      // the worker issues the sequence (reading the trigger on the host) and
-      // records done_ev; the scheduler retires the request after both
+    if (rc == FAB_OK) {
+      // the worker issues the sequence (a whitened basis reads its trigger on
+      // the host meanwhile) and records done_ev; the scheduler retires the
+      // request after both.  Only the worker touches r.plan until then.
       Request* rp = &r;
       const int dev = ctx->device;
       const hipStream_t side = ctx->pool_side[si];
       const hipEvent_t pev = ctx->pool_ev[si];
       r.worker_done.store(false);
       r.worker_rc = FAB_OK;
-      r.worker = std::thread([rp, dev, st, side, pev, rows, ws]() {
+      r.worker = std::thread([rp, dev, st, side, pev, rows, ws, blk]() {
         hipSetDevice(dev);
-        int wrc = enqueue_solve(rp->plan, ws, st, side, pev, rows, rp->host_info, nullptr, rp->wflag_host);
+        int wrc = enqueue_solve(rp->plan, ws, st, side, pev, rows, rp->host_info, nullptr,
+                                rp->plan.whiten ? rp->wflag_host : nullptr);
+        if (wrc == FAB_OK && blk && scatter_block(*rp, st) != hipSuccess) wrc = FAB_EDEVICE;
         if (wrc == FAB_OK && hipEventRecord(rp->done_ev, st) != hipSuccess) wrc = FAB_EDEVICE;
         rp->worker_rc = wrc;
         rp->worker_done.store(true);
@@ -1110,10 +1151,7 @@ void admit_locked(fab_ctx ctx) {
       r.state = 1;
       continue;
     }
-    if (rc == FAB_OK) rc = enqueue_solve(r.plan, ws, st, ctx->pool_side[si], ctx->pool_ev[si], rows, r.host_info);
-    if (rc == FAB_OK && blk && scatter_block(r, st) != hipSuccess) rc = FAB_EDEVICE;
-    if (rc == FAB_OK && hipEventRecord(r.done_ev, st) != hipSuccess) rc = FAB_EDEVICE;
-    if (rc != FAB_OK) {
+    {
       hipStreamSynchronize(st);
       ctx->arena.release(ws);
       r.ws = nullptr;
@@ -1136,9 +1174,7 @@ void admit_locked(fab_ctx ctx) {
         u.state = 2;
       }
       r.state = 3;
-      continue;
     }
-    r.state = 1;
   }
 }
 
@@ -1147,7 +1183,7 @@ void drop_blocks_locked(fab_ctx ctx) {
   for (auto it = ctx->reqs.begin(); it != ctx->reqs.end();) {
     if (it->second->state == 3) {
       if (it->second->done_ev) hipEventDestroy(it->second->done_ev);
-      if (it->second->host_info) hipHostFree(it->second->host_info);
+      ctx->pinned.put(it->second->host_info);
       it = ctx->reqs.erase(it);
     } else {
       ++it;
@@ -1632,22 +1668,18 @@ int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
   r->plan.out = out;
   hipSetDevice(ctx->device);
   if (hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) return FAB_EDEVICE;
-  if (hipHostMalloc((void**)&r->host_info, host_info_doubles(nrhs) * 8, hipHostMallocDefault) != hipSuccess) {
-    hipEventDestroy(r->done_ev);
-    return FAB_EDEVICE;
-  }
-  if (r->plan.whiten && hipHostMalloc((void**)&r->wflag_host, 256, hipHostMallocDefault) != hipSuccess) {
-    hipEventDestroy(r->done_ev);
-    hipHostFree(r->host_info);
-    return FAB_EDEVICE;
-  }
   r->t_submit = now_us();
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (!ctx->arena.could_ever_fit(r->plan.bytes)) {
     hipEventDestroy(r->done_ev);
-    hipHostFree(r->host_info);
-    if (r->wflag_host) hipHostFree(r->wflag_host);
     return FAB_ENOMEM;
+  }
+  r->host_info = (double*)ctx->pinned.get();
+  if (r->host_info && r->plan.whiten) r->wflag_host = (int*)ctx->pinned.get();
+  if (!r->host_info || (r->plan.whiten && !r->wflag_host)) {
+    hipEventDestroy(r->done_ev);
+    ctx->pinned.put(r->host_info);
+    return FAB_EDEVICE;
   }
   r->id = ctx->next_id++;
   r->plan.A->refs.fetch_add(1);   // released at retirement
@@ -1680,8 +1712,8 @@ static int finish_request(fab_ctx ctx, std::unordered_map<uint64_t, std::shared_
   if (info)
     for (size_t q = 0; q < r.info.size(); ++q) info[q] = r.info[q];
   hipEventDestroy(r.done_ev);
-  hipHostFree(r.host_info);
-  if (r.wflag_host) hipHostFree(r.wflag_host);
+  ctx->pinned.put(r.host_info);
+  ctx->pinned.put(r.wflag_host);
   ctx->reqs.erase(it);
   return rc;
 }
@@ -1723,8 +1755,6 @@ int fab_finalize(fab_ctx ctx) {
   for (auto& kv : ctx->reqs) {
     if (kv.second->worker.joinable()) kv.second->worker.join();
     if (kv.second->done_ev) hipEventDestroy(kv.second->done_ev);
-    if (kv.second->host_info) hipHostFree(kv.second->host_info);
-    if (kv.second->wflag_host) hipHostFree(kv.second->wflag_host);
   }
   ctx->reqs.clear();
   for (auto* M : ctx->matrices) delete M;
@@ -1750,6 +1780,7 @@ int fab_finalize(fab_ctx ctx) {
     hipGraphDestroy(g.graph);
   }
   ctx->graphs.clear();
+  ctx->pinned.release_all();
   if (ctx->host_info) hipHostFree(ctx->host_info);
   if (ctx->host_flag) hipHostFree(ctx->host_flag);
   for (auto ev : ctx->prof.pool) hipEventDestroy(ev);
