@@ -916,14 +916,18 @@ bool needs_refine(const Plan& P, int rc, const std::vector<fab_info>& fi) {
 }
 
 // FAB_PREC_AUTO: an FP32-basis result is recomputed with an FP64 basis when
-// the basis-rounding estimate exceeds tol/4 or the FP32 run produced
-// non-finite values.
+// the basis-rounding estimate exceeds tol/2 or the FP32 run produced
+// non-finite values.  Decided once, on the solve's own result (before any
+// least-squares refinement), in blocking and served calls alike.  The
+// estimate overestimates the rounding error (first-order bound), and a
+// refinement stops at a least-squares measure of tol/10, so an accepted
+// result stays below tol.
 bool needs_fp64_rerun(const Plan& P, int rc, const std::vector<fab_info>& fi) {
   if (P.p.prec != FAB_PREC_AUTO || P.esize != 4) return false;
   if (rc == FAB_ENUMERIC) return true;
   if (rc != FAB_OK) return false;
   for (const auto& x : fi)
-    if (!(x.round_est <= P.p.tol / 4)) return true;
+    if (!(x.round_est <= P.p.tol / 2)) return true;
   return false;
 }
 
@@ -962,7 +966,9 @@ void retire_locked(fab_ctx ctx, Request& r) {
   } else {
     r.status = collect_info(r.plan, r.host_info, r.info);
   }
-  if (r.worker_rc == FAB_OK && !r.fell_back && needs_fp64_rerun(r.plan, r.status, r.info)) {
+  // the precision decision is taken on the solve's result, as in blocking
+  // calls (a refinement's result is not judged again)
+  if (r.worker_rc == FAB_OK && !r.fell_back && !r.refined && needs_fp64_rerun(r.plan, r.status, r.info)) {
     // FAB_PREC_AUTO: queue the request again, first in line, with an FP64 basis
     Plan P2;
     const fab_func f2 = plan_func(r.plan);

@@ -120,3 +120,39 @@ def test_wait_while_another_thread_submits(ctx):
         else:
             assert krylov.relerr(got, ref) < 1e-6
     A.destroy()
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-8])
+def test_served_auto_policies_match_blocking(ctx, tol):
+    """FAB_PREC_AUTO with FAB_LS_AUTO on an unconverged inverse square root
+    (the least-squares gate fails, so the refinement runs): the served call
+    takes the same decisions as the blocking one (the precision is judged on
+    the solve's own result, before the refinement) and returns the same
+    result bit for bit.  At tol = 1e-8 the FP32 rounding estimate fails, so
+    both calls recompute with an FP64 basis and then refine: that rerun must
+    refine too (it once came back unrefined, 2.5e-2 off f_m), and the result
+    meets tol against f_m."""
+    from paper_2212_12758_amd import make_params
+
+    st = W.laplacian2d(128)
+    b = W.rhs(st.n, 71)
+    f = W.FuncSpec("pow", sigma=1e-3, p=-0.5)
+    m, k, s = 60, 3, 120
+    ref = krylov.fm(operators.as_matrix(st), b, f, m)
+    A = ctx.matrix(st)
+    p = make_params(m, k, s, "srht", 8, 9, "auto", "auto", tol)
+    print(f"case auto policies tol={tol}", flush=True)
+    out_b, info_b = ctx.solve(A, _dev(b), f, p)
+    info_b = info_b[0]
+    assert info_b["ls_iters"] > 0                       # the refinement ran
+    if tol < 1e-6:
+        assert info_b["fell_back"] == 1                 # FP32 rounding alone exceeds tol / 2
+    ctx.set_block_limit(1)
+    o = _dev(np.zeros(st.n))
+    info_s = ctx.submit(A, _dev(b), f, p, o).wait()[0]
+    ctx.set_block_limit(32)
+    for key in ("fell_back", "ls_iters", "prec_used"):
+        assert info_s[key] == info_b[key], key
+    assert np.array_equal(o.cpu().numpy(), out_b.cpu().numpy())
+    assert krylov.relerr(out_b.cpu().numpy(), ref) <= tol
+    A.destroy()
