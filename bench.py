@@ -292,10 +292,10 @@ def serving_main(args):
        those of a single server fed the same trace);
     4. accuracy: the oracle's f_m for a sample of requests (both paths).
 
-    The context's 8 serving streams (and their side streams) run concurrently
-    only on as many hardware queues: HIP's default of 4 per process would
-    serialise them, so this mode asks for 16 (GPU_MAX_HW_QUEUES, read when HIP
-    starts; --hw-queues, at most 32)."""
+    The context's serving streams (12) run concurrently only on as many
+    hardware queues: HIP's default of 4 per process would serialise them, so
+    this mode asks for 16 (GPU_MAX_HW_QUEUES, read when HIP starts;
+    --hw-queues, at most 32)."""
     os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     import numpy as np
     import torch
@@ -385,6 +385,9 @@ def serving_main(args):
         lat64[i] = (done - a) * 1e3
     print(f"plain fp64: {rate64:.1f} solves/s", file=sys.stderr, flush=True)
     res64 = [o.clone() for o in outs]
+    # every served result against the plain FP64 path's (on the GPU)
+    e_vs64 = np.array([float(torch.linalg.norm(res32[i] - res64[i]) / torch.linalg.norm(res64[i]))
+                       for i in range(nreq)])
     # 4. accuracy on a sample (the smallest requests, every f kind and both
     # kinds of matrix), oracle timed as the CPU baseline
     from oracle import krylov, operators
@@ -424,6 +427,9 @@ def serving_main(args):
             "fell_back": int(sum(inf["fell_back"] for inf in infos)),
             "refined": int(sum(inf["ls_iters"] > 0 for inf in infos)),
             "plain_fp64_solves_per_s": rate64, "fp32_over_plain_fp64": value / rate64,
+            "saturated_over_plain_fp64": rate_sat / rate64,
+            "relerr_vs_plain_fp64_all_max": float(e_vs64.max()),
+            "relerr_vs_plain_fp64_all_median": float(np.median(e_vs64)),
             "plain_fp64_p50_ms": float(np.percentile(lat64, 50)), "plain_fp64_p99_ms": float(np.percentile(lat64, 99)),
             "oracle_sample": len(sample), "relerr_vs_oracle_max": float(errs32.max()),
             "relerr_vs_oracle_median": float(np.median(errs32)),

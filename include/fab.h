@@ -177,7 +177,11 @@ typedef struct {
  * matrices and per-request workspaces; pass NULL to let the library allocate
  * an arena of `arena_bytes` itself (freed by fab_finalize).  `hip_stream` is
  * the hipStream_t the blocking calls run on (NULL = the library's own stream);
- * served requests run on library-owned streams of the same device.
+ * served requests run on library-owned streams of the same device, one
+ * admitted request per stream at a time: 12 of them, or FAB_SERVING_STREAMS
+ * (1..16) from the environment.  They run concurrently only on as many HIP
+ * hardware queues (GPU_MAX_HW_QUEUES, read when HIP starts: give one per
+ * stream, plus the caller's own streams).
  * Errors: FAB_EINVAL (null ctx, arena_bytes < 1 MiB), FAB_EDEVICE.           */
 int fab_init(fab_ctx* ctx, int device, void* arena_dev_ptr, size_t arena_bytes, void* hip_stream);
 

@@ -473,13 +473,9 @@ struct fab_ctx_s {
   std::mutex mu;                 // arena + request table
   std::condition_variable cv;
   std::vector<hipStream_t> pool; // serving streams
-  std::vector<hipStream_t> pool_side;   // paired side streams (incremental QR)
-  std::vector<hipEvent_t> pool_ev;
   std::vector<int> pool_busy;
   int block_max = 32;            // largest block of merged single-rhs requests (1: no merging)
   bool hold = false;             // fab_hold: admit nothing while set
-  hipStream_t side = nullptr;    // side stream of the blocking path
-  hipEvent_t ev = nullptr;
   // sampled SRHT rows per (padded length, s, seed), device arrays in the arena
   std::map<std::tuple<long long, int, uint64_t>, int*> srht_cache;
   std::deque<uint64_t> queue;
@@ -674,8 +670,8 @@ void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev
 
 }
 
-int enqueue_solve(Plan& P, char* ws, hipStream_t st, hipStream_t side, hipEvent_t ev, const int* rows, double* hinfo,
-                  Prof* prof = nullptr, int* host_flag = nullptr) {
+int enqueue_solve(Plan& P, char* ws, hipStream_t st, const int* rows, double* hinfo, Prof* prof = nullptr,
+                  int* host_flag = nullptr) {
   const int m = P.p.m, nr = P.nrhs;
   SolveDev d;
   DenseDev g;
@@ -1141,13 +1137,11 @@ void admit_locked(fab_ctx ctx) {
       // request after both.  Only the worker touches r.plan until then.
       Request* rp = &r;
       const int dev = ctx->device;
-      const hipStream_t side = ctx->pool_side[si];
-      const hipEvent_t pev = ctx->pool_ev[si];
       r.worker_done.store(false);
       r.worker_rc = FAB_OK;
-      r.worker = std::thread([rp, dev, st, side, pev, rows, ws, blk]() {
+      r.worker = std::thread([rp, dev, st, rows, ws, blk]() {
         hipSetDevice(dev);
-        int wrc = enqueue_solve(rp->plan, ws, st, side, pev, rows, rp->host_info, nullptr,
+        int wrc = enqueue_solve(rp->plan, ws, st, rows, rp->host_info, nullptr,
                                 rp->plan.whiten ? rp->wflag_host : nullptr);
         if (wrc == FAB_OK && blk && scatter_block(*rp, st) != hipSuccess) wrc = FAB_EDEVICE;
         if (wrc == FAB_OK && hipEventRecord(rp->done_ev, st) != hipSuccess) wrc = FAB_EDEVICE;
@@ -1283,24 +1277,20 @@ int fab_init(fab_ctx* out, int device, void* arena_dev_ptr, size_t arena_bytes, 
     delete ctx;
     return FAB_EDEVICE;
   }
-  if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ev, hipEventDisableTiming) != hipSuccess) {
-    delete ctx;
-    return FAB_EDEVICE;
+  // serving streams: FAB_SERVING_STREAMS (1..16), default 12; each runs one
+  // admitted request at a time and should have a hardware queue of its own
+  int npool = 12;
+  if (const char* ev = std::getenv("FAB_SERVING_STREAMS")) {
+    const int v = std::atoi(ev);
+    if (v >= 1 && v <= 16) npool = v;
   }
-  const int npool = 8;
   for (int i = 0; i < npool; ++i) {
-    hipStream_t s, s2;
-    hipEvent_t e;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
       delete ctx;
       return FAB_EDEVICE;
     }
     ctx->pool.push_back(s);
-    ctx->pool_side.push_back(s2);
-    ctx->pool_ev.push_back(e);
     ctx->pool_busy.push_back(0);
   }
   if (hipHostMalloc((void**)&ctx->host_info, host_info_doubles(32) * 8, hipHostMallocDefault) != hipSuccess ||
@@ -1455,7 +1445,7 @@ static int launch_solve(fab_ctx ctx, Plan& P, char* ws, const int* rows, const f
   // timed (profiled) solves use direct launches of the same kernels
   // whitening reads its trigger on the host during the solve: direct launches
   if (!ctx->use_graphs || prof || P.whiten)
-    return enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, prof, ctx->host_flag);
+    return enqueue_solve(P, ws, ctx->stream, rows, ctx->host_info, prof, ctx->host_flag);
   const std::string key = graph_key(P, ws, rows, ctx->host_info, ctx->prof.mask, f);
   for (auto& g : ctx->graphs) {
     if (g.key == key) {
@@ -1479,9 +1469,9 @@ static int launch_solve(fab_ctx ctx, Plan& P, char* ws, const int* rows, const f
   if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
     ctx->use_graphs = false;
-    return enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, prof);
+    return enqueue_solve(P, ws, ctx->stream, rows, ctx->host_info, prof);
   }
-  int rc = enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, prof);
+  int rc = enqueue_solve(P, ws, ctx->stream, rows, ctx->host_info, prof);
   hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
   hipGraphExec_t exec = nullptr;
   if (rc == FAB_OK && e == hipSuccess && graph) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1491,7 +1481,7 @@ static int launch_solve(fab_ctx ctx, Plan& P, char* ws, const int* rows, const f
     if (graph) hipGraphDestroy(graph);
     ctx->use_graphs = false;
     if (prof) { prof->marks.clear(); prof->used = 0; }
-    return enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, prof);
+    return enqueue_solve(P, ws, ctx->stream, rows, ctx->host_info, prof);
   }
   fab_ctx_s::GraphEntry ge;
   ge.key = key;
@@ -1563,7 +1553,7 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
       }
     }
     if (rc == FAB_OK)
-      rc = ws_fixed ? enqueue_solve(P, ws, ctx->stream, ctx->side, ctx->ev, rows, ctx->host_info, nullptr,
+      rc = ws_fixed ? enqueue_solve(P, ws, ctx->stream, rows, ctx->host_info, nullptr,
                                     ctx->host_flag)
                     : launch_solve(ctx, P, ws, rows, f);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == FAB_OK) rc = FAB_EDEVICE;
@@ -1769,16 +1759,6 @@ int fab_finalize(fab_ctx ctx) {
     hipStreamSynchronize(s);
     hipStreamDestroy(s);
   }
-  for (auto s : ctx->pool_side) {
-    hipStreamSynchronize(s);
-    hipStreamDestroy(s);
-  }
-  for (auto e : ctx->pool_ev) hipEventDestroy(e);
-  if (ctx->side) {
-    hipStreamSynchronize(ctx->side);
-    hipStreamDestroy(ctx->side);
-  }
-  if (ctx->ev) hipEventDestroy(ctx->ev);
   if (ctx->own_stream) hipStreamDestroy(ctx->stream);
   else hipStreamSynchronize(ctx->stream);
   for (auto& g : ctx->graphs) {
