@@ -292,7 +292,11 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
   P.R = (int)(tile / nrhs);
   P.logR = ilog2(P.R);
   P.ntiles = (int)((nel + tile - 1) / tile);
-  P.nblk = std::min(P.ntiles, P.LT == 11 ? 512 : 2048);
+  // at most 512 blocks: every block of the update pass first reduces the
+  // previous pass's per-block partials (fixed order), a cost that grows with
+  // the square of the block count (2048 blocks of 512 elements: 0.37 GB of
+  // partial reads per launch at n = 2^20)
+  P.nblk = std::min(P.ntiles, 512);
   const long long snr = (long long)p.s * nrhs;
   P.nred = (int)std::max<long long>(1, std::min<long long>((snr + 7) / 8, 128));   // one per 8 sketch rows
   // streaming blocks in 8 XCD groups when the grid divides; the leading
@@ -536,7 +540,7 @@ struct Request {
   std::thread worker;
   std::atomic<bool> worker_done{false};
   int worker_rc = FAB_OK;
-  int* wflag_host = nullptr;            // pinned: the trigger flag read by the worker
+  int* flag_host = nullptr;             // pinned: flags the worker reads (whitening trigger, LSQR stop)
 };
 
 // Sampled SRHT rows for (npad, s, seed): computed once on `st` (which the
@@ -877,10 +881,11 @@ int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* h
   } else if (!host_flag) {
     if (lsqr_launch(d, g, L, P.esize, st) != hipSuccess) return FAB_EDEVICE;
   } else {
-    constexpr int CHUNK = 16;
+    // chunks of 2, 4, 8, then 16 iterations: a refinement that stops after
+    // an iteration or two issues few launches past its end
     if (lsqr_begin(d, g, L, P.esize, st) != hipSuccess) return FAB_EDEVICE;
-    for (int it = 0; it < L.maxit; it += CHUNK) {
-      if (lsqr_iterate(d, g, L, P.esize, st, std::min(CHUNK, L.maxit - it)) != hipSuccess) return FAB_EDEVICE;
+    for (int it = 0, chunk = 2; it < L.maxit; it += chunk, chunk = std::min(2 * chunk, 16)) {
+      if (lsqr_iterate(d, g, L, P.esize, st, std::min(chunk, L.maxit - it)) != hipSuccess) return FAB_EDEVICE;
       *host_flag = 0;
       if (hipMemcpyAsync(host_flag, L.alldone, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess)
@@ -994,7 +999,9 @@ void retire_locked(fab_ctx ctx, Request& r) {
     r.worker_rc = FAB_OK;
     r.worker = std::thread([rp, dev, st, blk]() {
       hipSetDevice(dev);
-      int wrc = enqueue_refine(rp->plan, rp->ws, st, nullptr, rp->host_info);
+      // the worker may wait: it issues the iterations in chunks and stops
+      // once the device flag says every rhs stopped, as blocking calls do
+      int wrc = enqueue_refine(rp->plan, rp->ws, st, nullptr, rp->host_info, rp->flag_host);
       if (wrc == FAB_OK && blk && scatter_block(*rp, st) != hipSuccess) wrc = FAB_EDEVICE;
       if (wrc == FAB_OK && hipEventRecord(rp->done_ev, st) != hipSuccess) wrc = FAB_EDEVICE;
       rp->worker_rc = wrc;
@@ -1142,7 +1149,7 @@ void admit_locked(fab_ctx ctx) {
       r.worker = std::thread([rp, dev, st, rows, ws, blk]() {
         hipSetDevice(dev);
         int wrc = enqueue_solve(rp->plan, ws, st, rows, rp->host_info, nullptr,
-                                rp->plan.whiten ? rp->wflag_host : nullptr);
+                                rp->plan.whiten ? rp->flag_host : nullptr);
         if (wrc == FAB_OK && blk && scatter_block(*rp, st) != hipSuccess) wrc = FAB_EDEVICE;
         if (wrc == FAB_OK && hipEventRecord(rp->done_ev, st) != hipSuccess) wrc = FAB_EDEVICE;
         rp->worker_rc = wrc;
@@ -1671,8 +1678,8 @@ int fab_submit(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_func f,
     return FAB_ENOMEM;
   }
   r->host_info = (double*)ctx->pinned.get();
-  if (r->host_info && r->plan.whiten) r->wflag_host = (int*)ctx->pinned.get();
-  if (!r->host_info || (r->plan.whiten && !r->wflag_host)) {
+  if (r->host_info) r->flag_host = (int*)ctx->pinned.get();
+  if (!r->host_info || !r->flag_host) {
     hipEventDestroy(r->done_ev);
     ctx->pinned.put(r->host_info);
     return FAB_EDEVICE;
@@ -1709,7 +1716,7 @@ static int finish_request(fab_ctx ctx, std::unordered_map<uint64_t, std::shared_
     for (size_t q = 0; q < r.info.size(); ++q) info[q] = r.info[q];
   hipEventDestroy(r.done_ev);
   ctx->pinned.put(r.host_info);
-  ctx->pinned.put(r.wflag_host);
+  ctx->pinned.put(r.flag_host);
   ctx->reqs.erase(it);
   return rc;
 }
