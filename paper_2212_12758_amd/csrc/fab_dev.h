@@ -84,6 +84,14 @@ struct SolveDev {
   double unit_round;     // unit roundoff of the basis storage
 };
 
+// Window length a streaming kernel is instantiated for (k <= KT).
+__host__ __device__ constexpr int window_kt(int k) { return k <= 2 ? 2 : (k <= 4 ? 4 : 8); }
+// SRHT with 8 rhs: sampled rows (multiples of the block size) whose sums a
+// thread of k_update keeps in registers, by window length: what fits beside
+// the rest in 256 VGPRs (2 waves per SIMD).  0: every sum in LDS and one tile
+// buffer.  The host sizes k_update's LDS from the same function.
+__host__ __device__ constexpr int srht_qrows(int kt) { return kt <= 2 ? 1 : (kt <= 4 ? 2 : 0); }
+
 // Per-rhs workspace of the small dense stages (FP64, column-major).
 constexpr int MAXCOEF = 64;
 constexpr int NINFO = 20;

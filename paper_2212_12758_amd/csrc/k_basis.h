@@ -731,6 +731,44 @@ __device__ inline void fwht_tile(double* v, double* X, int lnr) {
   __syncthreads();
 }
 
+// As fwht_tile with two tile buffers used in turn, one barrier per exchange
+// (a buffer is written again only after the barrier that follows all reads
+// of it).  Returns the buffer that holds the transformed tile: XA after an
+// odd number of stores, XB after an even number; the next transform starts
+// with XA again, so a caller that read XA must pass a barrier first.
+template <int LT>
+__device__ inline double* fwht_tile2(double* v, double* XA, double* XB, int lnr) {
+  const int tid = threadIdx.x;
+  butterflies_range(v, 0, lnr, 3);
+  int cur = 0;
+  double* Xc = XA;
+#pragma unroll
+  for (int p = 3; p < LT; p += 3) {
+    const int pos = p + 3 <= LT ? p : LT - 3;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = (tid & ((1 << cur) - 1)) | (j << cur) | ((tid >> cur) << (cur + 3));
+      Xc[padx(e)] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = (tid & ((1 << pos) - 1)) | (j << pos) | ((tid >> pos) << (pos + 3));
+      v[j] = Xc[padx(e)];
+    }
+    cur = pos;
+    butterflies_range(v, pos, p > lnr ? p : lnr, p + 3 < LT ? p + 3 : LT);
+    Xc = Xc == XA ? XB : XA;
+  }
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int e = (tid & ((1 << cur) - 1)) | (j << cur) | ((tid >> cur) << (cur + 3));
+    Xc[padx(e)] = v[j];
+  }
+  __syncthreads();
+  return Xc;
+}
+
 // ------------------------------------------------------------------ pass 2
 // Slot pq of the s x nrhs SRHT accumulators belongs to thread pq mod BLOCK
 // for the whole launch.  With one rhs (at most srht_reg_slots * BLOCK slots)
@@ -741,6 +779,7 @@ __device__ inline void fwht_tile(double* v, double* X, int lnr) {
 template <int QC>
 constexpr int srht_reg_slots() { return QC == 1 ? 4 : 0; }
 constexpr int SK_BATCH = 8;
+
 
 // Update coefficient `slot` (0: of w~, 1 + j: of window vector j) of the rhs
 // of element j of this thread.  One rhs: uniform registers; several: read
@@ -802,24 +841,39 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
     cf.tab = cfl;
   }
 
-  double* X = lds;                                                   // SRHT tile (padded)
-  double* acc = lds + (SK == SK_SRHT ? padx(TILE) : 0);              // sketch accumulator [s][nr] (LDS path)
   const int snr = d.s * nr;
   const bool reg_acc = SK == SK_SRHT && srht_reg_slots<QC>() > 0 && d.sk_reg;
-  // SRHT sums kept by rhs pairs (several rhs per row, LDS path)
+  // SRHT with 8 or more rhs (several rhs per grid row): sums kept by rhs
+  // pairs.  With exactly 8 rhs the sums of the sampled rows p < QROWS BLOCK
+  // live in registers (thread tid owns rows tid + a BLOCK), the others in
+  // LDS, and the LDS this frees holds a second tile buffer for the
+  // transform.  The host sizes LDS the same way.
   const bool qmajor = SK == SK_SRHT && QC > 1 && !reg_acc && nr >= EPT;
+  constexpr int QROWS = srht_qrows(KT) > 0 ? srht_qrows(KT) : 1;   // register array size
+  const bool q8 = qmajor && nr == EPT && srht_qrows(KT) > 0;
+  const int rreg = q8 ? QROWS * BLOCK : 0;
+  const int sacc = d.s > rreg ? d.s - rreg : 0;                      // sampled rows summed in LDS
+  double* X = lds;                                                   // SRHT tile (padded)
+  double* X2 = q8 ? X + padx(TILE) : X;                              // second tile buffer
+  double* acc = lds + (SK == SK_SRHT ? (q8 ? 2 : 1) * padx(TILE) : 0);   // sketch sums (LDS part)
+  const int lslots = sacc * nr;   // = snr except on the 8-rhs path
   // sparse sign: one accumulator per wave when the host sized LDS for it, so
   // that the LDS atomics of different waves never meet (fixed order)
   const int nsl = (SK == SK_SPARSE && NW > 1 && d.sk_slices == NW) ? NW : 1;
   double* acc_w = acc + (nsl > 1 ? wv * snr : 0);
-  int* rows_l = (int*)(acc + (reg_acc ? 0 : snr * nsl));             // sampled SRHT rows
+  int* rows_l = (int*)(acc + (reg_acc ? 0 : lslots * nsl));          // sampled SRHT rows
   if (!reg_acc)
-    for (int x = tid; x < snr * nsl; x += BLOCK) acc[x] = 0.0;
+    for (int x = tid; x < lslots * nsl; x += BLOCK) acc[x] = 0.0;
   if (SK == SK_SRHT)
     for (int x = tid; x < d.s; x += BLOCK) rows_l[x] = d.srht_rows[x];
   double racc[RA];
 #pragma unroll
   for (int a = 0; a < RA; ++a) racc[a] = 0.0;
+  double qacc[QROWS][EPT];   // register sums of the 8-rhs path: sampled rows tid + a BLOCK
+#pragma unroll
+  for (int a = 0; a < QROWS; ++a)
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) qacc[a][q] = 0.0;
   __syncthreads();
 
   double nrm[QC];
@@ -954,7 +1008,9 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
         if (j == 0 || (ej & (nr - 1)) == 0) neg = (sm64_out(d.key_a, (unsigned long long)(ej >> d.lognrhs)) >> 63) != 0;
         if (neg) uu[j] = -uu[j];
       }
-      fwht_tile<LT>(uu, X, d.lognrhs);
+      double* XF = X;   // the buffer holding the transformed tile
+      if (q8) XF = fwht_tile2<LT>(uu, X, X2, d.lognrhs);
+      else fwht_tile<LT>(uu, X, d.lognrhs);
       // sampled rows r = (r_hi, r_lo): contribution (-1)^popcount(r_hi & t) * X[r_lo]
       if (reg_acc) {
         const int lomask = d.rows_per_tile - 1;
@@ -974,31 +1030,42 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
           // several rhs: thread tid owns the sampled rows p = tid + a BLOCK
           // with all their rhs; the rhs of a row are consecutive in the tile,
           // so one row index, one sign and one address serve nr sums.  The
-          // accumulators are kept by rhs pairs (sum (p, q) at
-          // ((q/2) s + p) 2 + q mod 2), so each access moves two sums and the
-          // lanes of a wave touch consecutive 16-byte words.
-          for (int p = tid; p < d.s; p += BLOCK) {
+          // LDS accumulators are kept by rhs pairs (sum (p, q) at
+          // ((q/2) sacc + p - rreg) 2 + q mod 2), so each access moves two
+          // sums and the lanes of a wave touch consecutive 16-byte words.
+          // The sign is applied as a mask on the sign bit of the values.
+#pragma unroll
+          for (int a = 0; a < QROWS; ++a) {
+            if (tid + a * BLOCK < rreg && tid + a * BLOCK < d.s) {
+              const int rr = rows_l[tid + a * BLOCK];
+              const int smask = (int)((unsigned)__popc((unsigned)(rr >> d.log_rows) & (unsigned)t) << 31);
+              const double* xp = XF + padx((rr & lomask) << d.lognrhs);
+#pragma unroll
+              for (int q = 0; q < EPT; ++q)
+                qacc[a][q] += __hiloint2double(__double2hiint(xp[q]) ^ smask, __double2loint(xp[q]));
+            }
+          }
+          for (int p = rreg + tid; p < d.s; p += BLOCK) {
             const int rr = rows_l[p];
-            // the sign as a mask on the sign bit of the transformed values
             const int smask = (int)((unsigned)__popc((unsigned)(rr >> d.log_rows) & (unsigned)t) << 31);
             const int b = (rr & lomask) << d.lognrhs;
             for (int q0 = 0; q0 < nr; q0 += EPT) {
               // 8 consecutive elements from a multiple of 8 share one
               // padding group of the tile
-              const double* xp = X + padx(b + q0);
-              double2* ap = reinterpret_cast<double2*>(acc) + (q0 / 2) * d.s + p;
+              const double* xp = XF + padx(b + q0);
+              double2* ap = reinterpret_cast<double2*>(acc) + (q0 / 2) * sacc + (p - rreg);
               double xv[EPT];
               double2 av[EPT / 2];
 #pragma unroll
               for (int q = 0; q < EPT; ++q) xv[q] = xp[q];
 #pragma unroll
-              for (int h = 0; h < EPT / 2; ++h) av[h] = ap[h * d.s];
+              for (int h = 0; h < EPT / 2; ++h) av[h] = ap[h * sacc];
 #pragma unroll
               for (int h = 0; h < EPT / 2; ++h) {
                 double2 o;
                 o.x = av[h].x + __hiloint2double(__double2hiint(xv[2 * h]) ^ smask, __double2loint(xv[2 * h]));
                 o.y = av[h].y + __hiloint2double(__double2hiint(xv[2 * h + 1]) ^ smask, __double2loint(xv[2 * h + 1]));
-                ap[h * d.s] = o;
+                ap[h * sacc] = o;
               }
             }
           }
@@ -1025,7 +1092,10 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
           }
         }
       }
-      __syncthreads();
+      // the next tile's transform writes X first: after a read of X, a
+      // barrier; after a read of X2 none is needed (the next write of X2
+      // follows the next transform's first barrier)
+      if (XF == X) __syncthreads();
     }
   }
   __syncthreads();
@@ -1036,10 +1106,25 @@ __global__ void __launch_bounds__(1 << (LT - 3)) k_update(SolveDev d, int i) {
       const int pq = tid + a * BLOCK;
       if (pq < snr) skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = racc[a];
     }
+  } else if (qmajor) {
+#pragma unroll
+    for (int a = 0; a < QROWS; ++a)
+      if (tid + a * BLOCK < rreg && tid + a * BLOCK < d.s) {
+        const int p = tid + a * BLOCK;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+          const int pq = p * EPT + q;
+          skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = qacc[a][q];
+        }
+      }
+    for (int x = tid; x < lslots; x += BLOCK) {
+      const int q = x & (nr - 1), pl = x >> d.lognrhs;
+      const int pq = (pl + rreg) * nr + q;
+      skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = acc[(((q >> 1) * sacc + pl) << 1) + (q & 1)];
+    }
   } else {
     for (int pq = tid; pq < snr; pq += BLOCK) {
-      const int q = pq & (nr - 1);
-      double a = acc[qmajor ? (((q >> 1) * d.s + (pq >> d.lognrhs)) << 1) + (q & 1) : pq];
+      double a = acc[pq];
       for (int sl = 1; sl < nsl; ++sl) a += acc[sl * snr + pq];
       skp[((long long)(pq >> 3) * d.nblk + blk) * 8 + (pq & 7)] = a;
     }

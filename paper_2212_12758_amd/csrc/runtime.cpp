@@ -343,6 +343,15 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
     P.sk_reg = 1;
     P.lds_kupdate = (size_t)(tile + tile / 32) * 8 + (size_t)p.s * 4;
   }
+  // SRHT with 8 rhs: the sums of the first srht_qrows(KT) * BLOCK sampled
+  // rows in registers, two tile buffers (as k_update, KT the window length
+  // it is instantiated for); never more than lds_update
+  const int kt = window_kt(P.p.k);
+  if (p.sketch == FAB_SKETCH_SRHT && nrhs == 8 && srht_qrows(kt) > 0) {
+    const long long rreg = (long long)srht_qrows(kt) * (tile / 8);
+    const long long sacc = p.s > rreg ? p.s - rreg : 0;
+    P.lds_kupdate = (size_t)(2 * (tile + tile / 32) + sacc * nrhs) * 8 + (size_t)p.s * 4;
+  }
   P.ldv = (nel + 63) & ~63LL;
   const int m = p.m, s = p.s;
   // dense workspace per rhs
