@@ -839,6 +839,15 @@ int collect_info(const Plan& P, const double* hinfo, std::vector<fab_info>& out)
     // only accepted when kappa(R)^2 u <= tol / 10)
     if (fi.ls_iters > 0) fi.err_est = std::max(in[INFO_LSQR_RATIO], fi.round_est);
     if (P.gram_used) fi.err_est = fi.round_est;
+    // a whitened FP32 basis: the transform V R^{-1} multiplies the storage
+    // rounding of the vectors it whitens by up to kappa(R), which exceeded
+    // WH_THRESH when it triggered (Section 2.1.2); the rounding estimate,
+    // first order in the final basis, does not see that, so the bound is
+    // added (with or without the automatic policies)
+    if (P.whitened_at && P.esize == 4) {
+      fi.round_est = std::max(fi.round_est, std::ldexp(1.0, -24) * WH_THRESH);
+      fi.err_est = std::max(fi.err_est, fi.round_est);
+    }
     fi.fell_back = 0;
     fi.whitened_at = P.whitened_at;
     fi.block_rhs = 1;

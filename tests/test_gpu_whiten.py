@@ -78,6 +78,15 @@ def test_whitening_restores_the_basis(ctx):
     assert 0 < info32[0]["whitened_at"] <= 90
     print("fp32 whitened", info32[0], krylov.relerr(out32.cpu().numpy(), fm), flush=True)
     assert krylov.relerr(out32.cpu().numpy(), fm) < 1e-6
+    # ... but nothing bounds it there: the whitening multiplies the FP32
+    # storage rounding by up to kappa(R) > 1000 (at 2^20 nodes the same FP32
+    # solve lands 2e-6 off), and the reported estimate says so; with
+    # FAB_PREC_AUTO the request is recomputed with an FP64 basis
+    assert info32[0]["round_est"] >= 2.0 ** -24 * 1000 and info32[0]["err_est"] >= info32[0]["round_est"]
+    print("case whiten rgg4096 auto", flush=True)
+    outa, infoa = ctx.solve(A, _dev(b), w.f, _params(w, "auto", tol=1e-6))
+    assert infoa[0]["fell_back"] == 1 and infoa[0]["prec_used"] == 2
+    assert krylov.relerr(outa.cpu().numpy(), fm) < 1e-6
     A.destroy()
 
 
