@@ -78,6 +78,8 @@ struct SolveDev {
   long long tchunk;      // tiles per group: group g walks tiles [g*tchunk, (g+1)*tchunk)
   int wtp, wc, wpen;     // pencil walk (wtp > 0): tiles per z-plane, tiles per pencil row,
                          // pencils per group (3D stencils with large planes)
+  int wz;                // z-march walk (> 0: tiles per block; wtp tiles per plane, wc
+                         // tile columns per group)
   const int* srht_rows;  // [s] sampled rows of the padded Hadamard transform
   unsigned long long key_a, key_b;   // SRHT: signs key; sparse: rows key, signs key
   double sk_scale;       // 1/sqrt(s) (SRHT) or 1/sqrt(zeta) (sparse sign)
@@ -270,7 +272,16 @@ __device__ inline double wave_sum_rhs(double v, int nrhs) {
 //  * pencil walk (3D stencil whose z-plane is large): a z-plane of wtp tiles
 //    is cut into pencils of wc consecutive tiles; group g takes pencils
 //    g, g + 8, ... (wpen of them) and walks each through all z-planes, so
-//    the planes z - 1, z, z + 1 of a pencil are touched close together.
+//    the planes z - 1, z, z + 1 of a pencil are touched close together;
+//  * z-march (the same case, when each group can own whole tile columns):
+//    tile (z, y) = z wtp + y; group g owns the wc columns y in
+//    [g wc, (g+1) wc) through all planes, ordered column by column with z
+//    fastest, and block u of the group walks its own wz consecutive tiles
+//    of that order (u0 = u wz, step 1).  A block's next tile is the
+//    z + 1 neighbour of its current one (its z - 1 neighbour is the tile it
+//    did before), and the group's blocks advance through the planes side by
+//    side, so a tile's y-neighbours are read by sibling blocks of the same
+//    XCD at the same time.
 struct TileWalk {
   int u0, uhi, step, g;
   long long lo;
@@ -281,7 +292,13 @@ __device__ inline TileWalk tile_walk(const SolveDev& d, int blk) {
   w.g = blk % G;
   w.u0 = blk / G;
   w.step = d.nblk / G;
-  if (d.wtp > 0) {
+  if (d.wz > 0) {
+    w.lo = 0;
+    w.u0 = (blk / G) * d.wz;
+    const int tot = d.wc * d.nz;
+    w.uhi = w.u0 + d.wz < tot ? w.u0 + d.wz : tot;
+    w.step = 1;
+  } else if (d.wtp > 0) {
     w.lo = 0;
     w.uhi = d.wpen * d.nz * d.wc;
   } else {
@@ -292,6 +309,10 @@ __device__ inline TileWalk tile_walk(const SolveDev& d, int blk) {
   return w;
 }
 __device__ inline int walk_tile(const SolveDev& d, const TileWalk& w, int u) {
+  if (d.wz > 0) {
+    const int col = u / d.nz, z = u - col * d.nz;
+    return z * d.wtp + w.g * d.wc + col;
+  }
   if (d.wtp <= 0) return (int)(w.lo + u);
   const int zc = d.nz * d.wc;
   const int j = u / zc, rem = u - j * zc;

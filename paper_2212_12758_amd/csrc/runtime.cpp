@@ -225,6 +225,7 @@ struct Plan {
   int sk_reg = 0;              // SRHT accumulators in registers (k_update)
   int tgroups = 1;             // XCD groups of the streaming blocks
   int wtp = 0, wc = 0, wpen = 0;   // pencil walk of the streaming blocks (wtp = 0: linear)
+  int wz = 0;                      // z-march walk: tiles per block (0: not used)
   size_t bytes = 0;
   // offsets in the workspace
   size_t oV, oW, oH, oEta, oWn, oCoef, oS, oPart, oNpart, oSk, oCnt, oStatus, oRows, oDense, oCf, oInfoHost;
@@ -309,13 +310,24 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
   // group work on at least 4 consecutive planes of their pencil at a time, so
   // a tile's z-neighbours are being read by sibling blocks of the same XCD
   // (a whole plane per vector no longer fits its L2)
-  P.wtp = P.wc = P.wpen = 0;
+  P.wtp = P.wc = P.wpen = P.wz = 0;
   {
     const long long plane = (long long)A->nx * A->ny;   // rows per z-plane
     const long long rows_tile = tile / nrhs;
     const long long tile_bytes = tile * esize;
-    if (A->op == OP_STENCIL && !sign && A->nz > 1 && P.tgroups == 8 && plane % rows_tile == 0 &&
-        plane * nrhs * esize > (256LL << 10)) {
+    const bool big_planes = A->op == OP_STENCIL && !sign && A->nz > 1 && P.tgroups == 8 &&
+                            plane % rows_tile == 0 && plane * nrhs * esize > (256LL << 10);
+    // z-march when the tiles of a plane split evenly over the 8 groups (each
+    // block then reads its tiles' z-neighbours as its previous and next
+    // tiles; the pencils below keep 4 planes per group in flight, whose
+    // z-neighbours no longer all stay in L2 while the window streams past)
+    if (big_planes && (plane / rows_tile) % 8 == 0) {
+      const long long tp = plane / rows_tile, cols = tp / 8;
+      const long long per_blk = (cols * A->nz + P.nblk / 8 - 1) / (P.nblk / 8);
+      P.wtp = (int)tp;
+      P.wc = (int)cols;
+      P.wz = (int)per_blk;
+    } else if (big_planes) {
       const long long tp = plane / rows_tile;
       long long c = tp / 8;
       while (c > 1 && (c * tile_bytes > (256LL << 10) || 4 * c > P.nblk / 8)) c /= 2;
@@ -647,6 +659,7 @@ void build_descs(const Plan& P, char* ws, const int* rows, SolveDev& d, DenseDev
   d.wtp = P.wtp;
   d.wc = P.wc;
   d.wpen = P.wpen;
+  d.wz = P.wz;
   d.srht_rows = rows;
   if (d.sketch == SK_SRHT) {
     d.key_a = sm64_out(p.seed, 1);
