@@ -75,6 +75,10 @@ hipError_t wh_set_attributes();
 // steps against WH_THRESH (the threshold of Section 5.1.3).
 constexpr int WH_EVERY = 5;
 constexpr double WH_THRESH = 1000.0;
+// Internal status of enqueue_solve (never returned through the C ABI): an
+// FP32 attempt under FAB_PREC_AUTO stopped at its whitening trigger, since
+// its result could not be accepted (the caller recomputes with FP64).
+constexpr int RC_RERUN_FP64 = 100;
 size_t lsqr_state_stride(int m);
 size_t lsqr_pass_lds(int m, int nrhs);
 hipError_t gather_cols(const ColPtrs& src, int logg, long long n, double* dst, hipStream_t st);
@@ -774,6 +778,11 @@ int enqueue_solve(Plan& P, char* ws, hipStream_t st, const int* rows, double* hi
       return FAB_EDEVICE;
     if (!*host_flag) continue;
     P.whitened_at = i;
+    // an FP32 basis whitened here carries up to 2^-24 kappa(R) > 2^-24
+    // WH_THRESH of rounding (the bound collect_info reports): when that
+    // alone fails the FP64 rerun test, the rest of this attempt is wasted
+    if (P.p.prec == FAB_PREC_AUTO && P.esize == 4 && !(std::ldexp(1.0, -24) * WH_THRESH <= P.p.tol / 2))
+      return RC_RERUN_FP64;
     B(FAB_K_OTHER);
     e = wh_whiten(d, g, P.esize, i, st);
     E();
@@ -990,17 +999,22 @@ hipError_t scatter_block(const Request& r, hipStream_t st) {
 void retire_locked(fab_ctx ctx, Request& r) {
   if (r.worker.joinable()) r.worker.join();
   const bool blk = !r.members.empty();
-  if (r.worker_rc != FAB_OK) {
+  const bool stopped = r.worker_rc == RC_RERUN_FP64;   // FP32 attempt stopped at its whitening
+  if (r.worker_rc != FAB_OK && !stopped) {
     // the worker could not issue the phase: wait for what it did issue, then
     // complete the request (or the block's members) with its error
     hipStreamSynchronize(ctx->pool[r.stream_idx]);
     r.status = r.worker_rc;
+  } else if (stopped) {
+    r.status = FAB_ENOMEM;   // unless the FP64 rerun below is queued
+    r.info.assign(r.plan.nrhs, fab_info{});
   } else {
     r.status = collect_info(r.plan, r.host_info, r.info);
   }
   // the precision decision is taken on the solve's result, as in blocking
   // calls (a refinement's result is not judged again)
-  if (r.worker_rc == FAB_OK && !r.fell_back && !r.refined && needs_fp64_rerun(r.plan, r.status, r.info)) {
+  if ((stopped || (r.worker_rc == FAB_OK && needs_fp64_rerun(r.plan, r.status, r.info))) && !r.fell_back &&
+      !r.refined) {
     // FAB_PREC_AUTO: queue the request again, first in line, with an FP64 basis
     Plan P2;
     const fab_func f2 = plan_func(r.plan);
@@ -1182,7 +1196,8 @@ void admit_locked(fab_ctx ctx) {
         int wrc = enqueue_solve(rp->plan, ws, st, rows, rp->host_info, nullptr,
                                 rp->plan.whiten ? rp->flag_host : nullptr);
         if (wrc == FAB_OK && blk && scatter_block(*rp, st) != hipSuccess) wrc = FAB_EDEVICE;
-        if (wrc == FAB_OK && hipEventRecord(rp->done_ev, st) != hipSuccess) wrc = FAB_EDEVICE;
+        if ((wrc == FAB_OK || wrc == RC_RERUN_FP64) && hipEventRecord(rp->done_ev, st) != hipSuccess)
+          wrc = FAB_EDEVICE;
         rp->worker_rc = wrc;
         rp->worker_done.store(true);
       });
@@ -1601,7 +1616,7 @@ static int solve_impl(fab_ctx ctx, fab_matrix A, const double* b, int nrhs, fab_
       const int rc2 = collect_info(P, ctx->host_info, fi);
       if (rc == FAB_OK) rc = rc2;
     }
-    if (attempt == 0 && needs_fp64_rerun(P, rc, fi)) {
+    if (attempt == 0 && (rc == RC_RERUN_FP64 || needs_fp64_rerun(P, rc, fi))) {
       // FAB_PREC_AUTO: recompute the whole request with an FP64 basis
       if (!ws_fixed) {
         std::lock_guard<std::mutex> lk(ctx->mu);

@@ -83,10 +83,16 @@ def test_whitening_restores_the_basis(ctx):
     # solve lands 2e-6 off), and the reported estimate says so; with
     # FAB_PREC_AUTO the request is recomputed with an FP64 basis
     assert info32[0]["round_est"] >= 2.0 ** -24 * 1000 and info32[0]["err_est"] >= info32[0]["round_est"]
+    # (the FP32 attempt stops at its trigger, before the whitening)
     print("case whiten rgg4096 auto", flush=True)
     outa, infoa = ctx.solve(A, _dev(b), w.f, _params(w, "auto", tol=1e-6))
     assert infoa[0]["fell_back"] == 1 and infoa[0]["prec_used"] == 2
     assert krylov.relerr(outa.cpu().numpy(), fm) < 1e-6
+    # served: the same decisions and the same result
+    os_ = _dev(np.zeros(w.n))
+    infos = ctx.submit(A, _dev(b), w.f, _params(w, "auto", tol=1e-6), os_).wait()[0]
+    assert infos["fell_back"] == 1 and infos["whitened_at"] == infoa[0]["whitened_at"]
+    assert np.array_equal(os_.cpu().numpy(), outa.cpu().numpy())
     A.destroy()
 
 
