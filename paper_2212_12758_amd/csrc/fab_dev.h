@@ -139,6 +139,7 @@ struct LsqrDev {
   double* st;            // [nrhs][stride] per-rhs vectors and scalars
   long long stride;
   int* alldone;          // every rhs stopped: remaining launches return
+  double* rinv;          // [nrhs][2][m*m]: X = R_m^{-1} (upper, ld m_used) and X^T
   int nblk, maxit;
   double tol;            // stop when ||M^T r|| <= tol ||M||_F ||r|| (Paige-Saunders)
 };

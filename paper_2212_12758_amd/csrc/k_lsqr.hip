@@ -80,71 +80,6 @@ __device__ void upper_t_solve_any(int n, const double* U, long long ldu, const d
   else wave_upper_t_solve<8>(n, U, ldu, z, x);
 }
 
-// The same substitutions on a packed upper triangle (column c at c(c+1)/2,
-// rows 0..c), for factors too large to keep whole in LDS; the order of
-// operations is that of the full-storage versions.
-template <int R>
-__device__ void wave_upper_solve_packed(int n, const double* Up, const double* z, double* x) {
-  const int lane = threadIdx.x & 63;
-  double y[R];
-#pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const int r = lane + 64 * u;
-    y[u] = r < n ? z[r] : 0.0;
-  }
-  for (int j = n - 1; j >= 0; --j) {
-    const int uj = j >> 6;
-    double src = y[0];
-#pragma unroll
-    for (int u = 1; u < R; ++u)
-      if (uj == u) src = y[u];
-    const int cb = j * (j + 1) / 2;
-    const double ujj = Up[cb + j];
-    const double xj = ujj != 0.0 ? readlane_d(src, j & 63) / ujj : 0.0;
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int r = lane + 64 * u;
-      if (r == j) y[u] = xj;
-      else if (r < j) y[u] -= Up[cb + r] * xj;
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const int r = lane + 64 * u;
-    if (r < n) x[r] = y[u];
-  }
-}
-template <int R>
-__device__ void wave_upper_t_solve_packed(int n, const double* Up, const double* z, double* x) {
-  const int lane = threadIdx.x & 63;
-  double y[R];
-#pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const int r = lane + 64 * u;
-    y[u] = r < n ? z[r] : 0.0;
-  }
-  for (int j = 0; j < n; ++j) {
-    const int uj = j >> 6;
-    double src = y[0];
-#pragma unroll
-    for (int u = 1; u < R; ++u)
-      if (uj == u) src = y[u];
-    const double ujj = Up[j * (j + 1) / 2 + j];
-    const double xj = ujj != 0.0 ? readlane_d(src, j & 63) / ujj : 0.0;
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int r = lane + 64 * u;
-      if (r == j) y[u] = xj;
-      else if (r > j && r < n) y[u] -= Up[r * (r + 1) / 2 + j] * xj;
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const int r = lane + 64 * u;
-    if (r < n) x[r] = y[u];
-  }
-}
-
 __device__ inline double bsum256(double v, double* sh) {
   v = wave_sum_all(v);
   __syncthreads();
@@ -158,13 +93,6 @@ __device__ inline double bsum256(double v, double* sh) {
 }  // namespace
 
 size_t lsqr_state_stride(int m) { return (size_t)5 * (m + 1) + LS_NSCAL; }
-// R_m is staged in LDS by the step kernel up to this order (its triangular
-// solves are sequential in the column index, so each access is latency-bound)
-constexpr int STEP_LDS_M = 140;
-size_t lsqr_step_lds(int m) { return m <= STEP_LDS_M ? (size_t)m * m * 8 : 0; }
-// R_m packed (upper triangle only) in LDS above STEP_LDS_M, while it fits
-size_t lsqr_step_lds_packed(int m) { return (size_t)m * (m + 1) / 2 * 8; }
-bool lsqr_step_packed(int m) { return m > STEP_LDS_M && m <= 199 && lsqr_step_lds_packed(m) <= 160 * 1024; }
 size_t lsqr_pass_lds(int m, int nrhs) { return (size_t)4 * nrhs * (m + 1) * 8; }
 
 // Stream the basis once.  first: u~ = u_m / eta_m (the right-hand side
@@ -269,15 +197,90 @@ __global__ void __launch_bounds__(256) k_lsqr_pass(SolveDev d, LsqrDev L, int fi
     L.part[(long long)blockIdx.x * nr * m1 + x] = (acc[x] + acc[nr * m1 + x]) + (acc[2 * nr * m1 + x] + acc[3 * nr * m1 + x]);
 }
 
-// One LSQR step per rhs (first: the initialisation).  RL: R_m is copied to
-// LDS (a compile-time choice, so that its accesses compile to LDS loads).
-// RL: 0 R_m read from global memory, 1 R_m staged in LDS, 2 its upper
-// triangle staged packed in LDS.
-template <int RL>
+// X = R_m^{-1} and X^T for the LSQR steps, computed once per refinement, so
+// that each step applies the preconditioner as two triangular matrix-vector
+// products spread over the block instead of two sequential substitutions on
+// one wave.  Column j of X solves R x = e_j: x_i /= r_ii, then
+// x[0..i-1] -= R[0..i-1, i] x_i for i = j, j-1, .., 0 (column-oriented back
+// substitution), one wave per column, each lane holding rows lane + 64 u, the
+// next column of R loaded while the current one is applied.  LSQR then runs
+// on M = V_m X, and the refined y = X z, so the iterates and the result use
+// the same operator.
+constexpr int RINV_RMAX = 8;   // rows per lane: m_used <= 512
+__global__ void __launch_bounds__(256) k_lsqr_rinv(SolveDev d, DenseDev g, LsqrDev L) {
+  const int q = blockIdx.x, lane = threadIdx.x & 63;
+  const int mu = d.status[4 + 2 * q];
+  const int brk = d.status[5 + 2 * q];
+  if (brk || mu == 0 || g.ls_mode == 2) return;
+  const int j = blockIdx.y * 4 + wave_id();
+  if (j >= mu) return;   // (no block barrier below)
+  const int m = d.m;
+  const double* R = g.base + (long long)q * g.stride + g.oR;   // ld mu
+  double* X = L.rinv + (long long)q * 2 * m * m;
+  double* XT = X + (long long)m * m;
+  double x[RINV_RMAX], rc[RINV_RMAX], rn[RINV_RMAX];
+#pragma unroll
+  for (int u = 0; u < RINV_RMAX; ++u) {
+    const int r = lane + 64 * u;
+    x[u] = r == j ? 1.0 : 0.0;
+    rc[u] = r <= j ? R[r + (long long)j * mu] : 0.0;
+  }
+  for (int i = j; i >= 0; --i) {
+#pragma unroll
+    for (int u = 0; u < RINV_RMAX; ++u) {
+      const int r = lane + 64 * u;
+      rn[u] = (i > 0 && r <= i - 1) ? R[r + (long long)(i - 1) * mu] : 0.0;
+    }
+    const int ui = i >> 6, li = i & 63;
+    double xs = x[0], rs = rc[0];
+#pragma unroll
+    for (int u = 1; u < RINV_RMAX; ++u)
+      if (ui == u) { xs = x[u]; rs = rc[u]; }
+    const double xi = readlane_d(xs, li) / readlane_d(rs, li);
+#pragma unroll
+    for (int u = 0; u < RINV_RMAX; ++u) {
+      const int r = lane + 64 * u;
+      if (r == i) x[u] = xi;
+      else if (r < i) x[u] -= rc[u] * xi;
+    }
+#pragma unroll
+    for (int u = 0; u < RINV_RMAX; ++u) rc[u] = rn[u];
+  }
+#pragma unroll
+  for (int u = 0; u < RINV_RMAX; ++u) {
+    const int r = lane + 64 * u;
+    if (r < mu) {
+      X[r + (long long)j * mu] = r <= j ? x[u] : 0.0;
+      XT[j + (long long)r * mu] = r <= j ? x[u] : 0.0;
+    }
+  }
+}
+
+// out = X^T c (first == false: X c) for the block's threads, X upper
+// triangular (ld mu, XT = its transpose): row i of the result sums over the
+// k <= i (X^T) or k >= i (X) of one column-major operand, so consecutive
+// threads read consecutive words.
+__device__ inline void rinv_apply(int mu, const double* __restrict__ A, bool lower, const double* c, double* out) {
+  for (int i = threadIdx.x; i < mu; i += 256) {
+    const int k0 = lower ? 0 : i, k1 = lower ? i + 1 : mu;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
+      s0 += A[i + (long long)k * mu] * c[k];
+      s1 += A[i + (long long)(k + 1) * mu] * c[k + 1];
+      s2 += A[i + (long long)(k + 2) * mu] * c[k + 2];
+      s3 += A[i + (long long)(k + 3) * mu] * c[k + 3];
+    }
+    for (; k < k1; ++k) s0 += A[i + (long long)k * mu] * c[k];
+    out[i] = (s0 + s1) + (s2 + s3);
+  }
+}
+
+// One LSQR step per rhs (first: the initialisation).  The preconditioner is
+// applied through X = R_m^{-1} (k_lsqr_rinv).
 __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrDev L, int first) {
   if (*L.alldone) return;
   const int q = blockIdx.x, tid = threadIdx.x;
-  extern __shared__ double rlds[];
   __shared__ double sh[8];
   const int nr = d.nrhs, m = d.m, m1 = m + 1;
   double* st = L.st + (long long)q * L.stride;
@@ -289,8 +292,6 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
   double* sc = st + 5 * m1;
   const int mu = d.status[4 + 2 * q];
   const int brk = d.status[5 + 2 * q];
-  const double* ws = g.base + (long long)q * g.stride;
-  const double* Rg = ws + g.oR;                      // R_m, ld m_used
   const double* eta = d.eta + (long long)q * m1;
   if (first) {
     if (tid == 0) {
@@ -304,38 +305,6 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
     __syncthreads();
   }
   if (sc[LS_DONE] != 0.0) return;
-  if (RL == 1) {
-    // sixteen loads in flight per thread (visible after the barrier below)
-    const int n2 = mu * mu;
-    int x = tid;
-    for (; x + 15 * 256 < n2; x += 16 * 256) {
-      double t[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) t[u] = Rg[x + u * 256];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) rlds[x + u * 256] = t[u];
-    }
-    for (; x < n2; x += 256) rlds[x] = Rg[x];
-  } else if (RL == 2) {
-    // the upper triangle, column c at c(c+1)/2 (eight loads in flight)
-    const int n2 = mu * mu;
-    int x = tid;
-    for (; x + 7 * 256 < n2; x += 8 * 256) {
-      double t[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] = Rg[x + u * 256];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int r = (x + u * 256) % mu, c = (x + u * 256) / mu;
-        if (r <= c) rlds[c * (c + 1) / 2 + r] = t[u];
-      }
-    }
-    for (; x < n2; x += 256) {
-      const int r = x % mu, c = x / mu;
-      if (r <= c) rlds[c * (c + 1) / 2 + r] = Rg[x];
-    }
-  }
-  const double* R = RL == 1 ? (const double*)rlds : Rg;
   // reduce the pass partials in a fixed order: thread (group g, slot j)
   // sums blocks [g nb / G, (g+1) nb / G) in order, eight loads in flight,
   // then the G group sums are added in order
@@ -381,14 +350,8 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
   // s = R^{-T} (d / eta) / beta  ->  cf (scratch)
   for (int j = tid; j < mu; j += 256) cf[j] = beta > 0.0 ? tmp[j] / (eta[j] * beta) : 0.0;
   __syncthreads();
-  if (tid < 64) {
-    if constexpr (RL == 2) {
-      if (mu <= 128) wave_upper_t_solve_packed<2>(mu, rlds, cf, tmp);
-      else wave_upper_t_solve_packed<4>(mu, rlds, cf, tmp);
-    } else {
-      upper_t_solve_any(mu, R, mu, cf, tmp);
-    }
-  }
+  const double* Xq = L.rinv + (long long)q * 2 * m * m;   // X = R^{-1}, then X^T
+  rinv_apply(mu, Xq + (long long)m * m, true, cf, tmp);    // tmp = R^{-T} cf
   __syncthreads();
   // alpha v = s - beta v_old
   double p2 = 0.0;
@@ -441,14 +404,7 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
   }
   __syncthreads();
   // coefficients of the next pass: cf = R^{-1} v / eta, a = alpha / beta
-  if (tid < 64) {
-    if constexpr (RL == 2) {
-      if (mu <= 128) wave_upper_solve_packed<2>(mu, rlds, v, tmp);
-      else wave_upper_solve_packed<4>(mu, rlds, v, tmp);
-    } else {
-      upper_solve_any(mu, R, mu, v, tmp);
-    }
-  }
+  rinv_apply(mu, Xq, false, v, tmp);
   __syncthreads();
   for (int j = tid; j < m; j += 256) cf[j] = j < mu ? tmp[j] / eta[j] : 0.0;
   if (tid == 0) sc[LS_A] = beta > 0.0 ? alpha / beta : 0.0;
@@ -480,7 +436,7 @@ __global__ void __launch_bounds__(256) k_lsqr_finish(SolveDev d, DenseDev g, Lsq
   }
   if (brk || mu == 0 || g.ls_mode == 2) return;
   __shared__ double y[512];
-  if (tid < 64) upper_solve_any(mu, ws + g.oR, mu, st + 2 * m1, y);
+  rinv_apply(mu, L.rinv + (long long)q * 2 * m * m, false, st + 2 * m1, y);   // y = X z
   __syncthreads();
   double* yout = ws + g.oVec + 2 * (long long)m;
   for (int j = tid; j < mu; j += 256) yout[j] = y[j];
@@ -734,12 +690,7 @@ void pass_launch_t(const SolveDev& d, const LsqrDev& L, hipStream_t st, int firs
   else hipLaunchKernelGGL((k_lsqr_pass<T, false>), dim3(L.nblk), dim3(256), lds, st, d, L, first);
 }
 void step_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, hipStream_t st, int first) {
-  if (d.m <= STEP_LDS_M)
-    hipLaunchKernelGGL(k_lsqr_step<1>, dim3(d.nrhs), dim3(256), lsqr_step_lds(d.m), st, d, g, L, first);
-  else if (lsqr_step_packed(d.m))
-    hipLaunchKernelGGL(k_lsqr_step<2>, dim3(d.nrhs), dim3(256), lsqr_step_lds_packed(d.m), st, d, g, L, first);
-  else
-    hipLaunchKernelGGL(k_lsqr_step<0>, dim3(d.nrhs), dim3(256), 0, st, d, g, L, first);
+  hipLaunchKernelGGL(k_lsqr_step, dim3(d.nrhs), dim3(256), 0, st, d, g, L, first);
 }
 void lsqr_pass_launch(const SolveDev& d, const LsqrDev& L, int esize, hipStream_t st, int first) {
   const size_t lds = lsqr_pass_lds(d.m, d.nrhs);
@@ -750,6 +701,7 @@ void lsqr_pass_launch(const SolveDev& d, const LsqrDev& L, int esize, hipStream_
 
 // Initialisation (u = v_{m+1}, first bidiagonalisation step).
 hipError_t lsqr_begin(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st) {
+  hipLaunchKernelGGL(k_lsqr_rinv, dim3(d.nrhs, (d.m + 3) / 4), dim3(256), 0, st, d, g, L);
   lsqr_pass_launch(d, L, esize, st, 1);
   step_launch(d, g, L, st, 1);
   hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
@@ -803,10 +755,6 @@ hipError_t lsqr_set_attributes() {
     if ((r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024)) != hipSuccess) e = r;
   if ((r = hipFuncSetAttribute((const void*)k_vgram_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
                                GR_MAXC * GR_MAXC * 8)) != hipSuccess) e = r;
-  if ((r = hipFuncSetAttribute((const void*)k_lsqr_step<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lsqr_step_lds(STEP_LDS_M))) != hipSuccess) e = r;
-  if ((r = hipFuncSetAttribute((const void*)k_lsqr_step<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               160 * 1024)) != hipSuccess) e = r;
   return e;
 }
 

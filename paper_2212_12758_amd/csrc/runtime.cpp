@@ -219,7 +219,7 @@ struct Plan {
   size_t oGpart = 0, oGflag = 0;
   size_t oWflag = 0;           // whitening trigger flag
   int lnblk = 0;               // LSQR pass blocks
-  size_t oLu = 0, oLpart = 0, oLst = 0, oLflag = 0;
+  size_t oLu = 0, oLpart = 0, oLst = 0, oLflag = 0, oLri = 0;
   // derived
   int LT = 12, R = 0, logR = 0, ntiles = 0, nblk = 0, nred = 0;
   long long ldv = 0;
@@ -415,6 +415,7 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
       P.oLpart = take((size_t)P.lnblk * nrhs * (m + 1) * 8);
       P.oLst = take((size_t)nrhs * lsqr_state_stride(m) * 8);
       P.oLflag = take(256);
+      P.oLri = take((size_t)nrhs * 2 * m * m * 8);   // R_m^{-1} and its transpose
     }
   }
   P.gram = p.ls_mode == FAB_LS_GRAM && nrhs == 1 && m + 1 <= 128;
@@ -899,6 +900,7 @@ int enqueue_refine(Plan& P, char* ws, hipStream_t st, const int* rows, double* h
   L.st = (double*)(ws + P.oLst);
   L.stride = (long long)lsqr_state_stride(P.p.m);
   L.alldone = (int*)(ws + P.oLflag);
+  L.rinv = (double*)(ws + P.oLri);
   L.nblk = P.lnblk;
   L.maxit = P.p.ls_maxit > 0 ? P.p.ls_maxit : ((P.bg || P.whitened_at) ? 128 : 32);
   L.tol = P.p.tol / 10;
