@@ -261,18 +261,27 @@ __global__ void __launch_bounds__(256) k_lsqr_rinv(SolveDev d, DenseDev g, LsqrD
 // k <= i (X^T) or k >= i (X) of one column-major operand, so consecutive
 // threads read consecutive words.
 __device__ inline void rinv_apply(int mu, const double* __restrict__ A, bool lower, const double* c, double* out) {
+  // row i per thread; 16 entries of the row (and of c) loaded per round
+  // before they are used, so that a row of mu entries takes mu / 16 load
+  // latencies rather than mu / 4; eight partial sums in a fixed order
   for (int i = threadIdx.x; i < mu; i += 256) {
     const int k0 = lower ? 0 : i, k1 = lower ? i + 1 : mu;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    double s[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] = 0.0;
     int k = k0;
-    for (; k + 4 <= k1; k += 4) {
-      s0 += A[i + (long long)k * mu] * c[k];
-      s1 += A[i + (long long)(k + 1) * mu] * c[k + 1];
-      s2 += A[i + (long long)(k + 2) * mu] * c[k + 2];
-      s3 += A[i + (long long)(k + 3) * mu] * c[k + 3];
+    for (; k + 16 <= k1; k += 16) {
+      double a[16], cc[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        a[u] = A[i + (long long)(k + u) * mu];
+        cc[u] = c[k + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s[u & 7] += a[u] * cc[u];
     }
-    for (; k < k1; ++k) s0 += A[i + (long long)k * mu] * c[k];
-    out[i] = (s0 + s1) + (s2 + s3);
+    for (; k < k1; ++k) s[0] += A[i + (long long)k * mu] * c[k];
+    out[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   }
 }
 
@@ -306,7 +315,7 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
   }
   if (sc[LS_DONE] != 0.0) return;
   // reduce the pass partials in a fixed order: thread (group g, slot j)
-  // sums blocks [g nb / G, (g+1) nb / G) in order, eight loads in flight,
+  // sums blocks [g nb / G, (g+1) nb / G) in order, up to 64 loads in flight,
   // then the G group sums are added in order
   {
     __shared__ double gsum[256];
@@ -318,14 +327,14 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
       if (j < ns && grp < G) {
         const int slot = j < mu ? j : m;
         const int b0 = (int)((long long)grp * L.nblk / G), b1 = (int)((long long)(grp + 1) * L.nblk / G);
-        // 32 loads in flight (the sum itself stays in block order)
+        // 64 loads in flight (the sum itself stays in block order)
         int b = b0;
-        for (; b + 32 <= b1; b += 32) {
-          double t[32];
+        for (; b + 64 <= b1; b += 64) {
+          double t[64];
 #pragma unroll
-          for (int u = 0; u < 32; ++u) t[u] = L.part[((long long)(b + u) * nr + q) * m1 + slot];
+          for (int u = 0; u < 64; ++u) t[u] = L.part[((long long)(b + u) * nr + q) * m1 + slot];
 #pragma unroll
-          for (int u = 0; u < 32; ++u) a += t[u];
+          for (int u = 0; u < 64; ++u) a += t[u];
         }
         for (; b + 8 <= b1; b += 8) {
           double t[8];
