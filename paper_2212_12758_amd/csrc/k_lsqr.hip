@@ -206,7 +206,9 @@ __global__ void __launch_bounds__(256) k_lsqr_pass(SolveDev d, LsqrDev L, int fi
 // next column of R loaded while the current one is applied.  LSQR then runs
 // on M = V_m X, and the refined y = X z, so the iterates and the result use
 // the same operator.
-constexpr int RINV_RMAX = 8;   // rows per lane: m_used <= 512
+// RINV_RMAX rows per lane: m <= 64 RINV_RMAX (instances for 2, 4 and 8, so
+// that a step touches only the registers its rows need)
+template <int RINV_RMAX>
 __global__ void __launch_bounds__(256) k_lsqr_rinv(SolveDev d, DenseDev g, LsqrDev L) {
   const int q = blockIdx.x, lane = threadIdx.x & 63;
   const int mu = d.status[4 + 2 * q];
@@ -710,7 +712,10 @@ void lsqr_pass_launch(const SolveDev& d, const LsqrDev& L, int esize, hipStream_
 
 // Initialisation (u = v_{m+1}, first bidiagonalisation step).
 hipError_t lsqr_begin(const SolveDev& d, const DenseDev& g, const LsqrDev& L, int esize, hipStream_t st) {
-  hipLaunchKernelGGL(k_lsqr_rinv, dim3(d.nrhs, (d.m + 3) / 4), dim3(256), 0, st, d, g, L);
+  const dim3 rg(d.nrhs, (d.m + 3) / 4);
+  if (d.m <= 128) hipLaunchKernelGGL(k_lsqr_rinv<2>, rg, dim3(256), 0, st, d, g, L);
+  else if (d.m <= 256) hipLaunchKernelGGL(k_lsqr_rinv<4>, rg, dim3(256), 0, st, d, g, L);
+  else hipLaunchKernelGGL(k_lsqr_rinv<8>, rg, dim3(256), 0, st, d, g, L);
   lsqr_pass_launch(d, L, esize, st, 1);
   step_launch(d, g, L, st, 1);
   hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
