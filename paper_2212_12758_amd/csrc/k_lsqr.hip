@@ -258,33 +258,52 @@ __global__ void __launch_bounds__(256) k_lsqr_rinv(SolveDev d, DenseDev g, LsqrD
   }
 }
 
-// out = X^T c (first == false: X c) for the block's threads, X upper
-// triangular (ld mu, XT = its transpose): row i of the result sums over the
-// k <= i (X^T) or k >= i (X) of one column-major operand, so consecutive
-// threads read consecutive words.
-__device__ inline void rinv_apply(int mu, const double* __restrict__ A, bool lower, const double* c, double* out) {
-  // row i per thread; 16 entries of the row (and of c) loaded per round
-  // before they are used, so that a row of mu entries takes mu / 16 load
-  // latencies rather than mu / 4; eight partial sums in a fixed order
-  for (int i = threadIdx.x; i < mu; i += 256) {
-    const int k0 = lower ? 0 : i, k1 = lower ? i + 1 : mu;
-    double s[8];
+// Entries [ka, kb) of row i of A (column-major, ld mu) times c (in LDS): 16
+// entries of the row loaded per round before they are used, eight partial
+// sums in a fixed order.
+__device__ inline double rinv_row(const double* __restrict__ A, int mu, int i, const double* cs, int ka, int kb) {
+  double s[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] = 0.0;
-    int k = k0;
-    for (; k + 16 <= k1; k += 16) {
-      double a[16], cc[16];
+  for (int u = 0; u < 8; ++u) s[u] = 0.0;
+  int k = ka;
+  for (; k + 16 <= kb; k += 16) {
+    double a[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        a[u] = A[i + (long long)(k + u) * mu];
-        cc[u] = c[k + u];
-      }
+    for (int u = 0; u < 16; ++u) a[u] = A[i + (long long)(k + u) * mu];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) s[u & 7] += a[u] * cc[u];
-    }
-    for (; k < k1; ++k) s[0] += A[i + (long long)k * mu] * c[k];
-    out[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    for (int u = 0; u < 16; ++u) s[u & 7] += a[u] * cs[k + u];
   }
+  for (; k < kb; ++k) s[0] += A[i + (long long)k * mu] * cs[k];
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+// out = X^T c (lower: the transpose, stored) or X c, X upper triangular: row
+// i sums over k <= i (lower) or k >= i.  c is staged in LDS first; with at
+// most 128 rows two threads share a row (the two halves of its range, added
+// in that order).  Every thread of the block calls it (it has barriers);
+// out must not alias c.
+__device__ inline void rinv_apply(int mu, const double* __restrict__ A, bool lower, const double* c, double* out) {
+  __shared__ double cs[512];
+  __shared__ double hsum[128];
+  const int tid = threadIdx.x;
+  for (int k = tid; k < mu; k += 256) cs[k] = c[k];
+  __syncthreads();
+  if (mu <= 128) {
+    const int i = tid & 127, h = tid >> 7;
+    double part = 0.0;
+    if (i < mu) {
+      const int k0 = lower ? 0 : i, k1 = lower ? i + 1 : mu;
+      const int mid = k0 + (k1 - k0) / 2;
+      part = h ? rinv_row(A, mu, i, cs, mid, k1) : rinv_row(A, mu, i, cs, k0, mid);
+    }
+    if (h) hsum[i] = part;
+    __syncthreads();
+    if (!h && i < mu) out[i] = part + hsum[i];
+  } else {
+    for (int i = tid; i < mu; i += 256)
+      out[i] = rinv_row(A, mu, i, cs, lower ? 0 : i, lower ? i + 1 : mu);
+  }
+  __syncthreads();
 }
 
 // One LSQR step per rhs (first: the initialisation).  The preconditioner is
