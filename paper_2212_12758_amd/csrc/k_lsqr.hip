@@ -334,7 +334,10 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
     for (int j = tid; j < m1; j += 256) x[j] = 0.0;
     __syncthreads();
   }
-  if (sc[LS_DONE] != 0.0) return;
+  if (sc[LS_DONE] != 0.0) {
+    if (nr == 1 && tid == 0) *L.alldone = 1;   // one rhs: no separate all-done launch
+    return;
+  }
   // reduce the pass partials in a fixed order: thread (group g, slot j)
   // sums blocks [g nb / G, (g+1) nb / G) in order, up to 64 loads in flight,
   // then the G group sums are added in order
@@ -432,6 +435,7 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
       }
     }
   }
+  if (nr == 1 && tid == 0 && sc[LS_DONE] != 0.0) *L.alldone = 1;
   __syncthreads();
   // coefficients of the next pass: cf = R^{-1} v / eta, a = alpha / beta
   rinv_apply(mu, Xq, false, v, tmp);
@@ -440,7 +444,8 @@ __global__ void __launch_bounds__(256) k_lsqr_step(SolveDev d, DenseDev g, LsqrD
   if (tid == 0) sc[LS_A] = beta > 0.0 ? alpha / beta : 0.0;
 }
 
-// All rhs stopped?  (one thread; keeps the remaining launches empty)
+// All rhs stopped?  (one thread; keeps the remaining launches empty.  With
+// one rhs the step kernel sets the flag itself and this is not launched.)
 __global__ void k_lsqr_alldone(SolveDev d, LsqrDev L) {
   if (threadIdx.x != 0 || *L.alldone) return;
   const int m1 = d.m + 1;
@@ -737,7 +742,7 @@ hipError_t lsqr_begin(const SolveDev& d, const DenseDev& g, const LsqrDev& L, in
   else hipLaunchKernelGGL(k_lsqr_rinv<8>, rg, dim3(256), 0, st, d, g, L);
   lsqr_pass_launch(d, L, esize, st, 1);
   step_launch(d, g, L, st, 1);
-  hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
+  if (d.nrhs > 1) hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
   return hipGetLastError();
 }
 
@@ -747,7 +752,7 @@ hipError_t lsqr_iterate(const SolveDev& d, const DenseDev& g, const LsqrDev& L, 
   for (int it = 0; it < count; ++it) {
     lsqr_pass_launch(d, L, esize, st, 0);
     step_launch(d, g, L, st, 0);
-    hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
+    if (d.nrhs > 1) hipLaunchKernelGGL(k_lsqr_alldone, dim3(1), dim3(64), 0, st, d, L);
   }
   return hipGetLastError();
 }
