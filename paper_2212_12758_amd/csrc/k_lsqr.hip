@@ -94,6 +94,17 @@ __device__ inline double bsum256(double v, double* sh) {
 
 size_t lsqr_state_stride(int m) { return (size_t)5 * (m + 1) + LS_NSCAL; }
 size_t lsqr_pass_lds(int m, int nrhs) { return (size_t)4 * nrhs * (m + 1) * 8; }
+size_t lsqr_pass1_lds(int m, int ch, int esize) {
+  return ((size_t)m * (ch + 1) * esize + 7) / 8 * 8 + (size_t)ch * 8 + (size_t)m * 8;
+}
+// Chunk of the one-read pass (0: the two-read pass): one rhs, m + 1 <= 256,
+// and the staged tile within 80 KB, so that two blocks share a CU.
+int lsqr_pass1_chunk(int m, int nrhs, int esize) {
+  if (nrhs != 1 || m + 1 > 256) return 0;
+  if (lsqr_pass1_lds(m, 128, esize) <= 80 * 1024) return 128;
+  if (lsqr_pass1_lds(m, 64, esize) <= 80 * 1024) return 64;
+  return 0;
+}
 
 // Stream the basis once.  first: u~ = u_m / eta_m (the right-hand side
 // v_{m+1}); else u~ <- sum_j cf_j u_j - a u~.  Partials per block and rhs:
@@ -195,6 +206,97 @@ __global__ void __launch_bounds__(256) k_lsqr_pass(SolveDev d, LsqrDev L, int fi
   __syncthreads();
   for (int x = tid; x < nr * m1; x += 256)
     L.part[(long long)blockIdx.x * nr * m1 + x] = (acc[x] + acc[nr * m1 + x]) + (acc[2 * nr * m1 + x] + acc[3 * nr * m1 + x]);
+}
+
+// One-read pass for one rhs: each chunk of CH elements of every basis
+// vector u_0..u_{m-1} is staged once in LDS (row j at j * (CH + 1): odd
+// stride, so the column reads of the dots spread over the banks); thread t
+// forms u~ on element t from the staged values (the same operations, in the
+// same order, as k_lsqr_pass), then thread j accumulates u_j^T u~ over the
+// chunk (thread m: ||u~||^2), so the basis is read from memory once per pass
+// instead of twice.  Per-block partials in the same layout as k_lsqr_pass.
+// Requires m + 1 <= 256 and the LDS of lsqr_pass1_lds.
+template <typename T, int CH>
+__global__ void __launch_bounds__(256) k_lsqr_pass1(SolveDev d, LsqrDev L, int first) {
+  if (*L.alldone) return;
+  extern __shared__ double p1lds[];
+  constexpr int LD = CH + 1;
+  constexpr int VW = 16 / sizeof(T);   // elements per 16-byte load
+  const int tid = threadIdx.x;
+  const int m = d.m, m1 = m + 1;
+  T* Vs = reinterpret_cast<T*>(p1lds);                                    // [m][LD]
+  double* us = p1lds + ((long long)m * LD * (long long)sizeof(T) + 7) / 8;   // [CH]
+  double* cfs = us + CH;                                                  // [m]
+  const T* __restrict__ V = (const T*)d.V;
+  const long long nel = d.n;
+  const double a = first ? 0.0 : L.st[5 * m1 + LS_A];
+  const double em = d.eta[m];
+  for (int j = tid; j < m; j += 256) cfs[j] = first ? 0.0 : L.st[3 * m1 + j];
+  double dacc = 0.0;
+  const int items = m * (CH / VW);   // 16-byte pieces of the staged tile
+  const long long nchunk = (nel + CH - 1) / CH;
+  for (long long c = blockIdx.x; c < nchunk; c += gridDim.x) {
+    const long long e0 = c * CH;
+    __syncthreads();   // the previous chunk's dots are done with Vs and us
+    for (int x0 = tid; x0 < items; x0 += 256 * 8) {
+      T w[8][VW];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int x = x0 + 256 * r;
+        const int j = x / (CH / VW), t = (x - j * (CH / VW)) * VW;
+        const long long e = e0 + t;
+        if (x < items && e + VW <= nel) {
+          const T* src = V + (long long)j * d.ldv + e;
+          if constexpr (VW == 4) {
+            const float4 f = *reinterpret_cast<const float4*>(src);
+            w[r][0] = f.x; w[r][1] = f.y; w[r][2] = f.z; w[r][3] = f.w;
+          } else {
+            const double2 f = *reinterpret_cast<const double2*>(src);
+            w[r][0] = f.x; w[r][1] = f.y;
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < VW; ++v) w[r][v] = (x < items && e + v < nel) ? V[(long long)j * d.ldv + e + v] : (T)0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int x = x0 + 256 * r;
+        if (x < items) {
+          const int j = x / (CH / VW), t = (x - j * (CH / VW)) * VW;
+#pragma unroll
+          for (int v = 0; v < VW; ++v) Vs[j * LD + t + v] = w[r][v];
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < CH) {
+      const long long e = e0 + tid;
+      double un = 0.0;
+      if (e < nel) {
+        if (first) {
+          un = (double)V[(long long)m * d.ldv + e] / em;
+        } else {
+          un = -a * L.u[e];
+          for (int j = 0; j < m; ++j) un += cfs[j] * (double)Vs[j * LD + tid];
+        }
+        L.u[e] = un;
+      }
+      us[tid] = un;
+    }
+    __syncthreads();
+    if (tid < m) {
+      const T* row = Vs + tid * LD;
+      double sdot = 0.0;
+      for (int t = 0; t < CH; ++t) sdot += (double)row[t] * us[t];
+      dacc += sdot;
+    } else if (tid == m) {
+      double sdot = 0.0;
+      for (int t = 0; t < CH; ++t) sdot += us[t] * us[t];
+      dacc += sdot;
+    }
+  }
+  if (tid < m1) L.part[(long long)blockIdx.x * m1 + tid] = dacc;
 }
 
 // X = R_m^{-1} and X^T for the LSQR steps, computed once per refinement, so
@@ -728,6 +830,18 @@ void step_launch(const SolveDev& d, const DenseDev& g, const LsqrDev& L, hipStre
   hipLaunchKernelGGL(k_lsqr_step, dim3(d.nrhs), dim3(256), 0, st, d, g, L, first);
 }
 void lsqr_pass_launch(const SolveDev& d, const LsqrDev& L, int esize, hipStream_t st, int first) {
+  const int ch = lsqr_pass1_chunk(d.m, d.nrhs, esize);
+  if (ch) {
+    const size_t lds = lsqr_pass1_lds(d.m, ch, esize);
+    if (esize == 4) {
+      if (ch == 128) hipLaunchKernelGGL((k_lsqr_pass1<float, 128>), dim3(L.nblk), dim3(256), lds, st, d, L, first);
+      else hipLaunchKernelGGL((k_lsqr_pass1<float, 64>), dim3(L.nblk), dim3(256), lds, st, d, L, first);
+    } else {
+      if (ch == 128) hipLaunchKernelGGL((k_lsqr_pass1<double, 128>), dim3(L.nblk), dim3(256), lds, st, d, L, first);
+      else hipLaunchKernelGGL((k_lsqr_pass1<double, 64>), dim3(L.nblk), dim3(256), lds, st, d, L, first);
+    }
+    return;
+  }
   const size_t lds = lsqr_pass_lds(d.m, d.nrhs);
   if (esize == 4) pass_launch_t<float>(d, L, st, first, lds);
   else pass_launch_t<double>(d, L, st, first, lds);
@@ -789,6 +903,10 @@ hipError_t lsqr_set_attributes() {
   hipError_t e = hipSuccess, r;
   const void* passes[4] = {(const void*)k_lsqr_pass<float, true>, (const void*)k_lsqr_pass<float, false>,
                            (const void*)k_lsqr_pass<double, true>, (const void*)k_lsqr_pass<double, false>};
+  const void* passes1[4] = {(const void*)k_lsqr_pass1<float, 128>, (const void*)k_lsqr_pass1<float, 64>,
+                            (const void*)k_lsqr_pass1<double, 128>, (const void*)k_lsqr_pass1<double, 64>};
+  for (const void* k : passes1)
+    if ((r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024)) != hipSuccess) e = r;
   for (const void* k : passes)
     if ((r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024)) != hipSuccess) e = r;
   if ((r = hipFuncSetAttribute((const void*)k_vgram_solve, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -81,6 +81,7 @@ constexpr double WH_THRESH = 1000.0;
 constexpr int RC_RERUN_FP64 = 100;
 size_t lsqr_state_stride(int m);
 size_t lsqr_pass_lds(int m, int nrhs);
+int lsqr_pass1_chunk(int m, int nrhs, int esize);
 hipError_t gather_cols(const ColPtrs& src, int logg, long long n, double* dst, hipStream_t st);
 hipError_t scatter_cols(const double* src, int logg, long long n, const OutPtrs& dst, hipStream_t st);
 // Per-device address of the static scratch of fab_solve_noalloc (noalloc.hip).
@@ -410,7 +411,9 @@ int make_plan(fab_matrix A, int nrhs, const fab_func& fin, const fab_params* pp,
     if (!fits && (p.ls_mode == FAB_LS_LSQR || p.ls_mode == FAB_LS_GRAM || bg || whiten)) return FAB_EINVAL;
     if (fits) {
       P.lsqr = true;
-      P.lnblk = (int)std::min<long long>((nel + 2047) / 2048, 512);
+      // the one-read pass (one rhs) loops over chunks of ch elements
+      const int ch = lsqr_pass1_chunk(m, nrhs, esize);
+      P.lnblk = (int)std::min<long long>((nel + (ch ? ch : 2048) - 1) / (ch ? ch : 2048), 512);
       P.oLu = take((size_t)nel * 8);
       P.oLpart = take((size_t)P.lnblk * nrhs * (m + 1) * 8);
       P.oLst = take((size_t)nrhs * lsqr_state_stride(m) * 8);
